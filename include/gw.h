@@ -1,0 +1,166 @@
+/*
+ * gw.h - C ABI of libgw.so: entropic Gromov-Wasserstein on uniform grids for
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The operations follow arXiv 2404.08970 ("Fast Gradient Computation for
+ * Gromov-Wasserstein Distance"):
+ *   - grids and distance matrices: Sec. 2, Eq. (1d distance matrices);
+ *     2D grids Sec. 3.1, Eq. (2d Dx);
+ *   - gradient: Sec. 2, the decomposition C_1 - 4 D_X Gamma D_Y that follows
+ *     Eq. (gradient entry); the fast evaluation of D_X Gamma D_Y is Sec. 3,
+ *     Eq. (Dx), Eq. (1d recursive relation) and Eq. (2D kronecker);
+ *   - Sinkhorn sub-problem: Sec. 2.1, Eq. (GW sinkhorn) with tau = eps (Remark);
+ *   - solve: mirror descent, Sec. 2.1, Eq. (GW proximal gradient).
+ *
+ * Conventions shared by every call:
+ *   - Matrices are row-major FP64 (unless a path says otherwise) with a leading
+ *     dimension in elements.  Pointers marked "device" are device pointers that
+ *     must be 8-byte aligned; the workspace must be 256-byte aligned.
+ *   - Every call is asynchronous on `stream` (a hipStream_t; NULL = the null
+ *     stream).  A return of GW_OK means the arguments were valid and the work
+ *     was enqueued.  On any other return nothing was enqueued.
+ *   - The caller owns every buffer, including the workspace sized by
+ *     gw_workspace_bytes().  The library never frees caller memory and does not
+ *     allocate device memory on these calls.
+ *   - Marginals are expected to be non-negative, finite and to sum to 1; zero
+ *     entries are allowed (their potential is -inf and their plan row/column
+ *     is zero).  These preconditions are documented, not checked per call.
+ */
+#ifndef GW_H
+#define GW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t gw_status;
+#define GW_OK 0
+#define GW_EINVAL (-1)        /* invalid argument (null/misaligned pointer, bad size, bad scalar) */
+#define GW_ENOMEM (-2)        /* workspace too small */
+#define GW_EDEVICE (-3)       /* a HIP runtime call failed */
+#define GW_ENUMERIC (-4)      /* device detected a non-finite value (gw_check_status) */
+#define GW_EUNSUPPORTED (-5)  /* valid request outside what this build implements */
+
+/* Distance on a grid (Sec. 2 and Sec. 3.1).
+ *   GW_METRIC_L1POW:    h^k * (|dr| + |dc|)^k; in 1D h^k * |i - j|^k.
+ *   GW_METRIC_SQEUCLID: h^2 * (dr^2 + dc^2) (requires k = 2; in 1D equal to
+ *                       L1POW with k = 2). */
+#define GW_METRIC_L1POW 0
+#define GW_METRIC_SQEUCLID 1
+
+#define GW_KMAX 4
+
+/* Gradient evaluation paths.
+ *   FAST_F64:   the paper's exact O(MN) recursion (Sec. 3), FP64.
+ *   DENSE_F64:  the plain product D_X T D_Y on FP64 matrix cores (the O(N^3)
+ *               "original" computation), distance tiles generated from indices.
+ *   DENSE_F32:  as DENSE_F64 with FP32 inputs and FP32 accumulation.
+ *   DENSE_BF16: BF16 inputs, FP32 accumulation.
+ *   DENSE_BF16_SPLIT / DENSE_F32_SPLIT: split-precision refinement (the
+ *               inputs are split into a high and a low part and the leading
+ *               cross products are accumulated in FP64 over K-chunks). */
+#define GW_PATH_FAST_F64 0
+#define GW_PATH_DENSE_F64 1
+#define GW_PATH_DENSE_F32 2
+#define GW_PATH_DENSE_BF16 3
+#define GW_PATH_DENSE_BF16_SPLIT 4
+#define GW_PATH_DENSE_F32_SPLIT 5
+
+#define GW_OP_GRAD 0
+#define GW_OP_SINKHORN 1
+#define GW_OP_SOLVE 2
+#define GW_OP_OBJECTIVE 3
+
+/* gw_solve flags */
+#define GW_FLAG_WARM_START 1  /* Sinkhorn starts from the previous outer step's potentials */
+
+/* A uniform grid (Sec. 2; Sec. 3.1).  ndim = 1: shape = {n, 1}; ndim = 2:
+ * shape = {H, W}, points flattened row-major (flat = r * W + c).  h > 0 is the
+ * spacing, k in [1, GW_KMAX] the exponent, metric one of GW_METRIC_*. */
+typedef struct gw_grid {
+  int32_t ndim;
+  int32_t k;
+  int32_t metric;
+  int32_t reserved; /* must be 0 */
+  int64_t shape[2];
+  double h;
+} gw_grid;
+
+/* Bytes of device workspace needed by `op` (GW_OP_*) for grids X (rows, M
+ * points) and Y (columns, N points) on `path` (GW_PATH_*; ignored for
+ * GW_OP_SINKHORN).  Returns 0 for invalid arguments.  Host-only arithmetic. */
+size_t gw_workspace_bytes(const gw_grid* X, const gw_grid* Y, int32_t path, int32_t op);
+
+/* G = c1 1^T + 1 c2^T - 2 D_X T D_Y with c1 = (D_X o D_X) p, c2 = (D_Y o D_Y) q
+ * (Sec. 2, decomposition after Eq. (gradient entry); G is half of the paper's
+ * gradient).  X has M points, Y has N points.
+ *   p [M], q [N], T [M x N, ldT >= N], G [M x N, ldG >= N]: device FP64.
+ *   G must not overlap T.  ws: device workspace of ws_bytes bytes. */
+gw_status gw_grad(const gw_grid* X, const gw_grid* Y, const double* p, const double* q,
+                  const double* T, int64_t ldT, double* G, int64_t ldG, int32_t path, void* ws,
+                  size_t ws_bytes, void* stream);
+
+/* Log-domain Sinkhorn for min <C_eff, P> + eps H(P) over couplings of (p, q),
+ * C_eff = c_scale * C (Sec. 2.1, Eq. (GW sinkhorn) is this problem with
+ * C_eff = the gradient).  One iteration sets
+ *   f_i = eps ln p_i - eps LSE_p((g_p - C_eff_ip)/eps), then
+ *   g_p = eps ln q_p - eps LSE_i((f_i - C_eff_ip)/eps).
+ * If init_zero != 0 the potentials start at 0, else at the values in f, g.
+ *   C [M x N, ldC >= N], p [M], q [N]: device FP64 inputs.
+ *   f [M], g [N]: device FP64 in/out.
+ *   T: optional (may be NULL) device FP64 [M x N, ldT >= N]; receives the plan
+ *      P_ip = exp((f_i + g_p - C_eff_ip)/eps) after the last iteration.
+ * Requires N <= 16384 (a row is held on chip) and eps > 0. */
+gw_status gw_sinkhorn(const double* C, int64_t ldC, int64_t M, int64_t N, double c_scale,
+                      const double* p, const double* q, double eps, int32_t iters,
+                      int32_t init_zero, double* f, double* g, double* T, int64_t ldT, void* ws,
+                      size_t ws_bytes, void* stream);
+
+/* Entropic GW by mirror descent with tau = eps (Sec. 2.1): T^0 = p q^T, then
+ * `outer` times { G = gw_grad(T); Sinkhorn on the cost 2G with `inner`
+ * iterations; T = its plan }.  Afterwards obj[0] = E(T) (the QAP objective of
+ * Sec. 2 with T's own marginals) and obj[1] = E(T) + eps H(T).
+ *   p [M], q [N]: device FP64.  T [M x N, ldT >= N], f [M], g [N]: device FP64
+ *   outputs.  obj: device double[2] (may be NULL to skip the objective).
+ *   flags: GW_FLAG_*. */
+gw_status gw_solve(const gw_grid* X, const gw_grid* Y, const double* p, const double* q,
+                   double eps, int32_t outer, int32_t inner, int32_t path, int32_t flags,
+                   double* T, int64_t ldT, double* f, double* g, double* obj, void* ws,
+                   size_t ws_bytes, void* stream);
+
+/* obj[0] = E(T), obj[1] = E(T) + eps H(T) for an arbitrary non-negative T
+ * (Sec. 2, discrete objective and Eq. (entropic GW)).  T [M x N]: device FP64;
+ * obj: device double[2]. */
+gw_status gw_objective(const gw_grid* X, const gw_grid* Y, const double* T, int64_t ldT,
+                       double eps, double* obj, void* ws, size_t ws_bytes, void* stream);
+
+/* Human-readable name of a status code (static storage). */
+const char* gw_status_string(gw_status s);
+
+/* Waits for `stream`, then reports GW_EDEVICE if a HIP error is pending and
+ * GW_ENUMERIC if a kernel that used workspace `ws` (may be NULL) flagged a
+ * non-finite value since the workspace was last cleared; the flag is cleared. */
+gw_status gw_check_status(void* ws, void* stream);
+
+/* Kernel timing with HIP events on the launching stream.  Families:
+ *   0 fast-gradient main tile kernel, 1 fast-gradient carry/moment kernels,
+ *   2 dense gradient GEMMs, 3 Sinkhorn row pass, 4 Sinkhorn column merge,
+ *   5 plan materialisation, 6 other (init, objective, constant terms),
+ *   7 2D gradient kernels.
+ * gw_profile_enable(1) starts recording (and clears counts); gw_profile_read
+ * waits for the recorded events and returns total milliseconds and launch
+ * count of a family.  Timing adds an event pair around each launch. */
+void gw_profile_enable(int32_t on);
+gw_status gw_profile_read(int32_t family, double* total_ms, int64_t* launches);
+
+/* Library version string. */
+const char* gw_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GW_H */

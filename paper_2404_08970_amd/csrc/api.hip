@@ -1,0 +1,396 @@
+// C ABI entry points of libgw.so: argument validation, workspace layout,
+// dispatch to the kernel launchers, status reporting and kernel timing.
+#include <math.h>
+#include <string.h>
+
+#include <mutex>
+#include <vector>
+
+#include "runtime.h"
+
+namespace gwr {
+
+static const int64_t kMaxExtent = 65535;
+
+gw_status to_grid(const gw_grid* g, Grid* out) {
+  if (!g) return GW_EINVAL;
+  if (g->reserved != 0) return GW_EINVAL;
+  if (g->ndim != 1 && g->ndim != 2) return GW_EINVAL;
+  if (g->metric != GW_METRIC_L1POW && g->metric != GW_METRIC_SQEUCLID) return GW_EINVAL;
+  if (g->k < 1 || g->k > GW_KMAX) return GW_EINVAL;
+  if (g->metric == GW_METRIC_SQEUCLID && g->k != 2) return GW_EINVAL;
+  if (!(g->h > 0.0) || !isfinite(g->h)) return GW_EINVAL;
+  if (g->shape[0] < 1 || g->shape[1] < 1) return GW_EINVAL;
+  if (g->ndim == 1 && g->shape[1] != 1) return GW_EINVAL;
+  Grid r;
+  r.ndim = g->ndim;
+  r.k = g->k;
+  r.metric = g->metric;
+  r.h = g->h;
+  if (g->ndim == 1) {
+    r.H = 1;
+    r.W = g->shape[0];
+  } else {
+    r.H = g->shape[0];
+    r.W = g->shape[1];
+  }
+  if (r.H > kMaxExtent || r.W > kMaxExtent || r.n() > kMaxExtent) return GW_EUNSUPPORTED;
+  *out = r;
+  return GW_OK;
+}
+
+size_t ws_status_bytes() { return 256; }
+
+size_t ws_grad_bytes(const Grid& X, const Grid& Y, int path) {
+  if (path == GW_PATH_FAST_F64) {
+    if (X.ndim == 1 && Y.ndim == 1) return gwl::fast1d_ws_bytes(X, Y);
+    return gwl::fast_generic_ws_bytes(X, Y);
+  }
+  return gwl::dense_ws_bytes(X, Y, path);
+}
+
+size_t ws_sinkhorn_bytes(int64_t M, int64_t N) { return gwl::sinkhorn_ws_bytes(M, N); }
+
+// Objective scratch after the M x N gradient buffer: marginals, the FAST
+// gradient's own workspace and the reduction partials.
+size_t ws_objective_tail_bytes(const Grid& X, const Grid& Y) {
+  Arena a{nullptr, 0, 0};
+  a.take<double>(X.n());  // row sums
+  a.take<double>(Y.n());  // column sums
+  return a.used + ws_grad_bytes(X, Y, GW_PATH_FAST_F64) +
+         gwl::objective_reduce_ws_bytes(X.n(), Y.n());
+}
+
+size_t ws_objective_bytes(const Grid& X, const Grid& Y) {
+  Arena a{nullptr, 0, 0};
+  a.take<double>((size_t)X.n() * Y.n());  // gradient at T's own marginals
+  return a.used + ws_objective_tail_bytes(X, Y);
+}
+
+// ------------------------------------------------------------------ timing
+namespace {
+struct ProfState {
+  std::mutex mu;
+  bool on = false;
+  std::vector<hipEvent_t> pool[kNumFamilies];
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[kNumFamilies];
+  size_t used[kNumFamilies] = {};
+  double total_ms[kNumFamilies] = {};
+  int64_t launches[kNumFamilies] = {};
+  hipEvent_t open[kNumFamilies] = {};
+};
+ProfState& prof() {
+  static ProfState* p = new ProfState();
+  return *p;
+}
+hipEvent_t pool_event(ProfState& P, int fam) {
+  if (P.used[fam] < P.pool[fam].size()) return P.pool[fam][P.used[fam]++];
+  hipEvent_t e;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  P.pool[fam].push_back(e);
+  P.used[fam]++;
+  return e;
+}
+void drain(ProfState& P, int fam) {
+  for (auto& pr : P.pending[fam]) {
+    float ms = 0.f;
+    if (hipEventSynchronize(pr.second) == hipSuccess &&
+        hipEventElapsedTime(&ms, pr.first, pr.second) == hipSuccess) {
+      P.total_ms[fam] += ms;
+      P.launches[fam] += 1;
+    }
+  }
+  P.pending[fam].clear();
+  P.used[fam] = 0;
+}
+}  // namespace
+
+void prof_begin(int fam, hipStream_t s) {
+  ProfState& P = prof();
+  if (!P.on) return;
+  std::lock_guard<std::mutex> g(P.mu);
+  if (P.used[fam] + 2 > 4096) drain(P, fam);
+  hipEvent_t e = pool_event(P, fam);
+  if (e) (void)hipEventRecord(e, s);
+  P.open[fam] = e;
+}
+
+void prof_end(int fam, hipStream_t s) {
+  ProfState& P = prof();
+  if (!P.on) return;
+  std::lock_guard<std::mutex> g(P.mu);
+  hipEvent_t b = P.open[fam];
+  hipEvent_t e = pool_event(P, fam);
+  if (b && e) {
+    (void)hipEventRecord(e, s);
+    P.pending[fam].push_back({b, e});
+  }
+  P.open[fam] = nullptr;
+}
+
+}  // namespace gwr
+
+using gwr::Arena;
+using gwr::Grid;
+
+namespace {
+
+bool aligned8(const void* p) { return ((uintptr_t)p & 7u) == 0; }
+bool aligned256(const void* p) { return ((uintptr_t)p & 255u) == 0; }
+
+bool overlaps(const void* a, size_t an, const void* b, size_t bn) {
+  const char* ca = (const char*)a;
+  const char* cb = (const char*)b;
+  return ca < cb + bn && cb < ca + an;
+}
+
+gw_status check_matrix(const double* ptr, int64_t rows, int64_t cols, int64_t ld) {
+  if (!ptr || !aligned8(ptr)) return GW_EINVAL;
+  if (ld < cols) return GW_EINVAL;
+  if (rows > 0 && ld > (int64_t(1) << 40) / rows) return GW_EINVAL;
+  return GW_OK;
+}
+
+gw_status check_vec(const double* ptr) { return (ptr && aligned8(ptr)) ? GW_OK : GW_EINVAL; }
+
+gw_status check_ws(void* ws, size_t ws_bytes, size_t need) {
+  if (need > ws_bytes) return GW_ENOMEM;
+  if (need > 0 && (!ws || !aligned256(ws))) return GW_EINVAL;
+  return GW_OK;
+}
+
+gwr::StatusWord* status_of(void* ws) { return reinterpret_cast<gwr::StatusWord*>(ws); }
+
+size_t grad_need(const Grid& X, const Grid& Y, int path) {
+  return gwr::ws_status_bytes() + gwr::ws_grad_bytes(X, Y, path);
+}
+
+bool path_valid(int path) { return path >= GW_PATH_FAST_F64 && path <= GW_PATH_DENSE_F32_SPLIT; }
+
+gw_status run_grad(const Grid& X, const Grid& Y, const double* p, const double* q,
+                   const double* T, int64_t ldT, double* G, int64_t ldG, int path, Arena& a,
+                   hipStream_t s, const double* c1, const double* c2) {
+  if (path == GW_PATH_FAST_F64) {
+    if (X.ndim == 1 && Y.ndim == 1) return gwl::fast1d(X, Y, p, q, T, ldT, G, ldG, a, s, c1, c2);
+    return gwl::fast_generic(X, Y, p, q, T, ldT, G, ldG, a, s, c1, c2);
+  }
+  return gwl::dense(X, Y, p, q, T, ldT, G, ldG, path, a, s, c1, c2);
+}
+
+size_t solve_need(const Grid& X, const Grid& Y, int path) {
+  const int64_t M = X.n(), N = Y.n();
+  Arena a{nullptr, 0, 0};
+  a.take<char>(gwr::ws_status_bytes());
+  a.take<double>((size_t)M * N);  // G
+  a.take<double>(M);              // c1
+  a.take<double>(N);              // c2
+  size_t tail = gwr::ws_grad_bytes(X, Y, path);
+  const size_t sk = gwr::ws_sinkhorn_bytes(M, N);
+  if (sk > tail) tail = sk;
+  const size_t ob = gwr::ws_objective_tail_bytes(X, Y);  // the objective reuses G
+  if (ob > tail) tail = ob;
+  return a.used + tail;
+}
+
+gw_status run_objective(const Grid& X, const Grid& Y, const double* T, int64_t ldT, double eps,
+                        double* obj, double* Gbuf, Arena& a, hipStream_t s,
+                        gwr::StatusWord* status) {
+  const int64_t M = X.n(), N = Y.n();
+  double* r = a.take<double>(M);
+  double* c = a.take<double>(N);
+  gw_status st = gwl::marginals(T, ldT, M, N, r, c, a, s);
+  if (st != GW_OK) return st;
+  st = run_grad(X, Y, r, c, T, ldT, Gbuf, N, GW_PATH_FAST_F64, a, s, nullptr, nullptr);
+  if (st != GW_OK) return st;
+  return gwl::objective_reduce(Gbuf, N, T, ldT, M, N, eps, obj, a, s, status);
+}
+
+__global__ void k_clear_status(gwr::StatusWord* st) { st->nonfinite = 0; }
+
+}  // namespace
+
+extern "C" {
+
+size_t gw_workspace_bytes(const gw_grid* Xp, const gw_grid* Yp, int32_t path, int32_t op) {
+  Grid X, Y;
+  if (gwr::to_grid(Xp, &X) != GW_OK || gwr::to_grid(Yp, &Y) != GW_OK) return 0;
+  switch (op) {
+    case GW_OP_GRAD:
+      if (!path_valid(path)) return 0;
+      return grad_need(X, Y, path);
+    case GW_OP_SINKHORN:
+      return gwr::ws_status_bytes() + gwr::ws_sinkhorn_bytes(X.n(), Y.n());
+    case GW_OP_SOLVE:
+      if (!path_valid(path)) return 0;
+      return solve_need(X, Y, path);
+    case GW_OP_OBJECTIVE:
+      return gwr::ws_status_bytes() + gwr::ws_objective_bytes(X, Y);
+  }
+  return 0;
+}
+
+gw_status gw_grad(const gw_grid* Xp, const gw_grid* Yp, const double* p, const double* q,
+                  const double* T, int64_t ldT, double* G, int64_t ldG, int32_t path, void* ws,
+                  size_t ws_bytes, void* stream) {
+  Grid X, Y;
+  gw_status st;
+  if ((st = gwr::to_grid(Xp, &X)) != GW_OK) return st;
+  if ((st = gwr::to_grid(Yp, &Y)) != GW_OK) return st;
+  if (!path_valid(path)) return GW_EINVAL;
+  const int64_t M = X.n(), N = Y.n();
+  if ((st = check_vec(p)) != GW_OK || (st = check_vec(q)) != GW_OK) return st;
+  if ((st = check_matrix(T, M, N, ldT)) != GW_OK) return st;
+  if ((st = check_matrix(G, M, N, ldG)) != GW_OK) return st;
+  if (overlaps(T, sizeof(double) * ((M - 1) * ldT + N), G, sizeof(double) * ((M - 1) * ldG + N)))
+    return GW_EINVAL;
+  if ((st = check_ws(ws, ws_bytes, grad_need(X, Y, path))) != GW_OK) return st;
+  if (path != GW_PATH_FAST_F64 && (X.ndim != 1 || Y.ndim != 1)) return GW_EUNSUPPORTED;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  Arena a{static_cast<char*>(ws), 0, ws_bytes};
+  a.take<char>(gwr::ws_status_bytes());
+  return run_grad(X, Y, p, q, T, ldT, G, ldG, path, a, s, nullptr, nullptr);
+}
+
+gw_status gw_sinkhorn(const double* C, int64_t ldC, int64_t M, int64_t N, double c_scale,
+                      const double* p, const double* q, double eps, int32_t iters,
+                      int32_t init_zero, double* f, double* g, double* T, int64_t ldT, void* ws,
+                      size_t ws_bytes, void* stream) {
+  gw_status st;
+  if (M < 1 || N < 1) return GW_EINVAL;
+  if (M > gwr::kMaxExtent || N > gwr::kMaxExtent) return GW_EUNSUPPORTED;
+  if (N > 16384) return GW_EUNSUPPORTED;
+  if (!(eps > 0.0) || !isfinite(eps) || !isfinite(c_scale) || iters < 0) return GW_EINVAL;
+  if ((st = check_matrix(C, M, N, ldC)) != GW_OK) return st;
+  if ((st = check_vec(p)) != GW_OK || (st = check_vec(q)) != GW_OK) return st;
+  if ((st = check_vec(f)) != GW_OK || (st = check_vec(g)) != GW_OK) return st;
+  if (T && (st = check_matrix(T, M, N, ldT)) != GW_OK) return st;
+  const size_t need = gwr::ws_status_bytes() + gwr::ws_sinkhorn_bytes(M, N);
+  if ((st = check_ws(ws, ws_bytes, need)) != GW_OK) return st;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  Arena a{static_cast<char*>(ws), 0, ws_bytes};
+  a.take<char>(gwr::ws_status_bytes());
+  return gwl::sinkhorn(C, ldC, M, N, c_scale, p, q, eps, iters, init_zero, f, g, T, ldT, a, s,
+                       status_of(ws));
+}
+
+gw_status gw_solve(const gw_grid* Xp, const gw_grid* Yp, const double* p, const double* q,
+                   double eps, int32_t outer, int32_t inner, int32_t path, int32_t flags,
+                   double* T, int64_t ldT, double* f, double* g, double* obj, void* ws,
+                   size_t ws_bytes, void* stream) {
+  Grid X, Y;
+  gw_status st;
+  if ((st = gwr::to_grid(Xp, &X)) != GW_OK) return st;
+  if ((st = gwr::to_grid(Yp, &Y)) != GW_OK) return st;
+  if (!path_valid(path)) return GW_EINVAL;
+  if (!(eps > 0.0) || !isfinite(eps) || outer < 0 || inner < 0) return GW_EINVAL;
+  if (flags & ~GW_FLAG_WARM_START) return GW_EINVAL;
+  const int64_t M = X.n(), N = Y.n();
+  if (N > 16384) return GW_EUNSUPPORTED;
+  if ((st = check_vec(p)) != GW_OK || (st = check_vec(q)) != GW_OK) return st;
+  if ((st = check_vec(f)) != GW_OK || (st = check_vec(g)) != GW_OK) return st;
+  if ((st = check_matrix(T, M, N, ldT)) != GW_OK) return st;
+  if (obj && !aligned8(obj)) return GW_EINVAL;
+  if ((st = check_ws(ws, ws_bytes, solve_need(X, Y, path))) != GW_OK) return st;
+  if (path != GW_PATH_FAST_F64 && (X.ndim != 1 || Y.ndim != 1)) return GW_EUNSUPPORTED;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  Arena a{static_cast<char*>(ws), 0, ws_bytes};
+  a.take<char>(gwr::ws_status_bytes());
+  double* G = a.take<double>((size_t)M * N);
+  double* c1 = a.take<double>(M);
+  double* c2 = a.take<double>(N);
+  const size_t mark = a.used;
+  if ((st = gwl::const_term(X, p, c1, s)) != GW_OK) return st;
+  if ((st = gwl::const_term(Y, q, c2, s)) != GW_OK) return st;
+  if ((st = gwl::outer_product(p, q, M, N, T, ldT, s)) != GW_OK) return st;
+  {
+    gwr::ProfScope ps(gwr::kFamOther, s);
+    k_clear_status<<<1, 1, 0, s>>>(status_of(ws));
+  }
+  for (int l = 0; l < outer; ++l) {
+    a.used = mark;
+    st = run_grad(X, Y, p, q, T, ldT, G, N, path, a, s, c1, c2);
+    if (st != GW_OK) return st;
+    a.used = mark;
+    const int cold = (flags & GW_FLAG_WARM_START) && l > 0 ? 0 : 1;
+    st = gwl::sinkhorn(G, N, M, N, 2.0, p, q, eps, inner, cold, f, g, T, ldT, a, s, status_of(ws));
+    if (st != GW_OK) return st;
+  }
+  if (obj) {
+    a.used = mark;
+    return run_objective(X, Y, T, ldT, eps, obj, G, a, s, status_of(ws));
+  }
+  return gwr::last_launch_status();
+}
+
+gw_status gw_objective(const gw_grid* Xp, const gw_grid* Yp, const double* T, int64_t ldT,
+                       double eps, double* obj, void* ws, size_t ws_bytes, void* stream) {
+  Grid X, Y;
+  gw_status st;
+  if ((st = gwr::to_grid(Xp, &X)) != GW_OK) return st;
+  if ((st = gwr::to_grid(Yp, &Y)) != GW_OK) return st;
+  if (!isfinite(eps) || eps < 0.0) return GW_EINVAL;
+  const int64_t M = X.n(), N = Y.n();
+  if ((st = check_matrix(T, M, N, ldT)) != GW_OK) return st;
+  if (!obj || !aligned8(obj)) return GW_EINVAL;
+  if ((st = check_ws(ws, ws_bytes, gwr::ws_status_bytes() + gwr::ws_objective_bytes(X, Y))) != GW_OK)
+    return st;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  Arena a{static_cast<char*>(ws), 0, ws_bytes};
+  a.take<char>(gwr::ws_status_bytes());
+  double* Gbuf = a.take<double>((size_t)M * N);
+  return run_objective(X, Y, T, ldT, eps, obj, Gbuf, a, s, status_of(ws));
+}
+
+const char* gw_status_string(gw_status s) {
+  switch (s) {
+    case GW_OK: return "GW_OK";
+    case GW_EINVAL: return "GW_EINVAL: invalid argument";
+    case GW_ENOMEM: return "GW_ENOMEM: workspace too small";
+    case GW_EDEVICE: return "GW_EDEVICE: HIP runtime error";
+    case GW_ENUMERIC: return "GW_ENUMERIC: non-finite value detected on the device";
+    case GW_EUNSUPPORTED: return "GW_EUNSUPPORTED: request outside this build's coverage";
+  }
+  return "unknown gw_status";
+}
+
+gw_status gw_check_status(void* ws, void* stream) {
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (hipStreamSynchronize(s) != hipSuccess) return GW_EDEVICE;
+  if (hipGetLastError() != hipSuccess) return GW_EDEVICE;
+  if (!ws) return GW_OK;
+  gwr::StatusWord w{0};
+  if (hipMemcpy(&w, ws, sizeof(w), hipMemcpyDeviceToHost) != hipSuccess) return GW_EDEVICE;
+  if (w.nonfinite) {
+    k_clear_status<<<1, 1, 0, s>>>(status_of(ws));
+    if (hipStreamSynchronize(s) != hipSuccess) return GW_EDEVICE;
+    return GW_ENUMERIC;
+  }
+  return GW_OK;
+}
+
+void gw_profile_enable(int32_t on) {
+  gwr::ProfState& P = gwr::prof();
+  std::lock_guard<std::mutex> g(P.mu);
+  for (int f = 0; f < gwr::kNumFamilies; ++f) {
+    P.pending[f].clear();
+    P.used[f] = 0;
+    P.total_ms[f] = 0.0;
+    P.launches[f] = 0;
+    P.open[f] = nullptr;
+  }
+  P.on = on != 0;
+}
+
+gw_status gw_profile_read(int32_t family, double* total_ms, int64_t* launches) {
+  if (family < 0 || family >= gwr::kNumFamilies || !total_ms || !launches) return GW_EINVAL;
+  gwr::ProfState& P = gwr::prof();
+  std::lock_guard<std::mutex> g(P.mu);
+  gwr::drain(P, family);
+  *total_ms = P.total_ms[family];
+  *launches = P.launches[family];
+  return GW_OK;
+}
+
+const char* gw_version(void) { return "libgw 0.1 (gfx950)"; }
+
+}  // extern "C"

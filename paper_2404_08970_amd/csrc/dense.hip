@@ -1,0 +1,157 @@
+// Dense ("original", O(N^3)) gradient on matrix cores: G = c1 1^T + 1 c2^T -
+// 2 h_X^k h_Y^k D~_X T D~_Y, as two GEMMs (Sec. 2, the decomposition after
+// Eq. (gradient entry); Sec. 5 calls this the original computation).  The
+// integer distance operand is generated from its indices inside the kernel,
+// so only T and the intermediate A = T D~_Y move through memory.
+//
+// FP64 path: v_mfma_f64_16x16x4f64.  Lower-precision paths (FP32, BF16 and
+// their split refinements) live in dense_lp.hip.
+#include "common.h"
+#include "runtime.h"
+
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+constexpr int BM = 64, BN = 64, BK = 16;
+constexpr int NTHR = 256;
+
+// C = op(A) * op(B) where exactly one operand is the distance matrix
+// |i-j|^kd generated from indices.
+//   SYN_B: C[M x N] = A[M x K] (memory, lda) * D[K x N]  (D[k][n] = |k-n|^kd)
+//   !SYN_B: C[M x N] = D[M x K] (D[m][k] = |m-k|^kd) * B[K x N] (memory, ldb)
+// Epilogue: if c1 != null, C = (c1[m] + c2[n]) - s2 * acc; else C = acc.
+template <bool SYN_B>
+__global__ __launch_bounds__(NTHR) void k_dense_f64(const double* __restrict__ Amem, int64_t lda,
+                                                     int M, int N, int K, int kd,
+                                                     double* __restrict__ C, int64_t ldc,
+                                                     const double* __restrict__ c1,
+                                                     const double* __restrict__ c2, double s2) {
+  // SYN_B: stage A tile [BM][BK]; else stage B tile [BK][BN].
+  __shared__ double As[SYN_B ? BM : BK][SYN_B ? BK + 1 : BN + 1];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;  // wave tile origin in block
+  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  d4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+  const int li = lane & 15, lk = lane >> 4;  // operand lane mapping
+  for (int k0 = 0; k0 < K; k0 += BK) {
+    __syncthreads();
+    if (SYN_B) {
+      // A tile: 64 rows x 16 k; thread t loads row t/4, k (t%4)*4 .. +4
+      const int r = t >> 2, kk = (t & 3) * 4;
+      const int gm = m0 + r;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int gk = k0 + kk + u;
+        As[r][kk + u] = (gm < M && gk < K) ? Amem[(int64_t)gm * lda + gk] : 0.0;
+      }
+    } else {
+      // B tile: 16 k x 64 cols; thread t loads row t/16, cols (t%16)*4 .. +4
+      const int r = t >> 4, cc = (t & 15) * 4;
+      const int gk = k0 + r;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int gn = n0 + cc + u;
+        As[r][cc + u] = (gk < K && gn < N) ? Amem[(int64_t)gk * lda + gn] : 0.0;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < BK; ks += 4) {
+      const int kg = k0 + ks + lk;  // global k of this lane's operand element
+      double a[2], b[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const int row = wm + i * 16 + li;
+        if (SYN_B) {
+          a[i] = As[row][ks + lk];
+        } else {
+          const int gm = m0 + row;
+          const int d = gm > kg ? gm - kg : kg - gm;
+          a[i] = gwk::ipow((double)d, kd);
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int col = wn + j * 16 + li;
+        if (SYN_B) {
+          const int gn = n0 + col;
+          const int d = gn > kg ? gn - kg : kg - gn;
+          b[j] = gwk::ipow((double)d, kd);
+        } else {
+          b[j] = As[ks + lk][col];
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+  }
+  // store: for the FP64 16x16x4 instruction, accumulator slot v of a lane holds
+  // row 4 * v + lane / 16 and column lane % 16 of its 16 x 16 block
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int gm = m0 + wm + i * 16 + 4 * v + lk;
+        const int gn = n0 + wn + j * 16 + li;
+        if (gm < M && gn < N) {
+          const double x = acc[i][j][v];
+          C[(int64_t)gm * ldc + gn] = c1 ? (c1[gm] + c2[gn]) - s2 * x : x;
+        }
+      }
+}
+
+}  // namespace
+
+namespace gwl {
+
+gw_status dense_lp(const gwr::Grid& X, const gwr::Grid& Y, const double* T, int64_t ldT,
+                   double* G, int64_t ldG, int path, gwr::Arena& ws, hipStream_t s,
+                   const double* c1, const double* c2);
+size_t dense_lp_ws_bytes(const gwr::Grid& X, const gwr::Grid& Y, int path);
+
+size_t dense_ws_bytes(const gwr::Grid& X, const gwr::Grid& Y, int path) {
+  gwr::Arena a{nullptr, 0, 0};
+  a.take<double>(X.n());
+  a.take<double>(Y.n());
+  if (path == GW_PATH_DENSE_F64) {
+    a.take<double>((size_t)X.n() * Y.n());
+    return a.used;
+  }
+  return a.used + dense_lp_ws_bytes(X, Y, path);
+}
+
+gw_status dense(const gwr::Grid& X, const gwr::Grid& Y, const double* p, const double* q,
+                const double* T, int64_t ldT, double* G, int64_t ldG, int path, gwr::Arena& ws,
+                hipStream_t s, const double* c1_pre, const double* c2_pre) {
+  if (X.ndim != 1 || Y.ndim != 1) return GW_EUNSUPPORTED;
+  const int M = (int)X.n(), N = (int)Y.n();
+  double* c1 = ws.take<double>(M);
+  double* c2 = ws.take<double>(N);
+  gw_status st;
+  if (c1_pre) c1 = const_cast<double*>(c1_pre);
+  else if ((st = const_term(X, p, c1, s)) != GW_OK) return st;
+  if (c2_pre) c2 = const_cast<double*>(c2_pre);
+  else if ((st = const_term(Y, q, c2, s)) != GW_OK) return st;
+  const double s2 = 2.0 * (X.hk() * Y.hk());
+  if (path != GW_PATH_DENSE_F64) return dense_lp(X, Y, T, ldT, G, ldG, path, ws, s, c1, c2);
+  double* A = ws.take<double>((size_t)M * N);
+  gwr::ProfScope ps(gwr::kFamDense, s);
+  dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM);
+  // A = T D~_Y
+  k_dense_f64<true><<<grid, NTHR, 0, s>>>(T, ldT, M, N, N, Y.k1d(), A, N, nullptr, nullptr, 0.0);
+  // B = D~_X A, G = (c1 + c2) - s2 B
+  k_dense_f64<false><<<grid, NTHR, 0, s>>>(A, N, M, N, M, X.k1d(), G, ldG, c1, c2, s2);
+  return gwr::last_launch_status();
+}
+
+}  // namespace gwl

@@ -1,0 +1,405 @@
+// Constant terms and the FAST gradient for grids that are not both 1D.
+//
+// Constant terms c = (D o D) w are evaluated directly, O(n^2) per vector, as
+// the paper does once per solve (Sec. 2, "computed once").
+//
+// 2D grids (Sec. 3.1): the grid operator is a sum of Kronecker products of 1D
+// operators on the image axes, D^ = sum_r C(k,r) D_1^{o(k-r)} (x) D_1^{o r}
+// (Eq. (2D kronecker)), with D_1^{o0} = J; SQEUCLID is D^{o2} (x) J + J (x) D^{o2}.
+//
+// Separable path (SQEUCLID, and (l1)^1): every term carries a J factor on one
+// image axis, so J is applied first as a sum.  For T viewed as a 4-index
+// tensor T[(a,b),(a',b')], B = D^_X T D^_Y is the sum of four broadcasts of
+// small matrices S R S, where R are the two-axis marginals of T
+// (R1[a][a'] = sum_{b,b'} T, R2[a][b'] = sum_{b,a'} T, R3[b][a'] = sum_{a,b'} T,
+// R4[b][b'] = sum_{a,a'} T) and S = [|i-j|^m] on the short axes.  One read of
+// T and one write of G.
+//
+// Generic path (any 1D/2D combination, any k): the grid operator of Y is
+// applied to every row of T as an image (all Kronecker terms), the result is
+// transposed, the operator of X is applied to its rows, and the final
+// transpose writes G with the constant terms.
+#include "common.h"
+#include "runtime.h"
+
+namespace {
+
+constexpr int NT = 256;
+
+// ------------------------------------------------------------ constant terms
+// c[i] = hk^2 * sum_j (d_ij)^2 w_j, d_ij the integer distance of the grid.
+__global__ __launch_bounds__(NT) void k_const_term(int ndim, int k, int metric, int64_t H,
+                                                    int64_t W, double hk,
+                                                    const double* __restrict__ w,
+                                                    double* __restrict__ c) {
+  // 64 outputs per block, 4 partial sums each.
+  __shared__ double part[4][64];
+  const int64_t n = H * W;
+  const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
+  const int64_t i = (int64_t)blockIdx.x * 64 + lane;
+  double acc = 0.0;
+  if (i < n) {
+    const int64_t ri = i / W, ci = i % W;
+    const int64_t chunk = (n + 3) / 4;
+    const int64_t j0 = grp * chunk, j1 = min(n, j0 + chunk);
+    int64_t rj = j0 / W, cj = j0 % W;
+    for (int64_t j = j0; j < j1; ++j) {
+      double d;
+      const int64_t dr = ri > rj ? ri - rj : rj - ri;
+      const int64_t dc = ci > cj ? ci - cj : cj - ci;
+      if (metric == GW_METRIC_SQEUCLID)
+        d = (double)(dr * dr + dc * dc);
+      else
+        d = gwk::ipow((double)(dr + dc), k);
+      const double D = hk * d;
+      acc = fma(D * D, w[j], acc);
+      if (++cj == W) {
+        cj = 0;
+        ++rj;
+      }
+    }
+  }
+  part[grp][lane] = acc;
+  __syncthreads();
+  if (grp == 0 && i < n) c[i] = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
+}
+
+// ---------------------------------------------------------------- transpose
+// out[j][i] = in[i][j] (rows x cols input); with epilogue when c1 != null:
+// out[j][i] = (c1[j] + c2[i]) - s2 * in[i][j].
+__global__ __launch_bounds__(NT) void k_transpose(const double* __restrict__ in, int64_t ldi,
+                                                   int64_t rows, int64_t cols,
+                                                   double* __restrict__ out, int64_t ldo,
+                                                   const double* __restrict__ c1,
+                                                   const double* __restrict__ c2, double s2) {
+  __shared__ double tile[32][33];
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  const int64_t r0 = (int64_t)blockIdx.y * 32, c0 = (int64_t)blockIdx.x * 32;
+  for (int y = ty; y < 32; y += 8) {
+    const int64_t r = r0 + y, c = c0 + tx;
+    tile[y][tx] = (r < rows && c < cols) ? in[r * ldi + c] : 0.0;
+  }
+  __syncthreads();
+  for (int y = ty; y < 32; y += 8) {
+    const int64_t orow = c0 + y, ocol = r0 + tx;  // out[orow][ocol] = in[ocol][orow]
+    if (orow < cols && ocol < rows) {
+      const double v = tile[tx][y];
+      out[orow * ldo + ocol] = c1 ? (c1[orow] + c2[ocol]) - s2 * v : v;
+    }
+  }
+}
+
+// ------------------------------------------------ 1D operator on a strided line
+// y[i*ys] (+)= coef * sum_j |i-j|^m x[j*xs] for i < L, via the recursion; m = 0
+// means J (total sum).  Sequential, one thread per line.
+template <int K>
+__device__ void line_apply(const double* x, int64_t xs, double* y, int64_t ys, int64_t L,
+                           double coef, bool accumulate) {
+  double a[K + 1], b[K + 1];
+#pragma unroll
+  for (int r = 0; r <= K; ++r) a[r] = b[r] = 0.0;
+  // suffix pass writes, prefix pass adds
+  for (int64_t i = L - 1; i >= 0; --i) {
+    const double v = coef * b[K];
+    y[i * ys] = accumulate ? y[i * ys] + v : v;
+    gwk::pascal_step<K>(b, x[i * xs]);
+  }
+  for (int64_t i = 0; i < L; ++i) {
+    y[i * ys] += coef * a[K];
+    gwk::pascal_step<K>(a, x[i * xs]);
+  }
+}
+
+__device__ void line_sum(const double* x, int64_t xs, double* y, int64_t ys, int64_t L,
+                         double coef, bool accumulate) {
+  double s = 0.0;
+  for (int64_t i = 0; i < L; ++i) s += x[i * xs];
+  s *= coef;
+  for (int64_t i = 0; i < L; ++i) y[i * ys] = accumulate ? y[i * ys] + s : s;
+}
+
+__device__ void line_op(int m, const double* x, int64_t xs, double* y, int64_t ys, int64_t L,
+                        double coef, bool acc) {
+  switch (m) {
+    case 0: line_sum(x, xs, y, ys, L, coef, acc); break;
+    case 1: line_apply<1>(x, xs, y, ys, L, coef, acc); break;
+    case 2: line_apply<2>(x, xs, y, ys, L, coef, acc); break;
+    case 3: line_apply<3>(x, xs, y, ys, L, coef, acc); break;
+    case 4: line_apply<4>(x, xs, y, ys, L, coef, acc); break;
+  }
+}
+
+// Apply the (unscaled) grid operator to each row of `in` (rows x n, n = H*W)
+// treating the row as an H x W image; one block per row.  `tmp` is a rows x n
+// scratch.  1D grids (H = 1) use a single sequential line per row.
+__global__ __launch_bounds__(NT) void k_rowop(const double* __restrict__ in, int64_t ldi,
+                                               int64_t rows, int ndim, int k, int metric,
+                                               int64_t H, int64_t W, double* __restrict__ out,
+                                               int64_t ldo, double* __restrict__ tmp) {
+  const int64_t row = blockIdx.x;
+  const double* x = in + row * ldi;
+  double* y = out + row * ldo;
+  double* t = tmp + row * (H * W);
+  const int tid = threadIdx.x;
+  if (ndim == 1) {
+    if (tid == 0) line_op(metric == GW_METRIC_SQEUCLID ? 2 : k, x, 1, y, 1, W, 1.0, false);
+    return;
+  }
+  int nterms;
+  int coefs[GW_KMAX + 1], mh[GW_KMAX + 1], mw[GW_KMAX + 1];
+  if (metric == GW_METRIC_SQEUCLID) {
+    nterms = 2;
+    coefs[0] = 1; mh[0] = 2; mw[0] = 0;
+    coefs[1] = 1; mh[1] = 0; mw[1] = 2;
+  } else {
+    nterms = k + 1;
+    int cb = 1;
+    for (int r = 0; r <= k; ++r) {
+      coefs[r] = cb;
+      mh[r] = k - r;
+      mw[r] = r;
+      cb = cb * (k - r) / (r + 1);
+    }
+  }
+  for (int term = 0; term < nterms; ++term) {
+    // along W (image rows): t = x D^{o mw}
+    for (int64_t a = tid; a < H; a += NT) line_op(mw[term], x + a * W, 1, t + a * W, 1, W, 1.0, false);
+    __syncthreads();
+    // along H (image columns): y (+)= coef D^{o mh} t
+    for (int64_t b = tid; b < W; b += NT)
+      line_op(mh[term], t + b, W, y + b, W, H, (double)coefs[term], term > 0);
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------ separable path
+struct SepGrid {
+  int64_t H, W;
+  int m;             // exponent of the non-J factor
+  double alpha;      // coefficient of D_H^{m} (x) J
+  double beta;       // coefficient of J (x) D_W^{m}
+};
+
+// U[i][a'] = sum_{b'} T[i][(a',b')], V[i][b'] = sum_{a'} T[i][(a',b')]; one
+// block per row of T, row staged in LDS.
+__global__ __launch_bounds__(NT) void k_sep_rowreduce(const double* __restrict__ T, int64_t ldT,
+                                                       int64_t M, int64_t H2, int64_t W2,
+                                                       double* __restrict__ U,
+                                                       double* __restrict__ V) {
+  extern __shared__ double img[];
+  const int64_t i = blockIdx.x;
+  const int64_t n2 = H2 * W2;
+  for (int64_t p = threadIdx.x; p < n2; p += NT) img[p] = T[i * ldT + p];
+  __syncthreads();
+  for (int64_t a = threadIdx.x; a < H2; a += NT) {
+    double s = 0.0;
+    for (int64_t b = 0; b < W2; ++b) s += img[a * W2 + b];
+    U[i * H2 + a] = s;
+  }
+  for (int64_t b = threadIdx.x; b < W2; b += NT) {
+    double s = 0.0;
+    for (int64_t a = 0; a < H2; ++a) s += img[a * W2 + b];
+    V[i * W2 + b] = s;
+  }
+}
+
+// R1[a][a'] = sum_b U[(a,b)][a'], R2[a][b'] = sum_b V[(a,b)][b'],
+// R3[b][a'] = sum_a U[(a,b)][a'], R4[b][b'] = sum_a V[(a,b)][b'].
+__global__ __launch_bounds__(NT) void k_sep_colreduce(const double* __restrict__ U,
+                                                       const double* __restrict__ V, int64_t H1,
+                                                       int64_t W1, int64_t H2, int64_t W2,
+                                                       double* __restrict__ R1,
+                                                       double* __restrict__ R2,
+                                                       double* __restrict__ R3,
+                                                       double* __restrict__ R4) {
+  const int64_t idx = (int64_t)blockIdx.x * NT + threadIdx.x;
+  const int64_t n1 = H1 * H2, n2 = H1 * W2, n3 = W1 * H2, n4 = W1 * W2;
+  if (idx < n1) {
+    const int64_t a = idx / H2, ap = idx % H2;
+    double s = 0.0;
+    for (int64_t b = 0; b < W1; ++b) s += U[(a * W1 + b) * H2 + ap];
+    R1[idx] = s;
+  } else if (idx < n1 + n2) {
+    const int64_t j = idx - n1, a = j / W2, bp = j % W2;
+    double s = 0.0;
+    for (int64_t b = 0; b < W1; ++b) s += V[(a * W1 + b) * W2 + bp];
+    R2[j] = s;
+  } else if (idx < n1 + n2 + n3) {
+    const int64_t j = idx - n1 - n2, b = j / H2, ap = j % H2;
+    double s = 0.0;
+    for (int64_t a = 0; a < H1; ++a) s += U[(a * W1 + b) * H2 + ap];
+    R3[j] = s;
+  } else if (idx < n1 + n2 + n3 + n4) {
+    const int64_t j = idx - n1 - n2 - n3, b = j / W2, bp = j % W2;
+    double s = 0.0;
+    for (int64_t a = 0; a < H1; ++a) s += V[(a * W1 + b) * W2 + bp];
+    R4[j] = s;
+  }
+}
+
+// Q = S_x R S_y for the four small matrices (S = |i-j|^m, dense, short axes),
+// scaled by the Kronecker coefficients.  Two stages: P = S_x R, Q = P S_y.
+__global__ __launch_bounds__(NT) void k_sep_left(const double* __restrict__ R, int64_t nx,
+                                                  int64_t ny, int m, double* __restrict__ P) {
+  const int64_t idx = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (idx >= nx * ny) return;
+  const int64_t i = idx / ny, j = idx % ny;
+  double s = 0.0;
+  for (int64_t l = 0; l < nx; ++l) {
+    const double d = gwk::ipow((double)(i > l ? i - l : l - i), m);
+    s = fma(d, R[l * ny + j], s);
+  }
+  P[idx] = s;
+}
+
+__global__ __launch_bounds__(NT) void k_sep_right(const double* __restrict__ P, int64_t nx,
+                                                   int64_t ny, int m, double coef,
+                                                   double* __restrict__ Q) {
+  const int64_t idx = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (idx >= nx * ny) return;
+  const int64_t i = idx / ny, j = idx % ny;
+  double s = 0.0;
+  for (int64_t l = 0; l < ny; ++l) {
+    const double d = gwk::ipow((double)(j > l ? j - l : l - j), m);
+    s = fma(P[i * ny + l], d, s);
+  }
+  Q[idx] = coef * s;
+}
+
+// G[(a,b)][(a',b')] = (c1 + c2) - s2 (Q1[a][a'] + Q2[a][b'] + Q3[b][a'] + Q4[b][b'])
+__global__ __launch_bounds__(NT) void k_sep_write(int64_t H1, int64_t W1, int64_t H2, int64_t W2,
+                                                   const double* __restrict__ Q1,
+                                                   const double* __restrict__ Q2,
+                                                   const double* __restrict__ Q3,
+                                                   const double* __restrict__ Q4,
+                                                   const double* __restrict__ c1,
+                                                   const double* __restrict__ c2, double s2,
+                                                   double* __restrict__ G, int64_t ldG) {
+  const int64_t i = blockIdx.x;
+  const int64_t a = i / W1, b = i % W1;
+  const int64_t n2 = H2 * W2;
+  const double c1v = c1[i];
+  for (int64_t p = threadIdx.x; p < n2; p += NT) {
+    const int64_t ap = p / W2, bp = p % W2;
+    const double Bv = ((Q1[a * H2 + ap] + Q2[a * W2 + bp]) + Q3[b * H2 + ap]) + Q4[b * W2 + bp];
+    G[i * ldG + p] = (c1v + c2[p]) - s2 * Bv;
+  }
+}
+
+bool separable(const gwr::Grid& g, SepGrid* s) {
+  if (g.ndim != 2) return false;
+  if (g.metric == GW_METRIC_SQEUCLID) {
+    *s = SepGrid{g.H, g.W, 2, 1.0, 1.0};
+    return true;
+  }
+  if (g.k == 1) {
+    *s = SepGrid{g.H, g.W, 1, 1.0, 1.0};
+    return true;
+  }
+  return false;
+}
+
+unsigned blocks_for(int64_t n) { return (unsigned)((n + NT - 1) / NT); }
+
+}  // namespace
+
+namespace gwl {
+
+gw_status const_term(const gwr::Grid& g, const double* w, double* c, hipStream_t s) {
+  gwr::ProfScope ps(gwr::kFamOther, s);
+  const int64_t n = g.n();
+  k_const_term<<<(unsigned)((n + 63) / 64), NT, 0, s>>>(g.ndim, g.k, g.metric, g.H, g.W, g.hk(), w, c);
+  return gwr::last_launch_status();
+}
+
+size_t fast_generic_ws_bytes(const gwr::Grid& X, const gwr::Grid& Y) {
+  const int64_t M = X.n(), N = Y.n();
+  gwr::Arena a{nullptr, 0, 0};
+  SepGrid sx, sy;
+  if (separable(X, &sx) && separable(Y, &sy)) {
+    a.take<double>(M * Y.H);
+    a.take<double>(M * Y.W);
+    for (int t = 0; t < 3; ++t) {  // R, P, Q sets
+      a.take<double>(X.H * Y.H);
+      a.take<double>(X.H * Y.W);
+      a.take<double>(X.W * Y.H);
+      a.take<double>(X.W * Y.W);
+    }
+  } else {
+    a.take<double>((size_t)M * N);
+    a.take<double>((size_t)M * N);
+    a.take<double>((size_t)M * N);
+  }
+  a.take<double>(M);
+  a.take<double>(N);
+  return a.used;
+}
+
+gw_status fast_generic(const gwr::Grid& X, const gwr::Grid& Y, const double* p,
+                       const double* q, const double* T, int64_t ldT, double* G, int64_t ldG,
+                       gwr::Arena& ws, hipStream_t s, const double* c1_pre,
+                       const double* c2_pre) {
+  const int64_t M = X.n(), N = Y.n();
+  SepGrid sx, sy;
+  const bool sep = separable(X, &sx) && separable(Y, &sy);
+  double *U = nullptr, *V = nullptr, *R[4] = {}, *P[4] = {}, *Q[4] = {};
+  double *A = nullptr, *At = nullptr, *tmp = nullptr;
+  if (sep) {
+    U = ws.take<double>(M * Y.H);
+    V = ws.take<double>(M * Y.W);
+    double** sets[3] = {R, P, Q};
+    for (int t = 0; t < 3; ++t) {
+      sets[t][0] = ws.take<double>(X.H * Y.H);
+      sets[t][1] = ws.take<double>(X.H * Y.W);
+      sets[t][2] = ws.take<double>(X.W * Y.H);
+      sets[t][3] = ws.take<double>(X.W * Y.W);
+    }
+  } else {
+    A = ws.take<double>((size_t)M * N);
+    At = ws.take<double>((size_t)M * N);
+    tmp = ws.take<double>((size_t)M * N);
+  }
+  double* c1 = ws.take<double>(M);
+  double* c2 = ws.take<double>(N);
+  gw_status st;
+  if (c1_pre) c1 = const_cast<double*>(c1_pre);
+  else if ((st = const_term(X, p, c1, s)) != GW_OK) return st;
+  if (c2_pre) c2 = const_cast<double*>(c2_pre);
+  else if ((st = const_term(Y, q, c2, s)) != GW_OK) return st;
+  const double s2 = 2.0 * (X.hk() * Y.hk());
+  gwr::ProfScope ps(gwr::kFam2D, s);
+  if (sep) {
+    const size_t shm = (size_t)N * sizeof(double);
+    if (shm > 160 * 1024) return GW_EUNSUPPORTED;
+    static bool attr_set = false;
+    if (!attr_set) {
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sep_rowreduce),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+      attr_set = true;
+    }
+    k_sep_rowreduce<<<(unsigned)M, NT, shm, s>>>(T, ldT, M, Y.H, Y.W, U, V);
+    const int64_t ntot = X.H * Y.H + X.H * Y.W + X.W * Y.H + X.W * Y.W;
+    k_sep_colreduce<<<blocks_for(ntot), NT, 0, s>>>(U, V, X.H, X.W, Y.H, Y.W, R[0], R[1], R[2], R[3]);
+    // term t: (x axis, y axis) = (H,H), (H,W), (W,H), (W,W)
+    const int64_t nx[4] = {X.H, X.H, X.W, X.W};
+    const int64_t ny[4] = {Y.H, Y.W, Y.H, Y.W};
+    const double cx[4] = {sx.alpha, sx.alpha, sx.beta, sx.beta};
+    const double cy[4] = {sy.alpha, sy.beta, sy.alpha, sy.beta};
+    for (int t = 0; t < 4; ++t) {
+      k_sep_left<<<blocks_for(nx[t] * ny[t]), NT, 0, s>>>(R[t], nx[t], ny[t], sx.m, P[t]);
+      k_sep_right<<<blocks_for(nx[t] * ny[t]), NT, 0, s>>>(P[t], nx[t], ny[t], sy.m, cx[t] * cy[t], Q[t]);
+    }
+    k_sep_write<<<(unsigned)M, NT, 0, s>>>(X.H, X.W, Y.H, Y.W, Q[0], Q[1], Q[2], Q[3], c1, c2, s2, G, ldG);
+    return gwr::last_launch_status();
+  }
+  // generic: A = T D^_Y (rows), At = A^T, Bt = At D^_X (rows), G = epilogue(Bt^T)
+  k_rowop<<<(unsigned)M, NT, 0, s>>>(T, ldT, M, Y.ndim, Y.k, Y.metric, Y.H, Y.W, A, N, tmp);
+  dim3 tg1((unsigned)((N + 31) / 32), (unsigned)((M + 31) / 32));
+  k_transpose<<<tg1, NT, 0, s>>>(A, N, M, N, At, M, nullptr, nullptr, 0.0);
+  k_rowop<<<(unsigned)N, NT, 0, s>>>(At, M, N, X.ndim, X.k, X.metric, X.H, X.W, A, M, tmp);
+  dim3 tg2((unsigned)((M + 31) / 32), (unsigned)((N + 31) / 32));
+  k_transpose<<<tg2, NT, 0, s>>>(A, M, N, M, G, ldG, c1, c2, s2);
+  return gwr::last_launch_status();
+}
+
+}  // namespace gwl

@@ -1,0 +1,127 @@
+// Host-side helpers shared by the launchers: grid descriptors, workspace
+// layout, kernel timing and error mapping.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/gw.h"
+
+namespace gwr {
+
+// A validated grid in the form the kernels use.
+struct Grid {
+  int ndim;
+  int k;
+  int metric;
+  int64_t H, W;  // 1D: H = 1, W = n
+  double h;
+  int64_t n() const { return H * W; }
+  // h^k as k left-to-right products (h^2 for SQEUCLID).
+  double hk() const {
+    int kk = metric == GW_METRIC_SQEUCLID ? 2 : k;
+    double v = 1.0;
+    for (int i = 0; i < kk; ++i) v = v * h;
+    return v;
+  }
+  // Exponent used by the 1D recursion (1D grids only).
+  int k1d() const { return metric == GW_METRIC_SQEUCLID ? 2 : k; }
+};
+
+// Host-side validation of a public grid; returns GW_OK or GW_EINVAL.
+gw_status to_grid(const gw_grid* g, Grid* out);
+
+inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Bump allocator over a caller workspace.
+struct Arena {
+  char* base;
+  size_t used;
+  size_t cap;
+  template <class T>
+  T* take(size_t count) {
+    size_t off = align_up(used, 256);
+    used = off + align_up(count * sizeof(T), 256);
+    return base ? reinterpret_cast<T*>(base + off) : nullptr;
+  }
+};
+
+// Workspace bytes for each building block (all multiples of 256).
+size_t ws_status_bytes();
+size_t ws_grad_bytes(const Grid& X, const Grid& Y, int path);
+size_t ws_sinkhorn_bytes(int64_t M, int64_t N);
+size_t ws_objective_bytes(const Grid& X, const Grid& Y);
+size_t ws_objective_tail_bytes(const Grid& X, const Grid& Y);
+
+// Kernel timing families (see gw.h).
+enum Family {
+  kFamFastMain = 0,
+  kFamFastCarry = 1,
+  kFamDense = 2,
+  kFamSinkRow = 3,
+  kFamSinkCol = 4,
+  kFamPlan = 5,
+  kFamOther = 6,
+  kFam2D = 7,
+  kNumFamilies = 8
+};
+void prof_begin(int family, hipStream_t s);
+void prof_end(int family, hipStream_t s);
+
+struct ProfScope {
+  int fam;
+  hipStream_t s;
+  ProfScope(int f, hipStream_t st) : fam(f), s(st) { prof_begin(fam, s); }
+  ~ProfScope() { prof_end(fam, s); }
+};
+
+inline gw_status last_launch_status() {
+  return hipGetLastError() == hipSuccess ? GW_OK : GW_EDEVICE;
+}
+
+// Status word kept at the start of every workspace (first 256 bytes).
+struct StatusWord {
+  int32_t nonfinite;
+};
+
+}  // namespace gwr
+
+// Launchers implemented in the kernel translation units.
+namespace gwl {
+// c[i] = hk^2 * sum_j d(i,j)^2 w[j] for grid g (direct evaluation).
+gw_status const_term(const gwr::Grid& g, const double* w, double* c, hipStream_t s);
+// FAST 1D x 1D gradient (tiled recursion).  ws: arena for its scratch.
+gw_status fast1d(const gwr::Grid& X, const gwr::Grid& Y, const double* p, const double* q,
+                 const double* T, int64_t ldT, double* G, int64_t ldG, gwr::Arena& ws,
+                 hipStream_t s, const double* c1_pre, const double* c2_pre);
+size_t fast1d_ws_bytes(const gwr::Grid& X, const gwr::Grid& Y);
+// Generic FAST gradient for 2D (and mixed 1D/2D) grids.
+gw_status fast_generic(const gwr::Grid& X, const gwr::Grid& Y, const double* p,
+                       const double* q, const double* T, int64_t ldT, double* G, int64_t ldG,
+                       gwr::Arena& ws, hipStream_t s, const double* c1_pre,
+                       const double* c2_pre);
+size_t fast_generic_ws_bytes(const gwr::Grid& X, const gwr::Grid& Y);
+// Dense gradient on matrix cores.
+gw_status dense(const gwr::Grid& X, const gwr::Grid& Y, const double* p, const double* q,
+                const double* T, int64_t ldT, double* G, int64_t ldG, int path, gwr::Arena& ws,
+                hipStream_t s, const double* c1_pre, const double* c2_pre);
+size_t dense_ws_bytes(const gwr::Grid& X, const gwr::Grid& Y, int path);
+// Sinkhorn.
+gw_status sinkhorn(const double* C, int64_t ldC, int64_t M, int64_t N, double c_scale,
+                   const double* p, const double* q, double eps, int iters, int init_zero,
+                   double* f, double* g, double* T, int64_t ldT, gwr::Arena& ws, hipStream_t s,
+                   gwr::StatusWord* status);
+size_t sinkhorn_ws_bytes(int64_t M, int64_t N);
+gw_status plan(const double* C, int64_t ldC, int64_t M, int64_t N, double c_scale,
+               const double* f, const double* g, double eps, double* T, int64_t ldT,
+               hipStream_t s);
+gw_status outer_product(const double* p, const double* q, int64_t M, int64_t N, double* T,
+                        int64_t ldT, hipStream_t s);
+// Row sums, column sums, and the reductions sum G*T, sum T(ln T - 1).
+gw_status marginals(const double* T, int64_t ldT, int64_t M, int64_t N, double* r, double* c,
+                    gwr::Arena& ws, hipStream_t s);
+gw_status objective_reduce(const double* G, int64_t ldG, const double* T, int64_t ldT,
+                           int64_t M, int64_t N, double eps, double* obj, gwr::Arena& ws,
+                           hipStream_t s, gwr::StatusWord* status);
+size_t objective_reduce_ws_bytes(int64_t M, int64_t N);
+}  // namespace gwl

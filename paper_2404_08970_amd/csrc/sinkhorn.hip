@@ -1,0 +1,393 @@
+// Log-domain Sinkhorn for the entropic OT sub-problem of each mirror-descent
+// step (Sec. 2.1, Eq. (GW sinkhorn); tau = eps Remark), plan materialisation,
+// and the reductions behind the objective.
+//
+// One iteration is f_i = eps ln p_i - eps LSE_p((g_p - C_ip)/eps), then
+// g_p = eps ln q_p - eps LSE_i((f_i - C_ip)/eps).  It is done in one pass over
+// C plus a small merge:
+//   row pass   a block owns a band of rows; for each row it computes the
+//              shifted exponentials E_ip = exp(z_ip - m_i), z = (g - C)/eps,
+//              m_i = max_p z_ip, and f_i from their sum s_i.  The column
+//              quantity exp((f_i - C_ip)/eps) equals E_ip (p_i/s_i) e^{-g_p/eps},
+//              so the same E_ip feed the column sums without a second
+//              exponential.  Because E_ip (p_i/s_i) can be far below the
+//              double range for a column that no row favours, each E is kept
+//              as mantissa x 2^n (the exponent comes from the argument
+//              reduction exp(x) = 2^n exp(x - n ln 2), Cody-Waite split of
+//              ln 2) and the column sums are accumulated as (mantissa, shared
+//              binary exponent) pairs, rescaled with ldexp, never with exp;
+//   col merge  one thread per column merges the bands' pairs and sets
+//              g_p = g_p + eps (ln q_p - ln S_p), ln S_p = ln(mant) + e ln 2,
+//              which is the LSE update rewritten with the old g as the shift.
+// Zero-mass rows/columns get f = -inf / g = -inf directly and contribute
+// nothing.  All reductions are in a fixed order (no atomics).
+#include <limits.h>
+
+#include "common.h"
+#include "runtime.h"
+
+namespace {
+
+// ln 2 = LN2_HI + LN2_LO with LN2_HI carrying 32 significant bits, so n*LN2_HI
+// is exact for |n| < 2^21 (Cody and Waite's two-constant argument reduction).
+constexpr double LN2_HI = 0x1.62e42fee00000p-1;
+constexpr double LN2_LO = 0x1.a39ef35793c76p-33;
+constexpr double INV_LN2 = 0x1.71547652b82fep+0;
+constexpr int EXP_SENTINEL = -(1 << 30);
+constexpr double X_FLOOR = -1.0e6;  // exp(-1e6) is 0 in any precision used here
+
+template <int NTH>
+GW_DEV double block_max(double v, double* red) {
+  v = gwk::wave_max(v);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  double r = red[0];
+#pragma unroll
+  for (int i = 1; i < NTH / 64; ++i) r = fmax(r, red[i]);
+  return r;
+}
+
+template <int NTH>
+GW_DEV double block_sum(double v, double* red) {
+  v = gwk::wave_sum(v);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  double r = red[0];
+#pragma unroll
+  for (int i = 1; i < NTH / 64; ++i) r += red[i];
+  return r;
+}
+
+// exp(x) for x <= 0 as E * 2^n, E in [0.70, 1.42].
+GW_DEV double exp_split(double x, int* n) {
+  x = fmax(x, X_FLOOR);
+  const double nd = rint(x * INV_LN2);
+  double r = fma(-nd, LN2_HI, x);
+  r = fma(-nd, LN2_LO, r);
+  *n = (int)nd;
+  return exp(r);
+}
+
+__global__ __launch_bounds__(256) void k_sk_prep(const double* __restrict__ p,
+                                                  const double* __restrict__ q, int M, int N,
+                                                  int init_zero, double* __restrict__ logp,
+                                                  double* __restrict__ logq,
+                                                  double* __restrict__ f,
+                                                  double* __restrict__ g) {
+  const int idx = blockIdx.x * 256 + threadIdx.x;
+  if (idx < M) logp[idx] = p[idx] > 0.0 ? log(p[idx]) : -INFINITY;
+  if (idx < N) {
+    logq[idx] = q[idx] > 0.0 ? log(q[idx]) : -INFINITY;
+    if (init_zero) g[idx] = 0.0;
+  }
+  if (init_zero && idx < M) f[idx] = 0.0;
+}
+
+template <int NTH, int EPT>
+__global__ __launch_bounds__(NTH) void k_sk_row(const double* __restrict__ C, int64_t ldC, int M,
+                                                 int N, int RB, double cs, double inv_eps,
+                                                 double eps, const double* __restrict__ p,
+                                                 const double* __restrict__ logp,
+                                                 const double* __restrict__ g,
+                                                 double* __restrict__ f,
+                                                 double* __restrict__ partS,
+                                                 int* __restrict__ partX,
+                                                 gwr::StatusWord* status) {
+  __shared__ double red[NTH / 64];
+  const int t = threadIdx.x;
+  double S[EPT];
+  int Xe[EPT];
+  double gv[EPT];
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    const int col = t + NTH * e;
+    S[e] = 0.0;
+    Xe[e] = EXP_SENTINEL;
+    gv[e] = col < N ? g[col] : -INFINITY;
+  }
+  const int i0 = blockIdx.x * RB, i1 = min(M, i0 + RB);
+  for (int i = i0; i < i1; ++i) {
+    const double pi = p[i];
+    if (!(pi > 0.0)) {
+      if (t == 0) f[i] = -INFINITY;
+      continue;
+    }
+    const double* row = C + (int64_t)i * ldC;
+    double z[EPT];
+    double mloc = -INFINITY;
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const int col = t + NTH * e;
+      z[e] = col < N ? (gv[e] - cs * row[col]) * inv_eps : -INFINITY;
+      mloc = fmax(mloc, z[e]);
+    }
+    const double m = block_max<NTH>(mloc, red);
+    double E[EPT];
+    int nE[EPT];
+    double sloc = 0.0;
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      E[e] = exp_split(z[e] - m, &nE[e]);
+      sloc += ldexp(E[e], nE[e]);
+    }
+    const double s = block_sum<NTH>(sloc, red);
+    const double fi = eps * ((logp[i] - m) - log(s));
+    if (t == 0) {
+      f[i] = fi;
+      if (!isfinite(fi)) status->nonfinite = 1;
+    }
+    int ew;
+    const double mw = frexp(pi / s, &ew);
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const double tv = E[e] * mw;
+      const int te = nE[e] + ew;
+      const int ne = max(Xe[e], te);
+      S[e] = ldexp(S[e], Xe[e] - ne) + ldexp(tv, te - ne);
+      Xe[e] = ne;
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    const int col = t + NTH * e;
+    if (col < N) {
+      partS[(int64_t)blockIdx.x * N + col] = S[e];
+      partX[(int64_t)blockIdx.x * N + col] = Xe[e];
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_sk_col(int N, int nb, const double* __restrict__ partS,
+                                                 const int* __restrict__ partX,
+                                                 const double* __restrict__ q,
+                                                 const double* __restrict__ logq, double eps,
+                                                 double* __restrict__ g,
+                                                 gwr::StatusWord* status) {
+  const int col = blockIdx.x * 256 + threadIdx.x;
+  if (col >= N) return;
+  double S = 0.0;
+  int X = EXP_SENTINEL;
+  for (int b = 0; b < nb; ++b) {
+    const double sb = partS[(int64_t)b * N + col];
+    const int xb = partX[(int64_t)b * N + col];
+    const int ne = max(X, xb);
+    S = ldexp(S, X - ne) + ldexp(sb, xb - ne);
+    X = ne;
+  }
+  if (!(q[col] > 0.0)) {
+    g[col] = -INFINITY;
+    return;
+  }
+  // ln(S 2^X) with X ln 2 split so that X * LN2_HI is exact
+  const double lnS = fma((double)X, LN2_HI, fma((double)X, LN2_LO, log(S)));
+  const double gn = g[col] + eps * (logq[col] - lnS);
+  g[col] = gn;
+  if (!isfinite(gn)) status->nonfinite = 1;
+}
+
+__global__ __launch_bounds__(256) void k_plan(const double* __restrict__ C, int64_t ldC, int M,
+                                               int N, double cs, const double* __restrict__ f,
+                                               const double* __restrict__ g, double inv_eps,
+                                               double* __restrict__ T, int64_t ldT) {
+  const int64_t i = blockIdx.y;
+  const double fi = f[i];
+  for (int64_t col = (int64_t)blockIdx.x * 256 + threadIdx.x; col < N;
+       col += (int64_t)gridDim.x * 256)
+    T[i * ldT + col] = exp(((fi + g[col]) - cs * C[i * ldC + col]) * inv_eps);
+}
+
+__global__ __launch_bounds__(256) void k_outer(const double* __restrict__ p,
+                                                const double* __restrict__ q, int M, int N,
+                                                double* __restrict__ T, int64_t ldT) {
+  const int64_t i = blockIdx.y;
+  const double pi = p[i];
+  for (int64_t col = (int64_t)blockIdx.x * 256 + threadIdx.x; col < N;
+       col += (int64_t)gridDim.x * 256)
+    T[i * ldT + col] = pi * q[col];
+}
+
+// row sums: one block per row
+__global__ __launch_bounds__(256) void k_rowsum(const double* __restrict__ T, int64_t ldT, int N,
+                                                 double* __restrict__ r) {
+  __shared__ double red[4];
+  const int64_t i = blockIdx.x;
+  double s = 0.0;
+  for (int col = threadIdx.x; col < N; col += 256) s += T[i * ldT + col];
+  s = block_sum<256>(s, red);
+  if (threadIdx.x == 0) r[i] = s;
+}
+
+// column sums: block of 256 threads covers 64 columns x 4 row-quarters
+__global__ __launch_bounds__(256) void k_colsum(const double* __restrict__ T, int64_t ldT, int M,
+                                                 int N, double* __restrict__ c) {
+  __shared__ double part[4][64];
+  const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
+  const int col = blockIdx.x * 64 + lane;
+  double s = 0.0;
+  if (col < N) {
+    const int chunk = (M + 3) / 4;
+    const int r0 = grp * chunk, r1 = min(M, r0 + chunk);
+    for (int i = r0; i < r1; ++i) s += T[(int64_t)i * ldT + col];
+  }
+  part[grp][lane] = s;
+  __syncthreads();
+  if (grp == 0 && col < N) c[col] = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
+}
+
+// partial sums of G*T and T (ln T - 1) per block (rows band), fixed order
+__global__ __launch_bounds__(256) void k_obj_partial(const double* __restrict__ G, int64_t ldG,
+                                                      const double* __restrict__ T, int64_t ldT,
+                                                      int M, int N, int RB,
+                                                      double* __restrict__ part,
+                                                      gwr::StatusWord* status) {
+  __shared__ double red[4];
+  const int i0 = blockIdx.x * RB, i1 = min(M, i0 + RB);
+  double a = 0.0, h = 0.0;
+  bool bad = false;
+  for (int i = i0; i < i1; ++i)
+    for (int col = threadIdx.x; col < N; col += 256) {
+      const double tv = T[(int64_t)i * ldT + col];
+      const double gv = G[(int64_t)i * ldG + col];
+      a = fma(gv, tv, a);
+      if (tv > 0.0) h = fma(tv, log(tv) - 1.0, h);
+      bad |= !isfinite(tv) || !isfinite(gv);
+    }
+  a = block_sum<256>(a, red);
+  h = block_sum<256>(h, red);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = a;
+    part[2 * blockIdx.x + 1] = h;
+  }
+  if (bad) status->nonfinite = 1;
+}
+
+__global__ __launch_bounds__(256) void k_obj_final(const double* __restrict__ part, int nb,
+                                                    double eps, double* __restrict__ obj) {
+  __shared__ double red[4];
+  double a = 0.0, h = 0.0;
+  for (int b = threadIdx.x; b < nb; b += 256) {
+    a += part[2 * b];
+    h += part[2 * b + 1];
+  }
+  a = block_sum<256>(a, red);
+  h = block_sum<256>(h, red);
+  if (threadIdx.x == 0) {
+    obj[0] = a;
+    obj[1] = a + eps * h;
+  }
+}
+
+int sk_rows_per_block(int64_t M) {
+  int rb = (int)((M + 255) / 256);
+  return rb < 1 ? 1 : rb;
+}
+
+template <int NTH, int EPT>
+void launch_row(int nb, hipStream_t s, const double* C, int64_t ldC, int M, int N, int RB,
+                double cs, double inv_eps, double eps, const double* p, const double* logp,
+                const double* g, double* f, double* pS, int* pX, gwr::StatusWord* st) {
+  k_sk_row<NTH, EPT><<<nb, NTH, 0, s>>>(C, ldC, M, N, RB, cs, inv_eps, eps, p, logp, g, f, pS, pX, st);
+}
+
+}  // namespace
+
+namespace gwl {
+
+size_t sinkhorn_ws_bytes(int64_t M, int64_t N) {
+  const int rb = sk_rows_per_block(M);
+  const int64_t nb = (M + rb - 1) / rb;
+  gwr::Arena a{nullptr, 0, 0};
+  a.take<double>(M);
+  a.take<double>(N);
+  a.take<double>((size_t)nb * N);
+  a.take<int>((size_t)nb * N);
+  return a.used;
+}
+
+gw_status sinkhorn(const double* C, int64_t ldC, int64_t M, int64_t N, double c_scale,
+                   const double* p, const double* q, double eps, int iters, int init_zero,
+                   double* f, double* g, double* T, int64_t ldT, gwr::Arena& ws, hipStream_t s,
+                   gwr::StatusWord* status) {
+  if (N > 16384) return GW_EUNSUPPORTED;
+  const int rb = sk_rows_per_block(M);
+  const int nb = (int)((M + rb - 1) / rb);
+  double* logp = ws.take<double>(M);
+  double* logq = ws.take<double>(N);
+  double* pS = ws.take<double>((size_t)nb * N);
+  int* pX = ws.take<int>((size_t)nb * N);
+  const double inv_eps = 1.0 / eps;
+  {
+    gwr::ProfScope ps(gwr::kFamOther, s);
+    const int64_t mx = M > N ? M : N;
+    k_sk_prep<<<(unsigned)((mx + 255) / 256), 256, 0, s>>>(p, q, (int)M, (int)N, init_zero, logp, logq, f, g);
+  }
+  const int Mi = (int)M, Ni = (int)N;
+  for (int it = 0; it < iters; ++it) {
+    {
+      gwr::ProfScope ps(gwr::kFamSinkRow, s);
+      if (N <= 256) launch_row<256, 1>(nb, s, C, ldC, Mi, Ni, rb, c_scale, inv_eps, eps, p, logp, g, f, pS, pX, status);
+      else if (N <= 512) launch_row<256, 2>(nb, s, C, ldC, Mi, Ni, rb, c_scale, inv_eps, eps, p, logp, g, f, pS, pX, status);
+      else if (N <= 1024) launch_row<256, 4>(nb, s, C, ldC, Mi, Ni, rb, c_scale, inv_eps, eps, p, logp, g, f, pS, pX, status);
+      else if (N <= 2048) launch_row<256, 8>(nb, s, C, ldC, Mi, Ni, rb, c_scale, inv_eps, eps, p, logp, g, f, pS, pX, status);
+      else if (N <= 4096) launch_row<256, 16>(nb, s, C, ldC, Mi, Ni, rb, c_scale, inv_eps, eps, p, logp, g, f, pS, pX, status);
+      else if (N <= 8192) launch_row<512, 16>(nb, s, C, ldC, Mi, Ni, rb, c_scale, inv_eps, eps, p, logp, g, f, pS, pX, status);
+      else launch_row<1024, 16>(nb, s, C, ldC, Mi, Ni, rb, c_scale, inv_eps, eps, p, logp, g, f, pS, pX, status);
+    }
+    {
+      gwr::ProfScope ps(gwr::kFamSinkCol, s);
+      k_sk_col<<<(unsigned)((N + 255) / 256), 256, 0, s>>>(Ni, nb, pS, pX, q, logq, eps, g, status);
+    }
+  }
+  if (T) return plan(C, ldC, M, N, c_scale, f, g, eps, T, ldT, s);
+  return gwr::last_launch_status();
+}
+
+gw_status plan(const double* C, int64_t ldC, int64_t M, int64_t N, double c_scale,
+               const double* f, const double* g, double eps, double* T, int64_t ldT,
+               hipStream_t s) {
+  gwr::ProfScope ps(gwr::kFamPlan, s);
+  const unsigned gx = (unsigned)((N + 255) / 256 < 16 ? (N + 255) / 256 : 16);
+  k_plan<<<dim3(gx, (unsigned)M), 256, 0, s>>>(C, ldC, (int)M, (int)N, c_scale, f, g, 1.0 / eps, T, ldT);
+  return gwr::last_launch_status();
+}
+
+gw_status outer_product(const double* p, const double* q, int64_t M, int64_t N, double* T,
+                        int64_t ldT, hipStream_t s) {
+  gwr::ProfScope ps(gwr::kFamOther, s);
+  const unsigned gx = (unsigned)((N + 255) / 256 < 16 ? (N + 255) / 256 : 16);
+  k_outer<<<dim3(gx, (unsigned)M), 256, 0, s>>>(p, q, (int)M, (int)N, T, ldT);
+  return gwr::last_launch_status();
+}
+
+gw_status marginals(const double* T, int64_t ldT, int64_t M, int64_t N, double* r, double* c,
+                    gwr::Arena&, hipStream_t s) {
+  gwr::ProfScope ps(gwr::kFamOther, s);
+  k_rowsum<<<(unsigned)M, 256, 0, s>>>(T, ldT, (int)N, r);
+  k_colsum<<<(unsigned)((N + 63) / 64), 256, 0, s>>>(T, ldT, (int)M, (int)N, c);
+  return gwr::last_launch_status();
+}
+
+size_t objective_reduce_ws_bytes(int64_t M, int64_t) {
+  const int64_t nb = (M + 15) / 16;
+  gwr::Arena a{nullptr, 0, 0};
+  a.take<double>(2 * nb);
+  return a.used;
+}
+
+gw_status objective_reduce(const double* G, int64_t ldG, const double* T, int64_t ldT,
+                           int64_t M, int64_t N, double eps, double* obj, gwr::Arena& ws,
+                           hipStream_t s, gwr::StatusWord* status) {
+  gwr::ProfScope ps(gwr::kFamOther, s);
+  const int RB = 16;
+  const int nb = (int)((M + RB - 1) / RB);
+  double* part = ws.take<double>(2 * (size_t)nb);
+  k_obj_partial<<<(unsigned)nb, 256, 0, s>>>(G, ldG, T, ldT, (int)M, (int)N, RB, part, status);
+  k_obj_final<<<1, 256, 0, s>>>(part, nb, eps, obj);
+  return gwr::last_launch_status();
+}
+
+}  // namespace gwl

@@ -1,0 +1,272 @@
+"""Python binding of libgw.so (argument marshalling only).
+
+Every computation runs in the HIP kernels of ``libgw.so``; this module checks
+tensor placement, allocates the caller-owned workspace with PyTorch and passes
+raw device pointers plus the current HIP stream.  If the library has not been
+built, importing this module raises: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgw.so")
+
+GW_OK, GW_EINVAL, GW_ENOMEM, GW_EDEVICE, GW_ENUMERIC, GW_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+METRIC_L1POW, METRIC_SQEUCLID = 0, 1
+PATH_FAST_F64, PATH_DENSE_F64, PATH_DENSE_F32, PATH_DENSE_BF16 = 0, 1, 2, 3
+PATH_DENSE_BF16_SPLIT, PATH_DENSE_F32_SPLIT = 4, 5
+OP_GRAD, OP_SINKHORN, OP_SOLVE, OP_OBJECTIVE = 0, 1, 2, 3
+FLAG_WARM_START = 1
+KMAX = 4
+
+PATHS = {
+    "fast": PATH_FAST_F64, "fast_f64": PATH_FAST_F64,
+    "dense": PATH_DENSE_F64, "dense_f64": PATH_DENSE_F64,
+    "dense_f32": PATH_DENSE_F32, "dense_bf16": PATH_DENSE_BF16,
+    "dense_bf16_split": PATH_DENSE_BF16_SPLIT, "dense_f32_split": PATH_DENSE_F32_SPLIT,
+}
+
+# timing families (gw.h)
+FAM_FAST_MAIN, FAM_FAST_CARRY, FAM_DENSE, FAM_SINK_ROW, FAM_SINK_COL, FAM_PLAN, FAM_OTHER, FAM_2D = range(8)
+
+
+class GWError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__(f"{what}: {_lib().gw_status_string(status).decode()} ({status})")
+        self.status = status
+
+
+class c_grid(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int32), ("k", ctypes.c_int32), ("metric", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("shape", ctypes.c_int64 * 2), ("h", ctypes.c_double)]
+
+
+_LIB = None
+
+
+def _lib():
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_2404_08970_amd.build_lib` (no CPU fallback exists)")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I32, I64, D, SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
+    G = ctypes.POINTER(c_grid)
+    lib.gw_workspace_bytes.argtypes = [G, G, I32, I32]
+    lib.gw_workspace_bytes.restype = SZ
+    lib.gw_grad.argtypes = [G, G, P, P, P, I64, P, I64, I32, P, SZ, P]
+    lib.gw_grad.restype = I32
+    lib.gw_sinkhorn.argtypes = [P, I64, I64, I64, D, P, P, D, I32, I32, P, P, P, I64, P, SZ, P]
+    lib.gw_sinkhorn.restype = I32
+    lib.gw_solve.argtypes = [G, G, P, P, D, I32, I32, I32, I32, P, I64, P, P, P, P, SZ, P]
+    lib.gw_solve.restype = I32
+    lib.gw_objective.argtypes = [G, G, P, I64, D, P, P, SZ, P]
+    lib.gw_objective.restype = I32
+    lib.gw_status_string.argtypes = [I32]
+    lib.gw_status_string.restype = ctypes.c_char_p
+    lib.gw_check_status.argtypes = [P, P]
+    lib.gw_check_status.restype = I32
+    lib.gw_profile_enable.argtypes = [I32]
+    lib.gw_profile_enable.restype = None
+    lib.gw_profile_read.argtypes = [I32, ctypes.POINTER(D), ctypes.POINTER(I64)]
+    lib.gw_profile_read.restype = I32
+    lib.gw_version.argtypes = []
+    lib.gw_version.restype = ctypes.c_char_p
+    _LIB = lib
+    return lib
+
+
+def library():
+    """The loaded ctypes library (raises if it is not built)."""
+    return _lib()
+
+
+@dataclass(frozen=True)
+class Grid:
+    """Uniform grid: ``shape=(n,)`` (1D) or ``(H, W)`` (2D, row-major)."""
+    shape: tuple
+    h: float
+    k: int
+    metric: int = METRIC_L1POW
+
+    @property
+    def ndim(self):
+        return len(self.shape)
+
+    @property
+    def size(self):
+        n = 1
+        for s in self.shape:
+            n *= int(s)
+        return n
+
+    def c(self) -> c_grid:
+        g = c_grid()
+        g.ndim = self.ndim
+        g.k = self.k
+        g.metric = self.metric
+        g.reserved = 0
+        g.shape[0] = int(self.shape[0])
+        g.shape[1] = int(self.shape[1]) if self.ndim == 2 else 1
+        g.h = float(self.h)
+        return g
+
+
+def unit_grid(shape, k: int, metric: int = METRIC_L1POW) -> Grid:
+    """Grid on [0,1] (or [0,1]^2) with h = 1/(n-1)."""
+    shape = tuple(int(s) for s in shape)
+    h = 1.0 / max(shape[0] - 1, 1)
+    return Grid(shape, h, k, metric)
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _check_f64(name, t, shape=None):
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64):
+        raise TypeError(f"{name} must be a CUDA float64 tensor")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    if t.dim() == 2:
+        if t.stride(1) != 1:
+            raise ValueError(f"{name} must be row-major with unit column stride")
+    elif t.dim() == 1 and t.stride(0) != 1:
+        raise ValueError(f"{name} must be contiguous")
+
+
+_WS_CACHE = {}
+
+
+def workspace(nbytes: int, device=None, key="default") -> torch.Tensor:
+    """A 256-byte aligned device workspace of at least ``nbytes`` (cached)."""
+    dev = torch.device("cuda") if device is None else torch.device(device)
+    idx = dev.index if dev.index is not None else torch.cuda.current_device()
+    ck = (key, idx)
+    buf = _WS_CACHE.get(ck)
+    if buf is None or buf.numel() < nbytes + 256:
+        buf = torch.empty(max(nbytes, 1) + 256, dtype=torch.uint8, device=f"cuda:{idx}")
+        _WS_CACHE[ck] = buf
+    off = (-buf.data_ptr()) % 256
+    return buf[off:off + max(nbytes, 1)]
+
+
+def workspace_bytes(X: Grid, Y: Grid, path=PATH_FAST_F64, op=OP_GRAD) -> int:
+    xc, yc = X.c(), Y.c()
+    return int(_lib().gw_workspace_bytes(ctypes.byref(xc), ctypes.byref(yc), int(path), int(op)))
+
+
+def _raise(st, what):
+    if st != GW_OK:
+        raise GWError(st, what)
+
+
+def grad(X: Grid, Y: Grid, p, q, T, path=PATH_FAST_F64, out=None, ws=None):
+    """G = c1 1^T + 1 c2^T - 2 D_X T D_Y on the GPU."""
+    path = PATHS.get(path, path)
+    M, N = X.size, Y.size
+    _check_f64("p", p, (M,)); _check_f64("q", q, (N,)); _check_f64("T", T, (M, N))
+    if out is None:
+        out = torch.empty((M, N), dtype=torch.float64, device=T.device)
+    _check_f64("out", out, (M, N))
+    nb = workspace_bytes(X, Y, path, OP_GRAD)
+    if nb == 0:
+        raise GWError(GW_EINVAL, "gw_workspace_bytes")
+    if ws is None:
+        ws = workspace(nb, T.device)
+    xc, yc = X.c(), Y.c()
+    st = _lib().gw_grad(ctypes.byref(xc), ctypes.byref(yc), _ptr(p), _ptr(q), _ptr(T), T.stride(0),
+                        _ptr(out), out.stride(0), int(path), _ptr(ws), ws.numel(), _stream())
+    _raise(st, "gw_grad")
+    return out
+
+
+def sinkhorn(C, p, q, eps: float, iters: int, c_scale: float = 1.0, f=None, g=None,
+             plan: bool = False, ws=None):
+    """Log-domain Sinkhorn on the GPU; returns (f, g) or (f, g, T)."""
+    M, N = C.shape
+    _check_f64("C", C, (M, N)); _check_f64("p", p, (M,)); _check_f64("q", q, (N,))
+    init_zero = 1 if (f is None and g is None) else 0
+    if f is None:
+        f = torch.zeros(M, dtype=torch.float64, device=C.device)
+    if g is None:
+        g = torch.zeros(N, dtype=torch.float64, device=C.device)
+    T = torch.empty((M, N), dtype=torch.float64, device=C.device) if plan else None
+    gx, gy = Grid((M,), 1.0, 1), Grid((N,), 1.0, 1)
+    nb = workspace_bytes(gx, gy, PATH_FAST_F64, OP_SINKHORN)
+    if ws is None:
+        ws = workspace(nb, C.device)
+    st = _lib().gw_sinkhorn(_ptr(C), C.stride(0), M, N, float(c_scale), _ptr(p), _ptr(q),
+                            float(eps), int(iters), init_zero, _ptr(f), _ptr(g), _ptr(T),
+                            T.stride(0) if T is not None else N, _ptr(ws), ws.numel(), _stream())
+    _raise(st, "gw_sinkhorn")
+    return (f, g, T) if plan else (f, g)
+
+
+def solve(X: Grid, Y: Grid, p, q, eps: float, outer: int, inner: int, path=PATH_FAST_F64,
+          warm: bool = False, objective: bool = True, T=None, f=None, g=None, obj=None, ws=None):
+    """Entropic GW mirror descent on the GPU; returns (T, f, g, obj[2] or None)."""
+    path = PATHS.get(path, path)
+    M, N = X.size, Y.size
+    _check_f64("p", p, (M,)); _check_f64("q", q, (N,))
+    dev = p.device
+    T = torch.empty((M, N), dtype=torch.float64, device=dev) if T is None else T
+    f = torch.empty(M, dtype=torch.float64, device=dev) if f is None else f
+    g = torch.empty(N, dtype=torch.float64, device=dev) if g is None else g
+    if objective and obj is None:
+        obj = torch.empty(2, dtype=torch.float64, device=dev)
+    nb = workspace_bytes(X, Y, path, OP_SOLVE)
+    if nb == 0:
+        raise GWError(GW_EINVAL, "gw_workspace_bytes")
+    if ws is None:
+        ws = workspace(nb, dev, key="solve")
+    xc, yc = X.c(), Y.c()
+    st = _lib().gw_solve(ctypes.byref(xc), ctypes.byref(yc), _ptr(p), _ptr(q), float(eps),
+                         int(outer), int(inner), int(path), FLAG_WARM_START if warm else 0,
+                         _ptr(T), T.stride(0), _ptr(f), _ptr(g), _ptr(obj if objective else None),
+                         _ptr(ws), ws.numel(), _stream())
+    _raise(st, "gw_solve")
+    return T, f, g, (obj if objective else None)
+
+
+def objective(X: Grid, Y: Grid, T, eps: float, ws=None):
+    """(E(T), E(T) + eps H(T)) as a device tensor of 2 doubles."""
+    M, N = X.size, Y.size
+    _check_f64("T", T, (M, N))
+    obj = torch.empty(2, dtype=torch.float64, device=T.device)
+    nb = workspace_bytes(X, Y, PATH_FAST_F64, OP_OBJECTIVE)
+    if ws is None:
+        ws = workspace(nb, T.device, key="objective")
+    xc, yc = X.c(), Y.c()
+    st = _lib().gw_objective(ctypes.byref(xc), ctypes.byref(yc), _ptr(T), T.stride(0), float(eps),
+                             _ptr(obj), _ptr(ws), ws.numel(), _stream())
+    _raise(st, "gw_objective")
+    return obj
+
+
+def check_status(ws=None):
+    """Synchronise and raise if a kernel flagged a non-finite value."""
+    st = _lib().gw_check_status(_ptr(ws), _stream())
+    _raise(st, "gw_check_status")
+
+
+def profile_enable(on: bool = True):
+    _lib().gw_profile_enable(1 if on else 0)
+
+
+def profile_read(family: int):
+    ms = ctypes.c_double(0.0)
+    n = ctypes.c_int64(0)
+    _raise(_lib().gw_profile_read(int(family), ctypes.byref(ms), ctypes.byref(n)), "gw_profile_read")
+    return ms.value, n.value
