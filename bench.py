@@ -1,0 +1,232 @@
+"""Benchmark: entropic GW solves on 1D grids, n = m = 4096 (one MI355X).
+
+One step = one FAST-gradient gw_solve (100 mirror-descent iterations x 100
+log-domain Sinkhorn iterations, eps = 1e-3) for each exponent k in {1, 2, 3},
+on seeded 3-Gaussian-mixture marginals; inputs are resident in HBM before the
+timed region.  `value` is solves per second over the K timed steps.
+
+Beside the headline the JSON line carries: gradient evaluations per second for
+the FAST recursion and the dense FP64 matrix-core product at n = 4096 (and the
+FAST/dense ratio at n = 16384), the roofline of the dominant kernel (the
+Sinkhorn row pass) measured with HIP events over the timed region, and the CPU
+oracle timed on a bounded sample.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-big]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "GW grads/s & solves/s (fast vs dense) at n=4096; % HBM peak; p50/p99"
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+N = 4096
+EPS = 1e-3
+OUTER = 100
+INNER = 100
+KS = (1, 2, 3)
+
+
+def marginals(n, k):
+    from paper_2404_08970_amd import inputs
+    rng_p = inputs.rng_for(2, 0, k)
+    rng_q = inputs.rng_for(2, 1, k)
+    return inputs.gauss_mixture_1d(n, rng_p), inputs.gauss_mixture_1d(n, rng_q)
+
+
+def time_gpu(fn, reps, torch):
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    fn()
+    torch.cuda.synchronize()
+    start.record()
+    for _ in range(reps):
+        fn()
+    stop.record()
+    torch.cuda.synchronize()
+    return start.elapsed_time(stop) / reps
+
+
+def cpu_baseline(k=2):
+    """The oracle (numpy FP64, single thread for these routines) on one outer
+    step of the same workload: its recursion gradient, a 10-iteration Sinkhorn
+    sample and the plan; scaled to solves/s for 100 x 100."""
+    import numpy as np
+    from oracle import gw_oracle as O
+    p, q = marginals(N, k)
+    g = O.Grid((N,), 1.0 / (N - 1), k)
+    T = np.outer(p, q)
+    t0 = time.perf_counter()
+    G = O.grad_pascal(g, g, p, q, T)
+    t1 = time.perf_counter()
+    its = 10
+    f, gg = O.sinkhorn(2.0 * G, p, q, EPS, its)
+    t2 = time.perf_counter()
+    O.plan(2.0 * G, f, gg, EPS)
+    t3 = time.perf_counter()
+    per_outer = (t1 - t0) + (t2 - t1) / its * INNER + (t3 - t2)
+    return {
+        "value": 1.0 / (OUTER * per_outer),
+        "unit": "solves/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"n=4096 k={k}: one recursion gradient ({t1 - t0:.2f} s), {its} Sinkhorn "
+                   f"iterations ({t2 - t1:.2f} s) and one plan ({t3 - t2:.2f} s), scaled to "
+                   f"{OUTER} outer x {INNER} inner iterations"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-big", action="store_true", help="skip the n=16384 FAST/dense ratio")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU "
+              "sharding of this path is a design note, not a runnable configuration.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2404_08970_amd import gw
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    X = {k: gw.unit_grid((N,), k) for k in KS}
+    pq = {}
+    for k in KS:
+        p, q = marginals(N, k)
+        pq[k] = (torch.tensor(p, dtype=torch.float64, device=dev),
+                 torch.tensor(q, dtype=torch.float64, device=dev))
+    T = torch.empty((N, N), dtype=torch.float64, device=dev)
+    f = torch.empty(N, dtype=torch.float64, device=dev)
+    g = torch.empty(N, dtype=torch.float64, device=dev)
+    obj = torch.empty(2, dtype=torch.float64, device=dev)
+    ws = gw.workspace(gw.workspace_bytes(X[3], X[3], gw.PATH_FAST_F64, gw.OP_SOLVE), dev, key="bench")
+
+    def step():
+        for k in KS:
+            gw.solve(X[k], X[k], pq[k][0], pq[k][1], EPS, OUTER, INNER, path="fast",
+                     T=T, f=f, g=g, obj=obj, ws=ws)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    gw.check_status(ws)
+
+    # ---- timed region: K steps; HIP events around the Sinkhorn row pass
+    gw.profile_enable([gw.FAM_SINK_ROW])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    row_ms, row_n = gw.profile_read(gw.FAM_SINK_ROW)
+    gw.profile_enable([])
+    gw.check_status(ws)
+    elapsed = t1 - t0
+    solves = args.steps * len(KS)
+    ms_per_step = elapsed * 1e3 / args.steps
+    objs = {}
+    for k in KS:
+        _, _, _, o = gw.solve(X[k], X[k], pq[k][0], pq[k][1], EPS, OUTER, INNER, path="fast",
+                              T=T, f=f, g=g, obj=obj, ws=ws)
+        objs[k] = float(o[0].item())
+
+    # ---- roofline of the dominant kernel: one row pass reads C (8 MN bytes)
+    row_avg_ms = row_ms / max(row_n, 1)
+    row_bytes = 8.0 * N * N
+    achieved = row_bytes / (row_avg_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "k_sk_row (Sinkhorn row pass)", "avg_us": round(row_avg_ms * 1e3, 2),
+                "launches": row_n, "algorithmic_bytes_per_launch": int(row_bytes)}
+    tf = os.path.join(ROOT, "profiles", "traffic_sinkhorn_row_n4096.json")
+    if os.path.exists(tf):
+        roofline["traffic"] = json.load(open(tf)).get("bytes_per_launch")
+
+    # ---- gradient throughput, FAST vs dense, n = 4096 (outside the timed region)
+    rng = np.random.default_rng([2, 9])
+    Tg = torch.tensor(rng.uniform(0, 1, size=(N, N)) / (N * N * 0.5), device=dev)
+    G = torch.empty_like(Tg)
+    grads = {}
+    for k in KS:
+        p, q = pq[k]
+        gws = gw.workspace(gw.workspace_bytes(X[k], X[k], gw.PATH_DENSE_F64, gw.OP_GRAD), dev, key="g")
+        fast_ms = time_gpu(lambda: gw.grad(X[k], X[k], p, q, Tg, path="fast", out=G, ws=gws), 20, torch)
+        dense_ms = time_gpu(lambda: gw.grad(X[k], X[k], p, q, Tg, path="dense", out=G, ws=gws), 3, torch)
+        gw.profile_enable([gw.FAM_FAST_MAIN, gw.FAM_FAST_CARRY])
+        gw.grad(X[k], X[k], p, q, Tg, path="fast", out=G, ws=gws)
+        torch.cuda.synchronize()
+        main_ms, _ = gw.profile_read(gw.FAM_FAST_MAIN)
+        carry_ms, _ = gw.profile_read(gw.FAM_FAST_CARRY)
+        gw.profile_enable([])
+        grads[f"k{k}"] = {
+            "fast_grads_per_s": round(1e3 / fast_ms, 1),
+            "dense_f64_grads_per_s": round(1e3 / dense_ms, 2),
+            "fast_us": round(fast_ms * 1e3, 1), "dense_us": round(dense_ms * 1e3, 1),
+            "speedup": round(dense_ms / fast_ms, 1),
+            "fast_tile_kernel_GBps": round(16.0 * N * N / (main_ms * 1e-3) / 1e9, 1),
+            "fast_moment_kernels_us": round(carry_ms * 1e3, 1),
+            "dense_mfma_frac": round(4.0 * N ** 3 / (dense_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4),
+        }
+    del Tg, G
+
+    big = None
+    if not args.no_big:
+        nb = 16384
+        Xb = gw.unit_grid((nb,), 2)
+        rngb = np.random.default_rng([4, 0])
+        pb = torch.tensor(rngb.dirichlet(np.ones(nb)), device=dev)
+        Tb = torch.outer(pb, torch.tensor(rngb.dirichlet(np.ones(nb)), device=dev))
+        Gb = torch.empty_like(Tb)
+        wsb = gw.workspace(gw.workspace_bytes(Xb, Xb, gw.PATH_DENSE_F64, gw.OP_GRAD), dev, key="big")
+        fast_ms = time_gpu(lambda: gw.grad(Xb, Xb, pb, pb, Tb, path="fast", out=Gb, ws=wsb), 10, torch)
+        dense_ms = time_gpu(lambda: gw.grad(Xb, Xb, pb, pb, Tb, path="dense", out=Gb, ws=wsb), 1, torch)
+        big = {"n": nb, "k": 2, "fast_ms": round(fast_ms, 3), "dense_f64_ms": round(dense_ms, 1),
+               "speedup": round(dense_ms / fast_ms, 1), "target_speedup": nb / 64,
+               "fast_GBps_at_24B_per_entry": round(24.0 * nb * nb / (fast_ms * 1e-3) / 1e9, 1)}
+        del Tb, Gb, wsb
+
+    out = {
+        "metric": METRIC,
+        "value": round(solves / elapsed, 4),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "1D n=m=4096 on [0,1], k in {1,2,3} (one solve each per step), "
+                               "3-Gaussian-mixture marginals, eps=1e-3, 100 outer x 100 Sinkhorn "
+                               "iterations, FAST FP64 gradient, log-domain Sinkhorn",
+                   "n": N, "solves_per_step": len(KS), "path": "fast_f64"},
+        "roofline": roofline,
+        "grads": grads,
+        "n16384": big,
+        "objective": objs,
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

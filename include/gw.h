@@ -150,10 +150,11 @@ gw_status gw_check_status(void* ws, void* stream);
  *   2 dense gradient GEMMs, 3 Sinkhorn row pass, 4 Sinkhorn column merge,
  *   5 plan materialisation, 6 other (init, objective, constant terms),
  *   7 2D gradient kernels.
- * gw_profile_enable(1) starts recording (and clears counts); gw_profile_read
+ * gw_profile_enable(mask) records the families whose bit (1 << family) is set
+ * in `mask` (0 stops recording; every call clears the counts); gw_profile_read
  * waits for the recorded events and returns total milliseconds and launch
- * count of a family.  Timing adds an event pair around each launch. */
-void gw_profile_enable(int32_t on);
+ * count of a family.  Timing adds an event pair around each recorded launch. */
+void gw_profile_enable(int32_t mask);
 gw_status gw_profile_read(int32_t family, double* total_ms, int64_t* launches);
 
 /* Library version string. */

@@ -71,7 +71,7 @@ size_t ws_objective_bytes(const Grid& X, const Grid& Y) {
 namespace {
 struct ProfState {
   std::mutex mu;
-  bool on = false;
+  int32_t mask = 0;
   std::vector<hipEvent_t> pool[kNumFamilies];
   std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[kNumFamilies];
   size_t used[kNumFamilies] = {};
@@ -107,9 +107,9 @@ void drain(ProfState& P, int fam) {
 
 void prof_begin(int fam, hipStream_t s) {
   ProfState& P = prof();
-  if (!P.on) return;
+  if (!(P.mask & (1 << fam))) return;
   std::lock_guard<std::mutex> g(P.mu);
-  if (P.used[fam] + 2 > 4096) drain(P, fam);
+  if (P.used[fam] + 2 > (size_t(1) << 20)) drain(P, fam);
   hipEvent_t e = pool_event(P, fam);
   if (e) (void)hipEventRecord(e, s);
   P.open[fam] = e;
@@ -117,7 +117,7 @@ void prof_begin(int fam, hipStream_t s) {
 
 void prof_end(int fam, hipStream_t s) {
   ProfState& P = prof();
-  if (!P.on) return;
+  if (!(P.mask & (1 << fam))) return;
   std::lock_guard<std::mutex> g(P.mu);
   hipEvent_t b = P.open[fam];
   hipEvent_t e = pool_event(P, fam);
@@ -368,7 +368,7 @@ gw_status gw_check_status(void* ws, void* stream) {
   return GW_OK;
 }
 
-void gw_profile_enable(int32_t on) {
+void gw_profile_enable(int32_t mask) {
   gwr::ProfState& P = gwr::prof();
   std::lock_guard<std::mutex> g(P.mu);
   for (int f = 0; f < gwr::kNumFamilies; ++f) {
@@ -378,7 +378,7 @@ void gw_profile_enable(int32_t on) {
     P.launches[f] = 0;
     P.open[f] = nullptr;
   }
-  P.on = on != 0;
+  P.mask = mask;
 }
 
 gw_status gw_profile_read(int32_t family, double* total_ms, int64_t* launches) {

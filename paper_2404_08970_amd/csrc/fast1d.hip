@@ -53,7 +53,52 @@ Layout make_layout(int64_t M, int64_t N, int kx, int ky) {
   return L;
 }
 
+// A line segment of SEG consecutive entries held in registers.
+constexpr int SEG = 16;
+constexpr int NSEG = TS / SEG;
+
+// Prefix summary at the segment's end and suffix summary at its start - 1 of
+// x[0..SEG) (zero state on entry): pre_r = sum_c (SEG - c)^r x_c,
+// suf_r = sum_c (c + 1)^r x_c.  The weights are compile-time integers.
+template <int K>
+GW_DEV void seg_summaries(const double (&x)[SEG], double (&pre)[K + 1], double (&suf)[K + 1]) {
+#pragma unroll
+  for (int r = 0; r <= K; ++r) pre[r] = suf[r] = 0.0;
+#pragma unroll
+  for (int c = 0; c < SEG; ++c) {
+    double wp = 1.0, ws = 1.0;
+#pragma unroll
+    for (int r = 0; r <= K; ++r) {
+      pre[r] = fma(wp, x[c], pre[r]);
+      suf[r] = fma(ws, x[c], suf[r]);
+      wp *= (double)(SEG - c);
+      ws *= (double)(c + 1);
+    }
+  }
+}
+
+// out[c] = a_K(c) + b_K(c) over the segment, starting from prefix state `a`
+// (at the segment's first entry) and suffix state `b` (at its last entry).
+template <int K>
+GW_DEV void seg_sweep(const double (&x)[SEG], double (&a)[K + 1], double (&b)[K + 1],
+                      double (&out)[SEG]) {
+#pragma unroll
+  for (int c = 0; c < SEG; ++c) {
+    out[c] = a[K];
+    gwk::pascal_step<K>(a, x[c]);
+  }
+#pragma unroll
+  for (int c = SEG - 1; c >= 0; --c) {
+    out[c] += b[K];
+    gwk::pascal_step<K>(b, x[c]);
+  }
+}
+
 // ---------------------------------------------------------------- P1 moments
+// Block of 256 threads per 64 x 64 tile: thread (line, seg) sums a 16-entry
+// segment of its row (for row moments) and of its column (column moments);
+// the 4 segment summaries of a line are combined with Pascal shifts.  Entries
+// beyond the matrix are zero, so every tile is handled at its nominal size.
 template <int KX, int KY>
 __global__ __launch_bounds__(256) void k_p1_moments(const double* __restrict__ T, int64_t ldT,
                                                      int M, int N, int nI, int nJ,
@@ -61,80 +106,91 @@ __global__ __launch_bounds__(256) void k_p1_moments(const double* __restrict__ T
                                                      double* __restrict__ colmom) {
   constexpr int KM = (KX > KY ? KX : KY) + 1;
   __shared__ double X[TS][LDS_STRIDE];
-  __shared__ double part[4][TS][2 * KM];
+  __shared__ double part[2][NSEG][TS][2 * KM];
   const int J = blockIdx.x, I = blockIdx.y, t = threadIdx.x;
   const int js = I * TS, qs = J * TS;
   const int h = min(TS, M - js), w = min(TS, N - qs);
+  const int line = t & (TS - 1), seg = t >> 6;
   {
-    const int c = t & (TS - 1);
-    for (int r = t >> 6; r < TS; r += 4)
-      X[r][c] = (r < h && c < w) ? T[(int64_t)(js + r) * ldT + qs + c] : 0.0;
-  }
-  __syncthreads();
-  const int grp = t >> 6, line = t & (TS - 1);
-  if (grp < 2) {
-    // row moments of tile row `line` over columns [32 grp, 32 grp + 32)
-    double pre[KY + 1], suf[KY + 1];
+    // column segment straight from global memory (lanes = columns)
+    double x[SEG];
 #pragma unroll
-    for (int r = 0; r <= KY; ++r) pre[r] = suf[r] = 0.0;
-    for (int cc = 32 * grp; cc < 32 * grp + 32; ++cc) {
-      const double x = X[line][cc];
-      const double wp = (double)(w - cc), wsu = (double)(cc + 1);
-      double pp = 1.0, ps = 1.0;
-#pragma unroll
-      for (int r = 0; r <= KY; ++r) {
-        pre[r] = fma(pp, x, pre[r]);
-        suf[r] = fma(ps, x, suf[r]);
-        pp *= wp;
-        ps *= wsu;
-      }
+    for (int i = 0; i < SEG; ++i) {
+      const int r = seg * SEG + i;
+      x[i] = (r < h && line < w) ? T[(int64_t)(js + r) * ldT + qs + line] : 0.0;
+      X[r][line] = x[i];
     }
-#pragma unroll
-    for (int r = 0; r <= KY; ++r) {
-      part[grp][line][r] = pre[r];
-      part[grp][line][KM + r] = suf[r];
-    }
-  } else {
-    const int g2 = grp - 2;
     double pre[KX + 1], suf[KX + 1];
-#pragma unroll
-    for (int r = 0; r <= KX; ++r) pre[r] = suf[r] = 0.0;
-    for (int rr = 32 * g2; rr < 32 * g2 + 32; ++rr) {
-      const double x = X[rr][line];
-      const double wp = (double)(h - rr), wsu = (double)(rr + 1);
-      double pp = 1.0, ps = 1.0;
-#pragma unroll
-      for (int r = 0; r <= KX; ++r) {
-        pre[r] = fma(pp, x, pre[r]);
-        suf[r] = fma(ps, x, suf[r]);
-        pp *= wp;
-        ps *= wsu;
-      }
-    }
+    seg_summaries<KX>(x, pre, suf);
 #pragma unroll
     for (int r = 0; r <= KX; ++r) {
-      part[grp][line][r] = pre[r];
-      part[grp][line][KM + r] = suf[r];
+      part[1][seg][line][r] = pre[r];
+      part[1][seg][line][KM + r] = suf[r];
     }
   }
   __syncthreads();
+  {
+    double x[SEG];
+#pragma unroll
+    for (int c = 0; c < SEG; ++c) x[c] = X[line][seg * SEG + c];
+    double pre[KY + 1], suf[KY + 1];
+    seg_summaries<KY>(x, pre, suf);
+#pragma unroll
+    for (int r = 0; r <= KY; ++r) {
+      part[0][seg][line][r] = pre[r];
+      part[0][seg][line][KM + r] = suf[r];
+    }
+  }
+  __syncthreads();
+  // combine: prefix at the tile end = sum_s P(16 (3 - s)) pre_s; suffix at
+  // the tile start - 1 = sum_s P(16 s) suf_s.  Threads 0..63 rows, 64..127 columns.
   if (t < TS) {
     if (t < h) {
+      double a[KY + 1], b[KY + 1];
 #pragma unroll
       for (int r = 0; r <= KY; ++r) {
-        rowmom[((size_t)(0 * nJ + J) * (KY + 1) + r) * M + js + t] = part[0][t][r] + part[1][t][r];
-        rowmom[((size_t)(1 * nJ + J) * (KY + 1) + r) * M + js + t] =
-            part[0][t][KM + r] + part[1][t][KM + r];
+        a[r] = part[0][0][t][r];
+        b[r] = part[0][NSEG - 1][t][KM + r];
+      }
+#pragma unroll
+      for (int sg = 1; sg < NSEG; ++sg) {
+        gwk::pascal_shift<KY>(a, (double)SEG);
+        gwk::pascal_shift<KY>(b, (double)SEG);
+#pragma unroll
+        for (int r = 0; r <= KY; ++r) {
+          a[r] += part[0][sg][t][r];
+          b[r] += part[0][NSEG - 1 - sg][t][KM + r];
+        }
+      }
+#pragma unroll
+      for (int r = 0; r <= KY; ++r) {
+        rowmom[((size_t)(0 * nJ + J) * (KY + 1) + r) * M + js + t] = a[r];
+        rowmom[((size_t)(1 * nJ + J) * (KY + 1) + r) * M + js + t] = b[r];
       }
     }
   } else if (t < 2 * TS) {
     const int c = t - TS;
     if (c < w) {
+      double a[KX + 1], b[KX + 1];
 #pragma unroll
       for (int r = 0; r <= KX; ++r) {
-        colmom[((size_t)(0 * nI + I) * (KX + 1) + r) * N + qs + c] = part[2][c][r] + part[3][c][r];
-        colmom[((size_t)(1 * nI + I) * (KX + 1) + r) * N + qs + c] =
-            part[2][c][KM + r] + part[3][c][KM + r];
+        a[r] = part[1][0][c][r];
+        b[r] = part[1][NSEG - 1][c][KM + r];
+      }
+#pragma unroll
+      for (int sg = 1; sg < NSEG; ++sg) {
+        gwk::pascal_shift<KX>(a, (double)SEG);
+        gwk::pascal_shift<KX>(b, (double)SEG);
+#pragma unroll
+        for (int r = 0; r <= KX; ++r) {
+          a[r] += part[1][sg][c][r];
+          b[r] += part[1][NSEG - 1 - sg][c][KM + r];
+        }
+      }
+#pragma unroll
+      for (int r = 0; r <= KX; ++r) {
+        colmom[((size_t)(0 * nI + I) * (KX + 1) + r) * N + qs + c] = a[r];
+        colmom[((size_t)(1 * nI + I) * (KX + 1) + r) * N + qs + c] = b[r];
       }
     }
   }
@@ -143,39 +199,40 @@ __global__ __launch_bounds__(256) void k_p1_moments(const double* __restrict__ T
 // In-place exclusive scan of the moments of one line across its tiles.
 // base[(dir * ntiles + t) * (K+1) + r) * stride]; prefix from the left, suffix
 // from the right; the state is advanced over the width of the tile it passes.
+// Loads are issued PF tiles ahead of the recurrence.
 template <int K>
 __device__ void scan_line(double* base, size_t stride, int ntiles, int64_t extent) {
-  double st[K + 1];
+  constexpr int PF = 8;
+  for (int dir = 0; dir < 2; ++dir) {
+    double* db = base + (size_t)dir * ntiles * (K + 1) * stride;
+    double st[K + 1];
 #pragma unroll
-  for (int r = 0; r <= K; ++r) st[r] = 0.0;
-  for (int tt = 0; tt < ntiles; ++tt) {
-    double* p = base + (size_t)tt * (K + 1) * stride;
-    double tmp[K + 1];
+    for (int r = 0; r <= K; ++r) st[r] = 0.0;
+    for (int s0 = 0; s0 < ntiles; s0 += PF) {
+      double buf[PF][K + 1];
 #pragma unroll
-    for (int r = 0; r <= K; ++r) {
-      tmp[r] = p[r * stride];
-      p[r * stride] = st[r];
+      for (int u = 0; u < PF; ++u) {
+        const int s = s0 + u;
+        const int tt = dir == 0 ? s : ntiles - 1 - s;
+        if (s < ntiles) {
+#pragma unroll
+          for (int r = 0; r <= K; ++r) buf[u][r] = db[((size_t)tt * (K + 1) + r) * stride];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < PF; ++u) {
+        const int s = s0 + u;
+        if (s < ntiles) {
+          const int tt = dir == 0 ? s : ntiles - 1 - s;
+#pragma unroll
+          for (int r = 0; r <= K; ++r) db[((size_t)tt * (K + 1) + r) * stride] = st[r];
+          const double wd = (double)min<int64_t>(TS, extent - (int64_t)tt * TS);
+          gwk::pascal_shift<K>(st, wd);
+#pragma unroll
+          for (int r = 0; r <= K; ++r) st[r] += buf[u][r];
+        }
+      }
     }
-    const double wd = (double)min<int64_t>(TS, extent - (int64_t)tt * TS);
-    gwk::pascal_shift<K>(st, wd);
-#pragma unroll
-    for (int r = 0; r <= K; ++r) st[r] += tmp[r];
-  }
-#pragma unroll
-  for (int r = 0; r <= K; ++r) st[r] = 0.0;
-  double* sbase = base + (size_t)ntiles * (K + 1) * stride;
-  for (int tt = ntiles - 1; tt >= 0; --tt) {
-    double* p = sbase + (size_t)tt * (K + 1) * stride;
-    double tmp[K + 1];
-#pragma unroll
-    for (int r = 0; r <= K; ++r) {
-      tmp[r] = p[r * stride];
-      p[r * stride] = st[r];
-    }
-    const double wd = (double)min<int64_t>(TS, extent - (int64_t)tt * TS);
-    gwk::pascal_shift<K>(st, wd);
-#pragma unroll
-    for (int r = 0; r <= K; ++r) st[r] += tmp[r];
   }
 }
 
@@ -192,88 +249,68 @@ __global__ __launch_bounds__(256) void k_p2_scan(int M, int N, int nI, int nJ,
   }
 }
 
-// ------------------- P2c: tile moments of the column-carry vectors (one wave each)
+// ------------- P2c: row carries of the column-carry vectors, one block per vector
+// Thread J computes the moments of its tile of the vector; two threads then
+// scan the tiles (prefix, suffix) out of LDS.  Output layout per vector:
+// [nJ][2][KY+1] (prefix state at the tile's first column, suffix state at its
+// last column).
 template <int KX, int KY>
-__global__ __launch_bounds__(64) void k_p2c_moments(int N, int nI, int nJ,
-                                                     const double* __restrict__ colmom,
-                                                     double* __restrict__ augmom) {
-  const int J = blockIdx.x;
-  const int v = blockIdx.y;  // (dirC * nI + I) * (KX+1) + r, matches colmom's vector order
-  const int c = threadIdx.x;
-  const int qs = J * TS;
-  const int w = min(TS, N - qs);
-  const double x = c < w ? colmom[(size_t)v * N + qs + c] : 0.0;
-  const double wp = (double)(w - c), wsu = (double)(c + 1);
-  double pp = 1.0, ps = 1.0;
-  double* out = augmom + ((size_t)v * nJ + J) * 2 * (KY + 1);
+__global__ __launch_bounds__(256) void k_p2c(int N, int nJ, const double* __restrict__ colmom,
+                                              double* __restrict__ augmom) {
+  extern __shared__ double mom[];  // [nJ][2][KY+1]
+  const int v = blockIdx.x;        // (dirC * nI + I) * (KX+1) + r, colmom's vector order
+  const double* vec = colmom + (size_t)v * N;
+  for (int J = threadIdx.x; J < nJ; J += blockDim.x) {
+    const int qs = J * TS;
+    const int w = min(TS, N - qs);
+    double pre[KY + 1], suf[KY + 1];
 #pragma unroll
-  for (int r = 0; r <= KY; ++r) {
-    const double a = gwk::wave_sum(pp * x);
-    const double b = gwk::wave_sum(ps * x);
-    if (c == 0) {
-      out[r] = a;
-      out[(KY + 1) + r] = b;
+    for (int r = 0; r <= KY; ++r) pre[r] = suf[r] = 0.0;
+    for (int c = 0; c < w; ++c) {
+      const double x = vec[qs + c];
+      double wp = 1.0, wsu = 1.0;
+      const double dp = (double)(w - c), ds = (double)(c + 1);
+#pragma unroll
+      for (int r = 0; r <= KY; ++r) {
+        pre[r] = fma(wp, x, pre[r]);
+        suf[r] = fma(wsu, x, suf[r]);
+        wp *= dp;
+        wsu *= ds;
+      }
     }
-    pp *= wp;
-    ps *= wsu;
+#pragma unroll
+    for (int r = 0; r <= KY; ++r) {
+      mom[(J * 2 + 0) * (KY + 1) + r] = pre[r];
+      mom[(J * 2 + 1) * (KY + 1) + r] = suf[r];
+    }
   }
-}
-
-// augmom layout per vector: [nJ][2][KY+1]; scan prefix over J, suffix over J.
-template <int KX, int KY>
-__global__ __launch_bounds__(64) void k_p2c_scan(int N, int nvec, int nJ,
-                                                  double* __restrict__ augmom) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= 2 * nvec) return;
-  const int v = idx >> 1, dir = idx & 1;
-  double* base = augmom + (size_t)v * nJ * 2 * (KY + 1) + dir * (KY + 1);
-  const size_t step = 2 * (KY + 1);
+  __syncthreads();
+  const int dir = threadIdx.x;
+  if (dir >= 2) return;
+  double* out = augmom + (size_t)v * nJ * 2 * (KY + 1);
   double st[KY + 1];
 #pragma unroll
   for (int r = 0; r <= KY; ++r) st[r] = 0.0;
   for (int s = 0; s < nJ; ++s) {
     const int J = dir == 0 ? s : nJ - 1 - s;
-    double* p = base + (size_t)J * step;
-    double tmp[KY + 1];
 #pragma unroll
-    for (int r = 0; r <= KY; ++r) {
-      tmp[r] = p[r];
-      p[r] = st[r];
-    }
+    for (int r = 0; r <= KY; ++r) out[(J * 2 + dir) * (KY + 1) + r] = st[r];
     const double wd = (double)min(TS, N - J * TS);
     gwk::pascal_shift<KY>(st, wd);
 #pragma unroll
-    for (int r = 0; r <= KY; ++r) st[r] += tmp[r];
-  }
-}
-
-// Sweep one line of length L held in LDS with stride `xs` from x, writing
-// D~ x (including the carried-in states) to y.  Both directions run in one
-// loop (independent recursions) to expose instruction-level parallelism.
-template <int K>
-__device__ void sweep_both(const double* x, double* y, int xs, int L, double (&a)[K + 1],
-                           double (&b)[K + 1]) {
-  for (int s = 0; s < L; ++s) {
-    const int cp = s, cs = L - 1 - s;
-    const double xp = x[cp * xs], xq = x[cs * xs];
-    const double op = a[K], oq = b[K];
-    gwk::pascal_step<K>(a, xp);
-    gwk::pascal_step<K>(b, xq);
-    if (cp < cs) {
-      y[cp * xs] = op;
-      y[cs * xs] = oq;
-    } else if (cp == cs) {
-      y[cp * xs] = op + oq;
-    } else {
-      y[cp * xs] += op;
-      y[cs * xs] += oq;
-    }
+    for (int r = 0; r <= KY; ++r) st[r] += mom[(J * 2 + dir) * (KY + 1) + r];
   }
 }
 
 // ---------------------------------------------------------- P3: tile sweeps
+// 320 threads: (line, seg) for 64 lines x 4 segments of 16, plus one wave for
+// the 2(KX+1) column-carry vectors (x 4 segments).  Row phase: each thread
+// loads its segment into registers, publishes segment summaries, combines the
+// summaries of the segments to its left/right with the tile's carries, sweeps
+// its segment and writes A in place.  Column phase: the same along columns
+// with A's column carries; results go from registers to G with the epilogue.
 template <int KX, int KY>
-__global__ __launch_bounds__(128) void k_p3_tile(const double* __restrict__ T, int64_t ldT, int M,
+__global__ __launch_bounds__(320) void k_p3_tile(const double* __restrict__ T, int64_t ldT, int M,
                                                   int N, int nI, int nJ,
                                                   const double* __restrict__ rowmom,
                                                   const double* __restrict__ colmom,
@@ -281,63 +318,124 @@ __global__ __launch_bounds__(128) void k_p3_tile(const double* __restrict__ T, i
                                                   const double* __restrict__ c1,
                                                   const double* __restrict__ c2, double s2,
                                                   double* __restrict__ G, int64_t ldG) {
+  constexpr int KM = (KX > KY ? KX : KY) + 1;
+  constexpr int NAUG = 2 * (KX + 1);
   __shared__ double X[TS][LDS_STRIDE];
-  __shared__ double Y[TS][LDS_STRIDE];
-  __shared__ double Vin[2][KX + 1][TS];
-  __shared__ double Vout[2][KX + 1][TS];
+  __shared__ double V[NAUG][TS];                   // column-carry vectors, then A's column carries
+  __shared__ double sums[2][NSEG][TS + NAUG][KM];  // [pre/suf][seg][line][r]
   const int J = blockIdx.x, I = blockIdx.y, t = threadIdx.x;
   const int js = I * TS, qs = J * TS;
   const int h = min(TS, M - js), w = min(TS, N - qs);
-  {
-    const int c = t & (TS - 1);
-    for (int r = t >> 6; r < TS; r += 2)
-      X[r][c] = (r < h && c < w) ? T[(int64_t)(js + r) * ldT + qs + c] : 0.0;
-    for (int v = t >> 6; v < 2 * (KX + 1); v += 2) {
+  const int lane = t & (TS - 1), wv = t >> 6;
+  // ---- load T tile (zero padded) and the column-carry vector slices
+  for (int r = wv; r < TS; r += 5)
+    X[r][lane] = (r < h && lane < w) ? T[(int64_t)(js + r) * ldT + qs + lane] : 0.0;
+  if (wv == 4) {
+    for (int v = 0; v < NAUG; ++v) {
       const int dirC = v / (KX + 1), r = v % (KX + 1);
-      Vin[dirC][r][c] = c < w ? colmom[((size_t)(dirC * nI + I) * (KX + 1) + r) * N + qs + c] : 0.0;
+      V[v][lane] = lane < w ? colmom[((size_t)(dirC * nI + I) * (KX + 1) + r) * N + qs + lane] : 0.0;
     }
   }
   __syncthreads();
-  if (t < TS) {
-    if (t < h) {
-      double a[KY + 1], b[KY + 1];
+  // ---- row phase: line = tile row (wv < 4) or column-carry vector (wv == 4)
+  const bool is_row = wv < 4;
+  const int seg = is_row ? wv : (lane & 3);
+  const int line = is_row ? lane : (TS + (lane >> 2));  // index into sums
+  const bool active = is_row ? true : ((lane >> 2) < NAUG);
+  double x[SEG];
+  if (active) {
+    const double* src = is_row ? &X[lane][0] : &V[lane >> 2][0];
+#pragma unroll
+    for (int c = 0; c < SEG; ++c) x[c] = src[seg * SEG + c];
+    double pre[KY + 1], suf[KY + 1];
+    seg_summaries<KY>(x, pre, suf);
+#pragma unroll
+    for (int r = 0; r <= KY; ++r) {
+      sums[0][seg][line][r] = pre[r];
+      sums[1][seg][line][r] = suf[r];
+    }
+  }
+  __syncthreads();
+  double out[SEG];
+  if (active) {
+    double a[KY + 1], b[KY + 1];
+    if (is_row) {
+      const bool real = lane < h;
 #pragma unroll
       for (int r = 0; r <= KY; ++r) {
-        a[r] = rowmom[((size_t)(0 * nJ + J) * (KY + 1) + r) * M + js + t];
-        b[r] = rowmom[((size_t)(1 * nJ + J) * (KY + 1) + r) * M + js + t];
+        a[r] = real ? rowmom[((size_t)(0 * nJ + J) * (KY + 1) + r) * M + js + lane] : 0.0;
+        b[r] = real ? rowmom[((size_t)(1 * nJ + J) * (KY + 1) + r) * M + js + lane] : 0.0;
       }
-      sweep_both<KY>(&X[t][0], &Y[t][0], 1, w, a, b);
-    }
-  } else if (t - TS < 2 * (KX + 1)) {
-    const int v = t - TS;
-    const int dirC = v / (KX + 1), r = v % (KX + 1);
-    const int vidx = (dirC * nI + I) * (KX + 1) + r;
-    const double* cor = augmom + ((size_t)vidx * nJ + J) * 2 * (KY + 1);
-    double a[KY + 1], b[KY + 1];
+    } else {
+      const int v = lane >> 2;
+      const int dirC = v / (KX + 1), rr = v % (KX + 1);
+      const int vidx = (dirC * nI + I) * (KX + 1) + rr;
+      const double* cor = augmom + ((size_t)vidx * nJ + J) * 2 * (KY + 1);
 #pragma unroll
-    for (int rr = 0; rr <= KY; ++rr) {
-      a[rr] = cor[rr];
-      b[rr] = cor[(KY + 1) + rr];
+      for (int r = 0; r <= KY; ++r) {
+        a[r] = cor[r];
+        b[r] = cor[(KY + 1) + r];
+      }
     }
-    sweep_both<KY>(&Vin[dirC][r][0], &Vout[dirC][r][0], 1, w, a, b);
+    // prefix state entering the segment: carries over segments 0..seg-1
+    for (int sg = 0; sg < seg; ++sg) {
+      gwk::pascal_shift<KY>(a, (double)SEG);
+#pragma unroll
+      for (int r = 0; r <= KY; ++r) a[r] += sums[0][sg][line][r];
+    }
+    // suffix state entering from the right: segments NSEG-1 .. seg+1
+    for (int sg = NSEG - 1; sg > seg; --sg) {
+      gwk::pascal_shift<KY>(b, (double)SEG);
+#pragma unroll
+      for (int r = 0; r <= KY; ++r) b[r] += sums[1][sg][line][r];
+    }
+    seg_sweep<KY>(x, a, b, out);
+  }
+  __syncthreads();  // everyone has read X / V
+  if (active) {
+    double* dst = is_row ? &X[lane][0] : &V[lane >> 2][0];
+#pragma unroll
+    for (int c = 0; c < SEG; ++c) dst[seg * SEG + c] = out[c];
   }
   __syncthreads();
-  if (t < w) {
+  // ---- column phase: 4 waves, (column = lane, segment of rows = wv)
+  if (wv < 4) {
+#pragma unroll
+    for (int i = 0; i < SEG; ++i) x[i] = X[wv * SEG + i][lane];
+    double pre[KX + 1], suf[KX + 1];
+    seg_summaries<KX>(x, pre, suf);
+#pragma unroll
+    for (int r = 0; r <= KX; ++r) {
+      sums[0][wv][lane][r] = pre[r];
+      sums[1][wv][lane][r] = suf[r];
+    }
+  }
+  __syncthreads();
+  if (wv < 4) {
     double a[KX + 1], b[KX + 1];
 #pragma unroll
     for (int r = 0; r <= KX; ++r) {
-      a[r] = Vout[0][r][t];
-      b[r] = Vout[1][r][t];
+      a[r] = V[r][lane];             // A's column carry from above (from Cpre)
+      b[r] = V[(KX + 1) + r][lane];  // from below (from Csuf)
     }
-    sweep_both<KX>(&Y[0][t], &X[0][t], LDS_STRIDE, h, a, b);
-  }
-  __syncthreads();
-  {
-    const int c = t & (TS - 1);
-    if (c < w) {
-      const double c2v = c2[qs + c];
-      for (int r = t >> 6; r < h; r += 2)
-        G[(int64_t)(js + r) * ldG + qs + c] = (c1[js + r] + c2v) - s2 * X[r][c];
+    for (int sg = 0; sg < wv; ++sg) {
+      gwk::pascal_shift<KX>(a, (double)SEG);
+#pragma unroll
+      for (int r = 0; r <= KX; ++r) a[r] += sums[0][sg][lane][r];
+    }
+    for (int sg = NSEG - 1; sg > wv; --sg) {
+      gwk::pascal_shift<KX>(b, (double)SEG);
+#pragma unroll
+      for (int r = 0; r <= KX; ++r) b[r] += sums[1][sg][lane][r];
+    }
+    seg_sweep<KX>(x, a, b, out);
+    if (lane < w) {
+      const double c2v = c2[qs + lane];
+#pragma unroll
+      for (int i = 0; i < SEG; ++i) {
+        const int r = wv * SEG + i;
+        if (r < h) G[(int64_t)(js + r) * ldG + qs + lane] = (c1[js + r] + c2v) - s2 * out[i];
+      }
     }
   }
 }
@@ -353,12 +451,12 @@ gw_status run_fast1d(const Layout& L, const double* T, int64_t ldT, double* G, i
     const int64_t lines = (int64_t)M + N;
     k_p2_scan<KX, KY><<<(unsigned)((lines + 255) / 256), 256, 0, s>>>(M, N, L.nI, L.nJ, rowmom, colmom);
     const int nvec = 2 * L.nI * (KX + 1);
-    k_p2c_moments<KX, KY><<<dim3(L.nJ, nvec), 64, 0, s>>>(N, L.nI, L.nJ, colmom, augmom);
-    k_p2c_scan<KX, KY><<<(2 * nvec + 63) / 64, 64, 0, s>>>(N, nvec, L.nJ, augmom);
+    const size_t shm = (size_t)L.nJ * 2 * (KY + 1) * sizeof(double);
+    k_p2c<KX, KY><<<nvec, 256, shm, s>>>(N, L.nJ, colmom, augmom);
   }
   {
     gwr::ProfScope ps(gwr::kFamFastMain, s);
-    k_p3_tile<KX, KY><<<dim3(L.nJ, L.nI), 128, 0, s>>>(T, ldT, M, N, L.nI, L.nJ, rowmom, colmom,
+    k_p3_tile<KX, KY><<<dim3(L.nJ, L.nI), 320, 0, s>>>(T, ldT, M, N, L.nI, L.nJ, rowmom, colmom,
                                                        augmom, c1, c2, s2, G, ldG);
   }
   return gwr::last_launch_status();

@@ -28,29 +28,33 @@ constexpr int NT = 256;
 
 // ------------------------------------------------------------ constant terms
 // c[i] = hk^2 * sum_j (d_ij)^2 w_j, d_ij the integer distance of the grid.
-__global__ __launch_bounds__(NT) void k_const_term(int ndim, int k, int metric, int64_t H,
-                                                    int64_t W, double hk,
-                                                    const double* __restrict__ w,
-                                                    double* __restrict__ c) {
-  // 64 outputs per block, 4 partial sums each.
-  __shared__ double part[4][64];
-  const int64_t n = H * W;
+// A block of 1024 threads owns 64 outputs; its 16 waves split j into 16
+// contiguous ranges and their partial sums are added in wave order.
+constexpr int CT_GROUPS = 16;
+
+__global__ __launch_bounds__(1024) void k_const_term(int metric, int k, int H, int W, double hk,
+                                                      const double* __restrict__ w,
+                                                      double* __restrict__ c) {
+  __shared__ double part[CT_GROUPS][64];
+  const int n = H * W;
   const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
-  const int64_t i = (int64_t)blockIdx.x * 64 + lane;
+  const int i = blockIdx.x * 64 + lane;
   double acc = 0.0;
   if (i < n) {
-    const int64_t ri = i / W, ci = i % W;
-    const int64_t chunk = (n + 3) / 4;
-    const int64_t j0 = grp * chunk, j1 = min(n, j0 + chunk);
-    int64_t rj = j0 / W, cj = j0 % W;
-    for (int64_t j = j0; j < j1; ++j) {
+    const int ri = i / W, ci = i % W;
+    const int chunk = (n + CT_GROUPS - 1) / CT_GROUPS;
+    const int j0 = grp * chunk, j1 = min(n, j0 + chunk);
+    int rj = j0 / W, cj = j0 % W;
+    for (int j = j0; j < j1; ++j) {
+      const int dr = abs(ri - rj), dc = abs(ci - cj);
       double d;
-      const int64_t dr = ri > rj ? ri - rj : rj - ri;
-      const int64_t dc = ci > cj ? ci - cj : cj - ci;
-      if (metric == GW_METRIC_SQEUCLID)
+      if (metric == GW_METRIC_SQEUCLID) {
         d = (double)(dr * dr + dc * dc);
-      else
-        d = gwk::ipow((double)(dr + dc), k);
+      } else {
+        const double e = (double)(dr + dc);
+        d = e;
+        for (int u = 1; u < k; ++u) d *= e;
+      }
       const double D = hk * d;
       acc = fma(D * D, w[j], acc);
       if (++cj == W) {
@@ -61,7 +65,12 @@ __global__ __launch_bounds__(NT) void k_const_term(int ndim, int k, int metric, 
   }
   part[grp][lane] = acc;
   __syncthreads();
-  if (grp == 0 && i < n) c[i] = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
+  if (grp == 0 && i < n) {
+    double s = part[0][lane];
+#pragma unroll
+    for (int g = 1; g < CT_GROUPS; ++g) s += part[g][lane];
+    c[i] = s;
+  }
 }
 
 // ---------------------------------------------------------------- transpose
@@ -308,7 +317,7 @@ namespace gwl {
 gw_status const_term(const gwr::Grid& g, const double* w, double* c, hipStream_t s) {
   gwr::ProfScope ps(gwr::kFamOther, s);
   const int64_t n = g.n();
-  k_const_term<<<(unsigned)((n + 63) / 64), NT, 0, s>>>(g.ndim, g.k, g.metric, g.H, g.W, g.hk(), w, c);
+  k_const_term<<<(unsigned)((n + 63) / 64), 1024, 0, s>>>(g.metric, g.k, (int)g.H, (int)g.W, g.hk(), w, c);
   return gwr::last_launch_status();
 }
 

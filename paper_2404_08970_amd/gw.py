@@ -261,8 +261,15 @@ def check_status(ws=None):
     _raise(st, "gw_check_status")
 
 
-def profile_enable(on: bool = True):
-    _lib().gw_profile_enable(1 if on else 0)
+def profile_enable(families=None):
+    """Record kernel times for the given families (None = all, [] = off)."""
+    if families is None:
+        mask = 0xFF
+    else:
+        mask = 0
+        for f in families:
+            mask |= 1 << int(f)
+    _lib().gw_profile_enable(mask)
 
 
 def profile_read(family: int):
