@@ -49,16 +49,44 @@ GW_DEV void pascal_shift(double (&a)[K + 1], double w) {
   }
 }
 
+// Move a double across lanes with one DPP pattern (both 32-bit halves);
+// lanes the pattern does not write receive `old`.
+template <int CTRL, int ROW_MASK = 0xF>
+GW_DEV double dpp_f64(double v, double old) {
+  const int lo = __builtin_amdgcn_update_dpp(__double2loint(old), __double2loint(v), CTRL,
+                                             ROW_MASK, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(__double2hiint(old), __double2hiint(v), CTRL,
+                                             ROW_MASK, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+GW_DEV double readlane_f64(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+
+// Wave64 reductions with DPP: swaps within quads, half-row and row mirrors,
+// then the two row broadcasts leave the total in lane 63 (GCN/CDNA pattern).
+// The result is returned in every lane.
 GW_DEV double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, kWave);
-  return v;
+  v += dpp_f64<0xB1>(v, 0.0);        // quad_perm [1,0,3,2]
+  v += dpp_f64<0x4E>(v, 0.0);        // quad_perm [2,3,0,1]
+  v += dpp_f64<0x141>(v, 0.0);       // row_half_mirror
+  v += dpp_f64<0x140>(v, 0.0);       // row_mirror
+  v += dpp_f64<0x142, 0xA>(v, 0.0);  // row_bcast:15 into rows 1 and 3
+  v += dpp_f64<0x143, 0xC>(v, 0.0);  // row_bcast:31 into rows 2 and 3
+  return readlane_f64(v, 63);
 }
 
 GW_DEV double wave_max(double v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, kWave));
-  return v;
+  v = fmax(v, dpp_f64<0xB1>(v, v));
+  v = fmax(v, dpp_f64<0x4E>(v, v));
+  v = fmax(v, dpp_f64<0x141>(v, v));
+  v = fmax(v, dpp_f64<0x140>(v, v));
+  v = fmax(v, dpp_f64<0x142, 0xA>(v, v));
+  v = fmax(v, dpp_f64<0x143, 0xC>(v, v));
+  return readlane_f64(v, 63);
 }
 
 GW_DEV int wave_max_int(int v) {

@@ -31,12 +31,12 @@ constexpr int LDS_STRIDE = TS + 1;
 // Workspace layout (doubles):
 //   rowmom [2][nJ][ky+1][M]   row moments, then (in place) row carries
 //   colmom [2][nI][kx+1][N]   column moments, then column carries
-//   augmom [2*nI*(kx+1)][nJ][2][ky+1]  tile moments of the column-carry vectors,
-//                                       then (in place) their row carries
+//   acarry [2][nI][kx+1][N]   column carries of A = T D~_Y (D~_Y applied to
+//                             the column carries of T)
 struct Layout {
   int64_t M, N;
   int nI, nJ, kx, ky;
-  size_t rowmom, colmom, augmom;  // element counts
+  size_t rowmom, colmom, acarry;  // element counts
 };
 
 Layout make_layout(int64_t M, int64_t N, int kx, int ky) {
@@ -49,7 +49,7 @@ Layout make_layout(int64_t M, int64_t N, int kx, int ky) {
   L.nJ = (int)((N + TS - 1) / TS);
   L.rowmom = (size_t)2 * L.nJ * (ky + 1) * M;
   L.colmom = (size_t)2 * L.nI * (kx + 1) * N;
-  L.augmom = (size_t)2 * L.nI * (kx + 1) * L.nJ * 2 * (ky + 1);
+  L.acarry = L.colmom;
   return L;
 }
 
@@ -94,11 +94,36 @@ GW_DEV void seg_sweep(const double (&x)[SEG], double (&a)[K + 1], double (&b)[K 
   }
 }
 
+// Combine the NSEG segment summaries of one line (LDS layout part[seg][line][*],
+// prefix in [0..K], suffix in [KM..KM+K]) into the line's tile moments:
+// prefix at the tile end = sum_s P(SEG (NSEG-1-s)) pre_s, suffix at the tile
+// start - 1 = sum_s P(SEG s) suf_s.
+template <int K, int KM, int LINES>
+GW_DEV void combine_segments(const double (*part)[LINES][2 * KM], int line, double (&a)[K + 1],
+                             double (&b)[K + 1]) {
+#pragma unroll
+  for (int r = 0; r <= K; ++r) {
+    a[r] = part[0][line][r];
+    b[r] = part[NSEG - 1][line][KM + r];
+  }
+#pragma unroll
+  for (int sg = 1; sg < NSEG; ++sg) {
+    gwk::pascal_shift<K>(a, (double)SEG);
+    gwk::pascal_shift<K>(b, (double)SEG);
+#pragma unroll
+    for (int r = 0; r <= K; ++r) {
+      a[r] += part[sg][line][r];
+      b[r] += part[NSEG - 1 - sg][line][KM + r];
+    }
+  }
+}
+
 // ---------------------------------------------------------------- P1 moments
-// Block of 256 threads per 64 x 64 tile: thread (line, seg) sums a 16-entry
-// segment of its row (for row moments) and of its column (column moments);
-// the 4 segment summaries of a line are combined with Pascal shifts.  Entries
-// beyond the matrix are zero, so every tile is handled at its nominal size.
+// Persistent blocks of 256 threads walk the tiles; thread (line, seg) holds a
+// 16-entry column segment of the tile in registers (loaded one tile ahead),
+// sums it for the column moments, and sums a row segment (through LDS) for
+// the row moments.  Entries beyond the matrix are zero, so every tile is
+// handled at its nominal size.
 template <int KX, int KY>
 __global__ __launch_bounds__(256) void k_p1_moments(const double* __restrict__ T, int64_t ldT,
                                                      int M, int N, int nI, int nJ,
@@ -107,92 +132,75 @@ __global__ __launch_bounds__(256) void k_p1_moments(const double* __restrict__ T
   constexpr int KM = (KX > KY ? KX : KY) + 1;
   __shared__ double X[TS][LDS_STRIDE];
   __shared__ double part[2][NSEG][TS][2 * KM];
-  const int J = blockIdx.x, I = blockIdx.y, t = threadIdx.x;
-  const int js = I * TS, qs = J * TS;
-  const int h = min(TS, M - js), w = min(TS, N - qs);
-  const int line = t & (TS - 1), seg = t >> 6;
-  {
-    // column segment straight from global memory (lanes = columns)
-    double x[SEG];
+  const int t = threadIdx.x, lane = t & (TS - 1), seg = t >> 6;
+  const int ntiles = nI * nJ;
+  double pf[SEG];
+  auto load_tile = [&](int tile) {
+    const int I = tile / nJ, J = tile - (tile / nJ) * nJ;
+    const int col = min(J * TS + lane, N - 1);
 #pragma unroll
     for (int i = 0; i < SEG; ++i) {
-      const int r = seg * SEG + i;
-      x[i] = (r < h && line < w) ? T[(int64_t)(js + r) * ldT + qs + line] : 0.0;
-      X[r][line] = x[i];
+      const int row = min(I * TS + seg * SEG + i, M - 1);
+      pf[i] = T[(int64_t)row * ldT + col];
     }
-    double pre[KX + 1], suf[KX + 1];
-    seg_summaries<KX>(x, pre, suf);
-#pragma unroll
-    for (int r = 0; r <= KX; ++r) {
-      part[1][seg][line][r] = pre[r];
-      part[1][seg][line][KM + r] = suf[r];
-    }
-  }
-  __syncthreads();
-  {
+  };
+  int tile = blockIdx.x;
+  if (tile < ntiles) load_tile(tile);
+  for (; tile < ntiles; tile += gridDim.x) {
+    const int I = tile / nJ, J = tile - I * nJ;
+    const int js = I * TS, qs = J * TS;
+    const int h = min(TS, M - js), w = min(TS, N - qs);
     double x[SEG];
 #pragma unroll
-    for (int c = 0; c < SEG; ++c) x[c] = X[line][seg * SEG + c];
-    double pre[KY + 1], suf[KY + 1];
-    seg_summaries<KY>(x, pre, suf);
+    for (int i = 0; i < SEG; ++i) x[i] = (seg * SEG + i < h && lane < w) ? pf[i] : 0.0;
+    load_tile(min(tile + (int)gridDim.x, ntiles - 1));
+    {
+      double pre[KX + 1], suf[KX + 1];
+      seg_summaries<KX>(x, pre, suf);
 #pragma unroll
-    for (int r = 0; r <= KY; ++r) {
-      part[0][seg][line][r] = pre[r];
-      part[0][seg][line][KM + r] = suf[r];
-    }
-  }
-  __syncthreads();
-  // combine: prefix at the tile end = sum_s P(16 (3 - s)) pre_s; suffix at
-  // the tile start - 1 = sum_s P(16 s) suf_s.  Threads 0..63 rows, 64..127 columns.
-  if (t < TS) {
-    if (t < h) {
-      double a[KY + 1], b[KY + 1];
-#pragma unroll
-      for (int r = 0; r <= KY; ++r) {
-        a[r] = part[0][0][t][r];
-        b[r] = part[0][NSEG - 1][t][KM + r];
+      for (int r = 0; r <= KX; ++r) {
+        part[1][seg][lane][r] = pre[r];
+        part[1][seg][lane][KM + r] = suf[r];
       }
 #pragma unroll
-      for (int sg = 1; sg < NSEG; ++sg) {
-        gwk::pascal_shift<KY>(a, (double)SEG);
-        gwk::pascal_shift<KY>(b, (double)SEG);
+      for (int i = 0; i < SEG; ++i) X[seg * SEG + i][lane] = x[i];
+    }
+    __syncthreads();
+    {
+#pragma unroll
+      for (int c = 0; c < SEG; ++c) x[c] = X[lane][seg * SEG + c];
+      double pre[KY + 1], suf[KY + 1];
+      seg_summaries<KY>(x, pre, suf);
+#pragma unroll
+      for (int r = 0; r <= KY; ++r) {
+        part[0][seg][lane][r] = pre[r];
+        part[0][seg][lane][KM + r] = suf[r];
+      }
+    }
+    __syncthreads();
+    if (t < TS) {
+      if (t < h) {
+        double a[KY + 1], b[KY + 1];
+        combine_segments<KY, KM, TS>(part[0], t, a, b);
 #pragma unroll
         for (int r = 0; r <= KY; ++r) {
-          a[r] += part[0][sg][t][r];
-          b[r] += part[0][NSEG - 1 - sg][t][KM + r];
+          rowmom[((size_t)(0 * nJ + J) * (KY + 1) + r) * M + js + t] = a[r];
+          rowmom[((size_t)(1 * nJ + J) * (KY + 1) + r) * M + js + t] = b[r];
         }
       }
-#pragma unroll
-      for (int r = 0; r <= KY; ++r) {
-        rowmom[((size_t)(0 * nJ + J) * (KY + 1) + r) * M + js + t] = a[r];
-        rowmom[((size_t)(1 * nJ + J) * (KY + 1) + r) * M + js + t] = b[r];
-      }
-    }
-  } else if (t < 2 * TS) {
-    const int c = t - TS;
-    if (c < w) {
-      double a[KX + 1], b[KX + 1];
-#pragma unroll
-      for (int r = 0; r <= KX; ++r) {
-        a[r] = part[1][0][c][r];
-        b[r] = part[1][NSEG - 1][c][KM + r];
-      }
-#pragma unroll
-      for (int sg = 1; sg < NSEG; ++sg) {
-        gwk::pascal_shift<KX>(a, (double)SEG);
-        gwk::pascal_shift<KX>(b, (double)SEG);
+    } else if (t < 2 * TS) {
+      const int c = t - TS;
+      if (c < w) {
+        double a[KX + 1], b[KX + 1];
+        combine_segments<KX, KM, TS>(part[1], c, a, b);
 #pragma unroll
         for (int r = 0; r <= KX; ++r) {
-          a[r] += part[1][sg][c][r];
-          b[r] += part[1][NSEG - 1 - sg][c][KM + r];
+          colmom[((size_t)(0 * nI + I) * (KX + 1) + r) * N + qs + c] = a[r];
+          colmom[((size_t)(1 * nI + I) * (KX + 1) + r) * N + qs + c] = b[r];
         }
       }
-#pragma unroll
-      for (int r = 0; r <= KX; ++r) {
-        colmom[((size_t)(0 * nI + I) * (KX + 1) + r) * N + qs + c] = a[r];
-        colmom[((size_t)(1 * nI + I) * (KX + 1) + r) * N + qs + c] = b[r];
-      }
     }
+    __syncthreads();
   }
 }
 
@@ -249,215 +257,275 @@ __global__ __launch_bounds__(256) void k_p2_scan(int M, int N, int nI, int nJ,
   }
 }
 
-// ------------- P2c: row carries of the column-carry vectors, one block per vector
-// Thread J computes the moments of its tile of the vector; two threads then
-// scan the tiles (prefix, suffix) out of LDS.  Output layout per vector:
-// [nJ][2][KY+1] (prefix state at the tile's first column, suffix state at its
-// last column).
+// ------------- P2c: column carries of A = T D~_Y, one block per vector.
+// A's column carries at the top (bottom) of tile-row I are D~_Y applied to the
+// column carries of T, vectors of length N (Cpre/Csuf, one per moment order).
+// Pass A sums each tile of the vector (4 threads x 16-entry segments per
+// tile), two threads scan the tile moments, pass B sweeps every tile with its
+// carries and writes the full vector to acarry (same layout as colmom).
 template <int KX, int KY>
 __global__ __launch_bounds__(256) void k_p2c(int N, int nJ, const double* __restrict__ colmom,
-                                              double* __restrict__ augmom) {
+                                              double* __restrict__ acarry) {
+  constexpr int KM = KY + 1;
   extern __shared__ double mom[];  // [nJ][2][KY+1]
-  const int v = blockIdx.x;        // (dirC * nI + I) * (KX+1) + r, colmom's vector order
+  __shared__ double part[NSEG][TS][2 * KM];
+  const int v = blockIdx.x;
   const double* vec = colmom + (size_t)v * N;
-  for (int J = threadIdx.x; J < nJ; J += blockDim.x) {
-    const int qs = J * TS;
-    const int w = min(TS, N - qs);
-    double pre[KY + 1], suf[KY + 1];
+  double* out = acarry + (size_t)v * N;
+  const int t = threadIdx.x, tl = t >> 2, seg = t & 3;
+  auto load = [&](double (&x)[SEG], int J) {
 #pragma unroll
-    for (int r = 0; r <= KY; ++r) pre[r] = suf[r] = 0.0;
-    for (int c = 0; c < w; ++c) {
-      const double x = vec[qs + c];
-      double wp = 1.0, wsu = 1.0;
-      const double dp = (double)(w - c), ds = (double)(c + 1);
-#pragma unroll
-      for (int r = 0; r <= KY; ++r) {
-        pre[r] = fma(wp, x, pre[r]);
-        suf[r] = fma(wsu, x, suf[r]);
-        wp *= dp;
-        wsu *= ds;
-      }
+    for (int c = 0; c < SEG; ++c) {
+      const int p = J * TS + seg * SEG + c;
+      x[c] = (J < nJ && p < N) ? vec[p] : 0.0;
     }
-#pragma unroll
-    for (int r = 0; r <= KY; ++r) {
-      mom[(J * 2 + 0) * (KY + 1) + r] = pre[r];
-      mom[(J * 2 + 1) * (KY + 1) + r] = suf[r];
-    }
-  }
-  __syncthreads();
-  const int dir = threadIdx.x;
-  if (dir >= 2) return;
-  double* out = augmom + (size_t)v * nJ * 2 * (KY + 1);
-  double st[KY + 1];
-#pragma unroll
-  for (int r = 0; r <= KY; ++r) st[r] = 0.0;
-  for (int s = 0; s < nJ; ++s) {
-    const int J = dir == 0 ? s : nJ - 1 - s;
-#pragma unroll
-    for (int r = 0; r <= KY; ++r) out[(J * 2 + dir) * (KY + 1) + r] = st[r];
-    const double wd = (double)min(TS, N - J * TS);
-    gwk::pascal_shift<KY>(st, wd);
-#pragma unroll
-    for (int r = 0; r <= KY; ++r) st[r] += mom[(J * 2 + dir) * (KY + 1) + r];
-  }
-}
-
-// ---------------------------------------------------------- P3: tile sweeps
-// 320 threads: (line, seg) for 64 lines x 4 segments of 16, plus one wave for
-// the 2(KX+1) column-carry vectors (x 4 segments).  Row phase: each thread
-// loads its segment into registers, publishes segment summaries, combines the
-// summaries of the segments to its left/right with the tile's carries, sweeps
-// its segment and writes A in place.  Column phase: the same along columns
-// with A's column carries; results go from registers to G with the epilogue.
-template <int KX, int KY>
-__global__ __launch_bounds__(320) void k_p3_tile(const double* __restrict__ T, int64_t ldT, int M,
-                                                  int N, int nI, int nJ,
-                                                  const double* __restrict__ rowmom,
-                                                  const double* __restrict__ colmom,
-                                                  const double* __restrict__ augmom,
-                                                  const double* __restrict__ c1,
-                                                  const double* __restrict__ c2, double s2,
-                                                  double* __restrict__ G, int64_t ldG) {
-  constexpr int KM = (KX > KY ? KX : KY) + 1;
-  constexpr int NAUG = 2 * (KX + 1);
-  __shared__ double X[TS][LDS_STRIDE];
-  __shared__ double V[NAUG][TS];                   // column-carry vectors, then A's column carries
-  __shared__ double sums[2][NSEG][TS + NAUG][KM];  // [pre/suf][seg][line][r]
-  const int J = blockIdx.x, I = blockIdx.y, t = threadIdx.x;
-  const int js = I * TS, qs = J * TS;
-  const int h = min(TS, M - js), w = min(TS, N - qs);
-  const int lane = t & (TS - 1), wv = t >> 6;
-  // ---- load T tile (zero padded) and the column-carry vector slices
-  for (int r = wv; r < TS; r += 5)
-    X[r][lane] = (r < h && lane < w) ? T[(int64_t)(js + r) * ldT + qs + lane] : 0.0;
-  if (wv == 4) {
-    for (int v = 0; v < NAUG; ++v) {
-      const int dirC = v / (KX + 1), r = v % (KX + 1);
-      V[v][lane] = lane < w ? colmom[((size_t)(dirC * nI + I) * (KX + 1) + r) * N + qs + lane] : 0.0;
-    }
-  }
-  __syncthreads();
-  // ---- row phase: line = tile row (wv < 4) or column-carry vector (wv == 4)
-  const bool is_row = wv < 4;
-  const int seg = is_row ? wv : (lane & 3);
-  const int line = is_row ? lane : (TS + (lane >> 2));  // index into sums
-  const bool active = is_row ? true : ((lane >> 2) < NAUG);
-  double x[SEG];
-  if (active) {
-    const double* src = is_row ? &X[lane][0] : &V[lane >> 2][0];
-#pragma unroll
-    for (int c = 0; c < SEG; ++c) x[c] = src[seg * SEG + c];
+  };
+  // pass A: tile moments
+  for (int J0 = 0; J0 < nJ; J0 += TS) {
+    const int J = J0 + tl;
+    double x[SEG];
+    load(x, J);
     double pre[KY + 1], suf[KY + 1];
     seg_summaries<KY>(x, pre, suf);
 #pragma unroll
     for (int r = 0; r <= KY; ++r) {
-      sums[0][seg][line][r] = pre[r];
-      sums[1][seg][line][r] = suf[r];
+      part[seg][tl][r] = pre[r];
+      part[seg][tl][KM + r] = suf[r];
+    }
+    __syncthreads();
+    if (seg == 0 && J < nJ) {
+      double a[KY + 1], b[KY + 1];
+      combine_segments<KY, KM, TS>(part, tl, a, b);
+#pragma unroll
+      for (int r = 0; r <= KY; ++r) {
+        mom[(J * 2 + 0) * KM + r] = a[r];
+        mom[(J * 2 + 1) * KM + r] = b[r];
+      }
+    }
+    __syncthreads();
+  }
+  // exclusive scans over the tiles: prefix (state at each tile's first entry)
+  // and suffix (state at each tile's last entry), in place
+  if (t < 2) {
+    const int dir = t;
+    double st[KY + 1];
+#pragma unroll
+    for (int r = 0; r <= KY; ++r) st[r] = 0.0;
+    for (int s = 0; s < nJ; ++s) {
+      const int J = dir == 0 ? s : nJ - 1 - s;
+      double tmp[KY + 1];
+#pragma unroll
+      for (int r = 0; r <= KY; ++r) {
+        tmp[r] = mom[(J * 2 + dir) * KM + r];
+        mom[(J * 2 + dir) * KM + r] = st[r];
+      }
+      gwk::pascal_shift<KY>(st, (double)TS);
+#pragma unroll
+      for (int r = 0; r <= KY; ++r) st[r] += tmp[r];
     }
   }
   __syncthreads();
-  double out[SEG];
-  if (active) {
-    double a[KY + 1], b[KY + 1];
-    if (is_row) {
-      const bool real = lane < h;
+  // pass B: in-tile sweeps with the tile carries
+  for (int J0 = 0; J0 < nJ; J0 += TS) {
+    const int J = J0 + tl;
+    double x[SEG];
+    load(x, J);
+    double pre[KY + 1], suf[KY + 1];
+    seg_summaries<KY>(x, pre, suf);
+#pragma unroll
+    for (int r = 0; r <= KY; ++r) {
+      part[seg][tl][r] = pre[r];
+      part[seg][tl][KM + r] = suf[r];
+    }
+    __syncthreads();
+    if (J < nJ) {
+      double a[KY + 1], b[KY + 1];
 #pragma unroll
       for (int r = 0; r <= KY; ++r) {
-        a[r] = real ? rowmom[((size_t)(0 * nJ + J) * (KY + 1) + r) * M + js + lane] : 0.0;
-        b[r] = real ? rowmom[((size_t)(1 * nJ + J) * (KY + 1) + r) * M + js + lane] : 0.0;
+        a[r] = mom[(J * 2 + 0) * KM + r];
+        b[r] = mom[(J * 2 + 1) * KM + r];
       }
-    } else {
-      const int v = lane >> 2;
-      const int dirC = v / (KX + 1), rr = v % (KX + 1);
-      const int vidx = (dirC * nI + I) * (KX + 1) + rr;
-      const double* cor = augmom + ((size_t)vidx * nJ + J) * 2 * (KY + 1);
+      for (int sg = 0; sg < seg; ++sg) {
+        gwk::pascal_shift<KY>(a, (double)SEG);
 #pragma unroll
-      for (int r = 0; r <= KY; ++r) {
-        a[r] = cor[r];
-        b[r] = cor[(KY + 1) + r];
+        for (int r = 0; r <= KY; ++r) a[r] += part[sg][tl][r];
+      }
+      for (int sg = NSEG - 1; sg > seg; --sg) {
+        gwk::pascal_shift<KY>(b, (double)SEG);
+#pragma unroll
+        for (int r = 0; r <= KY; ++r) b[r] += part[sg][tl][KM + r];
+      }
+      double o[SEG];
+      seg_sweep<KY>(x, a, b, o);
+#pragma unroll
+      for (int c = 0; c < SEG; ++c) {
+        const int p = J * TS + seg * SEG + c;
+        if (p < N) out[p] = o[c];
       }
     }
-    // prefix state entering the segment: carries over segments 0..seg-1
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------- P3: tile sweeps
+// Persistent blocks of 256 threads walk the tiles, the next tile's T already
+// in registers.  Row phase: thread (row = lane, seg = wave) sweeps a 16-entry
+// row segment; segment summaries pass through LDS and are combined with the
+// tile's row carries, and A overwrites T in LDS.  Column phase: thread
+// (column = lane, seg = wave) does the same along the column with A's column
+// carries, and writes G = (c1 + c2) - s2 B from registers.
+template <int KX, int KY>
+__global__ __launch_bounds__(256) void k_p3_tile(const double* __restrict__ T, int64_t ldT, int M,
+                                                  int N, int nI, int nJ,
+                                                  const double* __restrict__ rowmom,
+                                                  const double* __restrict__ acarry,
+                                                  const double* __restrict__ c1,
+                                                  const double* __restrict__ c2, double s2,
+                                                  double* __restrict__ G, int64_t ldG) {
+  constexpr int KM = (KX > KY ? KX : KY) + 1;
+  __shared__ double X[TS][LDS_STRIDE];
+  __shared__ double sums[2][NSEG][TS][KM];  // [pre/suf][seg][line][r]
+  const int t = threadIdx.x, lane = t & (TS - 1), seg = t >> 6;
+  const int ntiles = nI * nJ;
+  double pf[SEG];
+  auto load_tile = [&](int tile) {
+    const int I = tile / nJ, J = tile - (tile / nJ) * nJ;
+    const int col = min(J * TS + lane, N - 1);
+#pragma unroll
+    for (int i = 0; i < SEG; ++i) {
+      const int row = min(I * TS + seg * SEG + i, M - 1);
+      pf[i] = T[(int64_t)row * ldT + col];
+    }
+  };
+  int tile = blockIdx.x;
+  if (tile < ntiles) load_tile(tile);
+  for (; tile < ntiles; tile += gridDim.x) {
+    const int I = tile / nJ, J = tile - I * nJ;
+    const int js = I * TS, qs = J * TS;
+    const int h = min(TS, M - js), w = min(TS, N - qs);
+    double x[SEG];
+#pragma unroll
+    for (int i = 0; i < SEG; ++i) x[i] = (seg * SEG + i < h && lane < w) ? pf[i] : 0.0;
+    load_tile(min(tile + (int)gridDim.x, ntiles - 1));
+    // carries for this tile: row carries of the thread's row, A's column
+    // carries of its column (loaded now, used after the barriers)
+    double ra[KY + 1], rb[KY + 1], ca[KX + 1], cb[KX + 1];
+    {
+      const int row = min(js + lane, M - 1);
+      const double keep = lane < h ? 1.0 : 0.0;
+#pragma unroll
+      for (int r = 0; r <= KY; ++r) {
+        ra[r] = keep * rowmom[((size_t)(0 * nJ + J) * (KY + 1) + r) * M + row];
+        rb[r] = keep * rowmom[((size_t)(1 * nJ + J) * (KY + 1) + r) * M + row];
+      }
+      const int col = min(qs + lane, N - 1);
+#pragma unroll
+      for (int r = 0; r <= KX; ++r) {
+        ca[r] = acarry[((size_t)(0 * nI + I) * (KX + 1) + r) * N + col];
+        cb[r] = acarry[((size_t)(1 * nI + I) * (KX + 1) + r) * N + col];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < SEG; ++i) X[seg * SEG + i][lane] = x[i];
+    __syncthreads();
+    // ---- row phase
+#pragma unroll
+    for (int c = 0; c < SEG; ++c) x[c] = X[lane][seg * SEG + c];
+    {
+      double pre[KY + 1], suf[KY + 1];
+      seg_summaries<KY>(x, pre, suf);
+#pragma unroll
+      for (int r = 0; r <= KY; ++r) {
+        sums[0][seg][lane][r] = pre[r];
+        sums[1][seg][lane][r] = suf[r];
+      }
+    }
+    __syncthreads();
+    double out[SEG];
+    {
+      for (int sg = 0; sg < seg; ++sg) {
+        gwk::pascal_shift<KY>(ra, (double)SEG);
+#pragma unroll
+        for (int r = 0; r <= KY; ++r) ra[r] += sums[0][sg][lane][r];
+      }
+      for (int sg = NSEG - 1; sg > seg; --sg) {
+        gwk::pascal_shift<KY>(rb, (double)SEG);
+#pragma unroll
+        for (int r = 0; r <= KY; ++r) rb[r] += sums[1][sg][lane][r];
+      }
+      seg_sweep<KY>(x, ra, rb, out);
+#pragma unroll
+      for (int c = 0; c < SEG; ++c) X[lane][seg * SEG + c] = out[c];
+    }
+    __syncthreads();
+    // ---- column phase
+#pragma unroll
+    for (int i = 0; i < SEG; ++i) x[i] = X[seg * SEG + i][lane];
+    {
+      double pre[KX + 1], suf[KX + 1];
+      seg_summaries<KX>(x, pre, suf);
+#pragma unroll
+      for (int r = 0; r <= KX; ++r) {
+        sums[0][seg][lane][r] = pre[r];
+        sums[1][seg][lane][r] = suf[r];
+      }
+    }
+    __syncthreads();
     for (int sg = 0; sg < seg; ++sg) {
-      gwk::pascal_shift<KY>(a, (double)SEG);
+      gwk::pascal_shift<KX>(ca, (double)SEG);
 #pragma unroll
-      for (int r = 0; r <= KY; ++r) a[r] += sums[0][sg][line][r];
+      for (int r = 0; r <= KX; ++r) ca[r] += sums[0][sg][lane][r];
     }
-    // suffix state entering from the right: segments NSEG-1 .. seg+1
     for (int sg = NSEG - 1; sg > seg; --sg) {
-      gwk::pascal_shift<KY>(b, (double)SEG);
+      gwk::pascal_shift<KX>(cb, (double)SEG);
 #pragma unroll
-      for (int r = 0; r <= KY; ++r) b[r] += sums[1][sg][line][r];
+      for (int r = 0; r <= KX; ++r) cb[r] += sums[1][sg][lane][r];
     }
-    seg_sweep<KY>(x, a, b, out);
-  }
-  __syncthreads();  // everyone has read X / V
-  if (active) {
-    double* dst = is_row ? &X[lane][0] : &V[lane >> 2][0];
-#pragma unroll
-    for (int c = 0; c < SEG; ++c) dst[seg * SEG + c] = out[c];
-  }
-  __syncthreads();
-  // ---- column phase: 4 waves, (column = lane, segment of rows = wv)
-  if (wv < 4) {
-#pragma unroll
-    for (int i = 0; i < SEG; ++i) x[i] = X[wv * SEG + i][lane];
-    double pre[KX + 1], suf[KX + 1];
-    seg_summaries<KX>(x, pre, suf);
-#pragma unroll
-    for (int r = 0; r <= KX; ++r) {
-      sums[0][wv][lane][r] = pre[r];
-      sums[1][wv][lane][r] = suf[r];
-    }
-  }
-  __syncthreads();
-  if (wv < 4) {
-    double a[KX + 1], b[KX + 1];
-#pragma unroll
-    for (int r = 0; r <= KX; ++r) {
-      a[r] = V[r][lane];             // A's column carry from above (from Cpre)
-      b[r] = V[(KX + 1) + r][lane];  // from below (from Csuf)
-    }
-    for (int sg = 0; sg < wv; ++sg) {
-      gwk::pascal_shift<KX>(a, (double)SEG);
-#pragma unroll
-      for (int r = 0; r <= KX; ++r) a[r] += sums[0][sg][lane][r];
-    }
-    for (int sg = NSEG - 1; sg > wv; --sg) {
-      gwk::pascal_shift<KX>(b, (double)SEG);
-#pragma unroll
-      for (int r = 0; r <= KX; ++r) b[r] += sums[1][sg][lane][r];
-    }
-    seg_sweep<KX>(x, a, b, out);
+    seg_sweep<KX>(x, ca, cb, out);
     if (lane < w) {
       const double c2v = c2[qs + lane];
 #pragma unroll
       for (int i = 0; i < SEG; ++i) {
-        const int r = wv * SEG + i;
+        const int r = seg * SEG + i;
         if (r < h) G[(int64_t)(js + r) * ldG + qs + lane] = (c1[js + r] + c2v) - s2 * out[i];
       }
     }
+    __syncthreads();
   }
+}
+
+int persistent_blocks(int ntiles, int per_cu) {
+  static int ncu = 0;
+  if (ncu == 0) {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+      ncu = prop.multiProcessorCount;
+    if (ncu <= 0) ncu = 256;
+  }
+  const int g = ncu * per_cu;
+  return ntiles < g ? ntiles : g;
 }
 
 template <int KX, int KY>
 gw_status run_fast1d(const Layout& L, const double* T, int64_t ldT, double* G, int64_t ldG,
                      const double* c1, const double* c2, double s2, double* rowmom,
-                     double* colmom, double* augmom, hipStream_t s) {
+                     double* colmom, double* acarry, hipStream_t s) {
   const int M = (int)L.M, N = (int)L.N;
+  const int ntiles = L.nI * L.nJ;
   {
     gwr::ProfScope ps(gwr::kFamFastCarry, s);
-    k_p1_moments<KX, KY><<<dim3(L.nJ, L.nI), 256, 0, s>>>(T, ldT, M, N, L.nI, L.nJ, rowmom, colmom);
+    k_p1_moments<KX, KY><<<persistent_blocks(ntiles, 2), 256, 0, s>>>(T, ldT, M, N, L.nI, L.nJ, rowmom, colmom);
     const int64_t lines = (int64_t)M + N;
     k_p2_scan<KX, KY><<<(unsigned)((lines + 255) / 256), 256, 0, s>>>(M, N, L.nI, L.nJ, rowmom, colmom);
     const int nvec = 2 * L.nI * (KX + 1);
     const size_t shm = (size_t)L.nJ * 2 * (KY + 1) * sizeof(double);
-    k_p2c<KX, KY><<<nvec, 256, shm, s>>>(N, L.nJ, colmom, augmom);
+    k_p2c<KX, KY><<<nvec, 256, shm, s>>>(N, L.nJ, colmom, acarry);
   }
   {
     gwr::ProfScope ps(gwr::kFamFastMain, s);
-    k_p3_tile<KX, KY><<<dim3(L.nJ, L.nI), 320, 0, s>>>(T, ldT, M, N, L.nI, L.nJ, rowmom, colmom,
-                                                       augmom, c1, c2, s2, G, ldG);
+    k_p3_tile<KX, KY><<<persistent_blocks(ntiles, 3), 256, 0, s>>>(T, ldT, M, N, L.nI, L.nJ, rowmom,
+                                                                   acarry, c1, c2, s2, G, ldG);
   }
   return gwr::last_launch_status();
 }
@@ -484,7 +552,7 @@ size_t fast1d_ws_bytes(const gwr::Grid& X, const gwr::Grid& Y) {
   gwr::Arena a{nullptr, 0, 0};
   a.take<double>(L.rowmom);
   a.take<double>(L.colmom);
-  a.take<double>(L.augmom);
+  a.take<double>(L.acarry);
   a.take<double>(X.n());
   a.take<double>(Y.n());
   return a.used;
@@ -496,7 +564,7 @@ gw_status fast1d(const gwr::Grid& X, const gwr::Grid& Y, const double* p, const 
   Layout L = make_layout(X.n(), Y.n(), X.k1d(), Y.k1d());
   double* rm = ws.take<double>(L.rowmom);
   double* cm = ws.take<double>(L.colmom);
-  double* am = ws.take<double>(L.augmom);
+  double* am = ws.take<double>(L.acarry);
   double* c1 = ws.take<double>(X.n());
   double* c2 = ws.take<double>(Y.n());
   gw_status st;

@@ -137,22 +137,28 @@ __global__ __launch_bounds__(NTH) void k_sk_row(const double* __restrict__ C, in
   }
   const int i0 = blockIdx.x * RB, i1 = min(M, i0 + RB);
   double cur[R][EPT], nxt[R][EPT];
+  // Loads are unconditional (row and column indices clamped into range) so the
+  // compiler can keep the next rows in flight across the reductions.
   auto load = [&](double (&dst)[R][EPT], int ib) {
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      const int i = ib + r;
-      const double* row = C + (int64_t)min(i, i1 - 1) * ldC;
+      const int i = min(ib + r, i1 - 1);
+      const double* row = C + (int64_t)i * ldC;
 #pragma unroll
-      for (int e = 0; e < EPT; ++e) {
-        const int col = t + NTH * e;
-        dst[r][e] = (col < N) ? row[col] : 0.0;
-      }
+      for (int e = 0; e < EPT; ++e) dst[r][e] = row[min(t + NTH * e, N - 1)];
     }
   };
   constexpr bool PREFETCH = EPT <= 4;
   if (i0 < i1) load(cur, i0);
   for (int ib = i0; ib < i1; ib += R) {
-    if (PREFETCH && ib + R < i1) load(nxt, ib + R);
+    if (PREFETCH) load(nxt, ib + R);
+    double pv[R], lpv[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int i = min(ib + r, i1 - 1);
+      pv[r] = p[i];
+      lpv[r] = logp[i];
+    }
     double z[R][EPT];
     double mloc[R];
 #pragma unroll
@@ -165,7 +171,7 @@ __global__ __launch_bounds__(NTH) void k_sk_row(const double* __restrict__ C, in
         mloc[r] = fmax(mloc[r], z[r][e]);
       }
       mloc[r] = gwk::wave_max(mloc[r]);
-      if (lane == 0) red[0][r][wv] = mloc[r];
+      if (lane == 63) red[0][r][wv] = mloc[r];
     }
     __syncthreads();
     double m[R];
@@ -187,7 +193,7 @@ __global__ __launch_bounds__(NTH) void k_sk_row(const double* __restrict__ C, in
         sl[r] += ldexp(E[r][e], nE[r][e]);
       }
       sl[r] = gwk::wave_sum(sl[r]);
-      if (lane == 0) red[1][r][wv] = sl[r];
+      if (lane == 63) red[1][r][wv] = sl[r];
     }
     __syncthreads();
 #pragma unroll
@@ -197,12 +203,12 @@ __global__ __launch_bounds__(NTH) void k_sk_row(const double* __restrict__ C, in
       double s = red[1][r][0];
 #pragma unroll
       for (int w = 1; w < NW; ++w) s += red[1][r][w];
-      const double pi = p[i];
+      const double pi = pv[r];
       if (!(pi > 0.0)) {
         if (t == 0) f[i] = -INFINITY;
         continue;
       }
-      const double fi = eps * ((logp[i] - m[r]) - log(s));
+      const double fi = eps * ((lpv[r] - m[r]) - log(s));
       if (t == 0) {
         f[i] = fi;
         if (!isfinite(fi)) status->nonfinite = 1;
