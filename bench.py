@@ -84,6 +84,53 @@ def cpu_baseline(k=2):
     }
 
 
+def profile_target(target: str, reps: int):
+    """Run one kernel family a few times on the bench workload's shapes so a
+    profiler can attribute counters to it; prints a short JSON line."""
+    import numpy as np
+    import torch
+    from paper_2404_08970_amd import gw
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    rng = np.random.default_rng([2, 7])
+    if target == "copy":
+        n = 1 << 28
+        a = torch.ones(n, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(reps):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"target": "copy", "bytes_read_per_launch": n * 8,
+                          "bytes_written_per_launch": n * 8, "launches": reps}))
+        return
+    if target == "sinkhorn":
+        p, q = marginals(N, 2)
+        X = gw.unit_grid((N,), 2)
+        pd = torch.tensor(p, device=dev)
+        qd = torch.tensor(q, device=dev)
+        T = torch.outer(pd, qd)
+        C = gw.grad(X, X, pd, qd, T)
+        f, g = gw.sinkhorn(C, pd, qd, EPS, reps, c_scale=2.0)
+        torch.cuda.synchronize()
+        print(json.dumps({"target": "sinkhorn", "n": N, "iterations": reps,
+                          "row_pass_bytes_per_launch": 8 * N * N}))
+        return
+    if target in ("fast", "dense"):
+        for n in ((N, 16384) if target == "fast" else (N,)):
+            X = gw.unit_grid((n,), 2)
+            pd = torch.tensor(rng.dirichlet(np.ones(n)), device=dev)
+            T = torch.outer(pd, pd)
+            G = torch.empty_like(T)
+            for _ in range(reps):
+                gw.grad(X, X, pd, pd, T, path=target, out=G)
+            torch.cuda.synchronize()
+            del T, G
+        print(json.dumps({"target": target, "n": [N, 16384] if target == "fast" else [N],
+                          "k": 2, "launches_per_n": reps}))
+        return
+    raise SystemExit(f"unknown profile target {target}")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -91,7 +138,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-big", action="store_true", help="skip the n=16384 FAST/dense ratio")
+    ap.add_argument("--profile-target", choices=["sinkhorn", "fast", "dense", "copy"],
+                    help="run only one kernel family (for rocprofv3) and exit")
+    ap.add_argument("--reps", type=int, default=5)
     args = ap.parse_args()
+    if args.profile_target:
+        profile_target(args.profile_target, args.reps)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU "
               "sharding of this path is a design note, not a runnable configuration.",

@@ -73,6 +73,89 @@ __global__ __launch_bounds__(1024) void k_const_term(int metric, int k, int H, i
   }
 }
 
+// 1D grids: c = hk^2 [|i-j|^{2k}] w by the recursion with exponent K2 = 2k on a
+// single vector (one block).  Thread t owns entries [16 t, 16 t + 16); segment
+// summaries are combined by an inclusive Hillis-Steele scan in LDS (shift by
+// the window span, all weights non-negative), then each thread sweeps its
+// segment with the carries.  n <= 16384.
+constexpr int C1_THREADS = 1024, C1_SEG = 16;
+
+template <int K2>
+__global__ __launch_bounds__(C1_THREADS) void k_const_1d(int n, double hk2,
+                                                          const double* __restrict__ w,
+                                                          double* __restrict__ c) {
+  __shared__ double buf[C1_THREADS][K2 + 1];
+  const int t = threadIdx.x;
+  double x[C1_SEG];
+#pragma unroll
+  for (int e = 0; e < C1_SEG; ++e) {
+    const int i = t * C1_SEG + e;
+    x[e] = i < n ? w[i] : 0.0;
+  }
+  double pre[K2 + 1], suf[K2 + 1];
+#pragma unroll
+  for (int r = 0; r <= K2; ++r) pre[r] = suf[r] = 0.0;
+#pragma unroll
+  for (int e = 0; e < C1_SEG; ++e) {
+    double wp = 1.0, ws = 1.0;
+#pragma unroll
+    for (int r = 0; r <= K2; ++r) {
+      pre[r] = fma(wp, x[e], pre[r]);
+      suf[r] = fma(ws, x[e], suf[r]);
+      wp *= (double)(C1_SEG - e);
+      ws *= (double)(e + 1);
+    }
+  }
+  // inclusive scans: prefix from the left, then suffix from the right
+  double a[K2 + 1], b[K2 + 1];
+  for (int dir = 0; dir < 2; ++dir) {
+    double v[K2 + 1];
+#pragma unroll
+    for (int r = 0; r <= K2; ++r) v[r] = dir == 0 ? pre[r] : suf[r];
+    const int me = dir == 0 ? t : C1_THREADS - 1 - t;  // position along the scan
+    for (int d = 1; d < C1_THREADS; d <<= 1) {
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r <= K2; ++r) buf[me][r] = v[r];
+      __syncthreads();
+      if (me >= d) {
+        double o[K2 + 1];
+#pragma unroll
+        for (int r = 0; r <= K2; ++r) o[r] = buf[me - d][r];
+        gwk::pascal_shift<K2>(o, (double)(C1_SEG * d));
+#pragma unroll
+        for (int r = 0; r <= K2; ++r) v[r] += o[r];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r <= K2; ++r) buf[me][r] = v[r];
+    __syncthreads();
+    // exclusive: the inclusive value of the previous segment along the scan
+#pragma unroll
+    for (int r = 0; r <= K2; ++r) {
+      const double e = me > 0 ? buf[me - 1][r] : 0.0;
+      if (dir == 0) a[r] = e; else b[r] = e;
+    }
+  }
+  double out[C1_SEG];
+#pragma unroll
+  for (int e = 0; e < C1_SEG; ++e) {
+    out[e] = a[K2];
+    gwk::pascal_step<K2>(a, x[e]);
+  }
+#pragma unroll
+  for (int e = C1_SEG - 1; e >= 0; --e) {
+    out[e] += b[K2];
+    gwk::pascal_step<K2>(b, x[e]);
+  }
+#pragma unroll
+  for (int e = 0; e < C1_SEG; ++e) {
+    const int i = t * C1_SEG + e;
+    if (i < n) c[i] = hk2 * out[e];
+  }
+}
+
 // ---------------------------------------------------------------- transpose
 // out[j][i] = in[i][j] (rows x cols input); with epilogue when c1 != null:
 // out[j][i] = (c1[j] + c2[i]) - s2 * in[i][j].
@@ -317,6 +400,18 @@ namespace gwl {
 gw_status const_term(const gwr::Grid& g, const double* w, double* c, hipStream_t s) {
   gwr::ProfScope ps(gwr::kFamOther, s);
   const int64_t n = g.n();
+  if (g.ndim == 1 && n <= (int64_t)C1_THREADS * C1_SEG) {
+    const double hk = g.hk();
+    const double hk2 = hk * hk;
+    switch (g.k1d()) {
+      case 1: k_const_1d<2><<<1, C1_THREADS, 0, s>>>((int)n, hk2, w, c); break;
+      case 2: k_const_1d<4><<<1, C1_THREADS, 0, s>>>((int)n, hk2, w, c); break;
+      case 3: k_const_1d<6><<<1, C1_THREADS, 0, s>>>((int)n, hk2, w, c); break;
+      case 4: k_const_1d<8><<<1, C1_THREADS, 0, s>>>((int)n, hk2, w, c); break;
+      default: return GW_EUNSUPPORTED;
+    }
+    return gwr::last_launch_status();
+  }
   k_const_term<<<(unsigned)((n + 63) / 64), 1024, 0, s>>>(g.metric, g.k, (int)g.H, (int)g.W, g.hk(), w, c);
   return gwr::last_launch_status();
 }

@@ -118,9 +118,10 @@ __global__ __launch_bounds__(NTH) void k_sk_row(const double* __restrict__ C, in
                                                  const double* __restrict__ logp,
                                                  const double* __restrict__ g,
                                                  double* __restrict__ f,
+                                                 double* __restrict__ ms,
                                                  double* __restrict__ partS,
                                                  int* __restrict__ partX,
-                                                 gwr::StatusWord* status) {
+                                                 gwr::StatusWord* status, int write_f) {
   constexpr int NW = NTH / 64;
   __shared__ double red[2][R][NW];
   const int t = threadIdx.x, wv = t >> 6, lane = t & 63;
@@ -136,22 +137,26 @@ __global__ __launch_bounds__(NTH) void k_sk_row(const double* __restrict__ C, in
     gie[e] = col < N ? g[col] * inv_eps : -INFINITY;
   }
   const int i0 = blockIdx.x * RB, i1 = min(M, i0 + RB);
-  double cur[R][EPT], nxt[R][EPT];
+  double cur[R][EPT];
   // Loads are unconditional (row and column indices clamped into range) so the
   // compiler can keep the next rows in flight across the reductions.
+  int colc[EPT];  // column of each entry, clamped into range
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) colc[e] = min(t + NTH * e, N - 1);
   auto load = [&](double (&dst)[R][EPT], int ib) {
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int i = min(ib + r, i1 - 1);
       const double* row = C + (int64_t)i * ldC;
 #pragma unroll
-      for (int e = 0; e < EPT; ++e) dst[r][e] = row[min(t + NTH * e, N - 1)];
+      for (int e = 0; e < EPT; ++e) dst[r][e] = row[colc[e]];
     }
   };
-  constexpr bool PREFETCH = EPT <= 4;
+  // The next R rows are loaded into `cur` as soon as the current rows have
+  // been turned into exponents, so the loads overlap the reductions, the
+  // exponentials and the column updates.
   if (i0 < i1) load(cur, i0);
   for (int ib = i0; ib < i1; ib += R) {
-    if (PREFETCH) load(nxt, ib + R);
     double pv[R], lpv[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -167,9 +172,12 @@ __global__ __launch_bounds__(NTH) void k_sk_row(const double* __restrict__ C, in
 #pragma unroll
       for (int e = 0; e < EPT; ++e) {
         z[r][e] = fma(-csie, cur[r][e], gie[e]);
-        if (t + NTH * e >= N) z[r][e] = -INFINITY;
         mloc[r] = fmax(mloc[r], z[r][e]);
       }
+    }
+    load(cur, ib + R);  // clamped: past the band it re-reads the last row
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
       mloc[r] = gwk::wave_max(mloc[r]);
       if (lane == 63) red[0][r][wv] = mloc[r];
     }
@@ -181,7 +189,6 @@ __global__ __launch_bounds__(NTH) void k_sk_row(const double* __restrict__ C, in
 #pragma unroll
       for (int w = 1; w < NW; ++w) m[r] = fmax(m[r], red[0][r][w]);
     }
-    double E[R][EPT];
     int nE[R][EPT];
     double sl[R];
 #pragma unroll
@@ -189,9 +196,12 @@ __global__ __launch_bounds__(NTH) void k_sk_row(const double* __restrict__ C, in
       sl[r] = 0.0;
 #pragma unroll
       for (int e = 0; e < EPT; ++e) {
-        E[r][e] = exp_split(z[r][e] - m[r], &nE[r][e]);
-        sl[r] += ldexp(E[r][e], nE[r][e]);
+        z[r][e] = exp_split(z[r][e] - m[r], &nE[r][e]);
+        sl[r] += ldexp(z[r][e], nE[r][e]);
       }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
       sl[r] = gwk::wave_sum(sl[r]);
       if (lane == 63) red[1][r][wv] = sl[r];
     }
@@ -208,35 +218,162 @@ __global__ __launch_bounds__(NTH) void k_sk_row(const double* __restrict__ C, in
         if (t == 0) f[i] = -INFINITY;
         continue;
       }
-      const double fi = eps * ((lpv[r] - m[r]) - log(s));
-      if (t == 0) {
-        f[i] = fi;
-        if (!isfinite(fi)) status->nonfinite = 1;
+      // f_i is an output only (the next iteration rebuilds it from g): the last
+      // iteration leaves (m_i, s_i) for k_sk_f
+      if (write_f && t == 0) {
+        ms[2 * i] = m[r];
+        ms[2 * i + 1] = s;
       }
       int ew;
       const double mw = frexp(pi / s, &ew);
 #pragma unroll
       for (int e = 0; e < EPT; ++e) {
-        const double tv = E[r][e] * mw;
+        const double tv = z[r][e] * mw;
         const int te = nE[r][e] + ew;
         const int ne = max(Xe[e], te);
         S[e] = ldexp(S[e], Xe[e] - ne) + ldexp(tv, te - ne);
         Xe[e] = ne;
       }
     }
-    if (PREFETCH) {
-#pragma unroll
-      for (int r = 0; r < R; ++r)
-#pragma unroll
-        for (int e = 0; e < EPT; ++e) cur[r][e] = nxt[r][e];
-    } else if (ib + R < i1) {
-      load(cur, ib + R);
-    }
   }
 #pragma unroll
   for (int e = 0; e < EPT; ++e) {
     const int col = t + NTH * e;
     if (col < N) {
+      partS[(int64_t)blockIdx.x * N + col] = S[e];
+      partX[(int64_t)blockIdx.x * N + col] = Xe[e];
+    }
+  }
+}
+
+// Grouped row pass for rows of up to 8 x 512 entries: a block of 1024 threads
+// is split into NG groups of GT = 1024/NG threads and each group reduces its
+// own rows, so a lane owns EPT = N/GT entries of a row and the per-row work
+// (two reductions, the weight p_i/s_i) is spread over more entries.  g/eps
+// lives in LDS.  The NG groups' column pairs are merged through LDS in group
+// order and written as the block's partial.
+template <int EPT, int NG, bool PF>
+__global__ __launch_bounds__(1024) void k_sk_rowg(const double* __restrict__ C, int64_t ldC,
+                                                   int M, int N, int RB, double cs,
+                                                   double inv_eps, double eps,
+                                                   const double* __restrict__ p,
+                                                   const double* __restrict__ logp,
+                                                   const double* __restrict__ g,
+                                                   double* __restrict__ f,
+                                                   double* __restrict__ ms,
+                                                   double* __restrict__ partS,
+                                                   int* __restrict__ partX,
+                                                   gwr::StatusWord* status, int write_f) {
+  constexpr int GT = 1024 / NG, GW = GT / 64;
+  __shared__ double gie[EPT * GT];
+  __shared__ double red[2][NG][GW];
+  __shared__ double mS[NG > 1 ? NG - 1 : 1][GT];
+  __shared__ int mX[NG > 1 ? NG - 1 : 1][GT];
+  const int t = threadIdx.x, gi = t / GT, tl = t - gi * GT, wv = tl >> 6, lane = t & 63;
+  const double csie = cs * inv_eps;
+  for (int c = t; c < EPT * GT; c += 1024) gie[c] = c < N ? g[c] * inv_eps : -INFINITY;
+  double S[EPT];
+  int Xe[EPT];
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    S[e] = 0.0;
+    Xe[e] = EXP_SENTINEL;
+  }
+  const int i0 = blockIdx.x * RB, i1 = min(M, i0 + RB);
+  const int nr = (RB + NG - 1) / NG;  // row steps, the same for every group
+  int colc[EPT];                      // column of each entry, clamped into range
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) colc[e] = min(tl + GT * e, N - 1);
+  double x[EPT], nx[EPT];
+  auto load = [&](double (&dst)[EPT], int j) {
+    const int i = min(i0 + j * NG + gi, i1 - 1);
+    const double* row = C + (int64_t)i * ldC;
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) dst[e] = row[colc[e]];
+  };
+  __syncthreads();
+  load(x, 0);
+  for (int j = 0; j < nr; ++j) {
+    if (PF) load(nx, j + 1);
+    const int i = i0 + j * NG + gi;
+    const bool valid = i < i1;
+    const double pi = p[min(i, i1 - 1)];
+    double mloc = -INFINITY;
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      x[e] = fma(-csie, x[e], gie[tl + GT * e]);
+      mloc = fmax(mloc, x[e]);
+    }
+    mloc = gwk::wave_max(mloc);
+    if (lane == 63) red[0][gi][wv] = mloc;
+    __syncthreads();
+    double m = red[0][gi][0];
+#pragma unroll
+    for (int w = 1; w < GW; ++w) m = fmax(m, red[0][gi][w]);
+    int nE[EPT];
+    double sl = 0.0;
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      x[e] = exp_split(x[e] - m, &nE[e]);
+      sl += ldexp(x[e], nE[e]);
+    }
+    sl = gwk::wave_sum(sl);
+    if (lane == 63) red[1][gi][wv] = sl;
+    __syncthreads();
+    double s = red[1][gi][0];
+#pragma unroll
+    for (int w = 1; w < GW; ++w) s += red[1][gi][w];
+    if (valid) {
+      if (pi > 0.0) {
+        // f_i is an output only (the next iteration rebuilds it from g): the
+        // last iteration leaves (m_i, s_i) for k_sk_f
+        if (write_f && tl == 0) {
+          ms[2 * i] = m;
+          ms[2 * i + 1] = s;
+        }
+        int ew;
+        const double mw = frexp(pi / s, &ew);
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+          const double tv = x[e] * mw;
+          const int te = nE[e] + ew;
+          const int ne = max(Xe[e], te);
+          S[e] = ldexp(S[e], Xe[e] - ne) + ldexp(tv, te - ne);
+          Xe[e] = ne;
+        }
+      } else if (tl == 0) {
+        f[i] = -INFINITY;
+      }
+    }
+    if (PF) {
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) x[e] = nx[e];
+    } else {
+      load(x, j + 1);
+    }
+  }
+  // merge the groups' column pairs into group 0, one entry slot at a time
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    if (NG > 1) {
+      __syncthreads();
+      if (gi > 0) {
+        mS[gi - 1][tl] = S[e];
+        mX[gi - 1][tl] = Xe[e];
+      }
+      __syncthreads();
+      if (gi == 0) {
+#pragma unroll
+        for (int k = 0; k < NG - 1; ++k) {
+          const int xb = mX[k][tl];
+          const int ne = max(Xe[e], xb);
+          S[e] = ldexp(S[e], Xe[e] - ne) + ldexp(mS[k][tl], xb - ne);
+          Xe[e] = ne;
+        }
+      }
+    }
+    const int col = tl + GT * e;
+    if (gi == 0 && col < N) {
       partS[(int64_t)blockIdx.x * N + col] = S[e];
       partX[(int64_t)blockIdx.x * N + col] = Xe[e];
     }
@@ -290,6 +427,20 @@ __global__ __launch_bounds__(256) void k_sk_col(int N, int nb, const double* __r
   const double gn = g[col] + eps * (logq[col] - lnS);
   g[col] = gn;
   if (!isfinite(gn)) status->nonfinite = 1;
+}
+
+// f_i = eps (ln p_i - m_i - ln s_i) from the last row pass's row maximum and
+// shifted sum; zero-mass rows were already set to -inf by the row pass.
+__global__ __launch_bounds__(256) void k_sk_f(int M, const double* __restrict__ p,
+                                               const double* __restrict__ logp,
+                                               const double* __restrict__ ms, double eps,
+                                               double* __restrict__ f,
+                                               gwr::StatusWord* status) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= M || !(p[i] > 0.0)) return;
+  const double fi = eps * ((logp[i] - ms[2 * i]) - log(ms[2 * i + 1]));
+  f[i] = fi;
+  if (!isfinite(fi)) status->nonfinite = 1;
 }
 
 __global__ __launch_bounds__(256) void k_plan(const double* __restrict__ C, int64_t ldC, int M,
@@ -392,9 +543,10 @@ int sk_rows_per_block(int64_t M) {
 template <int NTH, int EPT>
 void launch_row(int nb, hipStream_t s, const double* C, int64_t ldC, int M, int N, int RB,
                 double cs, double inv_eps, double eps, const double* p, const double* logp,
-                const double* g, double* f, double* pS, int* pX, gwr::StatusWord* st) {
-  constexpr int R = EPT <= 4 ? 2 : 1;
-  k_sk_row<NTH, EPT, R><<<nb, NTH, 0, s>>>(C, ldC, M, N, RB, cs, inv_eps, eps, p, logp, g, f, pS, pX, st);
+                const double* g, double* f, double* ms, double* pS, int* pX,
+                gwr::StatusWord* st, int last) {
+  constexpr int R = EPT > 4 ? 1 : (NTH >= 1024 ? 2 : 4);
+  k_sk_row<NTH, EPT, R><<<nb, NTH, 0, s>>>(C, ldC, M, N, RB, cs, inv_eps, eps, p, logp, g, f, ms, pS, pX, st, last);
 }
 
 }  // namespace
@@ -409,6 +561,7 @@ size_t sinkhorn_ws_bytes(int64_t M, int64_t N) {
   a.take<double>(N);
   a.take<double>((size_t)nb * N);
   a.take<int>((size_t)nb * N);
+  a.take<double>(2 * (size_t)M);
   return a.used;
 }
 
@@ -423,6 +576,7 @@ gw_status sinkhorn(const double* C, int64_t ldC, int64_t M, int64_t N, double c_
   double* logq = ws.take<double>(N);
   double* pS = ws.take<double>((size_t)nb * N);
   int* pX = ws.take<int>((size_t)nb * N);
+  double* ms = ws.take<double>(2 * (size_t)M);
   const double inv_eps = 1.0 / eps;
   {
     gwr::ProfScope ps(gwr::kFamOther, s);
@@ -433,18 +587,22 @@ gw_status sinkhorn(const double* C, int64_t ldC, int64_t M, int64_t N, double c_
   for (int it = 0; it < iters; ++it) {
     {
       gwr::ProfScope ps(gwr::kFamSinkRow, s);
-      if (N <= 256) launch_row<256, 1>(nb, s, C, ldC, Mi, Ni, rb, c_scale, inv_eps, eps, p, logp, g, f, pS, pX, status);
-      else if (N <= 512) launch_row<512, 1>(nb, s, C, ldC, Mi, Ni, rb, c_scale, inv_eps, eps, p, logp, g, f, pS, pX, status);
-      else if (N <= 1024) launch_row<1024, 1>(nb, s, C, ldC, Mi, Ni, rb, c_scale, inv_eps, eps, p, logp, g, f, pS, pX, status);
-      else if (N <= 2048) launch_row<1024, 2>(nb, s, C, ldC, Mi, Ni, rb, c_scale, inv_eps, eps, p, logp, g, f, pS, pX, status);
-      else if (N <= 4096) launch_row<1024, 4>(nb, s, C, ldC, Mi, Ni, rb, c_scale, inv_eps, eps, p, logp, g, f, pS, pX, status);
-      else if (N <= 8192) launch_row<512, 16>(nb, s, C, ldC, Mi, Ni, rb, c_scale, inv_eps, eps, p, logp, g, f, pS, pX, status);
-      else launch_row<1024, 16>(nb, s, C, ldC, Mi, Ni, rb, c_scale, inv_eps, eps, p, logp, g, f, pS, pX, status);
+      if (N <= 256) launch_row<256, 1>(nb, s, C, ldC, Mi, Ni, rb, c_scale, inv_eps, eps, p, logp, g, f, ms, pS, pX, status, it == iters - 1);
+      else if (N <= 512) launch_row<512, 1>(nb, s, C, ldC, Mi, Ni, rb, c_scale, inv_eps, eps, p, logp, g, f, ms, pS, pX, status, it == iters - 1);
+      else if (N <= 1024) launch_row<1024, 1>(nb, s, C, ldC, Mi, Ni, rb, c_scale, inv_eps, eps, p, logp, g, f, ms, pS, pX, status, it == iters - 1);
+      else if (N <= 2048) launch_row<1024, 2>(nb, s, C, ldC, Mi, Ni, rb, c_scale, inv_eps, eps, p, logp, g, f, ms, pS, pX, status, it == iters - 1);
+      else if (N <= 4096) k_sk_rowg<8, 2, true><<<nb, 1024, 0, s>>>(C, ldC, Mi, Ni, rb, c_scale, inv_eps, eps, p, logp, g, f, ms, pS, pX, status, it == iters - 1);
+      else if (N <= 8192) launch_row<512, 16>(nb, s, C, ldC, Mi, Ni, rb, c_scale, inv_eps, eps, p, logp, g, f, ms, pS, pX, status, it == iters - 1);
+      else launch_row<1024, 16>(nb, s, C, ldC, Mi, Ni, rb, c_scale, inv_eps, eps, p, logp, g, f, ms, pS, pX, status, it == iters - 1);
     }
     {
       gwr::ProfScope ps(gwr::kFamSinkCol, s);
       k_sk_col<<<(unsigned)((N + MERGE_COLS - 1) / MERGE_COLS), 256, 0, s>>>(Ni, nb, pS, pX, q, logq, eps, g, status);
     }
+  }
+  if (iters > 0) {
+    gwr::ProfScope ps(gwr::kFamOther, s);
+    k_sk_f<<<(unsigned)((M + 255) / 256), 256, 0, s>>>(Mi, p, logp, ms, eps, f, status);
   }
   if (T) return plan(C, ldC, M, N, c_scale, f, g, eps, T, ldT, s);
   return gwr::last_launch_status();
