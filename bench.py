@@ -205,7 +205,7 @@ def main():
     achieved = row_bytes / (row_avg_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "k_sk_row (Sinkhorn row pass)", "avg_us": round(row_avg_ms * 1e3, 2),
+                "kernel": "k_sk_rowg (Sinkhorn row pass)", "avg_us": round(row_avg_ms * 1e3, 2),
                 "launches": row_n, "algorithmic_bytes_per_launch": int(row_bytes)}
     tf = os.path.join(ROOT, "profiles", "traffic_sinkhorn_row_n4096.json")
     if os.path.exists(tf):
