@@ -131,6 +131,52 @@ def profile_target(target: str, reps: int):
     raise SystemExit(f"unknown profile target {target}")
 
 
+def precision_study(n: int = 16384, k: int = 2, rows: int = 6):
+    """Dense gradient in FP64, FP32, BF16 and split refinements at n = 16384, k = 2,
+    Dirichlet(1) marginals, on two plans: p q^T and the plan after one FAST
+    FP64 outer iteration (eps = 1e-3, 100 Sinkhorn iterations).  Errors are
+    measured against the FP64 oracle on sampled rows (each computed from the
+    plain definition), relative to max |2 D_X T D_Y| of those rows."""
+    import numpy as np
+    import torch
+    from oracle import gw_oracle as O
+    from paper_2404_08970_amd import gw, inputs
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    X = gw.unit_grid((n,), k)
+    rp, rq = inputs.rng_for(4, 0), inputs.rng_for(4, 1)
+    p = inputs.dirichlet(n, rp)
+    q = inputs.dirichlet(n, rq)
+    pd, qd = torch.tensor(p, device=dev), torch.tensor(q, device=dev)
+    plans = {"pq": torch.outer(pd, qd)}
+    T1, _, _, _ = gw.solve(X, X, pd, qd, 1e-3, 1, 100, path="fast", objective=False)
+    plans["one_outer_step"] = T1
+    paths = ["fast", "dense_f64", "dense_f32", "dense_bf16", "dense_f32_split", "dense_bf16_split"]
+    ws = gw.workspace(max(gw.workspace_bytes(X, X, gw.PATHS[pth], gw.OP_GRAD) for pth in paths), dev, key="prec")
+    G = torch.empty((n, n), dtype=torch.float64, device=dev)
+    og = O.Grid((n,), X.h, k)
+    D = O.cost_matrix(og)
+    c1, c2 = O.const_terms(D, D, p, q)
+    sample = np.linspace(0, n - 1, rows).astype(int)
+    out = {"n": n, "k": k, "rows_sampled": sample.tolist(), "plans": {}}
+    for name, T in plans.items():
+        Tc = T.cpu().numpy()
+        ref_rows = {}
+        for i in sample:
+            u = D[i] @ Tc
+            ref_rows[int(i)] = c1[i] + c2 - 2.0 * (u @ D)
+        scale = max(np.max(np.abs(c1[i] + c2 - ref_rows[int(i)])) for i in sample)
+        res = {}
+        for pth in paths:
+            ms = time_gpu(lambda: gw.grad(X, X, pd, qd, T, path=pth, out=G, ws=ws), 1, torch)
+            Gs = G[torch.tensor(sample, device=dev)].cpu().numpy()
+            err = max(float(np.max(np.abs(Gs[r] - ref_rows[int(i)]))) for r, i in enumerate(sample))
+            res[pth] = {"ms": round(ms, 3), "err_bilinear": err / scale}
+        out["plans"][name] = res
+        del Tc
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -141,7 +187,12 @@ def main():
     ap.add_argument("--profile-target", choices=["sinkhorn", "fast", "dense", "copy"],
                     help="run only one kernel family (for rocprofv3) and exit")
     ap.add_argument("--reps", type=int, default=5)
+    ap.add_argument("--precision", action="store_true",
+                    help="run the precision study (dense FP64/FP32/BF16/split vs FAST, n=16384) and exit")
     args = ap.parse_args()
+    if args.precision:
+        print(json.dumps(precision_study()))
+        return
     if args.profile_target:
         profile_target(args.profile_target, args.reps)
         return

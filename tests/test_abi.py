@@ -53,8 +53,12 @@ def test_workspace_bytes_arithmetic():
     dense = gw.workspace_bytes(X, Y, gw.PATH_DENSE_F64, gw.OP_GRAD)
     solve = gw.workspace_bytes(X, Y, gw.PATH_FAST_F64, gw.OP_SOLVE)
     MN8 = 4096 * 4096 * 8
-    # FAST keeps only O(MN k / 64) of carries; dense needs the intermediate product
-    assert 0 < fast < MN8 // 4
+    # FAST keeps only O(MN k / 64) of carries: row moments, column moments and the
+    # D~_Y-applied column carries, each 2 (k + 1) values per line per 64-wide tile,
+    # plus c1 and c2; dense needs the full intermediate product
+    carries = 3 * 2 * (2 + 1) * (4096 // 64) * 4096 * 8
+    assert carries <= fast <= carries + 2 * 4096 * 8 + 4 * 256
+    assert fast < MN8 // 2
     assert dense >= MN8
     assert solve >= MN8            # the gradient buffer of the solve
     assert fast % 256 == 0 and solve % 256 == 0

@@ -260,3 +260,46 @@ def test_invalid_call_raises():
         gw.grad(X, X, p, p, T, out=T)          # output overlaps input
     with pytest.raises(gw.GWError):
         gw.sinkhorn(T, p, p, -1.0, 3)
+
+
+# ------------------------------------------------------------ precision study
+
+LP_PATHS = {
+    # path: (unit roundoff of the operands, FP32-accumulated chunk length or None = whole K)
+    "dense_f32": (2.0 ** -24, None),
+    "dense_bf16": (2.0 ** -8, None),
+    "dense_f32_split": (2.0 ** -48, 4),
+    "dense_bf16_split": (2.0 ** -16, 256),
+}
+
+
+def lp_bound(path, K):
+    """A-priori relative bound on the bilinear part for non-negative operands:
+    4 operand roundings (T, D_Y, A, D_X) plus FP32 accumulation over the
+    accumulated chunk in each of the two products (gamma_K = K u / (1 - K u))."""
+    u_in, chunk = LP_PATHS[path]
+    u32 = 2.0 ** -24
+    kk = K if chunk is None else min(chunk, K)
+    gamma = kk * u32 / (1 - kk * u32)
+    return 4 * u_in + 2 * gamma + 1e-12
+
+
+@pytest.mark.parametrize("n,k", [(200, 1), (1000, 2), (777, 3)])
+def test_dense_low_precision_within_bound(n, k):
+    gw, torch = _gw()
+    rng = inputs.rng_for(210, n, k)
+    X = gw.unit_grid((n,), k)
+    T = inputs.peaked_plan(n, n, rng)
+    p, q = inputs.dirichlet(n, rng), inputs.dirichlet(n, rng)
+    G0 = O.grad_dense(ogrid(X), ogrid(X), p, q, T)
+    c1, c2 = O.const_terms(O.cost_matrix(ogrid(X)), O.cost_matrix(ogrid(X)), p, q)
+    bil = c1[:, None] + c2[None, :] - G0           # = 2 D_X T D_Y
+    errs = {}
+    for path in LP_PATHS:
+        G = _grad(gw, torch, X, X, p, q, T, path)
+        e = float(np.max(np.abs(G - G0)) / np.max(np.abs(bil)))
+        errs[path] = e
+        print(f"{path} n={n} k={k} err_bilinear={e:.3e} bound={lp_bound(path, n):.3e}", flush=True)
+        assert e <= lp_bound(path, n)
+    assert errs["dense_f32_split"] < errs["dense_f32"]
+    assert errs["dense_bf16_split"] < errs["dense_bf16"]
