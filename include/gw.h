@@ -43,6 +43,7 @@ typedef int32_t gw_status;
 #define GW_EDEVICE (-3)       /* a HIP runtime call failed */
 #define GW_ENUMERIC (-4)      /* device detected a non-finite value (gw_check_status) */
 #define GW_EUNSUPPORTED (-5)  /* valid request outside what this build implements */
+#define GW_EAGAIN (-6)        /* request loop: the result is not ready yet */
 
 /* Distance on a grid (Sec. 2 and Sec. 3.1).
  *   GW_METRIC_L1POW:    h^k * (|dr| + |dc|)^k; in 1D h^k * |i - j|^k.
@@ -137,6 +138,118 @@ gw_status gw_solve(const gw_grid* X, const gw_grid* Y, const double* p, const do
 gw_status gw_objective(const gw_grid* X, const gw_grid* Y, const double* T, int64_t ldT,
                        double eps, double* obj, void* ws, size_t ws_bytes, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Request loop: continuous batching of gw_solve problems of uneven sizes.
+ *
+ * Not an operation of the paper; a serving layer that runs the mirror-descent
+ * solve of Sec. 2.1 (exactly the arithmetic of gw_solve on GW_PATH_FAST_F64)
+ * for many requests at once.  Each request keeps its plan T, potentials f, g,
+ * gradient and Sinkhorn state resident in the server's arena from admission
+ * until it is released.  One host thread drives a server (not thread-safe).
+ *
+ * A step (gw_server_step) does, on the server's stream:
+ *   1. admission: queued requests, in submission order, while a slot is free
+ *      and the arena has a free range of the request's footprint
+ *      (gw_server_request_bytes); the first that does not fit stops admission;
+ *   2. for each request at the start of an outer iteration: its gradient and
+ *      Sinkhorn set-up (per-request launches);
+ *   3. one replay of a captured HIP graph that runs `iters_per_step` Sinkhorn
+ *      iterations of every request in its Sinkhorn phase: persistent batched
+ *      kernels read a device work table (per request: sizes, pointers and
+ *      how many of the step's iterations it takes) that the host rewrites
+ *      between replays, so request shapes are data, not launch shapes;
+ *   4. for each request whose Sinkhorn call ended: its potentials and plan;
+ *      after the last outer iteration the objective (if asked) and a
+ *      completion event.
+ * The host never runs more than two steps ahead of the device.  A request's
+ * results do not depend on the other requests in the batch: each band of
+ * each iteration runs the single-problem kernel's arithmetic, and no
+ * reduction crosses requests.
+ * ------------------------------------------------------------------------ */
+typedef struct gw_server gw_server; /* opaque */
+
+#define GW_REQ_OBJECTIVE 2 /* request flag: compute obj after the last outer iteration */
+
+/* Request states reported by gw_server_poll. */
+#define GW_REQ_QUEUED 0  /* submitted, not admitted */
+#define GW_REQ_RUNNING 1 /* admitted; device work not finished */
+#define GW_REQ_DONE 2    /* device work finished; gw_server_result is ready */
+
+/* One solve: the arguments of gw_solve on GW_PATH_FAST_F64.
+ *   p [M], q [N]: device FP64, owned by the caller, read until the request is
+ *   released.  flags: GW_FLAG_WARM_START | GW_REQ_OBJECTIVE.  Requires
+ *   N <= 16384, eps > 0, outer >= 0, inner >= 0; reserved must be 0. */
+typedef struct gw_request {
+  gw_grid X;
+  gw_grid Y;
+  const double* p;
+  const double* q;
+  double eps;
+  int32_t outer;
+  int32_t inner;
+  int32_t flags;
+  int32_t reserved;
+} gw_request;
+
+/* Result of a finished request.  T [M x N] (leading dimension N), f [M], g [N]
+ * are device pointers into the server's arena, valid until the request is
+ * released.  f and g are the last Sinkhorn call's potentials (unset if
+ * outer = 0).  obj: host copy of gw_solve's obj (NaN without
+ * GW_REQ_OBJECTIVE).  done_ms: device time of completion in ms after
+ * gw_server_create returned (HIP event clock).  status: GW_OK, or
+ * GW_ENUMERIC if a kernel of this request saw a non-finite value. */
+typedef struct gw_result {
+  const double* T;
+  const double* f;
+  const double* g;
+  int64_t M;
+  int64_t N;
+  double obj[2];
+  double done_ms;
+  gw_status status;
+  int32_t reserved;
+} gw_result;
+
+/* Arena bytes one request holds while admitted (T, gradient, potentials,
+ * Sinkhorn partials, gradient scratch); 0 for an invalid request. Host-only. */
+size_t gw_server_request_bytes(const gw_request* r);
+
+/* Arena bytes the server keeps for its device work table. Host-only. */
+size_t gw_server_table_bytes(int32_t max_slots);
+
+/* Create a server over `arena` (device memory of arena_bytes bytes, 256-byte
+ * aligned, owned by the caller and not touched by it until
+ * gw_server_destroy).  max_slots (1..4096) bounds the requests admitted at
+ * once; iters_per_step (1..1000) is the Sinkhorn iterations per step.  The
+ * server allocates pinned host staging buffers, HIP events and graphs, never
+ * device memory.  stream: the hipStream_t all work goes to. */
+gw_status gw_server_create(void* arena, size_t arena_bytes, int32_t max_slots,
+                           int32_t iters_per_step, void* stream, gw_server** out);
+
+/* Queue a request; *id receives its handle.  GW_ENOMEM if its footprint can
+ * never fit the arena.  Nothing is launched. */
+gw_status gw_server_submit(gw_server* sv, const gw_request* r, int64_t* id);
+
+/* One step (see above).  *active: requests admitted and not finished after
+ * the step; *queued: requests waiting for admission (either may be NULL). */
+gw_status gw_server_step(gw_server* sv, int32_t* active, int32_t* queued);
+
+/* *state = GW_REQ_*; GW_EINVAL for an unknown or released id. */
+gw_status gw_server_poll(gw_server* sv, int64_t id, int32_t* state);
+
+/* Fill *out for a finished request (waits for its completion event if its
+ * work is all enqueued); GW_EAGAIN if the request is queued or still has
+ * steps to go. */
+gw_status gw_server_result(gw_server* sv, int64_t id, gw_result* out);
+
+/* Give back a finished or queued request's arena range and handle.
+ * GW_EAGAIN if it is admitted and not finished. */
+gw_status gw_server_release(gw_server* sv, int64_t id);
+
+/* Wait for the stream and free the server's host resources (the arena stays
+ * the caller's). */
+gw_status gw_server_destroy(gw_server* sv);
+
 /* Human-readable name of a status code (static storage). */
 const char* gw_status_string(gw_status s);
 
@@ -149,7 +262,7 @@ gw_status gw_check_status(void* ws, void* stream);
  *   0 fast-gradient main tile kernel, 1 fast-gradient carry/moment kernels,
  *   2 dense gradient GEMMs, 3 Sinkhorn row pass, 4 Sinkhorn column merge,
  *   5 plan materialisation, 6 other (init, objective, constant terms),
- *   7 2D gradient kernels.
+ *   7 2D gradient kernels, 8 request-loop step graphs (batched Sinkhorn).
  * gw_profile_enable(mask) records the families whose bit (1 << family) is set
  * in `mask` (0 stops recording; every call clears the counts); gw_profile_read
  * waits for the recorded events and returns total milliseconds and launch

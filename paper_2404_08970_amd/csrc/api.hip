@@ -167,16 +167,6 @@ size_t grad_need(const Grid& X, const Grid& Y, int path) {
 
 bool path_valid(int path) { return path >= GW_PATH_FAST_F64 && path <= GW_PATH_DENSE_F32_SPLIT; }
 
-gw_status run_grad(const Grid& X, const Grid& Y, const double* p, const double* q,
-                   const double* T, int64_t ldT, double* G, int64_t ldG, int path, Arena& a,
-                   hipStream_t s, const double* c1, const double* c2) {
-  if (path == GW_PATH_FAST_F64) {
-    if (X.ndim == 1 && Y.ndim == 1) return gwl::fast1d(X, Y, p, q, T, ldT, G, ldG, a, s, c1, c2);
-    return gwl::fast_generic(X, Y, p, q, T, ldT, G, ldG, a, s, c1, c2);
-  }
-  return gwl::dense(X, Y, p, q, T, ldT, G, ldG, path, a, s, c1, c2);
-}
-
 size_t solve_need(const Grid& X, const Grid& Y, int path) {
   const int64_t M = X.n(), N = Y.n();
   Arena a{nullptr, 0, 0};
@@ -192,6 +182,20 @@ size_t solve_need(const Grid& X, const Grid& Y, int path) {
   return a.used + tail;
 }
 
+}  // namespace
+
+namespace gwr {
+
+gw_status run_grad(const Grid& X, const Grid& Y, const double* p, const double* q,
+                   const double* T, int64_t ldT, double* G, int64_t ldG, int path, Arena& a,
+                   hipStream_t s, const double* c1, const double* c2) {
+  if (path == GW_PATH_FAST_F64) {
+    if (X.ndim == 1 && Y.ndim == 1) return gwl::fast1d(X, Y, p, q, T, ldT, G, ldG, a, s, c1, c2);
+    return gwl::fast_generic(X, Y, p, q, T, ldT, G, ldG, a, s, c1, c2);
+  }
+  return gwl::dense(X, Y, p, q, T, ldT, G, ldG, path, a, s, c1, c2);
+}
+
 gw_status run_objective(const Grid& X, const Grid& Y, const double* T, int64_t ldT, double eps,
                         double* obj, double* Gbuf, Arena& a, hipStream_t s,
                         gwr::StatusWord* status) {
@@ -205,7 +209,19 @@ gw_status run_objective(const Grid& X, const Grid& Y, const double* T, int64_t l
   return gwl::objective_reduce(Gbuf, N, T, ldT, M, N, eps, obj, a, s, status);
 }
 
-__global__ void k_clear_status(gwr::StatusWord* st) { st->nonfinite = 0; }
+__global__ void k_clear_status(StatusWord* st) { st->nonfinite = 0; }
+
+gw_status clear_status(StatusWord* st, hipStream_t s) {
+  ProfScope ps(kFamOther, s);
+  k_clear_status<<<1, 1, 0, s>>>(st);
+  return last_launch_status();
+}
+
+}  // namespace gwr
+
+namespace {
+using gwr::run_grad;
+using gwr::run_objective;
 
 }  // namespace
 
@@ -302,10 +318,7 @@ gw_status gw_solve(const gw_grid* Xp, const gw_grid* Yp, const double* p, const 
   if ((st = gwl::const_term(X, p, c1, s)) != GW_OK) return st;
   if ((st = gwl::const_term(Y, q, c2, s)) != GW_OK) return st;
   if ((st = gwl::outer_product(p, q, M, N, T, ldT, s)) != GW_OK) return st;
-  {
-    gwr::ProfScope ps(gwr::kFamOther, s);
-    k_clear_status<<<1, 1, 0, s>>>(status_of(ws));
-  }
+  if ((st = gwr::clear_status(status_of(ws), s)) != GW_OK) return st;
   for (int l = 0; l < outer; ++l) {
     a.used = mark;
     st = run_grad(X, Y, p, q, T, ldT, G, N, path, a, s, c1, c2);
@@ -361,7 +374,7 @@ gw_status gw_check_status(void* ws, void* stream) {
   gwr::StatusWord w{0};
   if (hipMemcpy(&w, ws, sizeof(w), hipMemcpyDeviceToHost) != hipSuccess) return GW_EDEVICE;
   if (w.nonfinite) {
-    k_clear_status<<<1, 1, 0, s>>>(status_of(ws));
+    if (gwr::clear_status(status_of(ws), s) != GW_OK) return GW_EDEVICE;
     if (hipStreamSynchronize(s) != hipSuccess) return GW_EDEVICE;
     return GW_ENUMERIC;
   }

@@ -63,7 +63,8 @@ enum Family {
   kFamPlan = 5,
   kFamOther = 6,
   kFam2D = 7,
-  kNumFamilies = 8
+  kFamServeStep = 8,
+  kNumFamilies = 9
 };
 void prof_begin(int family, hipStream_t s);
 void prof_end(int family, hipStream_t s);
@@ -83,6 +84,17 @@ inline gw_status last_launch_status() {
 struct StatusWord {
   int32_t nonfinite;
 };
+
+gw_status clear_status(StatusWord* st, hipStream_t s);
+
+// Gradient on `path` with optional precomputed constant terms, and the
+// objective of a plan (its own marginals, Gbuf [M x N] as scratch); both take
+// their scratch from `a`.
+gw_status run_grad(const Grid& X, const Grid& Y, const double* p, const double* q,
+                   const double* T, int64_t ldT, double* G, int64_t ldG, int path, Arena& a,
+                   hipStream_t s, const double* c1, const double* c2);
+gw_status run_objective(const Grid& X, const Grid& Y, const double* T, int64_t ldT, double eps,
+                        double* obj, double* Gbuf, Arena& a, hipStream_t s, StatusWord* status);
 
 }  // namespace gwr
 

@@ -23,6 +23,7 @@
 // nothing.  All reductions are in a fixed order (no atomics).
 #include <limits.h>
 
+#include "batch.h"
 #include "common.h"
 #include "runtime.h"
 
@@ -111,17 +112,15 @@ __global__ __launch_bounds__(256) void k_sk_prep(const double* __restrict__ p,
 // owns columns t + NTH * e.  Rows are taken R at a time (their reductions share
 // barriers) and the next R rows are loaded before the current ones are
 // reduced, so loads stay in flight across the barriers.
+// The body works on band `band` so that the batched kernels of the request
+// loop run exactly the same arithmetic on a band as the single-problem kernel.
 template <int NTH, int EPT, int R>
-__global__ __launch_bounds__(NTH) void k_sk_row(const double* __restrict__ C, int64_t ldC, int M,
-                                                 int N, int RB, double cs, double inv_eps,
-                                                 double eps, const double* __restrict__ p,
-                                                 const double* __restrict__ logp,
-                                                 const double* __restrict__ g,
-                                                 double* __restrict__ f,
-                                                 double* __restrict__ ms,
-                                                 double* __restrict__ partS,
-                                                 int* __restrict__ partX,
-                                                 gwr::StatusWord* status, int write_f) {
+GW_DEV void sk_row_band(const double* __restrict__ C, int64_t ldC, int M, int N, int RB,
+                        double cs, double inv_eps, const double* __restrict__ p,
+                        const double* __restrict__ logp, const double* __restrict__ g,
+                        double* __restrict__ f, double* __restrict__ ms,
+                        double* __restrict__ partS, int* __restrict__ partX, int write_f,
+                        int band) {
   constexpr int NW = NTH / 64;
   __shared__ double red[2][R][NW];
   const int t = threadIdx.x, wv = t >> 6, lane = t & 63;
@@ -136,7 +135,7 @@ __global__ __launch_bounds__(NTH) void k_sk_row(const double* __restrict__ C, in
     Xe[e] = EXP_SENTINEL;
     gie[e] = col < N ? g[col] * inv_eps : -INFINITY;
   }
-  const int i0 = blockIdx.x * RB, i1 = min(M, i0 + RB);
+  const int i0 = band * RB, i1 = min(M, i0 + RB);
   double cur[R][EPT];
   // Loads are unconditional (row and column indices clamped into range) so the
   // compiler can keep the next rows in flight across the reductions.
@@ -240,10 +239,24 @@ __global__ __launch_bounds__(NTH) void k_sk_row(const double* __restrict__ C, in
   for (int e = 0; e < EPT; ++e) {
     const int col = t + NTH * e;
     if (col < N) {
-      partS[(int64_t)blockIdx.x * N + col] = S[e];
-      partX[(int64_t)blockIdx.x * N + col] = Xe[e];
+      partS[(int64_t)band * N + col] = S[e];
+      partX[(int64_t)band * N + col] = Xe[e];
     }
   }
+}
+
+template <int NTH, int EPT, int R>
+__global__ __launch_bounds__(NTH) void k_sk_row(const double* __restrict__ C, int64_t ldC, int M,
+                                                 int N, int RB, double cs, double inv_eps,
+                                                 const double* __restrict__ p,
+                                                 const double* __restrict__ logp,
+                                                 const double* __restrict__ g,
+                                                 double* __restrict__ f,
+                                                 double* __restrict__ ms,
+                                                 double* __restrict__ partS,
+                                                 int* __restrict__ partX, int write_f) {
+  sk_row_band<NTH, EPT, R>(C, ldC, M, N, RB, cs, inv_eps, p, logp, g, f, ms, partS, partX,
+                           write_f, blockIdx.x);
 }
 
 // Grouped row pass for rows of up to 8 x 512 entries: a block of 1024 threads
@@ -253,17 +266,11 @@ __global__ __launch_bounds__(NTH) void k_sk_row(const double* __restrict__ C, in
 // lives in LDS.  The NG groups' column pairs are merged through LDS in group
 // order and written as the block's partial.
 template <int EPT, int NG, bool PF>
-__global__ __launch_bounds__(1024) void k_sk_rowg(const double* __restrict__ C, int64_t ldC,
-                                                   int M, int N, int RB, double cs,
-                                                   double inv_eps, double eps,
-                                                   const double* __restrict__ p,
-                                                   const double* __restrict__ logp,
-                                                   const double* __restrict__ g,
-                                                   double* __restrict__ f,
-                                                   double* __restrict__ ms,
-                                                   double* __restrict__ partS,
-                                                   int* __restrict__ partX,
-                                                   gwr::StatusWord* status, int write_f) {
+GW_DEV void sk_rowg_band(const double* __restrict__ C, int64_t ldC, int M, int N, int RB,
+                         double cs, double inv_eps, const double* __restrict__ p,
+                         const double* __restrict__ g, double* __restrict__ f,
+                         double* __restrict__ ms, double* __restrict__ partS,
+                         int* __restrict__ partX, int write_f, int band) {
   constexpr int GT = 1024 / NG, GW = GT / 64;
   __shared__ double gie[EPT * GT];
   __shared__ double red[2][NG][GW];
@@ -279,7 +286,7 @@ __global__ __launch_bounds__(1024) void k_sk_rowg(const double* __restrict__ C, 
     S[e] = 0.0;
     Xe[e] = EXP_SENTINEL;
   }
-  const int i0 = blockIdx.x * RB, i1 = min(M, i0 + RB);
+  const int i0 = band * RB, i1 = min(M, i0 + RB);
   const int nr = (RB + NG - 1) / NG;  // row steps, the same for every group
   int colc[EPT];                      // column of each entry, clamped into range
 #pragma unroll
@@ -374,27 +381,39 @@ __global__ __launch_bounds__(1024) void k_sk_rowg(const double* __restrict__ C, 
     }
     const int col = tl + GT * e;
     if (gi == 0 && col < N) {
-      partS[(int64_t)blockIdx.x * N + col] = S[e];
-      partX[(int64_t)blockIdx.x * N + col] = Xe[e];
+      partS[(int64_t)band * N + col] = S[e];
+      partX[(int64_t)band * N + col] = Xe[e];
     }
   }
+}
+
+template <int EPT, int NG, bool PF>
+__global__ __launch_bounds__(1024) void k_sk_rowg(const double* __restrict__ C, int64_t ldC,
+                                                   int M, int N, int RB, double cs,
+                                                   double inv_eps,
+                                                   const double* __restrict__ p,
+                                                   const double* __restrict__ g,
+                                                   double* __restrict__ f,
+                                                   double* __restrict__ ms,
+                                                   double* __restrict__ partS,
+                                                   int* __restrict__ partX, int write_f) {
+  sk_rowg_band<EPT, NG, PF>(C, ldC, M, N, RB, cs, inv_eps, p, g, f, ms, partS, partX, write_f,
+                            blockIdx.x);
 }
 
 // Column merge: a block covers 16 columns x 16 groups of bands; each thread
 // merges its groups' (mantissa, exponent) pairs in band order, then the 16
 // group results of a column are merged in group order.
-constexpr int MERGE_COLS = 16, MERGE_GRPS = 16;
+constexpr int MERGE_COLS = gwb::kMergeCols, MERGE_GRPS = 16;
 
-__global__ __launch_bounds__(256) void k_sk_col(int N, int nb, const double* __restrict__ partS,
-                                                 const int* __restrict__ partX,
-                                                 const double* __restrict__ q,
-                                                 const double* __restrict__ logq, double eps,
-                                                 double* __restrict__ g,
-                                                 gwr::StatusWord* status) {
+GW_DEV void sk_col_block(int N, int nb, const double* __restrict__ partS,
+                         const int* __restrict__ partX, const double* __restrict__ q,
+                         const double* __restrict__ logq, double eps, double* __restrict__ g,
+                         gwr::StatusWord* status, int cblock) {
   __shared__ double ms[MERGE_GRPS][MERGE_COLS];
   __shared__ int mx[MERGE_GRPS][MERGE_COLS];
   const int c = threadIdx.x & (MERGE_COLS - 1), grp = threadIdx.x / MERGE_COLS;
-  const int col = blockIdx.x * MERGE_COLS + c;
+  const int col = cblock * MERGE_COLS + c;
   double S = 0.0;
   int X = EXP_SENTINEL;
   if (col < N) {
@@ -427,6 +446,15 @@ __global__ __launch_bounds__(256) void k_sk_col(int N, int nb, const double* __r
   const double gn = g[col] + eps * (logq[col] - lnS);
   g[col] = gn;
   if (!isfinite(gn)) status->nonfinite = 1;
+}
+
+__global__ __launch_bounds__(256) void k_sk_col(int N, int nb, const double* __restrict__ partS,
+                                                 const int* __restrict__ partX,
+                                                 const double* __restrict__ q,
+                                                 const double* __restrict__ logq, double eps,
+                                                 double* __restrict__ g,
+                                                 gwr::StatusWord* status) {
+  sk_col_block(N, nb, partS, partX, q, logq, eps, g, status, blockIdx.x);
 }
 
 // f_i = eps (ln p_i - m_i - ln s_i) from the last row pass's row maximum and
@@ -540,14 +568,80 @@ int sk_rows_per_block(int64_t M) {
   return rb < 1 ? 1 : rb;
 }
 
+// Rows reduced together by the row pass: 4 for short rows, 2 at 1024
+// threads (register pressure), 1 for rows of 16 entries per thread.
+template <int NTH, int EPT>
+constexpr int row_group() {
+  return EPT > 4 ? 1 : (NTH >= 1024 ? 2 : 4);
+}
+
 template <int NTH, int EPT>
 void launch_row(int nb, hipStream_t s, const double* C, int64_t ldC, int M, int N, int RB,
-                double cs, double inv_eps, double eps, const double* p, const double* logp,
-                const double* g, double* f, double* ms, double* pS, int* pX,
-                gwr::StatusWord* st, int last) {
-  constexpr int R = EPT > 4 ? 1 : (NTH >= 1024 ? 2 : 4);
-  k_sk_row<NTH, EPT, R><<<nb, NTH, 0, s>>>(C, ldC, M, N, RB, cs, inv_eps, eps, p, logp, g, f, ms, pS, pX, st, last);
+                double cs, double inv_eps, const double* p, const double* logp,
+                const double* g, double* f, double* ms, double* pS, int* pX, int last) {
+  constexpr int R = row_group<NTH, EPT>();
+  k_sk_row<NTH, EPT, R><<<nb, NTH, 0, s>>>(C, ldC, M, N, RB, cs, inv_eps, p, logp, g, f, ms, pS, pX, last);
 }
+
+// ---------------------------------------------------------------------------
+// Batched kernels of the request loop.  Each block walks the item list of its
+// class with a fixed stride (the grid is fixed when the step is captured);
+// an item names a request slot and a band (row pass) or a column block
+// (merge).  A request takes part in iteration j of a step only if j < its.
+// The per-band arithmetic is the single-problem kernel's, so a request's
+// result does not depend on what else is in the batch.
+template <int NTH, int EPT>
+__global__ __launch_bounds__(NTH) void k_skb_row(const gwb::SkSlot* __restrict__ slots,
+                                                  const gwb::SkTableHead* __restrict__ head,
+                                                  const uint32_t* __restrict__ items, int cls,
+                                                  int j) {
+  const int n = head->count[cls];
+  const uint32_t* list = items + head->offset[cls];
+  for (int w = blockIdx.x; w < n; w += gridDim.x) {
+    const uint32_t code = list[w];
+    const gwb::SkSlot& a = slots[code >> gwb::kBandBits];
+    if (j >= a.its) continue;
+    __syncthreads();
+    sk_row_band<NTH, EPT, row_group<NTH, EPT>()>(
+        a.C, a.ldC, a.M, a.N, a.RB, a.cs, a.inv_eps, a.p, a.logp, a.g, a.f, a.ms, a.pS, a.pX,
+        a.last && j == a.its - 1, (int)(code & ((1u << gwb::kBandBits) - 1)));
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_skb_rowg(const gwb::SkSlot* __restrict__ slots,
+                                                    const gwb::SkTableHead* __restrict__ head,
+                                                    const uint32_t* __restrict__ items, int cls,
+                                                    int j) {
+  const int n = head->count[cls];
+  const uint32_t* list = items + head->offset[cls];
+  for (int w = blockIdx.x; w < n; w += gridDim.x) {
+    const uint32_t code = list[w];
+    const gwb::SkSlot& a = slots[code >> gwb::kBandBits];
+    if (j >= a.its) continue;
+    __syncthreads();
+    sk_rowg_band<8, 2, true>(a.C, a.ldC, a.M, a.N, a.RB, a.cs, a.inv_eps, a.p, a.g, a.f, a.ms,
+                             a.pS, a.pX, a.last && j == a.its - 1,
+                             (int)(code & ((1u << gwb::kBandBits) - 1)));
+  }
+}
+
+__global__ __launch_bounds__(256) void k_skb_col(const gwb::SkSlot* __restrict__ slots,
+                                                  const gwb::SkTableHead* __restrict__ head,
+                                                  const uint32_t* __restrict__ items, int j) {
+  const int n = head->count[gwb::kClsCol];
+  const uint32_t* list = items + head->offset[gwb::kClsCol];
+  for (int w = blockIdx.x; w < n; w += gridDim.x) {
+    const uint32_t code = list[w];
+    const gwb::SkSlot& a = slots[code >> gwb::kCBlockBits];
+    if (j >= a.its) continue;
+    __syncthreads();
+    sk_col_block(a.N, a.nb, a.pS, a.pX, a.q, a.logq, a.eps, a.g, a.status,
+                 (int)(code & ((1u << gwb::kCBlockBits) - 1)));
+  }
+}
+
+// Persistent grids: enough blocks to fill the chip at the class's occupancy.
+constexpr unsigned kBatchBlocks256 = 2048, kBatchBlocks512 = 1024, kBatchBlocks1024 = 512;
 
 }  // namespace
 
@@ -565,6 +659,44 @@ size_t sinkhorn_ws_bytes(int64_t M, int64_t N) {
   return a.used;
 }
 
+gw_status sinkhorn_prep(const double* p, const double* q, int64_t M, int64_t N, int init_zero,
+                        double* logp, double* logq, double* f, double* g, hipStream_t s) {
+  gwr::ProfScope ps(gwr::kFamOther, s);
+  const int64_t mx = M > N ? M : N;
+  k_sk_prep<<<(unsigned)((mx + 255) / 256), 256, 0, s>>>(p, q, (int)M, (int)N, init_zero, logp, logq, f, g);
+  return gwr::last_launch_status();
+}
+
+gw_status sinkhorn_finish(const double* C, int64_t ldC, int64_t M, int64_t N, double c_scale,
+                          const double* p, const double* logp, const double* ms, double eps,
+                          int iters, double* f, const double* g, double* T, int64_t ldT,
+                          hipStream_t s, gwr::StatusWord* status) {
+  if (iters > 0) {
+    gwr::ProfScope ps(gwr::kFamOther, s);
+    k_sk_f<<<(unsigned)((M + 255) / 256), 256, 0, s>>>((int)M, p, logp, ms, eps, f, status);
+  }
+  if (T) return plan(C, ldC, M, N, c_scale, f, g, eps, T, ldT, s);
+  return gwr::last_launch_status();
+}
+
+int sk_rows_per_band(int64_t M) { return sk_rows_per_block(M); }
+
+gw_status sk_batch_launch(int cls, int j, const gwb::SkSlot* slots, const gwb::SkTableHead* head,
+                          const uint32_t* items, hipStream_t s) {
+  switch (cls) {
+    case gwb::kClsN256: k_skb_row<256, 1><<<kBatchBlocks256, 256, 0, s>>>(slots, head, items, cls, j); break;
+    case gwb::kClsN512: k_skb_row<512, 1><<<kBatchBlocks512, 512, 0, s>>>(slots, head, items, cls, j); break;
+    case gwb::kClsN1024: k_skb_row<1024, 1><<<kBatchBlocks1024, 1024, 0, s>>>(slots, head, items, cls, j); break;
+    case gwb::kClsN2048: k_skb_row<1024, 2><<<kBatchBlocks1024, 1024, 0, s>>>(slots, head, items, cls, j); break;
+    case gwb::kClsN4096: k_skb_rowg<<<kBatchBlocks1024, 1024, 0, s>>>(slots, head, items, cls, j); break;
+    case gwb::kClsN8192: k_skb_row<512, 16><<<kBatchBlocks512, 512, 0, s>>>(slots, head, items, cls, j); break;
+    case gwb::kClsN16384: k_skb_row<1024, 16><<<kBatchBlocks1024, 1024, 0, s>>>(slots, head, items, cls, j); break;
+    case gwb::kClsCol: k_skb_col<<<kBatchBlocks256, 256, 0, s>>>(slots, head, items, j); break;
+    default: return GW_EINVAL;
+  }
+  return gwr::last_launch_status();
+}
+
 gw_status sinkhorn(const double* C, int64_t ldC, int64_t M, int64_t N, double c_scale,
                    const double* p, const double* q, double eps, int iters, int init_zero,
                    double* f, double* g, double* T, int64_t ldT, gwr::Arena& ws, hipStream_t s,
@@ -578,34 +710,26 @@ gw_status sinkhorn(const double* C, int64_t ldC, int64_t M, int64_t N, double c_
   int* pX = ws.take<int>((size_t)nb * N);
   double* ms = ws.take<double>(2 * (size_t)M);
   const double inv_eps = 1.0 / eps;
-  {
-    gwr::ProfScope ps(gwr::kFamOther, s);
-    const int64_t mx = M > N ? M : N;
-    k_sk_prep<<<(unsigned)((mx + 255) / 256), 256, 0, s>>>(p, q, (int)M, (int)N, init_zero, logp, logq, f, g);
-  }
+  gw_status st = sinkhorn_prep(p, q, M, N, init_zero, logp, logq, f, g, s);
+  if (st != GW_OK) return st;
   const int Mi = (int)M, Ni = (int)N;
   for (int it = 0; it < iters; ++it) {
     {
       gwr::ProfScope ps(gwr::kFamSinkRow, s);
-      if (N <= 256) launch_row<256, 1>(nb, s, C, ldC, Mi, Ni, rb, c_scale, inv_eps, eps, p, logp, g, f, ms, pS, pX, status, it == iters - 1);
-      else if (N <= 512) launch_row<512, 1>(nb, s, C, ldC, Mi, Ni, rb, c_scale, inv_eps, eps, p, logp, g, f, ms, pS, pX, status, it == iters - 1);
-      else if (N <= 1024) launch_row<1024, 1>(nb, s, C, ldC, Mi, Ni, rb, c_scale, inv_eps, eps, p, logp, g, f, ms, pS, pX, status, it == iters - 1);
-      else if (N <= 2048) launch_row<1024, 2>(nb, s, C, ldC, Mi, Ni, rb, c_scale, inv_eps, eps, p, logp, g, f, ms, pS, pX, status, it == iters - 1);
-      else if (N <= 4096) k_sk_rowg<8, 2, true><<<nb, 1024, 0, s>>>(C, ldC, Mi, Ni, rb, c_scale, inv_eps, eps, p, logp, g, f, ms, pS, pX, status, it == iters - 1);
-      else if (N <= 8192) launch_row<512, 16>(nb, s, C, ldC, Mi, Ni, rb, c_scale, inv_eps, eps, p, logp, g, f, ms, pS, pX, status, it == iters - 1);
-      else launch_row<1024, 16>(nb, s, C, ldC, Mi, Ni, rb, c_scale, inv_eps, eps, p, logp, g, f, ms, pS, pX, status, it == iters - 1);
+      if (N <= 256) launch_row<256, 1>(nb, s, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, it == iters - 1);
+      else if (N <= 512) launch_row<512, 1>(nb, s, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, it == iters - 1);
+      else if (N <= 1024) launch_row<1024, 1>(nb, s, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, it == iters - 1);
+      else if (N <= 2048) launch_row<1024, 2>(nb, s, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, it == iters - 1);
+      else if (N <= 4096) k_sk_rowg<8, 2, true><<<nb, 1024, 0, s>>>(C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, g, f, ms, pS, pX, it == iters - 1);
+      else if (N <= 8192) launch_row<512, 16>(nb, s, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, it == iters - 1);
+      else launch_row<1024, 16>(nb, s, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, it == iters - 1);
     }
     {
       gwr::ProfScope ps(gwr::kFamSinkCol, s);
       k_sk_col<<<(unsigned)((N + MERGE_COLS - 1) / MERGE_COLS), 256, 0, s>>>(Ni, nb, pS, pX, q, logq, eps, g, status);
     }
   }
-  if (iters > 0) {
-    gwr::ProfScope ps(gwr::kFamOther, s);
-    k_sk_f<<<(unsigned)((M + 255) / 256), 256, 0, s>>>(Mi, p, logp, ms, eps, f, status);
-  }
-  if (T) return plan(C, ldC, M, N, c_scale, f, g, eps, T, ldT, s);
-  return gwr::last_launch_status();
+  return sinkhorn_finish(C, ldC, M, N, c_scale, p, logp, ms, eps, iters, f, g, T, ldT, s, status);
 }
 
 gw_status plan(const double* C, int64_t ldC, int64_t M, int64_t N, double c_scale,

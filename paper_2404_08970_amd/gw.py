@@ -9,6 +9,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import time
 from dataclasses import dataclass
 
 import torch
@@ -17,11 +18,14 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgw.so")
 
 GW_OK, GW_EINVAL, GW_ENOMEM, GW_EDEVICE, GW_ENUMERIC, GW_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+GW_EAGAIN = -6
 METRIC_L1POW, METRIC_SQEUCLID = 0, 1
 PATH_FAST_F64, PATH_DENSE_F64, PATH_DENSE_F32, PATH_DENSE_BF16 = 0, 1, 2, 3
 PATH_DENSE_BF16_SPLIT, PATH_DENSE_F32_SPLIT = 4, 5
 OP_GRAD, OP_SINKHORN, OP_SOLVE, OP_OBJECTIVE = 0, 1, 2, 3
 FLAG_WARM_START = 1
+REQ_OBJECTIVE = 2
+REQ_QUEUED, REQ_RUNNING, REQ_DONE = 0, 1, 2
 KMAX = 4
 
 PATHS = {
@@ -32,7 +36,8 @@ PATHS = {
 }
 
 # timing families (gw.h)
-FAM_FAST_MAIN, FAM_FAST_CARRY, FAM_DENSE, FAM_SINK_ROW, FAM_SINK_COL, FAM_PLAN, FAM_OTHER, FAM_2D = range(8)
+(FAM_FAST_MAIN, FAM_FAST_CARRY, FAM_DENSE, FAM_SINK_ROW, FAM_SINK_COL, FAM_PLAN, FAM_OTHER, FAM_2D,
+ FAM_SERVE_STEP) = range(9)
 
 
 class GWError(RuntimeError):
@@ -44,6 +49,19 @@ class GWError(RuntimeError):
 class c_grid(ctypes.Structure):
     _fields_ = [("ndim", ctypes.c_int32), ("k", ctypes.c_int32), ("metric", ctypes.c_int32),
                 ("reserved", ctypes.c_int32), ("shape", ctypes.c_int64 * 2), ("h", ctypes.c_double)]
+
+
+class c_request(ctypes.Structure):
+    _fields_ = [("X", c_grid), ("Y", c_grid), ("p", ctypes.c_void_p), ("q", ctypes.c_void_p),
+                ("eps", ctypes.c_double), ("outer", ctypes.c_int32), ("inner", ctypes.c_int32),
+                ("flags", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class c_result(ctypes.Structure):
+    _fields_ = [("T", ctypes.c_void_p), ("f", ctypes.c_void_p), ("g", ctypes.c_void_p),
+                ("M", ctypes.c_int64), ("N", ctypes.c_int64), ("obj", ctypes.c_double * 2),
+                ("done_ms", ctypes.c_double), ("status", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 _LIB = None
@@ -79,6 +97,25 @@ def _lib():
     lib.gw_profile_read.restype = I32
     lib.gw_version.argtypes = []
     lib.gw_version.restype = ctypes.c_char_p
+    R, PS = ctypes.POINTER(c_request), ctypes.POINTER(ctypes.c_void_p)
+    lib.gw_server_request_bytes.argtypes = [R]
+    lib.gw_server_request_bytes.restype = SZ
+    lib.gw_server_table_bytes.argtypes = [I32]
+    lib.gw_server_table_bytes.restype = SZ
+    lib.gw_server_create.argtypes = [P, SZ, I32, I32, P, PS]
+    lib.gw_server_create.restype = I32
+    lib.gw_server_submit.argtypes = [P, R, ctypes.POINTER(I64)]
+    lib.gw_server_submit.restype = I32
+    lib.gw_server_step.argtypes = [P, ctypes.POINTER(I32), ctypes.POINTER(I32)]
+    lib.gw_server_step.restype = I32
+    lib.gw_server_poll.argtypes = [P, I64, ctypes.POINTER(I32)]
+    lib.gw_server_poll.restype = I32
+    lib.gw_server_result.argtypes = [P, I64, ctypes.POINTER(c_result)]
+    lib.gw_server_result.restype = I32
+    lib.gw_server_release.argtypes = [P, I64]
+    lib.gw_server_release.restype = I32
+    lib.gw_server_destroy.argtypes = [P]
+    lib.gw_server_destroy.restype = I32
     _LIB = lib
     return lib
 
@@ -264,7 +301,7 @@ def check_status(ws=None):
 def profile_enable(families=None):
     """Record kernel times for the given families (None = all, [] = off)."""
     if families is None:
-        mask = 0xFF
+        mask = 0x1FF
     else:
         mask = 0
         for f in families:
@@ -277,3 +314,117 @@ def profile_read(family: int):
     n = ctypes.c_int64(0)
     _raise(_lib().gw_profile_read(int(family), ctypes.byref(ms), ctypes.byref(n)), "gw_profile_read")
     return ms.value, n.value
+
+
+# ---------------------------------------------------------------- request loop
+
+def make_request(X: Grid, Y: Grid, p, q, eps: float, outer: int, inner: int,
+                 warm: bool = False, objective: bool = False) -> c_request:
+    r = c_request()
+    r.X, r.Y = X.c(), Y.c()
+    r.p, r.q = p.data_ptr() if p is not None else 0, q.data_ptr() if q is not None else 0
+    r.eps, r.outer, r.inner = float(eps), int(outer), int(inner)
+    r.flags = (FLAG_WARM_START if warm else 0) | (REQ_OBJECTIVE if objective else 0)
+    r.reserved = 0
+    return r
+
+
+def request_bytes(X: Grid, Y: Grid, eps: float = 1e-3, outer: int = 1, inner: int = 1) -> int:
+    """Arena bytes a request holds while admitted (host arithmetic)."""
+    r = make_request(X, Y, None, None, eps, outer, inner)
+    r.p = r.q = 256  # any aligned non-null address: only the sizes are read
+    return int(_lib().gw_server_request_bytes(ctypes.byref(r)))
+
+
+class _DeviceView:
+    """Exposes a device FP64 buffer through __cuda_array_interface__ (no copy)."""
+
+    def __init__(self, ptr: int, shape):
+        self.__cuda_array_interface__ = {"shape": tuple(int(s) for s in shape), "typestr": "<f8",
+                                         "data": (int(ptr), False), "version": 2, "strides": None}
+
+
+class Server:
+    """Request loop over a device arena: continuous batching of GW solves.
+
+    ``submit`` queues a solve, ``step`` admits what fits and advances every
+    admitted request by one step, ``poll``/``result`` report finished ones and
+    ``release`` returns their arena range.  ``p`` and ``q`` tensors are kept
+    alive here until release."""
+
+    def __init__(self, arena_bytes: int, max_slots: int = 64, iters_per_step: int = 10,
+                 device=None, stream=None):
+        dev = torch.device("cuda") if device is None else torch.device(device)
+        self.device = dev
+        self._arena = torch.empty(int(arena_bytes) + 256, dtype=torch.uint8, device=dev)
+        off = (-self._arena.data_ptr()) % 256
+        self.arena = self._arena[off:off + int(arena_bytes)]
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        h = ctypes.c_void_p(0)
+        st = _lib().gw_server_create(_ptr(self.arena), int(arena_bytes), int(max_slots),
+                                     int(iters_per_step), ctypes.c_void_p(self.stream.cuda_stream),
+                                     ctypes.byref(h))
+        _raise(st, "gw_server_create")
+        self.t0 = time.perf_counter()
+        self._h = h
+        self._keep = {}
+
+    def submit(self, X: Grid, Y: Grid, p, q, eps: float, outer: int, inner: int,
+               warm: bool = False, objective: bool = False) -> int:
+        _check_f64("p", p, (X.size,)); _check_f64("q", q, (Y.size,))
+        r = make_request(X, Y, p, q, eps, outer, inner, warm, objective)
+        rid = ctypes.c_int64(0)
+        _raise(_lib().gw_server_submit(self._h, ctypes.byref(r), ctypes.byref(rid)), "gw_server_submit")
+        self._keep[rid.value] = (p, q)
+        return rid.value
+
+    def step(self):
+        a, qd = ctypes.c_int32(0), ctypes.c_int32(0)
+        _raise(_lib().gw_server_step(self._h, ctypes.byref(a), ctypes.byref(qd)), "gw_server_step")
+        return a.value, qd.value
+
+    def poll(self, rid: int) -> int:
+        s = ctypes.c_int32(0)
+        _raise(_lib().gw_server_poll(self._h, int(rid), ctypes.byref(s)), "gw_server_poll")
+        return s.value
+
+    def result(self, rid: int, copy: bool = True):
+        """dict(T, f, g, obj, done_ms, done_t, status) of a finished request;
+        None if it is not finished.  With copy=False T, f, g are views of the
+        arena, valid until release."""
+        res = c_result()
+        st = _lib().gw_server_result(self._h, int(rid), ctypes.byref(res))
+        if st == GW_EAGAIN:
+            return None
+        _raise(st, "gw_server_result")
+        M, N = res.M, res.N
+        with torch.cuda.device(self.device):
+            T = torch.as_tensor(_DeviceView(res.T, (M, N)), device=self.device)
+            f = torch.as_tensor(_DeviceView(res.f, (M,)), device=self.device)
+            g = torch.as_tensor(_DeviceView(res.g, (N,)), device=self.device)
+        if copy:
+            with torch.cuda.stream(self.stream):
+                T, f, g = T.clone(), f.clone(), g.clone()
+        return {"T": T, "f": f, "g": g, "obj": (res.obj[0], res.obj[1]), "done_ms": res.done_ms,
+                "done_t": self.t0 + res.done_ms / 1e3, "status": res.status}
+
+    def release(self, rid: int):
+        _raise(_lib().gw_server_release(self._h, int(rid)), "gw_server_release")
+        self._keep.pop(int(rid), None)
+
+    def close(self):
+        if self._h:
+            st = _lib().gw_server_destroy(self._h)
+            self._h = None
+            self._keep.clear()
+            _raise(st, "gw_server_destroy")
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def server_table_bytes(max_slots: int) -> int:
+    return int(_lib().gw_server_table_bytes(int(max_slots)))

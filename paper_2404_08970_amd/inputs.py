@@ -15,6 +15,10 @@ Workload recipes (the paper's datasets are not used):
   then renormalised.
 * Dirichlet(alpha=1) marginals.
 * Random non-negative plans with unit mass for gradient tests.
+* Request stream for the request loop: 70% 1D grids with n ~ U{128..8192},
+  30% square 2D grids with side s ~ U{16..96} (L1POW), X and Y of the same
+  size with independently drawn marginals (mixtures in 1D, blobs without
+  floor in 2D), k ~ U{1,2}, eps ~ U[1e-3, 1e-2], Poisson arrivals.
 """
 from __future__ import annotations
 
@@ -88,3 +92,27 @@ def peaked_plan(M: int, N: int, rng: np.random.Generator, width: float = 0.02) -
 def integer_plan(M: int, N: int, rng: np.random.Generator, hi: int = 8) -> np.ndarray:
     """Integer-valued non-negative matrix (for bit-exact checks)."""
     return rng.integers(0, hi, size=(M, N)).astype(np.float64)
+
+
+def serving_requests(count: int, seed: int = 5, n_range=(128, 8192), side_range=(16, 96),
+                     frac_1d: float = 0.7, eps_range=(1e-3, 1e-2), rate: float = 1.0):
+    """`count` request descriptors: dict(shape, k, eps, p, q, arrival) with
+    Poisson arrivals of the given rate (exponential gaps, first at 0)."""
+    rng = rng_for(seed)
+    out = []
+    t = 0.0
+    for i in range(count):
+        if i > 0:
+            t += float(rng.exponential(1.0 / rate))
+        k = int(rng.integers(1, 3))
+        eps = float(rng.uniform(*eps_range))
+        if rng.uniform() < frac_1d:
+            n = int(rng.integers(n_range[0], n_range[1] + 1))
+            shape = (n,)
+            p, q = gauss_mixture_1d(n, rng), gauss_mixture_1d(n, rng)
+        else:
+            s = int(rng.integers(side_range[0], side_range[1] + 1))
+            shape = (s, s)
+            p, q = blobs_2d(s, s, rng), blobs_2d(s, s, rng)
+        out.append({"shape": shape, "k": k, "eps": eps, "p": p, "q": q, "arrival": t})
+    return out
