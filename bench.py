@@ -8,10 +8,13 @@ timed region.  `value` is solves per second over the K timed steps.
 Beside the headline the JSON line carries: gradient evaluations per second for
 the FAST recursion and the dense FP64 matrix-core product at n = 4096 (and the
 FAST/dense ratio at n = 16384), the roofline of the dominant kernel (the
-Sinkhorn row pass) measured with HIP events over the timed region, and the CPU
-oracle timed on a bounded sample.
+Sinkhorn row pass) measured with HIP events over the timed region, the CPU
+oracle timed on a bounded sample, and the request loop on a stream of uneven
+solves (saturated throughput, then Poisson arrivals at 0.8x of it: p50/p99
+latency and solves/s).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-big]
+                       [--no-serve] [--serve-requests R] [--serve-only]
 """
 from __future__ import annotations
 
@@ -33,6 +36,7 @@ EPS = 1e-3
 OUTER = 100
 INNER = 100
 KS = (1, 2, 3)
+GB = 1 << 30
 
 
 def marginals(n, k):
@@ -177,6 +181,95 @@ def precision_study(n: int = 16384, k: int = 2, rows: int = 6):
     return out
 
 
+def serve_bench(n_req: int = 200, n_sat: int = 64, slots: int = 32, iters: int = 10,
+                load: float = 0.8, arena_gb: float = 48.0, outer: int = 10, inner: int = 100):
+    """Request loop on the serving stream: 70% 1D n ~ U{128..8192}, 30% 2D
+    s ~ U{16..96} (L1POW), k ~ U{1,2}, eps ~ U[1e-3,1e-2], mixture / blob
+    marginals, 10 outer x 100 Sinkhorn iterations each.  First `n_sat`
+    requests all at t = 0 give the saturated rate; then `n_req` requests with
+    Poisson arrivals at `load` x that rate give p50/p99 of completion minus
+    arrival.  Completion times come from each request's HIP completion event."""
+    import numpy as np
+    import torch
+    from oracle import gw_oracle as O
+    from paper_2404_08970_amd import gw, inputs
+    dev = torch.device("cuda:0")
+    reqs = inputs.serving_requests(n_sat + n_req, seed=5)
+    dreqs = []
+    for r in reqs:
+        X = gw.unit_grid(r["shape"], r["k"])
+        dreqs.append((X, torch.tensor(r["p"], device=dev), torch.tensor(r["q"], device=dev), r["eps"]))
+    sv = gw.Server(int(arena_gb * GB), max_slots=slots, iters_per_step=iters)
+
+    def run(batch, arrivals, n_outer, n_inner):
+        t_start = time.perf_counter()
+        nxt, live, lat, fin = 0, {}, [], []
+        steps = 0
+        while nxt < len(batch) or live:
+            now = time.perf_counter() - t_start
+            while nxt < len(batch) and arrivals[nxt] <= now:
+                X, p, q, eps = batch[nxt]
+                live[sv.submit(X, X, p, q, eps, n_outer, n_inner)] = arrivals[nxt]
+                nxt += 1
+            if not live:
+                time.sleep(max(0.0, arrivals[nxt] - now))
+                continue
+            sv.step()
+            steps += 1
+            for rid in list(live):
+                if sv.poll(rid) == gw.REQ_DONE:
+                    res = sv.result(rid, copy=False)
+                    if res["status"] != 0:
+                        raise RuntimeError(f"request {rid} flagged a non-finite value")
+                    lat.append(res["done_t"] - (t_start + live.pop(rid)))
+                    fin.append(res["done_t"] - t_start)
+                    sv.release(rid)
+        return np.array(lat), np.array(fin), steps
+
+    # warm-up (not timed): one short solve of each request shape class in the stream
+    run(dreqs[:24], [0.0] * 24, 1, iters)
+    torch.cuda.synchronize()
+    _, fin_sat, steps_sat = run(dreqs[:n_sat], [0.0] * n_sat, outer, inner)
+    sat = n_sat / float(fin_sat.max())
+    rate = load * sat
+    arr = np.array([r["arrival"] for r in reqs[n_sat:]])
+    arr = (arr - arr[0]) / rate
+    lat, fin, steps = run(dreqs[n_sat:], arr.tolist(), outer, inner)
+
+    # accuracy: the smallest 1D request of the stream against the oracle (the
+    # result of a request is the same in any mix, so it is solved alone here)
+    ones = [i for i in range(n_sat, len(reqs)) if len(reqs[i]["shape"]) == 1]
+    ic = min(ones, key=lambda i: reqs[i]["shape"][0])
+    X, p, q, eps = dreqs[ic]
+    rid = sv.submit(X, X, p, q, eps, outer, inner)
+    while sv.poll(rid) != gw.REQ_DONE:
+        sv.step()
+    T = sv.result(rid)["T"].cpu().numpy()
+    sv.release(rid)
+    sv.close()
+    og = O.Grid(reqs[ic]["shape"], X.h, X.k)
+    T0 = O.solve(og, og, reqs[ic]["p"], reqs[ic]["q"], eps, outer, inner)[0]
+    acc = float(np.max(np.abs(T - T0)) / np.max(np.abs(T0)))
+    n1 = sum(1 for r in reqs[n_sat:] if len(r["shape"]) == 1)
+    return {
+        "workload": (f"{n_req} requests, Poisson arrivals at {load}x the saturated rate; "
+                     f"{n1} 1D n~U{{128..8192}}, {n_req - n1} 2D s~U{{16..96}} (L1POW); "
+                     f"k~U{{1,2}}, eps~U[1e-3,1e-2]; {outer} outer x {inner} Sinkhorn iterations"),
+        "saturated_solves_per_s": round(sat, 2),
+        "saturated_requests": n_sat,
+        "offered_rate_per_s": round(rate, 2),
+        "solves_per_s": round(n_req / float(fin.max()), 2),
+        "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 1),
+        "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 1),
+        "mean_ms": round(float(lat.mean()) * 1e3, 1),
+        "steps": steps,
+        "max_slots": slots, "iters_per_step": iters, "arena_GB": arena_gb,
+        "accuracy": {"request_n": reqs[ic]["shape"][0], "k": X.k, "eps": round(eps, 6),
+                     "rel_err_T_vs_oracle": acc,
+                     "note": "each result equals gw_solve (FAST FP64) bit for bit in any mix"},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -189,9 +282,19 @@ def main():
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--precision", action="store_true",
                     help="run the precision study (dense FP64/FP32/BF16/split vs FAST, n=16384) and exit")
+    ap.add_argument("--no-serve", action="store_true", help="skip the request-loop measurement")
+    ap.add_argument("--serve-only", action="store_true", help="run only the request loop and exit")
+    ap.add_argument("--serve-requests", type=int, default=200)
+    ap.add_argument("--serve-sat", type=int, default=64)
+    ap.add_argument("--serve-slots", type=int, default=32)
+    ap.add_argument("--serve-iters", type=int, default=10)
     args = ap.parse_args()
     if args.precision:
         print(json.dumps(precision_study()))
+        return
+    if args.serve_only:
+        print(json.dumps(serve_bench(args.serve_requests, args.serve_sat, args.serve_slots,
+                                     args.serve_iters)))
         return
     if args.profile_target:
         profile_target(args.profile_target, args.reps)
@@ -305,6 +408,11 @@ def main():
                "fast_GBps_at_24B_per_entry": round(24.0 * nb * nb / (fast_ms * 1e-3) / 1e9, 1)}
         del Tb, Gb, wsb
 
+    serving = None
+    if not args.no_serve:
+        serving = serve_bench(args.serve_requests, args.serve_sat, args.serve_slots,
+                              args.serve_iters)
+
     out = {
         "metric": METRIC,
         "value": round(solves / elapsed, 4),
@@ -326,6 +434,7 @@ def main():
         "grads": grads,
         "n16384": big,
         "objective": objs,
+        "serving": serving,
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()

@@ -11,16 +11,20 @@ namespace gwb {
 // Row-pass classes by row length N, each with the same block shape as the
 // single-problem Sinkhorn kernel for that length, plus the column merge.
 enum {
-  kClsN256 = 0,   // N <= 256:   256 threads, 1 entry per thread
-  kClsN512 = 1,   // N <= 512:   512 threads, 1 entry
-  kClsN1024 = 2,  // N <= 1024: 1024 threads, 1 entry
-  kClsN2048 = 3,  // N <= 2048: 1024 threads, 2 entries
-  kClsN4096 = 4,  // N <= 4096: two 512-thread row groups, 8 entries
-  kClsN8192 = 5,  // N <= 8192:  512 threads, 16 entries
-  kClsN16384 = 6, // N <= 16384: 1024 threads, 16 entries
-  kNumRowCls = 7,
-  kClsCol = 7,    // column merge items
-  kNumLists = 8
+  kClsN256 = 0,    // N <= 256:   256 threads, 1 entry per thread
+  kClsN512 = 1,    // N <= 512:   512 threads, 1 entry
+  kClsN1024 = 2,   // N <= 1024: 1024 threads, 1 entry
+  kClsN2048 = 3,   // N <= 2048: 1024 threads, 2 entries
+  kClsN3072 = 4,   // N <= 3072:  256 threads, 12 entries
+  kClsN4096 = 5,   // N <= 4096: two 512-thread row groups, 8 entries
+  kClsN6144 = 6,   // N <= 6144:  512 threads, 12 entries
+  kClsN8192 = 7,   // N <= 8192:  512 threads, 16 entries
+  kClsN9216 = 8,   // N <= 9216:  512 threads, 18 entries, g / eps in LDS
+  kClsN12288 = 9,  // N <= 12288: 512 threads, 24 entries, g / eps in LDS
+  kClsN16384 = 10, // N <= 16384: 512 threads, 32 entries, g / eps in LDS
+  kNumRowCls = 11,
+  kClsCol = 11,    // column merge items
+  kNumLists = 12
 };
 
 inline int row_class(int64_t N) {
@@ -28,8 +32,12 @@ inline int row_class(int64_t N) {
   if (N <= 512) return kClsN512;
   if (N <= 1024) return kClsN1024;
   if (N <= 2048) return kClsN2048;
+  if (N <= 3072) return kClsN3072;
   if (N <= 4096) return kClsN4096;
+  if (N <= 6144) return kClsN6144;
   if (N <= 8192) return kClsN8192;
+  if (N <= 9216) return kClsN9216;
+  if (N <= 12288) return kClsN12288;
   return kClsN16384;
 }
 

@@ -65,6 +65,15 @@ GW_DEV double block_sum(double v, double* red) {
 
 // e^r for |r| <= ln(2)/2 by its Taylor series to degree 13 (Horner); the
 // truncation error is below 4.2e-18 relative on that interval.
+// threadIdx.x behind an empty asm statement: values derived from it cannot be
+// hoisted out of the persistent item loops of the batched kernels, where they
+// would stay live across the loop and push the band bodies into spills.
+GW_DEV int opaque_tid() {
+  int t = (int)threadIdx.x;
+  asm volatile("" : "+v"(t));
+  return t;
+}
+
 GW_DEV double exp_reduced(double r) {
   double y = 1.0 / 6227020800.0;  // 1/13!
   y = fma(y, r, 1.0 / 479001600.0);
@@ -114,7 +123,11 @@ __global__ __launch_bounds__(256) void k_sk_prep(const double* __restrict__ p,
 // reduced, so loads stay in flight across the barriers.
 // The body works on band `band` so that the batched kernels of the request
 // loop run exactly the same arithmetic on a band as the single-problem kernel.
-template <int NTH, int EPT, int R>
+// GL: g_p / eps is kept in LDS instead of registers.  PF: the next rows are
+// loaded while the current ones are reduced (two row buffers); without it the
+// next rows are loaded after the column update into the same registers, which
+// leaves room for up to 32 entries per thread at 512 threads.
+template <int NTH, int EPT, int R, bool GL = false, bool PF = true>
 GW_DEV void sk_row_band(const double* __restrict__ C, int64_t ldC, int M, int N, int RB,
                         double cs, double inv_eps, const double* __restrict__ p,
                         const double* __restrict__ logp, const double* __restrict__ g,
@@ -123,18 +136,26 @@ GW_DEV void sk_row_band(const double* __restrict__ C, int64_t ldC, int M, int N,
                         int band) {
   constexpr int NW = NTH / 64;
   __shared__ double red[2][R][NW];
-  const int t = threadIdx.x, wv = t >> 6, lane = t & 63;
+  __shared__ double gls[GL ? EPT * NTH : 1];
+  const int t = opaque_tid(), wv = t >> 6, lane = t & 63;
   const double csie = cs * inv_eps;
   double S[EPT];
   int Xe[EPT];
-  double gie[EPT];  // g_p / eps
+  double gir[GL ? 1 : EPT];  // g_p / eps
 #pragma unroll
   for (int e = 0; e < EPT; ++e) {
     const int col = t + NTH * e;
     S[e] = 0.0;
     Xe[e] = EXP_SENTINEL;
-    gie[e] = col < N ? g[col] * inv_eps : -INFINITY;
+    const double gv = col < N ? g[col] * inv_eps : -INFINITY;
+    if constexpr (GL) gls[t + NTH * e] = gv;
+    else gir[e] = gv;
   }
+  if constexpr (GL) __syncthreads();
+  auto gie = [&](int e) -> double {
+    if constexpr (GL) return gls[t + NTH * e];
+    else return gir[e];
+  };
   const int i0 = band * RB, i1 = min(M, i0 + RB);
   double cur[R][EPT];
   // Loads are unconditional (row and column indices clamped into range) so the
@@ -170,11 +191,11 @@ GW_DEV void sk_row_band(const double* __restrict__ C, int64_t ldC, int M, int N,
       mloc[r] = -INFINITY;
 #pragma unroll
       for (int e = 0; e < EPT; ++e) {
-        z[r][e] = fma(-csie, cur[r][e], gie[e]);
+        z[r][e] = fma(-csie, cur[r][e], gie(e));
         mloc[r] = fmax(mloc[r], z[r][e]);
       }
     }
-    load(cur, ib + R);  // clamped: past the band it re-reads the last row
+    if constexpr (PF) load(cur, ib + R);  // clamped: past the band it re-reads the last row
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       mloc[r] = gwk::wave_max(mloc[r]);
@@ -234,6 +255,7 @@ GW_DEV void sk_row_band(const double* __restrict__ C, int64_t ldC, int M, int N,
         Xe[e] = ne;
       }
     }
+    if constexpr (!PF) load(cur, ib + R);
   }
 #pragma unroll
   for (int e = 0; e < EPT; ++e) {
@@ -245,7 +267,7 @@ GW_DEV void sk_row_band(const double* __restrict__ C, int64_t ldC, int M, int N,
   }
 }
 
-template <int NTH, int EPT, int R>
+template <int NTH, int EPT, int R, bool GL, bool PF>
 __global__ __launch_bounds__(NTH) void k_sk_row(const double* __restrict__ C, int64_t ldC, int M,
                                                  int N, int RB, double cs, double inv_eps,
                                                  const double* __restrict__ p,
@@ -255,8 +277,8 @@ __global__ __launch_bounds__(NTH) void k_sk_row(const double* __restrict__ C, in
                                                  double* __restrict__ ms,
                                                  double* __restrict__ partS,
                                                  int* __restrict__ partX, int write_f) {
-  sk_row_band<NTH, EPT, R>(C, ldC, M, N, RB, cs, inv_eps, p, logp, g, f, ms, partS, partX,
-                           write_f, blockIdx.x);
+  sk_row_band<NTH, EPT, R, GL, PF>(C, ldC, M, N, RB, cs, inv_eps, p, logp, g, f, ms, partS,
+                                   partX, write_f, blockIdx.x);
 }
 
 // Grouped row pass for rows of up to 8 x 512 entries: a block of 1024 threads
@@ -276,7 +298,7 @@ GW_DEV void sk_rowg_band(const double* __restrict__ C, int64_t ldC, int M, int N
   __shared__ double red[2][NG][GW];
   __shared__ double mS[NG > 1 ? NG - 1 : 1][GT];
   __shared__ int mX[NG > 1 ? NG - 1 : 1][GT];
-  const int t = threadIdx.x, gi = t / GT, tl = t - gi * GT, wv = tl >> 6, lane = t & 63;
+  const int t = opaque_tid(), gi = t / GT, tl = t - gi * GT, wv = tl >> 6, lane = t & 63;
   const double csie = cs * inv_eps;
   for (int c = t; c < EPT * GT; c += 1024) gie[c] = c < N ? g[c] * inv_eps : -INFINITY;
   double S[EPT];
@@ -575,12 +597,23 @@ constexpr int row_group() {
   return EPT > 4 ? 1 : (NTH >= 1024 ? 2 : 4);
 }
 
+// Rows of more than 16 entries per thread keep g / eps in LDS, and above 18
+// they give up the register prefetch.
+template <int NTH, int EPT>
+constexpr bool row_gl() {
+  return EPT > 16;
+}
+template <int NTH, int EPT>
+constexpr bool row_pf() {
+  return EPT <= 18;
+}
+
 template <int NTH, int EPT>
 void launch_row(int nb, hipStream_t s, const double* C, int64_t ldC, int M, int N, int RB,
                 double cs, double inv_eps, const double* p, const double* logp,
                 const double* g, double* f, double* ms, double* pS, int* pX, int last) {
   constexpr int R = row_group<NTH, EPT>();
-  k_sk_row<NTH, EPT, R><<<nb, NTH, 0, s>>>(C, ldC, M, N, RB, cs, inv_eps, p, logp, g, f, ms, pS, pX, last);
+  k_sk_row<NTH, EPT, R, row_gl<NTH, EPT>(), row_pf<NTH, EPT>()><<<nb, NTH, 0, s>>>(C, ldC, M, N, RB, cs, inv_eps, p, logp, g, f, ms, pS, pX, last);
 }
 
 // ---------------------------------------------------------------------------
@@ -602,7 +635,7 @@ __global__ __launch_bounds__(NTH) void k_skb_row(const gwb::SkSlot* __restrict__
     const gwb::SkSlot& a = slots[code >> gwb::kBandBits];
     if (j >= a.its) continue;
     __syncthreads();
-    sk_row_band<NTH, EPT, row_group<NTH, EPT>()>(
+    sk_row_band<NTH, EPT, row_group<NTH, EPT>(), row_gl<NTH, EPT>(), row_pf<NTH, EPT>()>(
         a.C, a.ldC, a.M, a.N, a.RB, a.cs, a.inv_eps, a.p, a.logp, a.g, a.f, a.ms, a.pS, a.pX,
         a.last && j == a.its - 1, (int)(code & ((1u << gwb::kBandBits) - 1)));
   }
@@ -688,9 +721,13 @@ gw_status sk_batch_launch(int cls, int j, const gwb::SkSlot* slots, const gwb::S
     case gwb::kClsN512: k_skb_row<512, 1><<<kBatchBlocks512, 512, 0, s>>>(slots, head, items, cls, j); break;
     case gwb::kClsN1024: k_skb_row<1024, 1><<<kBatchBlocks1024, 1024, 0, s>>>(slots, head, items, cls, j); break;
     case gwb::kClsN2048: k_skb_row<1024, 2><<<kBatchBlocks1024, 1024, 0, s>>>(slots, head, items, cls, j); break;
+    case gwb::kClsN3072: k_skb_row<256, 12><<<kBatchBlocks256, 256, 0, s>>>(slots, head, items, cls, j); break;
     case gwb::kClsN4096: k_skb_rowg<<<kBatchBlocks1024, 1024, 0, s>>>(slots, head, items, cls, j); break;
+    case gwb::kClsN6144: k_skb_row<512, 12><<<kBatchBlocks512, 512, 0, s>>>(slots, head, items, cls, j); break;
     case gwb::kClsN8192: k_skb_row<512, 16><<<kBatchBlocks512, 512, 0, s>>>(slots, head, items, cls, j); break;
-    case gwb::kClsN16384: k_skb_row<1024, 16><<<kBatchBlocks1024, 1024, 0, s>>>(slots, head, items, cls, j); break;
+    case gwb::kClsN9216: k_skb_row<512, 18><<<kBatchBlocks512, 512, 0, s>>>(slots, head, items, cls, j); break;
+    case gwb::kClsN12288: k_skb_row<512, 24><<<kBatchBlocks512, 512, 0, s>>>(slots, head, items, cls, j); break;
+    case gwb::kClsN16384: k_skb_row<512, 32><<<kBatchBlocks512, 512, 0, s>>>(slots, head, items, cls, j); break;
     case gwb::kClsCol: k_skb_col<<<kBatchBlocks256, 256, 0, s>>>(slots, head, items, j); break;
     default: return GW_EINVAL;
   }
@@ -716,13 +753,20 @@ gw_status sinkhorn(const double* C, int64_t ldC, int64_t M, int64_t N, double c_
   for (int it = 0; it < iters; ++it) {
     {
       gwr::ProfScope ps(gwr::kFamSinkRow, s);
-      if (N <= 256) launch_row<256, 1>(nb, s, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, it == iters - 1);
-      else if (N <= 512) launch_row<512, 1>(nb, s, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, it == iters - 1);
-      else if (N <= 1024) launch_row<1024, 1>(nb, s, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, it == iters - 1);
-      else if (N <= 2048) launch_row<1024, 2>(nb, s, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, it == iters - 1);
-      else if (N <= 4096) k_sk_rowg<8, 2, true><<<nb, 1024, 0, s>>>(C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, g, f, ms, pS, pX, it == iters - 1);
-      else if (N <= 8192) launch_row<512, 16>(nb, s, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, it == iters - 1);
-      else launch_row<1024, 16>(nb, s, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, it == iters - 1);
+      const int lst = it == iters - 1;
+      switch (gwb::row_class(N)) {
+        case gwb::kClsN256: launch_row<256, 1>(nb, s, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, lst); break;
+        case gwb::kClsN512: launch_row<512, 1>(nb, s, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, lst); break;
+        case gwb::kClsN1024: launch_row<1024, 1>(nb, s, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, lst); break;
+        case gwb::kClsN2048: launch_row<1024, 2>(nb, s, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, lst); break;
+        case gwb::kClsN3072: launch_row<256, 12>(nb, s, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, lst); break;
+        case gwb::kClsN4096: k_sk_rowg<8, 2, true><<<nb, 1024, 0, s>>>(C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, g, f, ms, pS, pX, lst); break;
+        case gwb::kClsN6144: launch_row<512, 12>(nb, s, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, lst); break;
+        case gwb::kClsN8192: launch_row<512, 16>(nb, s, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, lst); break;
+        case gwb::kClsN9216: launch_row<512, 18>(nb, s, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, lst); break;
+        case gwb::kClsN12288: launch_row<512, 24>(nb, s, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, lst); break;
+        default: launch_row<512, 32>(nb, s, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, lst); break;
+      }
     }
     {
       gwr::ProfScope ps(gwr::kFamSinkCol, s);

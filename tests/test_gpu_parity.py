@@ -137,8 +137,13 @@ def test_grad_deterministic():
 
 # ------------------------------------------------------------------- Sinkhorn
 
+# one case per row-pass length class (N <= 256, 512, 1024, 2048, 3072, 4096,
+# 6144, 8192, 9216, 12288, 16384), bands of one and of several rows
 SK_CASES = [(1, 1, 0.1, 3), (37, 29, 0.05, 1), (100, 130, 0.01, 37), (300, 257, 1e-3, 20),
-            (64, 1000, 2e-3, 10), (513, 4100, 5e-3, 5)]
+            (64, 1000, 2e-3, 10), (70, 2000, 3e-3, 6), (600, 2500, 2e-3, 4),
+            (513, 4100, 5e-3, 5), (200, 4096, 1e-3, 4), (70, 5000, 3e-3, 5),
+            (33, 7000, 1e-3, 4), (600, 9216, 2e-3, 3), (40, 9000, 2e-3, 4),
+            (25, 12000, 5e-3, 3), (300, 12288, 1e-3, 3), (19, 16384, 1e-3, 3)]
 
 
 @pytest.mark.parametrize("M,N,eps,iters", SK_CASES)

@@ -79,6 +79,9 @@ CLASS_CASES = [
     ((5000,), (5000,), 1, 0, 4e-3, 2, 7, False, True),
     ((100, 100), (100, 100), 1, 0, 5e-3, 1, 4, False, False),
     ((257,), (12, 12), 2, 1, 2e-3, 3, 5, True, True),
+    ((2500,), (2500,), 1, 0, 3e-3, 1, 5, False, False),
+    ((96, 96), (96, 96), 2, 0, 4e-3, 1, 4, True, True),
+    ((128, 128), (128, 128), 1, 0, 6e-3, 1, 3, False, False),
 ]
 
 
