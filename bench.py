@@ -181,12 +181,12 @@ def precision_study(n: int = 16384, k: int = 2, rows: int = 6):
     return out
 
 
-def serve_bench(n_req: int = 200, n_sat: int = 64, slots: int = 32, iters: int = 10,
-                load: float = 0.8, arena_gb: float = 48.0, outer: int = 10, inner: int = 100):
+def serve_bench(n_req: int = 200, slots: int = 32, iters: int = 10, load: float = 0.8,
+                arena_gb: float = 48.0, outer: int = 10, inner: int = 100):
     """Request loop on the serving stream: 70% 1D n ~ U{128..8192}, 30% 2D
     s ~ U{16..96} (L1POW), k ~ U{1,2}, eps ~ U[1e-3,1e-2], mixture / blob
-    marginals, 10 outer x 100 Sinkhorn iterations each.  First `n_sat`
-    requests all at t = 0 give the saturated rate; then `n_req` requests with
+    marginals, 10 outer x 100 Sinkhorn iterations each.  The `n_req` requests
+    all submitted at t = 0 give the saturated rate; the same requests with
     Poisson arrivals at `load` x that rate give p50/p99 of completion minus
     arrival.  Completion times come from each request's HIP completion event."""
     import numpy as np
@@ -194,7 +194,7 @@ def serve_bench(n_req: int = 200, n_sat: int = 64, slots: int = 32, iters: int =
     from oracle import gw_oracle as O
     from paper_2404_08970_amd import gw, inputs
     dev = torch.device("cuda:0")
-    reqs = inputs.serving_requests(n_sat + n_req, seed=5)
+    reqs = inputs.serving_requests(n_req, seed=5)
     dreqs = []
     for r in reqs:
         X = gw.unit_grid(r["shape"], r["k"])
@@ -229,16 +229,16 @@ def serve_bench(n_req: int = 200, n_sat: int = 64, slots: int = 32, iters: int =
     # warm-up (not timed): one short solve of each request shape class in the stream
     run(dreqs[:24], [0.0] * 24, 1, iters)
     torch.cuda.synchronize()
-    _, fin_sat, steps_sat = run(dreqs[:n_sat], [0.0] * n_sat, outer, inner)
-    sat = n_sat / float(fin_sat.max())
+    lat_sat, fin_sat, steps_sat = run(dreqs, [0.0] * n_req, outer, inner)
+    sat = n_req / float(fin_sat.max())
     rate = load * sat
-    arr = np.array([r["arrival"] for r in reqs[n_sat:]])
+    arr = np.array([r["arrival"] for r in reqs])
     arr = (arr - arr[0]) / rate
-    lat, fin, steps = run(dreqs[n_sat:], arr.tolist(), outer, inner)
+    lat, fin, steps = run(dreqs, arr.tolist(), outer, inner)
 
     # accuracy: the smallest 1D request of the stream against the oracle (the
     # result of a request is the same in any mix, so it is solved alone here)
-    ones = [i for i in range(n_sat, len(reqs)) if len(reqs[i]["shape"]) == 1]
+    ones = [i for i in range(len(reqs)) if len(reqs[i]["shape"]) == 1]
     ic = min(ones, key=lambda i: reqs[i]["shape"][0])
     X, p, q, eps = dreqs[ic]
     rid = sv.submit(X, X, p, q, eps, outer, inner)
@@ -250,13 +250,13 @@ def serve_bench(n_req: int = 200, n_sat: int = 64, slots: int = 32, iters: int =
     og = O.Grid(reqs[ic]["shape"], X.h, X.k)
     T0 = O.solve(og, og, reqs[ic]["p"], reqs[ic]["q"], eps, outer, inner)[0]
     acc = float(np.max(np.abs(T - T0)) / np.max(np.abs(T0)))
-    n1 = sum(1 for r in reqs[n_sat:] if len(r["shape"]) == 1)
+    n1 = sum(1 for r in reqs if len(r["shape"]) == 1)
     return {
         "workload": (f"{n_req} requests, Poisson arrivals at {load}x the saturated rate; "
                      f"{n1} 1D n~U{{128..8192}}, {n_req - n1} 2D s~U{{16..96}} (L1POW); "
                      f"k~U{{1,2}}, eps~U[1e-3,1e-2]; {outer} outer x {inner} Sinkhorn iterations"),
         "saturated_solves_per_s": round(sat, 2),
-        "saturated_requests": n_sat,
+        "saturated_p50_ms": round(float(np.percentile(lat_sat, 50)) * 1e3, 1),
         "offered_rate_per_s": round(rate, 2),
         "solves_per_s": round(n_req / float(fin.max()), 2),
         "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 1),
@@ -285,7 +285,6 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the request-loop measurement")
     ap.add_argument("--serve-only", action="store_true", help="run only the request loop and exit")
     ap.add_argument("--serve-requests", type=int, default=200)
-    ap.add_argument("--serve-sat", type=int, default=64)
     ap.add_argument("--serve-slots", type=int, default=32)
     ap.add_argument("--serve-iters", type=int, default=10)
     args = ap.parse_args()
@@ -293,8 +292,7 @@ def main():
         print(json.dumps(precision_study()))
         return
     if args.serve_only:
-        print(json.dumps(serve_bench(args.serve_requests, args.serve_sat, args.serve_slots,
-                                     args.serve_iters)))
+        print(json.dumps(serve_bench(args.serve_requests, args.serve_slots, args.serve_iters)))
         return
     if args.profile_target:
         profile_target(args.profile_target, args.reps)
@@ -410,8 +408,7 @@ def main():
 
     serving = None
     if not args.no_serve:
-        serving = serve_bench(args.serve_requests, args.serve_sat, args.serve_slots,
-                              args.serve_iters)
+        serving = serve_bench(args.serve_requests, args.serve_slots, args.serve_iters)
 
     out = {
         "metric": METRIC,
