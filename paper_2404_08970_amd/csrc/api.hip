@@ -315,8 +315,7 @@ gw_status gw_solve(const gw_grid* Xp, const gw_grid* Yp, const double* p, const 
   double* c1 = a.take<double>(M);
   double* c2 = a.take<double>(N);
   const size_t mark = a.used;
-  if ((st = gwl::const_term(X, p, c1, s)) != GW_OK) return st;
-  if ((st = gwl::const_term(Y, q, c2, s)) != GW_OK) return st;
+  if ((st = gwl::const_terms(X, p, c1, Y, q, c2, s)) != GW_OK) return st;
   if ((st = gwl::outer_product(p, q, M, N, T, ldT, s)) != GW_OK) return st;
   if ((st = gwr::clear_status(status_of(ws), s)) != GW_OK) return st;
   for (int l = 0; l < outer; ++l) {

@@ -137,11 +137,8 @@ gw_status dense(const gwr::Grid& X, const gwr::Grid& Y, const double* p, const d
   const int M = (int)X.n(), N = (int)Y.n();
   double* c1 = ws.take<double>(M);
   double* c2 = ws.take<double>(N);
-  gw_status st;
-  if (c1_pre) c1 = const_cast<double*>(c1_pre);
-  else if ((st = const_term(X, p, c1, s)) != GW_OK) return st;
-  if (c2_pre) c2 = const_cast<double*>(c2_pre);
-  else if ((st = const_term(Y, q, c2, s)) != GW_OK) return st;
+  gw_status st = resolve_const_terms(X, p, c1_pre, &c1, Y, q, c2_pre, &c2, s);
+  if (st != GW_OK) return st;
   const double s2 = 2.0 * (X.hk() * Y.hk());
   if (path != GW_PATH_DENSE_F64) return dense_lp(X, Y, T, ldT, G, ldG, path, ws, s, c1, c2);
   double* A = ws.take<double>((size_t)M * N);

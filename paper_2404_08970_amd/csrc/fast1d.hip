@@ -204,38 +204,95 @@ __global__ __launch_bounds__(256) void k_p1_moments(const double* __restrict__ T
   }
 }
 
-// In-place exclusive scan of the moments of one line across its tiles.
-// base[(dir * ntiles + t) * (K+1) + r) * stride]; prefix from the left, suffix
-// from the right; the state is advanced over the width of the tile it passes.
-// Loads are issued PF tiles ahead of the recurrence.
-template <int K>
-__device__ void scan_line(double* base, size_t stride, int ntiles, int64_t extent) {
-  constexpr int PF = 8;
-  for (int dir = 0; dir < 2; ++dir) {
-    double* db = base + (size_t)dir * ntiles * (K + 1) * stride;
+// In-place exclusive scans of the moments of 64 lines across their tiles
+// (layout base[((dir * ntiles + tile) * (K+1) + r) * stride + line]): prefix
+// from the left (dir 0), suffix from the right (dir 1); the state is advanced
+// over the width of each tile it passes.  The tiles of a line are cut into
+// SCAN_CH chunks, one thread per (line, chunk): each thread folds its chunk
+// into an aggregate, the aggregates of the earlier chunks (shifted over the
+// chunks between) give the thread's incoming state, and a second pass over
+// the chunk writes the exclusive states.
+constexpr int SCAN_LINES = 64, SCAN_CH = 4;
+// With at least this many lines the scan runs one thread per line (one read
+// and one write of the moments); below it, SCAN_CH threads share a line.
+constexpr int64_t SCAN_ONE_THREAD_LINES = 16384;
+
+GW_DEV int tile_width(int tt, int64_t extent) {
+  const int64_t w = extent - (int64_t)tt * TS;
+  return w < TS ? (int)w : TS;
+}
+
+template <int K, int CH>
+GW_DEV void scan_lines(double* base, size_t stride, int line, bool valid, int ntiles,
+                       int64_t extent, double (*agg)[SCAN_CH][SCAN_LINES][K + 1],
+                       double (*span)[SCAN_CH], int ln, int ch) {
+  constexpr int PF = 8;  // tiles loaded ahead of the recurrence
+  const int cs = (ntiles + CH - 1) / CH;
+  const int s0 = ch * cs, s1 = min(ntiles, s0 + cs);
+  auto load = [&](const double* db, double (&buf)[PF][K + 1], int sb, int dir) {
+#pragma unroll
+    for (int u = 0; u < PF; ++u) {
+      const int sidx = sb + u;
+      const int tt = dir == 0 ? sidx : ntiles - 1 - sidx;
+#pragma unroll
+      for (int r = 0; r <= K; ++r)
+        buf[u][r] = (valid && sidx < s1) ? db[((size_t)tt * (K + 1) + r) * stride] : 0.0;
+    }
+  };
+  // pass 1: chunk aggregates and spans in both directions
+#pragma unroll
+  for (int dir = 0; dir < 2 && CH > 1; ++dir) {
+    const double* db = base + (size_t)dir * ntiles * (K + 1) * stride + line;
     double st[K + 1];
 #pragma unroll
     for (int r = 0; r <= K; ++r) st[r] = 0.0;
-    for (int s0 = 0; s0 < ntiles; s0 += PF) {
+    int width = 0;
+    for (int sb = s0; sb < s1; sb += PF) {
       double buf[PF][K + 1];
+      load(db, buf, sb, dir);
 #pragma unroll
       for (int u = 0; u < PF; ++u) {
-        const int s = s0 + u;
-        const int tt = dir == 0 ? s : ntiles - 1 - s;
-        if (s < ntiles) {
+        const int sidx = sb + u;
+        if (sidx < s1) {
+          const int tt = dir == 0 ? sidx : ntiles - 1 - sidx;
+          const int wd = tile_width(tt, extent);
+          gwk::pascal_shift<K>(st, (double)wd);
 #pragma unroll
-          for (int r = 0; r <= K; ++r) buf[u][r] = db[((size_t)tt * (K + 1) + r) * stride];
+          for (int r = 0; r <= K; ++r) st[r] += buf[u][r];
+          width += wd;
         }
       }
+    }
+#pragma unroll
+    for (int r = 0; r <= K; ++r) agg[dir][ch][ln][r] = st[r];
+    if (ln == 0) span[dir][ch] = (double)width;
+  }
+  if (CH > 1) __syncthreads();
+  // pass 2: incoming state from the earlier chunks, then exclusive states
+#pragma unroll
+  for (int dir = 0; dir < 2; ++dir) {
+    double* db = base + (size_t)dir * ntiles * (K + 1) * stride + line;
+    double st[K + 1];
+#pragma unroll
+    for (int r = 0; r <= K; ++r) st[r] = 0.0;
+    for (int c = 0; c < ch; ++c) {
+      gwk::pascal_shift<K>(st, span[dir][c]);
+#pragma unroll
+      for (int r = 0; r <= K; ++r) st[r] += agg[dir][c][ln][r];
+    }
+    for (int sb = s0; sb < s1; sb += PF) {
+      double buf[PF][K + 1];
+      load(db, buf, sb, dir);
 #pragma unroll
       for (int u = 0; u < PF; ++u) {
-        const int s = s0 + u;
-        if (s < ntiles) {
-          const int tt = dir == 0 ? s : ntiles - 1 - s;
+        const int sidx = sb + u;
+        if (sidx < s1) {
+          const int tt = dir == 0 ? sidx : ntiles - 1 - sidx;
+          if (valid) {
 #pragma unroll
-          for (int r = 0; r <= K; ++r) db[((size_t)tt * (K + 1) + r) * stride] = st[r];
-          const double wd = (double)min<int64_t>(TS, extent - (int64_t)tt * TS);
-          gwk::pascal_shift<K>(st, wd);
+            for (int r = 0; r <= K; ++r) db[((size_t)tt * (K + 1) + r) * stride] = st[r];
+          }
+          gwk::pascal_shift<K>(st, (double)tile_width(tt, extent));
 #pragma unroll
           for (int r = 0; r <= K; ++r) st[r] += buf[u][r];
         }
@@ -245,125 +302,223 @@ __device__ void scan_line(double* base, size_t stride, int ntiles, int64_t exten
 }
 
 // ------------------------------------------- P2a/b: row and column carries of T
-template <int KX, int KY>
-__global__ __launch_bounds__(256) void k_p2_scan(int M, int N, int nI, int nJ,
-                                                  double* __restrict__ rowmom,
-                                                  double* __restrict__ colmom) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx < M) {
-    scan_line<KY>(rowmom + idx, (size_t)M, nJ, N);
-  } else if (idx < (int64_t)M + N) {
-    scan_line<KX>(colmom + (idx - M), (size_t)N, nI, M);
+// Blocks [0, ceil(M/64)) scan the row moments of 64 rows each, the rest the
+// column moments of 64 columns each.
+template <int KX, int KY, int CH>
+__global__ __launch_bounds__(SCAN_LINES * CH) void k_p2_scan(int M, int N, int nI, int nJ,
+                                                              double* __restrict__ rowmom,
+                                                              double* __restrict__ colmom) {
+  constexpr int KM = (KX > KY ? KX : KY) + 1;
+  __shared__ double agg[2][SCAN_CH][SCAN_LINES][KM];
+  __shared__ double span[2][SCAN_CH];
+  const int ln = threadIdx.x & (SCAN_LINES - 1), ch = threadIdx.x / SCAN_LINES;
+  const int rblocks = (M + SCAN_LINES - 1) / SCAN_LINES;
+  if ((int)blockIdx.x < rblocks) {
+    const int line = blockIdx.x * SCAN_LINES + ln;
+    scan_lines<KY, CH>(rowmom, (size_t)M, min(line, M - 1), line < M, nJ, N,
+                       reinterpret_cast<double (*)[SCAN_CH][SCAN_LINES][KY + 1]>(&agg[0][0][0][0]),
+                       span, ln, ch);
+  } else {
+    const int line = (blockIdx.x - rblocks) * SCAN_LINES + ln;
+    scan_lines<KX, CH>(colmom, (size_t)N, min(line, N - 1), line < N, nI, M,
+                       reinterpret_cast<double (*)[SCAN_CH][SCAN_LINES][KX + 1]>(&agg[0][0][0][0]),
+                       span, ln, ch);
   }
 }
 
 // ------------- P2c: column carries of A = T D~_Y, one block per vector.
 // A's column carries at the top (bottom) of tile-row I are D~_Y applied to the
-// column carries of T, vectors of length N (Cpre/Csuf, one per moment order).
-// Pass A sums each tile of the vector (4 threads x 16-entry segments per
-// tile), two threads scan the tile moments, pass B sweeps every tile with its
-// carries and writes the full vector to acarry (same layout as colmom).
-template <int KX, int KY>
+// column carries of T, vectors of length N (one per direction, tile-row and
+// moment order), zero-padded to nJ full tiles.  The vector is processed in
+// rounds of 64 tiles (4096 entries) staged through LDS with coalesced loads
+// and stores; thread (tile tl, segment seg) works on 16 entries.
+//   pass A  segment summaries -> tile moments (prefix at the tile end, suffix
+//           at its start - 1);
+//   scan    exclusive scans of the tile moments over the tiles: each thread
+//           folds a run of consecutive tiles, an inclusive Hillis-Steele scan
+//           combines the runs (shift over the span between them), and each
+//           thread writes the exclusive states of its run;
+//   pass B  each segment is swept with its tile's carries advanced over the
+//           segments before (after) it, and the output leaves through LDS.
+constexpr int P2C_TILES = 64;                       // tiles per round
+constexpr int P2C_ROUND = P2C_TILES * TS;           // entries per round
+constexpr int P2C_STG = P2C_ROUND + P2C_ROUND / SEG;  // one pad double per segment
+
+GW_DEV int stg_index(int i) { return i + (i >> 4); }
+
+// KEEP: rounds whose entries stay in registers between the passes (the
+// vector is then read once); 0 re-reads it in pass B.
+template <int KX, int KY, int KEEP>
 __global__ __launch_bounds__(256) void k_p2c(int N, int nJ, const double* __restrict__ colmom,
                                               double* __restrict__ acarry) {
-  constexpr int KM = KY + 1;
-  extern __shared__ double mom[];  // [nJ][2][KY+1]
-  __shared__ double part[NSEG][TS][2 * KM];
+  constexpr int K = KY, KM = KY + 1;
+  extern __shared__ double mom[];  // [2][nJ][KM]: tile moments, then exclusive carries
+  __shared__ double stg[P2C_STG];
+  __shared__ double part[NSEG][P2C_TILES][2 * KM];
   const int v = blockIdx.x;
   const double* vec = colmom + (size_t)v * N;
   double* out = acarry + (size_t)v * N;
   const int t = threadIdx.x, tl = t >> 2, seg = t & 3;
-  auto load = [&](double (&x)[SEG], int J) {
+  const int nround = (nJ + P2C_TILES - 1) / P2C_TILES;
+  const int sb = tl * TS + seg * SEG;  // segment start within a round
+  auto stage_in = [&](int e0) {
 #pragma unroll
-    for (int c = 0; c < SEG; ++c) {
-      const int p = J * TS + seg * SEG + c;
-      x[c] = (J < nJ && p < N) ? vec[p] : 0.0;
+    for (int c = 0; c < P2C_ROUND / 256; ++c) {
+      const int i = t + 256 * c;
+      const int p = e0 + i;
+      stg[stg_index(i)] = p < N ? vec[p] : 0.0;
     }
   };
+  auto summaries = [&](double (&x)[SEG]) {
+#pragma unroll
+    for (int c = 0; c < SEG; ++c) x[c] = stg[stg_index(sb + c)];
+    double pre[K + 1], suf[K + 1];
+    seg_summaries<K>(x, pre, suf);
+#pragma unroll
+    for (int r = 0; r <= K; ++r) {
+      part[seg][tl][r] = pre[r];
+      part[seg][tl][KM + r] = suf[r];
+    }
+  };
+  double keep[KEEP > 0 ? KEEP : 1][SEG];
   // pass A: tile moments
-  for (int J0 = 0; J0 < nJ; J0 += TS) {
-    const int J = J0 + tl;
+  for (int rd = 0; rd < nround; ++rd) {
+    __syncthreads();
+    stage_in(rd * P2C_ROUND);
+    __syncthreads();
     double x[SEG];
-    load(x, J);
-    double pre[KY + 1], suf[KY + 1];
-    seg_summaries<KY>(x, pre, suf);
+    summaries(x);
+    if constexpr (KEEP > 0) {
 #pragma unroll
-    for (int r = 0; r <= KY; ++r) {
-      part[seg][tl][r] = pre[r];
-      part[seg][tl][KM + r] = suf[r];
+      for (int k = 0; k < KEEP; ++k)
+        if (k == rd) {
+#pragma unroll
+          for (int c = 0; c < SEG; ++c) keep[k][c] = x[c];
+        }
     }
     __syncthreads();
+    const int J = rd * P2C_TILES + tl;
     if (seg == 0 && J < nJ) {
-      double a[KY + 1], b[KY + 1];
-      combine_segments<KY, KM, TS>(part, tl, a, b);
+      double a[K + 1], b[K + 1];
+      combine_segments<K, KM, P2C_TILES>(part, tl, a, b);
 #pragma unroll
-      for (int r = 0; r <= KY; ++r) {
-        mom[(J * 2 + 0) * KM + r] = a[r];
-        mom[(J * 2 + 1) * KM + r] = b[r];
+      for (int r = 0; r <= K; ++r) {
+        mom[(0 * nJ + J) * KM + r] = a[r];
+        mom[(1 * nJ + J) * KM + r] = b[r];
       }
+    }
+  }
+  // scans over the tiles; the Hillis-Steele buffers live in the staging area
+  const int run = (nJ + 255) / 256;  // tiles per thread
+  double* hs = stg;                  // [2 buffers][256][KM]
+#pragma unroll
+  for (int dir = 0; dir < 2; ++dir) {
+    __syncthreads();
+    double agg[K + 1];
+#pragma unroll
+    for (int r = 0; r <= K; ++r) agg[r] = 0.0;
+    for (int u = 0; u < run; ++u) {
+      const int pos = t * run + u;
+      if (pos < nJ) {
+        const int J = dir == 0 ? pos : nJ - 1 - pos;
+        gwk::pascal_shift<K>(agg, (double)TS);
+#pragma unroll
+        for (int r = 0; r <= K; ++r) agg[r] += mom[(dir * nJ + J) * KM + r];
+      }
+    }
+    int cur = 0;
+#pragma unroll
+    for (int r = 0; r <= K; ++r) hs[(cur * 256 + t) * KM + r] = agg[r];
+    for (int d = 1; d < 256; d <<= 1) {
+      __syncthreads();
+      if (t >= d) {
+        double o[K + 1];
+#pragma unroll
+        for (int r = 0; r <= K; ++r) o[r] = hs[(cur * 256 + t - d) * KM + r];
+        gwk::pascal_shift<K>(o, (double)TS * run * d);
+#pragma unroll
+        for (int r = 0; r <= K; ++r) agg[r] += o[r];
+      }
+      cur ^= 1;
+#pragma unroll
+      for (int r = 0; r <= K; ++r) hs[(cur * 256 + t) * KM + r] = agg[r];
     }
     __syncthreads();
-  }
-  // exclusive scans over the tiles: prefix (state at each tile's first entry)
-  // and suffix (state at each tile's last entry), in place
-  if (t < 2) {
-    const int dir = t;
-    double st[KY + 1];
+    double st[K + 1];
 #pragma unroll
-    for (int r = 0; r <= KY; ++r) st[r] = 0.0;
-    for (int s = 0; s < nJ; ++s) {
-      const int J = dir == 0 ? s : nJ - 1 - s;
-      double tmp[KY + 1];
+    for (int r = 0; r <= K; ++r) st[r] = t > 0 ? hs[(cur * 256 + t - 1) * KM + r] : 0.0;
+    for (int u = 0; u < run; ++u) {
+      const int pos = t * run + u;
+      if (pos < nJ) {
+        const int J = dir == 0 ? pos : nJ - 1 - pos;
+        double m[K + 1];
 #pragma unroll
-      for (int r = 0; r <= KY; ++r) {
-        tmp[r] = mom[(J * 2 + dir) * KM + r];
-        mom[(J * 2 + dir) * KM + r] = st[r];
+        for (int r = 0; r <= K; ++r) {
+          m[r] = mom[(dir * nJ + J) * KM + r];
+          mom[(dir * nJ + J) * KM + r] = st[r];
+        }
+        gwk::pascal_shift<K>(st, (double)TS);
+#pragma unroll
+        for (int r = 0; r <= K; ++r) st[r] += m[r];
       }
-      gwk::pascal_shift<KY>(st, (double)TS);
-#pragma unroll
-      for (int r = 0; r <= KY; ++r) st[r] += tmp[r];
     }
   }
-  __syncthreads();
   // pass B: in-tile sweeps with the tile carries
-  for (int J0 = 0; J0 < nJ; J0 += TS) {
-    const int J = J0 + tl;
+  for (int rd = 0; rd < nround; ++rd) {
+    const int e0 = rd * P2C_ROUND;
     double x[SEG];
-    load(x, J);
-    double pre[KY + 1], suf[KY + 1];
-    seg_summaries<KY>(x, pre, suf);
+    __syncthreads();
+    if constexpr (KEEP > 0) {
 #pragma unroll
-    for (int r = 0; r <= KY; ++r) {
-      part[seg][tl][r] = pre[r];
-      part[seg][tl][KM + r] = suf[r];
+      for (int k = 0; k < KEEP; ++k)
+        if (k == rd) {
+#pragma unroll
+          for (int c = 0; c < SEG; ++c) x[c] = keep[k][c];
+        }
+      double pre[K + 1], suf[K + 1];
+      seg_summaries<K>(x, pre, suf);
+#pragma unroll
+      for (int r = 0; r <= K; ++r) {
+        part[seg][tl][r] = pre[r];
+        part[seg][tl][KM + r] = suf[r];
+      }
+    } else {
+      stage_in(e0);
+      __syncthreads();
+      summaries(x);
     }
     __syncthreads();
+    const int J = rd * P2C_TILES + tl;
     if (J < nJ) {
-      double a[KY + 1], b[KY + 1];
+      double a[K + 1], b[K + 1];
 #pragma unroll
-      for (int r = 0; r <= KY; ++r) {
-        a[r] = mom[(J * 2 + 0) * KM + r];
-        b[r] = mom[(J * 2 + 1) * KM + r];
+      for (int r = 0; r <= K; ++r) {
+        a[r] = mom[(0 * nJ + J) * KM + r];
+        b[r] = mom[(1 * nJ + J) * KM + r];
       }
       for (int sg = 0; sg < seg; ++sg) {
-        gwk::pascal_shift<KY>(a, (double)SEG);
+        gwk::pascal_shift<K>(a, (double)SEG);
 #pragma unroll
-        for (int r = 0; r <= KY; ++r) a[r] += part[sg][tl][r];
+        for (int r = 0; r <= K; ++r) a[r] += part[sg][tl][r];
       }
       for (int sg = NSEG - 1; sg > seg; --sg) {
-        gwk::pascal_shift<KY>(b, (double)SEG);
+        gwk::pascal_shift<K>(b, (double)SEG);
 #pragma unroll
-        for (int r = 0; r <= KY; ++r) b[r] += part[sg][tl][KM + r];
+        for (int r = 0; r <= K; ++r) b[r] += part[sg][tl][KM + r];
       }
       double o[SEG];
-      seg_sweep<KY>(x, a, b, o);
+      seg_sweep<K>(x, a, b, o);
+      // each thread rewrites only its own segment of the staging area
 #pragma unroll
-      for (int c = 0; c < SEG; ++c) {
-        const int p = J * TS + seg * SEG + c;
-        if (p < N) out[p] = o[c];
-      }
+      for (int c = 0; c < SEG; ++c) stg[stg_index(sb + c)] = o[c];
     }
     __syncthreads();
+#pragma unroll
+    for (int c = 0; c < P2C_ROUND / 256; ++c) {
+      const int i = t + 256 * c;
+      const int p = e0 + i;
+      if (p < N) out[p] = stg[stg_index(i)];
+    }
   }
 }
 
@@ -516,11 +671,25 @@ gw_status run_fast1d(const Layout& L, const double* T, int64_t ldT, double* G, i
   {
     gwr::ProfScope ps(gwr::kFamFastCarry, s);
     k_p1_moments<KX, KY><<<persistent_blocks(ntiles, 2), 256, 0, s>>>(T, ldT, M, N, L.nI, L.nJ, rowmom, colmom);
-    const int64_t lines = (int64_t)M + N;
-    k_p2_scan<KX, KY><<<(unsigned)((lines + 255) / 256), 256, 0, s>>>(M, N, L.nI, L.nJ, rowmom, colmom);
+    const unsigned sblocks = (unsigned)((M + SCAN_LINES - 1) / SCAN_LINES + (N + SCAN_LINES - 1) / SCAN_LINES);
+    if ((int64_t)M + N >= SCAN_ONE_THREAD_LINES)
+      k_p2_scan<KX, KY, 1><<<sblocks, SCAN_LINES, 0, s>>>(M, N, L.nI, L.nJ, rowmom, colmom);
+    else
+      k_p2_scan<KX, KY, SCAN_CH><<<sblocks, SCAN_LINES * SCAN_CH, 0, s>>>(M, N, L.nI, L.nJ, rowmom, colmom);
     const int nvec = 2 * L.nI * (KX + 1);
     const size_t shm = (size_t)L.nJ * 2 * (KY + 1) * sizeof(double);
-    k_p2c<KX, KY><<<nvec, 256, shm, s>>>(N, L.nJ, colmom, acarry);
+    if (L.nJ <= 4 * P2C_TILES) {
+      k_p2c<KX, KY, 4><<<nvec, 256, shm, s>>>(N, L.nJ, colmom, acarry);
+    } else {
+      static size_t shm_set = 0;  // dynamic LDS above the default limit, set once per size
+      if (shm > shm_set) {
+        if (hipFuncSetAttribute(reinterpret_cast<const void*>(&k_p2c<KX, KY, 0>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm) != hipSuccess)
+          return GW_EDEVICE;
+        shm_set = shm;
+      }
+      k_p2c<KX, KY, 0><<<nvec, 256, shm, s>>>(N, L.nJ, colmom, acarry);
+    }
   }
   {
     gwr::ProfScope ps(gwr::kFamFastMain, s);
@@ -567,17 +736,8 @@ gw_status fast1d(const gwr::Grid& X, const gwr::Grid& Y, const double* p, const 
   double* am = ws.take<double>(L.acarry);
   double* c1 = ws.take<double>(X.n());
   double* c2 = ws.take<double>(Y.n());
-  gw_status st;
-  if (c1_pre) {
-    c1 = const_cast<double*>(c1_pre);
-  } else if ((st = const_term(X, p, c1, s)) != GW_OK) {
-    return st;
-  }
-  if (c2_pre) {
-    c2 = const_cast<double*>(c2_pre);
-  } else if ((st = const_term(Y, q, c2, s)) != GW_OK) {
-    return st;
-  }
+  gw_status st = resolve_const_terms(X, p, c1_pre, &c1, Y, q, c2_pre, &c2, s);
+  if (st != GW_OK) return st;
   const double s2 = 2.0 * (X.hk() * Y.hk());
   switch (L.kx) {
     case 1: return dispatch_ky<1>(L.ky, L, T, ldT, G, ldG, c1, c2, s2, rm, cm, am, s);

@@ -73,24 +73,40 @@ __global__ __launch_bounds__(1024) void k_const_term(int metric, int k, int H, i
   }
 }
 
-// 1D grids: c = hk^2 [|i-j|^{2k}] w by the recursion with exponent K2 = 2k on a
-// single vector (one block).  Thread t owns entries [16 t, 16 t + 16); segment
-// summaries are combined by an inclusive Hillis-Steele scan in LDS (shift by
-// the window span, all weights non-negative), then each thread sweeps its
-// segment with the carries.  n <= 16384.
-constexpr int C1_THREADS = 1024, C1_SEG = 16;
+// 1D grids: c = hk^2 [|i-j|^{2k}] w by the recursion with exponent K2 = 2k,
+// one block per vector (up to two vectors per launch: blockIdx.x selects the
+// job).  Thread t owns entries [16 t, 16 t + 16).  Segment summaries (prefix
+// state at the segment end, suffix state at its start - 1) are scanned along
+// the block in each direction: a shuffle scan inside each wave, then every
+// thread folds the totals of the waves before it, always shifting a state over
+// the span it crosses (all weights non-negative).  Each thread then sweeps its
+// segment with its carries.  n <= 16 NT.
+constexpr int C1_SEG = 16;
+
+struct ConstJob {
+  int n;
+  double hk2;
+  const double* w;
+  double* c;
+};
 
 template <int K2>
-__global__ __launch_bounds__(C1_THREADS) void k_const_1d(int n, double hk2,
-                                                          const double* __restrict__ w,
-                                                          double* __restrict__ c) {
-  __shared__ double buf[C1_THREADS][K2 + 1];
-  const int t = threadIdx.x;
+GW_DEV void shfl_state(const double (&v)[K2 + 1], double (&o)[K2 + 1], int src) {
+#pragma unroll
+  for (int r = 0; r <= K2; ++r) o[r] = __shfl(v[r], src, 64);
+}
+
+template <int K2, int NT>
+__global__ __launch_bounds__(NT) void k_const_1d(ConstJob j0, ConstJob j1) {
+  constexpr int NW = NT / 64;
+  __shared__ double wtot[2][NW][K2 + 1];
+  const ConstJob jb = blockIdx.x == 0 ? j0 : j1;
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   double x[C1_SEG];
 #pragma unroll
   for (int e = 0; e < C1_SEG; ++e) {
     const int i = t * C1_SEG + e;
-    x[e] = i < n ? w[i] : 0.0;
+    x[e] = i < jb.n ? jb.w[i] : 0.0;
   }
   double pre[K2 + 1], suf[K2 + 1];
 #pragma unroll
@@ -106,36 +122,57 @@ __global__ __launch_bounds__(C1_THREADS) void k_const_1d(int n, double hk2,
       ws *= (double)(e + 1);
     }
   }
-  // inclusive scans: prefix from the left, then suffix from the right
-  double a[K2 + 1], b[K2 + 1];
+  // inclusive scans in scan order: dir 0 left to right, dir 1 right to left
+  double inc[2][K2 + 1];
+#pragma unroll
   for (int dir = 0; dir < 2; ++dir) {
+    const int pos = dir == 0 ? lane : 63 - lane;  // position in the wave, scan order
     double v[K2 + 1];
 #pragma unroll
     for (int r = 0; r <= K2; ++r) v[r] = dir == 0 ? pre[r] : suf[r];
-    const int me = dir == 0 ? t : C1_THREADS - 1 - t;  // position along the scan
-    for (int d = 1; d < C1_THREADS; d <<= 1) {
-      __syncthreads();
 #pragma unroll
-      for (int r = 0; r <= K2; ++r) buf[me][r] = v[r];
-      __syncthreads();
-      if (me >= d) {
-        double o[K2 + 1];
-#pragma unroll
-        for (int r = 0; r <= K2; ++r) o[r] = buf[me - d][r];
+    for (int d = 1; d < 64; d <<= 1) {
+      double o[K2 + 1];
+      shfl_state<K2>(v, o, dir == 0 ? lane - d : lane + d);
+      if (pos >= d) {
         gwk::pascal_shift<K2>(o, (double)(C1_SEG * d));
 #pragma unroll
         for (int r = 0; r <= K2; ++r) v[r] += o[r];
       }
     }
-    __syncthreads();
+    const int wpos = dir == 0 ? wv : NW - 1 - wv;  // wave position, scan order
+    if (pos == 63) {
 #pragma unroll
-    for (int r = 0; r <= K2; ++r) buf[me][r] = v[r];
-    __syncthreads();
-    // exclusive: the inclusive value of the previous segment along the scan
+      for (int r = 0; r <= K2; ++r) wtot[dir][wpos][r] = v[r];
+    }
+#pragma unroll
+    for (int r = 0; r <= K2; ++r) inc[dir][r] = v[r];
+  }
+  __syncthreads();
+  double a[K2 + 1], b[K2 + 1];
+#pragma unroll
+  for (int dir = 0; dir < 2; ++dir) {
+    const int pos = dir == 0 ? lane : 63 - lane;
+    const int wpos = dir == 0 ? wv : NW - 1 - wv;
+    // state at the end of the previous waves (scan order)
+    double acc[K2 + 1];
+#pragma unroll
+    for (int r = 0; r <= K2; ++r) acc[r] = 0.0;
+    for (int w2 = 0; w2 < wpos; ++w2) {
+      gwk::pascal_shift<K2>(acc, (double)(64 * C1_SEG));
+#pragma unroll
+      for (int r = 0; r <= K2; ++r) acc[r] += wtot[dir][w2][r];
+    }
+    // exclusive state of this thread: the inclusive value of the previous
+    // position in the wave, plus the earlier waves shifted up to this segment
+    double ex[K2 + 1];
+    shfl_state<K2>(inc[dir], ex, dir == 0 ? lane - 1 : lane + 1);
+    gwk::pascal_shift<K2>(acc, (double)(C1_SEG * pos));
 #pragma unroll
     for (int r = 0; r <= K2; ++r) {
-      const double e = me > 0 ? buf[me - 1][r] : 0.0;
-      if (dir == 0) a[r] = e; else b[r] = e;
+      const double e = pos > 0 ? ex[r] : 0.0;
+      if (dir == 0) a[r] = e + acc[r];
+      else b[r] = e + acc[r];
     }
   }
   double out[C1_SEG];
@@ -152,8 +189,14 @@ __global__ __launch_bounds__(C1_THREADS) void k_const_1d(int n, double hk2,
 #pragma unroll
   for (int e = 0; e < C1_SEG; ++e) {
     const int i = t * C1_SEG + e;
-    if (i < n) c[i] = hk2 * out[e];
+    if (i < jb.n) jb.c[i] = jb.hk2 * out[e];
   }
+}
+
+template <int K2>
+void launch_const_1d(int nblocks, int nmax, ConstJob j0, ConstJob j1, hipStream_t s) {
+  if (nmax <= 256 * C1_SEG) k_const_1d<K2, 256><<<nblocks, 256, 0, s>>>(j0, j1);
+  else k_const_1d<K2, 1024><<<nblocks, 1024, 0, s>>>(j0, j1);
 }
 
 // ---------------------------------------------------------------- transpose
@@ -393,6 +436,27 @@ bool separable(const gwr::Grid& g, SepGrid* s) {
 
 unsigned blocks_for(int64_t n) { return (unsigned)((n + NT - 1) / NT); }
 
+// One launch for up to two 1D vectors of the same exponent (job 1 may be
+// empty: nblocks = 1).
+bool const_1d_ok(const gwr::Grid& g) { return g.ndim == 1 && g.n() <= (int64_t)1024 * C1_SEG; }
+
+gw_status launch_const_jobs(int k1d, int nblocks, int nmax, ConstJob j0, ConstJob j1,
+                            hipStream_t s) {
+  switch (k1d) {
+    case 1: launch_const_1d<2>(nblocks, nmax, j0, j1, s); break;
+    case 2: launch_const_1d<4>(nblocks, nmax, j0, j1, s); break;
+    case 3: launch_const_1d<6>(nblocks, nmax, j0, j1, s); break;
+    case 4: launch_const_1d<8>(nblocks, nmax, j0, j1, s); break;
+    default: return GW_EUNSUPPORTED;
+  }
+  return gwr::last_launch_status();
+}
+
+ConstJob job_of(const gwr::Grid& g, const double* w, double* c) {
+  const double hk = g.hk();
+  return ConstJob{(int)g.n(), hk * hk, w, c};
+}
+
 }  // namespace
 
 namespace gwl {
@@ -400,20 +464,36 @@ namespace gwl {
 gw_status const_term(const gwr::Grid& g, const double* w, double* c, hipStream_t s) {
   gwr::ProfScope ps(gwr::kFamOther, s);
   const int64_t n = g.n();
-  if (g.ndim == 1 && n <= (int64_t)C1_THREADS * C1_SEG) {
-    const double hk = g.hk();
-    const double hk2 = hk * hk;
-    switch (g.k1d()) {
-      case 1: k_const_1d<2><<<1, C1_THREADS, 0, s>>>((int)n, hk2, w, c); break;
-      case 2: k_const_1d<4><<<1, C1_THREADS, 0, s>>>((int)n, hk2, w, c); break;
-      case 3: k_const_1d<6><<<1, C1_THREADS, 0, s>>>((int)n, hk2, w, c); break;
-      case 4: k_const_1d<8><<<1, C1_THREADS, 0, s>>>((int)n, hk2, w, c); break;
-      default: return GW_EUNSUPPORTED;
-    }
-    return gwr::last_launch_status();
+  if (const_1d_ok(g)) {
+    const ConstJob j = job_of(g, w, c);
+    return launch_const_jobs(g.k1d(), 1, (int)n, j, j, s);
   }
   k_const_term<<<(unsigned)((n + 63) / 64), 1024, 0, s>>>(g.metric, g.k, (int)g.H, (int)g.W, g.hk(), w, c);
   return gwr::last_launch_status();
+}
+
+gw_status const_terms(const gwr::Grid& X, const double* p, double* c1, const gwr::Grid& Y,
+                      const double* q, double* c2, hipStream_t s) {
+  if (const_1d_ok(X) && const_1d_ok(Y) && X.k1d() == Y.k1d()) {
+    gwr::ProfScope ps(gwr::kFamOther, s);
+    const int nmax = (int)(X.n() > Y.n() ? X.n() : Y.n());
+    return launch_const_jobs(X.k1d(), 2, nmax, job_of(X, p, c1), job_of(Y, q, c2), s);
+  }
+  gw_status st = const_term(X, p, c1, s);
+  return st != GW_OK ? st : const_term(Y, q, c2, s);
+}
+
+gw_status resolve_const_terms(const gwr::Grid& X, const double* p, const double* c1_pre,
+                              double** c1, const gwr::Grid& Y, const double* q,
+                              const double* c2_pre, double** c2, hipStream_t s) {
+  if (!c1_pre && !c2_pre) return const_terms(X, p, *c1, Y, q, *c2, s);
+  gw_status st = GW_OK;
+  if (c1_pre) *c1 = const_cast<double*>(c1_pre);
+  else st = const_term(X, p, *c1, s);
+  if (st != GW_OK) return st;
+  if (c2_pre) *c2 = const_cast<double*>(c2_pre);
+  else st = const_term(Y, q, *c2, s);
+  return st;
 }
 
 size_t fast_generic_ws_bytes(const gwr::Grid& X, const gwr::Grid& Y) {
@@ -465,11 +545,8 @@ gw_status fast_generic(const gwr::Grid& X, const gwr::Grid& Y, const double* p,
   }
   double* c1 = ws.take<double>(M);
   double* c2 = ws.take<double>(N);
-  gw_status st;
-  if (c1_pre) c1 = const_cast<double*>(c1_pre);
-  else if ((st = const_term(X, p, c1, s)) != GW_OK) return st;
-  if (c2_pre) c2 = const_cast<double*>(c2_pre);
-  else if ((st = const_term(Y, q, c2, s)) != GW_OK) return st;
+  gw_status st = resolve_const_terms(X, p, c1_pre, &c1, Y, q, c2_pre, &c2, s);
+  if (st != GW_OK) return st;
   const double s2 = 2.0 * (X.hk() * Y.hk());
   gwr::ProfScope ps(gwr::kFam2D, s);
   if (sep) {

@@ -100,8 +100,17 @@ gw_status run_objective(const Grid& X, const Grid& Y, const double* T, int64_t l
 
 // Launchers implemented in the kernel translation units.
 namespace gwl {
-// c[i] = hk^2 * sum_j d(i,j)^2 w[j] for grid g (direct evaluation).
+// c[i] = hk^2 * sum_j d(i,j)^2 w[j] for grid g (recursion in 1D, direct in 2D).
 gw_status const_term(const gwr::Grid& g, const double* w, double* c, hipStream_t s);
+// c1 for (X, p) and c2 for (Y, q), in one launch when both are 1D with the same
+// exponent.
+gw_status const_terms(const gwr::Grid& X, const double* p, double* c1, const gwr::Grid& Y,
+                      const double* q, double* c2, hipStream_t s);
+// Use the precomputed constant terms where given (c1_pre, c2_pre may be null),
+// else compute them into *c1, *c2 (workspace).
+gw_status resolve_const_terms(const gwr::Grid& X, const double* p, const double* c1_pre,
+                              double** c1, const gwr::Grid& Y, const double* q,
+                              const double* c2_pre, double** c2, hipStream_t s);
 // FAST 1D x 1D gradient (tiled recursion).  ws: arena for its scratch.
 gw_status fast1d(const gwr::Grid& X, const gwr::Grid& Y, const double* p, const double* q,
                  const double* T, int64_t ldT, double* G, int64_t ldG, gwr::Arena& ws,

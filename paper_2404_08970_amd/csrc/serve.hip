@@ -233,8 +233,7 @@ gw_status admit(gw_server* sv, Req& q) {
   if ((st = hip_ok(hipEventCreate(&q.done))) != GW_OK) return st;
   if ((st = take_record(sv, &q.rec)) != GW_OK) return st;
   if ((st = gwr::clear_status(q.st, s)) != GW_OK) return st;
-  if ((st = gwl::const_term(q.X, q.r.p, q.c1, s)) != GW_OK) return st;
-  if ((st = gwl::const_term(q.Y, q.r.q, q.c2, s)) != GW_OK) return st;
+  if ((st = gwl::const_terms(q.X, q.r.p, q.c1, q.Y, q.r.q, q.c2, s)) != GW_OK) return st;
   if ((st = gwl::outer_product(q.r.p, q.r.q, q.M, q.N, q.T, q.N, s)) != GW_OK) return st;
   if (q.r.outer == 0) return complete(sv, q);
   q.phase = kGrad;
