@@ -134,8 +134,9 @@ __global__ __launch_bounds__(256) void k_p1_moments(const double* __restrict__ T
   __shared__ double part[2][NSEG][TS][2 * KM];
   const int t = threadIdx.x, lane = t & (TS - 1), seg = t >> 6;
   const int ntiles = nI * nJ;
-  double pf[SEG];
-  auto load_tile = [&](int tile) {
+  // Two tiles in flight: the tile processed now was requested two tiles ago.
+  double pfa[SEG], pfb[SEG];
+  auto load_tile = [&](double (&pf)[SEG], int tile) {
     const int I = tile / nJ, J = tile - (tile / nJ) * nJ;
     const int col = min(J * TS + lane, N - 1);
 #pragma unroll
@@ -144,16 +145,15 @@ __global__ __launch_bounds__(256) void k_p1_moments(const double* __restrict__ T
       pf[i] = T[(int64_t)row * ldT + col];
     }
   };
-  int tile = blockIdx.x;
-  if (tile < ntiles) load_tile(tile);
-  for (; tile < ntiles; tile += gridDim.x) {
+  const int stride = gridDim.x;
+  auto body = [&](double (&pf)[SEG], int tile) {
     const int I = tile / nJ, J = tile - I * nJ;
     const int js = I * TS, qs = J * TS;
     const int h = min(TS, M - js), w = min(TS, N - qs);
     double x[SEG];
 #pragma unroll
     for (int i = 0; i < SEG; ++i) x[i] = (seg * SEG + i < h && lane < w) ? pf[i] : 0.0;
-    load_tile(min(tile + (int)gridDim.x, ntiles - 1));
+    load_tile(pf, min(tile + 2 * stride, ntiles - 1));
     {
       double pre[KX + 1], suf[KX + 1];
       seg_summaries<KX>(x, pre, suf);
@@ -201,6 +201,15 @@ __global__ __launch_bounds__(256) void k_p1_moments(const double* __restrict__ T
       }
     }
     __syncthreads();
+  };
+  int tile = blockIdx.x;
+  if (tile < ntiles) {
+    load_tile(pfa, tile);
+    load_tile(pfb, min(tile + stride, ntiles - 1));
+  }
+  for (; tile < ntiles; tile += 2 * stride) {
+    body(pfa, tile);
+    if (tile + stride < ntiles) body(pfb, tile + stride);
   }
 }
 
@@ -542,26 +551,25 @@ __global__ __launch_bounds__(256) void k_p3_tile(const double* __restrict__ T, i
   __shared__ double sums[2][NSEG][TS][KM];  // [pre/suf][seg][line][r]
   const int t = threadIdx.x, lane = t & (TS - 1), seg = t >> 6;
   const int ntiles = nI * nJ;
-  double pf[SEG];
-  auto load_tile = [&](int tile) {
+  double pf[SEG];  // the next tile, requested while this one is processed
+  auto load_tile = [&](double (&dst)[SEG], int tile) {
     const int I = tile / nJ, J = tile - (tile / nJ) * nJ;
     const int col = min(J * TS + lane, N - 1);
 #pragma unroll
     for (int i = 0; i < SEG; ++i) {
       const int row = min(I * TS + seg * SEG + i, M - 1);
-      pf[i] = T[(int64_t)row * ldT + col];
+      dst[i] = T[(int64_t)row * ldT + col];
     }
   };
-  int tile = blockIdx.x;
-  if (tile < ntiles) load_tile(tile);
-  for (; tile < ntiles; tile += gridDim.x) {
+  const int stride = gridDim.x;
+  auto body = [&](int tile) {
     const int I = tile / nJ, J = tile - I * nJ;
     const int js = I * TS, qs = J * TS;
     const int h = min(TS, M - js), w = min(TS, N - qs);
     double x[SEG];
 #pragma unroll
     for (int i = 0; i < SEG; ++i) x[i] = (seg * SEG + i < h && lane < w) ? pf[i] : 0.0;
-    load_tile(min(tile + (int)gridDim.x, ntiles - 1));
+    load_tile(pf, min(tile + stride, ntiles - 1));
     // carries for this tile: row carries of the thread's row, A's column
     // carries of its column (loaded now, used after the barriers)
     double ra[KY + 1], rb[KY + 1], ca[KX + 1], cb[KX + 1];
@@ -646,10 +654,12 @@ __global__ __launch_bounds__(256) void k_p3_tile(const double* __restrict__ T, i
       }
     }
     __syncthreads();
-  }
+  };
+  if ((int)blockIdx.x < ntiles) load_tile(pf, blockIdx.x);
+  for (int tile = blockIdx.x; tile < ntiles; tile += stride) body(tile);
 }
 
-int persistent_blocks(int ntiles, int per_cu) {
+int cu_count() {
   static int ncu = 0;
   if (ncu == 0) {
     int dev = 0;
@@ -658,7 +668,18 @@ int persistent_blocks(int ntiles, int per_cu) {
       ncu = prop.multiProcessorCount;
     if (ncu <= 0) ncu = 256;
   }
-  const int g = ncu * per_cu;
+  return ncu;
+}
+
+// Persistent grid: as many blocks as are resident at once (occupancy of the
+// kernel on this device), at most one per tile.
+template <class K>
+int persistent_blocks(K kernel, int ntiles) {
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, 0) != hipSuccess ||
+      per_cu < 1)
+    per_cu = 1;
+  const int g = cu_count() * per_cu;
   return ntiles < g ? ntiles : g;
 }
 
@@ -670,7 +691,7 @@ gw_status run_fast1d(const Layout& L, const double* T, int64_t ldT, double* G, i
   const int ntiles = L.nI * L.nJ;
   {
     gwr::ProfScope ps(gwr::kFamFastCarry, s);
-    k_p1_moments<KX, KY><<<persistent_blocks(ntiles, 2), 256, 0, s>>>(T, ldT, M, N, L.nI, L.nJ, rowmom, colmom);
+    k_p1_moments<KX, KY><<<persistent_blocks(k_p1_moments<KX, KY>, ntiles), 256, 0, s>>>(T, ldT, M, N, L.nI, L.nJ, rowmom, colmom);
     const unsigned sblocks = (unsigned)((M + SCAN_LINES - 1) / SCAN_LINES + (N + SCAN_LINES - 1) / SCAN_LINES);
     if ((int64_t)M + N >= SCAN_ONE_THREAD_LINES)
       k_p2_scan<KX, KY, 1><<<sblocks, SCAN_LINES, 0, s>>>(M, N, L.nI, L.nJ, rowmom, colmom);
@@ -693,7 +714,7 @@ gw_status run_fast1d(const Layout& L, const double* T, int64_t ldT, double* G, i
   }
   {
     gwr::ProfScope ps(gwr::kFamFastMain, s);
-    k_p3_tile<KX, KY><<<persistent_blocks(ntiles, 3), 256, 0, s>>>(T, ldT, M, N, L.nI, L.nJ, rowmom,
+    k_p3_tile<KX, KY><<<persistent_blocks(k_p3_tile<KX, KY>, ntiles), 256, 0, s>>>(T, ldT, M, N, L.nI, L.nJ, rowmom,
                                                                    acarry, c1, c2, s2, G, ldG);
   }
   return gwr::last_launch_status();
