@@ -135,6 +135,48 @@ def profile_target(target: str, reps: int):
     raise SystemExit(f"unknown profile target {target}")
 
 
+def grid2d_bench(side: int = 64, eps: float = 2e-3, outer: int = 100, inner: int = 100):
+    """2D grids side x side vs side x side (N = side^2), squared Euclidean cost,
+    marginals = normalised images of 1-5 seeded Gaussian blobs plus a 1e-6
+    floor, FAST FP64 gradient fused with log-domain Sinkhorn: one full solve
+    timed (after a short warm-up solve), the FAST 2D gradient timed alone, and
+    the kernel time split between the 2D gradient and the Sinkhorn passes."""
+    import torch
+    from paper_2404_08970_amd import gw, inputs
+    dev = torch.device("cuda:0")
+    X = gw.unit_grid((side, side), 2, gw.METRIC_SQEUCLID)
+    p = torch.tensor(inputs.blobs_2d(side, side, inputs.rng_for(3, 0), floor=1e-6), device=dev)
+    q = torch.tensor(inputs.blobs_2d(side, side, inputs.rng_for(3, 1), floor=1e-6), device=dev)
+    n = X.size
+    T = torch.empty((n, n), dtype=torch.float64, device=dev)
+    f = torch.empty(n, dtype=torch.float64, device=dev)
+    g = torch.empty(n, dtype=torch.float64, device=dev)
+    obj = torch.empty(2, dtype=torch.float64, device=dev)
+    ws = gw.workspace(gw.workspace_bytes(X, X, gw.PATH_FAST_F64, gw.OP_SOLVE), dev, key="bench2d")
+    gw.solve(X, X, p, q, eps, 2, 5, T=T, f=f, g=g, obj=obj, ws=ws)
+    torch.cuda.synchronize()
+    gw.profile_enable([gw.FAM_2D, gw.FAM_OTHER, gw.FAM_SINK_ROW, gw.FAM_SINK_COL, gw.FAM_PLAN])
+    t0 = time.perf_counter()
+    gw.solve(X, X, p, q, eps, outer, inner, T=T, f=f, g=g, obj=obj, ws=ws)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    fams = {name: round(gw.profile_read(fam)[0], 2) for name, fam in
+            [("grad_2d_ms", gw.FAM_2D), ("sinkhorn_row_ms", gw.FAM_SINK_ROW),
+             ("sinkhorn_col_ms", gw.FAM_SINK_COL), ("plan_ms", gw.FAM_PLAN),
+             ("other_ms", gw.FAM_OTHER)]}
+    gw.profile_enable([])
+    gw.check_status(ws)
+    G = torch.empty_like(T)
+    gws = gw.workspace(gw.workspace_bytes(X, X, gw.PATH_FAST_F64, gw.OP_GRAD), dev, key="g2d")
+    grad_ms = time_gpu(lambda: gw.grad(X, X, p, q, T, path="fast", out=G, ws=gws), 20, torch)
+    return {"workload": f"2D {side}x{side} vs {side}x{side} (N = {n}), squared Euclidean, blob "
+                        f"marginals + 1e-6 floor, eps = {eps}, {outer} outer x {inner} Sinkhorn",
+            "solves_per_s": round(1.0 / dt, 4), "ms_per_solve": round(dt * 1e3, 1),
+            "fast_grad_us": round(grad_ms * 1e3, 1), "fast_grads_per_s": round(1e3 / grad_ms, 1),
+            "fast_grad_GBps_at_16B_per_entry": round(16.0 * n * n / (grad_ms * 1e-3) / 1e9, 1),
+            "kernel_ms_in_solve": fams, "objective": float(obj[0].item())}
+
+
 def precision_study(n: int = 16384, k: int = 2, rows: int = 6):
     """Dense gradient in FP64, FP32, BF16 and split refinements at n = 16384, k = 2,
     Dirichlet(1) marginals, on two plans: p q^T and the plan after one FAST
@@ -283,6 +325,8 @@ def main():
     ap.add_argument("--precision", action="store_true",
                     help="run the precision study (dense FP64/FP32/BF16/split vs FAST, n=16384) and exit")
     ap.add_argument("--no-serve", action="store_true", help="skip the request-loop measurement")
+    ap.add_argument("--no-2d", action="store_true", help="skip the 2D 64x64 solve")
+    ap.add_argument("--only-2d", action="store_true", help="run only the 2D 64x64 solve and exit")
     ap.add_argument("--serve-only", action="store_true", help="run only the request loop and exit")
     ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--serve-slots", type=int, default=32)
@@ -290,6 +334,9 @@ def main():
     args = ap.parse_args()
     if args.precision:
         print(json.dumps(precision_study()))
+        return
+    if args.only_2d:
+        print(json.dumps(grid2d_bench()))
         return
     if args.serve_only:
         print(json.dumps(serve_bench(args.serve_requests, args.serve_slots, args.serve_iters)))
@@ -406,6 +453,7 @@ def main():
                "fast_GBps_at_24B_per_entry": round(24.0 * nb * nb / (fast_ms * 1e-3) / 1e9, 1)}
         del Tb, Gb, wsb
 
+    grid2d = None if args.no_2d else grid2d_bench()
     serving = None
     if not args.no_serve:
         serving = serve_bench(args.serve_requests, args.serve_slots, args.serve_iters)
@@ -431,6 +479,7 @@ def main():
         "grads": grads,
         "n16384": big,
         "objective": objs,
+        "grid2d_64x64": grid2d,
         "serving": serving,
     }
     if not args.no_cpu:
