@@ -113,6 +113,23 @@ def cost_matrix(g: Grid) -> np.ndarray:
     return h_power(g) * integer_distance(g).astype(np.float64)
 
 
+def integer_distance_rows(g: Grid, rows) -> np.ndarray:
+    """Rows `rows` of integer_distance(g), by the same definition, for grids too
+    large to form the whole matrix."""
+    rows = np.asarray(rows, dtype=np.int64)
+    if g.ndim == 1:
+        idx = np.arange(g.shape[0], dtype=np.int64)
+        return np.abs(rows[:, None] - idx[None, :]) ** g.k
+    H, W = g.shape
+    flat = np.arange(H * W, dtype=np.int64)
+    r, c = flat // W, flat % W
+    dr = np.abs((rows // W)[:, None] - r[None, :])
+    dc = np.abs((rows % W)[:, None] - c[None, :])
+    if g.metric == METRIC_SQEUCLID:
+        return dr * dr + dc * dc
+    return (dr + dc) ** g.k
+
+
 # ---------------------------------------------------------------------------
 # Gradient: plain definition (the "original" computation)
 # ---------------------------------------------------------------------------
@@ -132,6 +149,31 @@ def grad_dense(gx: Grid, gy: Grid, p, q, T) -> np.ndarray:
 # ---------------------------------------------------------------------------
 # Gradient: the paper's recursion (Sec. 3)
 # ---------------------------------------------------------------------------
+
+def grad_rows(gx: Grid, gy: Grid, p, q, T, rows, block: int = 1024) -> np.ndarray:
+    """Rows `rows` of grad_dense(gx, gy, p, q, T) by the same plain definition,
+    G[rows] = c1[rows] 1^T + 1 c2^T - 2 D_X[rows] T D_Y (Sec. 2), with D_Y and
+    c2 = (D_Y o D_Y) q taken in blocks of rows of D_Y so that grids of 16384
+    points need no N x N distance matrix.  D_Y is symmetric, so its row blocks
+    are also its column blocks."""
+    p = np.asarray(p, dtype=np.float64)
+    q = np.asarray(q, dtype=np.float64)
+    T = np.asarray(T, dtype=np.float64)
+    rows = np.asarray(rows, dtype=np.int64)
+    DXr = h_power(gx) * integer_distance_rows(gx, rows).astype(np.float64)
+    c1r = (DXr * DXr) @ p
+    Wr = DXr @ T
+    N = gy.size
+    acc = np.zeros((rows.shape[0], N))
+    c2 = np.zeros(N)
+    hy = h_power(gy)
+    for j0 in range(0, N, block):
+        j1 = min(N, j0 + block)
+        DYb = hy * integer_distance_rows(gy, np.arange(j0, j1)).astype(np.float64)
+        acc += Wr[:, j0:j1] @ DYb
+        c2 += (DYb * DYb).T @ q[j0:j1]
+    return c1r[:, None] + c2[None, :] - 2.0 * acc
+
 
 def _binomials(m: int):
     return [[math.comb(r, s) for s in range(r + 1)] for r in range(m + 1)]

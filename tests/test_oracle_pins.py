@@ -394,3 +394,44 @@ def test_solve_small_properties():
     T0 = np.outer(p, q)
     E0, _ = O.objective(g, g, T0, 5e-3)
     assert E < E0
+
+
+# ------------------------------------------------------------ sampled rows
+
+@pytest.mark.parametrize("gx,gy", [
+    (O.Grid((37,), 1 / 36, 2), O.Grid((41,), 1 / 40, 3)),
+    (O.Grid((5, 7), 1 / 6, 1), O.Grid((6, 4), 1 / 5, 2)),
+    (O.Grid((6, 6), 1 / 5, 2, O.METRIC_SQEUCLID), O.Grid((30,), 1 / 29, 2)),
+])
+def test_grad_rows_equals_grad_dense(gx, gy):
+    """The blocked row evaluation used at full sizes is the plain definition:
+    it reproduces every row of grad_dense (block sizes that split D_Y)."""
+    rng = np.random.default_rng([17, gx.size, gy.size])
+    p = rng.dirichlet(np.ones(gx.size))
+    q = rng.dirichlet(np.ones(gy.size))
+    T = rng.uniform(0, 1, size=(gx.size, gy.size))
+    G = O.grad_dense(gx, gy, p, q, T)
+    rows = np.arange(gx.size)
+    for block in (1, 7, 1024):
+        Gr = O.grad_rows(gx, gy, p, q, T, rows, block=block)
+        assert np.max(np.abs(Gr - G)) <= 1e-13 * np.max(np.abs(G))
+
+
+def test_grad_rows_integer_inputs_exact():
+    """Integer plan, unit spacing and integer marginals: every value is an
+    integer below 2^53, so the sampled rows equal the full matrix exactly."""
+    g = O.Grid((50,), 1.0, 2)
+    rng = np.random.default_rng(18)
+    T = rng.integers(0, 5, size=(50, 50)).astype(float)
+    p = rng.integers(0, 3, size=50).astype(float)
+    q = rng.integers(0, 3, size=50).astype(float)
+    G = O.grad_dense(g, g, p, q, T)
+    rows = np.array([0, 17, 49])
+    assert np.array_equal(O.grad_rows(g, g, p, q, T, rows, block=16), G[rows])
+
+
+def test_integer_distance_rows_match():
+    for g in (O.Grid((9,), 1.0, 3), O.Grid((4, 5), 1.0, 2), O.Grid((3, 6), 1.0, 2, O.METRIC_SQEUCLID)):
+        D = O.integer_distance(g)
+        rows = np.arange(g.size)[::2]
+        assert np.array_equal(O.integer_distance_rows(g, rows), D[rows])
