@@ -62,10 +62,14 @@ struct SkSlot {
   double* pS;  // [nb x N] partial column mantissas
   int* pX;     // [nb x N] partial column exponents
   gwr::StatusWord* status;
+  double* lse;    // [M] upper bounds of the rows' log-sum-exp (row shifts)
+  double* gprev;  // [N] g before the last column merge
   double cs, inv_eps, eps;
   int32_t M, N, RB, nb;
   int32_t its;   // Sinkhorn iterations this request takes in the current step
   int32_t last;  // 1 if the step's last iteration is the request's last one
+  int32_t it0;   // index, within the request's Sinkhorn call, of the step's first iteration
+  int32_t pad;
 };
 
 struct SkTableHead {

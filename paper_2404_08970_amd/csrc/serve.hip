@@ -57,6 +57,7 @@ struct Req {
   gwr::StatusWord* st = nullptr;
   double *T = nullptr, *G = nullptr, *c1 = nullptr, *c2 = nullptr, *f = nullptr, *g = nullptr;
   double *obj = nullptr, *logp = nullptr, *logq = nullptr, *ms = nullptr, *pS = nullptr;
+  double *lse = nullptr, *gprev = nullptr;
   int* pX = nullptr;
   char* tail = nullptr;
   size_t tail_bytes = 0;
@@ -85,6 +86,8 @@ size_t carve(Req& q, char* base) {
   q.logp = a.take<double>(M);
   q.logq = a.take<double>(N);
   q.ms = a.take<double>(2 * (size_t)M);
+  q.lse = a.take<double>(M);
+  q.gprev = a.take<double>(N);
   q.pS = a.take<double>((size_t)q.nb * N);
   q.pX = a.take<int>((size_t)q.nb * N);
   q.tail_bytes = tail_bytes_of(q.X, q.Y);
@@ -296,6 +299,8 @@ uint32_t build_table(gw_server* sv, char* stage, size_t* upload) {
     d.pS = q.pS;
     d.pX = q.pX;
     d.status = q.st;
+    d.lse = q.lse;
+    d.gprev = q.gprev;
     d.cs = 2.0;
     d.inv_eps = 1.0 / q.r.eps;
     d.eps = q.r.eps;
@@ -305,6 +310,8 @@ uint32_t build_table(gw_server* sv, char* stage, size_t* upload) {
     d.nb = q.nb;
     d.its = q.its;
     d.last = q.inner_left <= sv->S ? 1 : 0;
+    d.it0 = q.r.inner - q.inner_left;
+    d.pad = 0;
     const int cls = gwb::row_class(q.N);
     mask |= 1u << cls;
     for (int b = 0; b < q.nb; ++b)

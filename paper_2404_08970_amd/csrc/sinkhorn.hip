@@ -20,8 +20,23 @@
 //              g_p = g_p + eps (ln q_p - ln S_p), ln S_p = ln(mant) + e ln 2,
 //              which is the LSE update rewritten with the old g as the shift.
 // Zero-mass rows/columns get f = -inf / g = -inf directly and contribute
-// nothing.  All reductions are in a fixed order (no atomics).
+// nothing.  All sums are in a fixed order.
+//
+// Row shift without a max pass: the shift of a row only has to bound its
+// maximum from above without being far above it.  Each pass leaves
+// a_i = m_i + e_i ln 2 (m_i its shift, 2^e_i > s_i), an upper bound of the
+// row's log-sum-exp.  If the column merge moved g by at most D+ up and D- down
+// (in units of eps), the next pass's row maximum is at most a_i + D+ and its
+// shifted sum at least e^{-(ln 2N + D+ + D-)}; with D+ + D- <= 600 the pass
+// shifts by a_i + D+ and skips the max reduction.  The first pass of a call,
+// and any pass after a larger move, takes the exact maximum.  D+ and D- are
+// maxima over columns: the column merge keeps the previous g beside the new
+// one, and every row-pass block reduces the move over all columns itself (one
+// block reduction per band, no atomics), so the choice, and every result, is
+// deterministic.
 #include <limits.h>
+
+#include <type_traits>
 
 #include "batch.h"
 #include "common.h"
@@ -36,6 +51,62 @@ constexpr double LN2_LO = 0x1.a39ef35793c76p-33;
 constexpr double INV_LN2 = 0x1.71547652b82fep+0;
 constexpr int EXP_SENTINEL = -(1 << 30);
 constexpr double X_FLOOR = -1.0e6;  // exp(-1e6) is 0 in any precision used here
+constexpr double SHIFT_SPREAD_MAX = 600.0;  // D+ + D- up to which the max pass is skipped
+
+// Shift for a pass given how far g moved up (D+) and down (D-) in the last
+// merge, in units of eps: D+ if the pass may shift rows by their bound, -1 if
+// it must take the exact row maxima.
+GW_DEV double shift_from_spread(double up, double dn) {
+  return up + dn <= SHIFT_SPREAD_MAX ? up : -1.0;
+}
+
+// D+ for the pass (or -1: exact maxima) from g and g before the last merge
+// (gprev, null in the first iteration of a call), reduced over all columns by
+// the block; every block computes the same value.
+template <int NT>
+GW_DEV double pass_shift(const double* __restrict__ g, const double* __restrict__ gprev, int N,
+                         double inv_eps, double (*red2)[2]);
+
+// Folds one column's move into (up, dn): g before and after the last merge.
+GW_DEV void fold_move(double gn, double go, double& up, double& dn) {
+  if (isfinite(gn) && isfinite(go)) {
+    up = fmax(up, gn - go);
+    dn = fmax(dn, go - gn);
+  } else if (isfinite(gn) != isfinite(go)) {
+    up = dn = INFINITY;
+  }
+}
+
+template <int NT>
+GW_DEV double pass_shift(const double* __restrict__ g, const double* __restrict__ gprev, int N,
+                         double inv_eps, double (*red2)[2]) {
+  if (gprev == nullptr) return -1.0;
+  double up = 0.0, dn = 0.0;
+  for (int c = threadIdx.x; c < N; c += NT) fold_move(g[c], gprev[c], up, dn);
+  up = gwk::wave_max(up) * inv_eps;
+  dn = gwk::wave_max(dn) * inv_eps;
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 63) {
+    red2[w][0] = up;
+    red2[w][1] = dn;
+  }
+  __syncthreads();
+  up = red2[0][0];
+  dn = red2[0][1];
+#pragma unroll
+  for (int k = 1; k < NT / 64; ++k) {
+    up = fmax(up, red2[k][0]);
+    dn = fmax(dn, red2[k][1]);
+  }
+  return shift_from_spread(up, dn);
+}
+
+// Upper bound of ln(sum) for the row shifted by m with shifted sum s > 0.
+GW_DEV double row_bound(double m, double s) {
+  int es;
+  (void)frexp(s, &es);
+  return m + (double)es * 0.6931471805599453;
+}
 
 template <int NTH>
 GW_DEV double block_max(double v, double* red) {
@@ -123,20 +194,51 @@ __global__ __launch_bounds__(256) void k_sk_prep(const double* __restrict__ p,
 // reduced, so loads stay in flight across the barriers.
 // The body works on band `band` so that the batched kernels of the request
 // loop run exactly the same arithmetic on a band as the single-problem kernel.
+// LDS of a row-pass shape, shared by its two row-shift variants (one static
+// allocation per shape, not per variant).
+template <int NTH, int EPT, int R, bool GL>
+struct RowLds {
+  double red[2][R][NTH / 64];
+  double dred[NTH / 64][2];
+  double gls[GL ? EPT * NTH : 1];
+};
+template <int NTH, int EPT, int R, bool GL>
+GW_DEV RowLds<NTH, EPT, R, GL>& row_lds() {
+  __shared__ RowLds<NTH, EPT, R, GL> l;
+  return l;
+}
+
+template <int EPT, int NG>
+struct RowgLds {
+  double gie[EPT * (1024 / NG)];
+  double dred[16][2];
+  double red[2][NG][1024 / NG / 64];
+  double mS[NG > 1 ? NG - 1 : 1][1024 / NG];
+  int mX[NG > 1 ? NG - 1 : 1][1024 / NG];
+};
+template <int EPT, int NG>
+GW_DEV RowgLds<EPT, NG>& rowg_lds() {
+  __shared__ RowgLds<EPT, NG> l;
+  return l;
+}
+
 // GL: g_p / eps is kept in LDS instead of registers.  PF: the next rows are
 // loaded while the current ones are reduced (two row buffers); without it the
 // next rows are loaded after the column update into the same registers, which
-// leaves room for up to 32 entries per thread at 512 threads.
-template <int NTH, int EPT, int R, bool GL = false, bool PF = true>
+// leaves room for up to 32 entries per thread at 512 threads.  gprev (g before
+// the last merge, null in the first iteration of a call) decides whether rows
+// are shifted by their bound lse_i + D+ or by their exact maximum.
+template <int NTH, int EPT, int R, bool GL, bool PF, bool SHIFT>
 GW_DEV void sk_row_band(const double* __restrict__ C, int64_t ldC, int M, int N, int RB,
                         double cs, double inv_eps, const double* __restrict__ p,
                         const double* __restrict__ logp, const double* __restrict__ g,
                         double* __restrict__ f, double* __restrict__ ms,
-                        double* __restrict__ partS, int* __restrict__ partX, int write_f,
-                        int band) {
+                        double* __restrict__ partS, int* __restrict__ partX,
+                        double* __restrict__ lse, double dup, int write_f, int band) {
   constexpr int NW = NTH / 64;
-  __shared__ double red[2][R][NW];
-  __shared__ double gls[GL ? EPT * NTH : 1];
+  auto& lds = row_lds<NTH, EPT, R, GL>();
+  auto& red = lds.red;
+  double* gls = lds.gls;
   const int t = opaque_tid(), wv = t >> 6, lane = t & 63;
   const double csie = cs * inv_eps;
   double S[EPT];
@@ -172,10 +274,10 @@ GW_DEV void sk_row_band(const double* __restrict__ C, int64_t ldC, int M, int N,
       for (int e = 0; e < EPT; ++e) dst[r][e] = row[colc[e]];
     }
   };
+  if (i0 < i1) load(cur, i0);
   // The next R rows are loaded into `cur` as soon as the current rows have
   // been turned into exponents, so the loads overlap the reductions, the
   // exponentials and the column updates.
-  if (i0 < i1) load(cur, i0);
   for (int ib = i0; ib < i1; ib += R) {
     double pv[R], lpv[R];
 #pragma unroll
@@ -185,29 +287,39 @@ GW_DEV void sk_row_band(const double* __restrict__ C, int64_t ldC, int M, int N,
       lpv[r] = logp[i];
     }
     double z[R][EPT];
-    double mloc[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      mloc[r] = -INFINITY;
-#pragma unroll
-      for (int e = 0; e < EPT; ++e) {
-        z[r][e] = fma(-csie, cur[r][e], gie(e));
-        mloc[r] = fmax(mloc[r], z[r][e]);
-      }
-    }
-    if constexpr (PF) load(cur, ib + R);  // clamped: past the band it re-reads the last row
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      mloc[r] = gwk::wave_max(mloc[r]);
-      if (lane == 63) red[0][r][wv] = mloc[r];
-    }
-    __syncthreads();
     double m[R];
+    if constexpr (SHIFT) {
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      m[r] = red[0][r][0];
+      for (int r = 0; r < R; ++r) {
+        m[r] = lse[min(ib + r, i1 - 1)] + dup;
 #pragma unroll
-      for (int w = 1; w < NW; ++w) m[r] = fmax(m[r], red[0][r][w]);
+        for (int e = 0; e < EPT; ++e) z[r][e] = fma(-csie, cur[r][e], gie(e));
+      }
+      if constexpr (PF) load(cur, ib + R);  // clamped: past the band it re-reads the last row
+    } else {
+      double mloc[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        mloc[r] = -INFINITY;
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+          z[r][e] = fma(-csie, cur[r][e], gie(e));
+          mloc[r] = fmax(mloc[r], z[r][e]);
+        }
+      }
+      if constexpr (PF) load(cur, ib + R);  // clamped: past the band it re-reads the last row
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        mloc[r] = gwk::wave_max(mloc[r]);
+        if (lane == 63) red[0][r][wv] = mloc[r];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        m[r] = red[0][r][0];
+#pragma unroll
+        for (int w = 1; w < NW; ++w) m[r] = fmax(m[r], red[0][r][w]);
+      }
     }
     int nE[R][EPT];
     double sl[R];
@@ -220,19 +332,24 @@ GW_DEV void sk_row_band(const double* __restrict__ C, int64_t ldC, int M, int N,
         sl[r] += ldexp(z[r][e], nE[r][e]);
       }
     }
+    // Without the max pass there is one barrier per row step, so the sums of
+    // consecutive steps alternate between the two buffers: a wave that writes
+    // step k + 2 has passed step k + 1's barrier, after every read of step k.
+    const int sb = SHIFT ? (((ib - i0) / R) & 1) : 1;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       sl[r] = gwk::wave_sum(sl[r]);
-      if (lane == 63) red[1][r][wv] = sl[r];
+      if (lane == 63) red[sb][r][wv] = sl[r];
     }
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int i = ib + r;
       if (i >= i1) break;
-      double s = red[1][r][0];
+      double s = red[sb][r][0];
 #pragma unroll
-      for (int w = 1; w < NW; ++w) s += red[1][r][w];
+      for (int w = 1; w < NW; ++w) s += red[sb][r][w];
+      if (PF && t == 0) lse[i] = row_bound(m[r], s);  // read only by shifted passes
       const double pi = pv[r];
       if (!(pi > 0.0)) {
         if (t == 0) f[i] = -INFINITY;
@@ -276,9 +393,20 @@ __global__ __launch_bounds__(NTH) void k_sk_row(const double* __restrict__ C, in
                                                  double* __restrict__ f,
                                                  double* __restrict__ ms,
                                                  double* __restrict__ partS,
-                                                 int* __restrict__ partX, int write_f) {
-  sk_row_band<NTH, EPT, R, GL, PF>(C, ldC, M, N, RB, cs, inv_eps, p, logp, g, f, ms, partS,
-                                   partX, write_f, blockIdx.x);
+                                                 int* __restrict__ partX,
+                                                 double* __restrict__ lse,
+                                                 const double* __restrict__ gprev,
+                                                 int write_f) {
+  // the longest rows (no register prefetch) always take the exact maxima:
+  // their shifted variant spills more registers than it saves
+  double dup = -1.0;
+  if constexpr (PF) dup = pass_shift<NTH>(g, gprev, N, inv_eps, row_lds<NTH, EPT, R, GL>().dred);
+  if (PF && dup >= 0.0)
+    sk_row_band<NTH, EPT, R, GL, PF, PF>(C, ldC, M, N, RB, cs, inv_eps, p, logp, g, f, ms,
+                                         partS, partX, lse, dup, write_f, blockIdx.x);
+  else
+    sk_row_band<NTH, EPT, R, GL, PF, false>(C, ldC, M, N, RB, cs, inv_eps, p, logp, g, f, ms,
+                                            partS, partX, lse, 0.0, write_f, blockIdx.x);
 }
 
 // Grouped row pass for rows of up to 8 x 512 entries: a block of 1024 threads
@@ -287,17 +415,19 @@ __global__ __launch_bounds__(NTH) void k_sk_row(const double* __restrict__ C, in
 // (two reductions, the weight p_i/s_i) is spread over more entries.  g/eps
 // lives in LDS.  The NG groups' column pairs are merged through LDS in group
 // order and written as the block's partial.
-template <int EPT, int NG, bool PF>
+template <int EPT, int NG, bool PF, bool SHIFT>
 GW_DEV void sk_rowg_band(const double* __restrict__ C, int64_t ldC, int M, int N, int RB,
                          double cs, double inv_eps, const double* __restrict__ p,
                          const double* __restrict__ g, double* __restrict__ f,
                          double* __restrict__ ms, double* __restrict__ partS,
-                         int* __restrict__ partX, int write_f, int band) {
+                         int* __restrict__ partX, double* __restrict__ lse, double dup,
+                         int write_f, int band) {
   constexpr int GT = 1024 / NG, GW = GT / 64;
-  __shared__ double gie[EPT * GT];
-  __shared__ double red[2][NG][GW];
-  __shared__ double mS[NG > 1 ? NG - 1 : 1][GT];
-  __shared__ int mX[NG > 1 ? NG - 1 : 1][GT];
+  auto& lds = rowg_lds<EPT, NG>();
+  double* gie = lds.gie;
+  auto& red = lds.red;
+  auto& mS = lds.mS;
+  auto& mX = lds.mX;
   const int t = opaque_tid(), gi = t / GT, tl = t - gi * GT, wv = tl >> 6, lane = t & 63;
   const double csie = cs * inv_eps;
   for (int c = t; c < EPT * GT; c += 1024) gie[c] = c < N ? g[c] * inv_eps : -INFINITY;
@@ -327,18 +457,25 @@ GW_DEV void sk_rowg_band(const double* __restrict__ C, int64_t ldC, int M, int N
     const int i = i0 + j * NG + gi;
     const bool valid = i < i1;
     const double pi = p[min(i, i1 - 1)];
-    double mloc = -INFINITY;
+    double m;
+    if constexpr (SHIFT) {
+      m = lse[min(i, i1 - 1)] + dup;
 #pragma unroll
-    for (int e = 0; e < EPT; ++e) {
-      x[e] = fma(-csie, x[e], gie[tl + GT * e]);
-      mloc = fmax(mloc, x[e]);
+      for (int e = 0; e < EPT; ++e) x[e] = fma(-csie, x[e], gie[tl + GT * e]);
+    } else {
+      double mloc = -INFINITY;
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) {
+        x[e] = fma(-csie, x[e], gie[tl + GT * e]);
+        mloc = fmax(mloc, x[e]);
+      }
+      mloc = gwk::wave_max(mloc);
+      if (lane == 63) red[0][gi][wv] = mloc;
+      __syncthreads();
+      m = red[0][gi][0];
+#pragma unroll
+      for (int w = 1; w < GW; ++w) m = fmax(m, red[0][gi][w]);
     }
-    mloc = gwk::wave_max(mloc);
-    if (lane == 63) red[0][gi][wv] = mloc;
-    __syncthreads();
-    double m = red[0][gi][0];
-#pragma unroll
-    for (int w = 1; w < GW; ++w) m = fmax(m, red[0][gi][w]);
     int nE[EPT];
     double sl = 0.0;
 #pragma unroll
@@ -346,12 +483,16 @@ GW_DEV void sk_rowg_band(const double* __restrict__ C, int64_t ldC, int M, int N
       x[e] = exp_split(x[e] - m, &nE[e]);
       sl += ldexp(x[e], nE[e]);
     }
+    // one barrier per row step without the max pass: alternate the buffers
+    // of consecutive steps (see the single-group pass)
+    const int sb = SHIFT ? (j & 1) : 1;
     sl = gwk::wave_sum(sl);
-    if (lane == 63) red[1][gi][wv] = sl;
+    if (lane == 63) red[sb][gi][wv] = sl;
     __syncthreads();
-    double s = red[1][gi][0];
+    double s = red[sb][gi][0];
 #pragma unroll
-    for (int w = 1; w < GW; ++w) s += red[1][gi][w];
+    for (int w = 1; w < GW; ++w) s += red[sb][gi][w];
+    if (valid && tl == 0) lse[i] = row_bound(m, s);
     if (valid) {
       if (pi > 0.0) {
         // f_i is an output only (the next iteration rebuilds it from g): the
@@ -418,9 +559,18 @@ __global__ __launch_bounds__(1024) void k_sk_rowg(const double* __restrict__ C, 
                                                    double* __restrict__ f,
                                                    double* __restrict__ ms,
                                                    double* __restrict__ partS,
-                                                   int* __restrict__ partX, int write_f) {
-  sk_rowg_band<EPT, NG, PF>(C, ldC, M, N, RB, cs, inv_eps, p, g, f, ms, partS, partX, write_f,
-                            blockIdx.x);
+                                                   int* __restrict__ partX,
+                                                   double* __restrict__ lse,
+                                                   const double* __restrict__ gprev,
+                                                   int write_f) {
+  auto& lds = rowg_lds<EPT, NG>();
+  const double dup = pass_shift<1024>(g, gprev, N, inv_eps, lds.dred);
+  if (dup >= 0.0)
+    sk_rowg_band<EPT, NG, PF, true>(C, ldC, M, N, RB, cs, inv_eps, p, g, f, ms, partS, partX,
+                                    lse, dup, write_f, blockIdx.x);
+  else
+    sk_rowg_band<EPT, NG, PF, false>(C, ldC, M, N, RB, cs, inv_eps, p, g, f, ms, partS, partX,
+                                     lse, 0.0, write_f, blockIdx.x);
 }
 
 // Column merge: a block covers 16 columns x 16 groups of bands; each thread
@@ -431,7 +581,7 @@ constexpr int MERGE_COLS = gwb::kMergeCols, MERGE_GRPS = 16;
 GW_DEV void sk_col_block(int N, int nb, const double* __restrict__ partS,
                          const int* __restrict__ partX, const double* __restrict__ q,
                          const double* __restrict__ logq, double eps, double* __restrict__ g,
-                         gwr::StatusWord* status, int cblock) {
+                         gwr::StatusWord* status, double* __restrict__ gprev, int cblock) {
   __shared__ double ms[MERGE_GRPS][MERGE_COLS];
   __shared__ int mx[MERGE_GRPS][MERGE_COLS];
   const int c = threadIdx.x & (MERGE_COLS - 1), grp = threadIdx.x / MERGE_COLS;
@@ -459,13 +609,15 @@ GW_DEV void sk_col_block(int N, int nb, const double* __restrict__ partS,
     S = ldexp(S, X - ne) + ldexp(ms[k][c], mx[k][c] - ne);
     X = ne;
   }
+  const double gold = g[col];
+  gprev[col] = gold;
   if (!(q[col] > 0.0)) {
     g[col] = -INFINITY;
     return;
   }
   // ln(S 2^X) with X ln 2 split so that X * LN2_HI is exact
   const double lnS = fma((double)X, LN2_HI, fma((double)X, LN2_LO, log(S)));
-  const double gn = g[col] + eps * (logq[col] - lnS);
+  const double gn = gold + eps * (logq[col] - lnS);
   g[col] = gn;
   if (!isfinite(gn)) status->nonfinite = 1;
 }
@@ -475,8 +627,8 @@ __global__ __launch_bounds__(256) void k_sk_col(int N, int nb, const double* __r
                                                  const double* __restrict__ q,
                                                  const double* __restrict__ logq, double eps,
                                                  double* __restrict__ g,
-                                                 gwr::StatusWord* status) {
-  sk_col_block(N, nb, partS, partX, q, logq, eps, g, status, blockIdx.x);
+                                                 gwr::StatusWord* status, double* gprev) {
+  sk_col_block(N, nb, partS, partX, q, logq, eps, g, status, gprev, blockIdx.x);
 }
 
 // f_i = eps (ln p_i - m_i - ln s_i) from the last row pass's row maximum and
@@ -611,9 +763,10 @@ constexpr bool row_pf() {
 template <int NTH, int EPT>
 void launch_row(int nb, hipStream_t s, const double* C, int64_t ldC, int M, int N, int RB,
                 double cs, double inv_eps, const double* p, const double* logp,
-                const double* g, double* f, double* ms, double* pS, int* pX, int last) {
+                const double* g, double* f, double* ms, double* pS, int* pX, double* lse,
+                const double* gprev, int last) {
   constexpr int R = row_group<NTH, EPT>();
-  k_sk_row<NTH, EPT, R, row_gl<NTH, EPT>(), row_pf<NTH, EPT>()><<<nb, NTH, 0, s>>>(C, ldC, M, N, RB, cs, inv_eps, p, logp, g, f, ms, pS, pX, last);
+  k_sk_row<NTH, EPT, R, row_gl<NTH, EPT>(), row_pf<NTH, EPT>()><<<nb, NTH, 0, s>>>(C, ldC, M, N, RB, cs, inv_eps, p, logp, g, f, ms, pS, pX, lse, gprev, last);
 }
 
 // ---------------------------------------------------------------------------
@@ -635,9 +788,24 @@ __global__ __launch_bounds__(NTH) void k_skb_row(const gwb::SkSlot* __restrict__
     const gwb::SkSlot& a = slots[code >> gwb::kBandBits];
     if (j >= a.its) continue;
     __syncthreads();
-    sk_row_band<NTH, EPT, row_group<NTH, EPT>(), row_gl<NTH, EPT>(), row_pf<NTH, EPT>()>(
-        a.C, a.ldC, a.M, a.N, a.RB, a.cs, a.inv_eps, a.p, a.logp, a.g, a.f, a.ms, a.pS, a.pX,
-        a.last && j == a.its - 1, (int)(code & ((1u << gwb::kBandBits) - 1)));
+    const int tt = a.it0 + j;  // iteration within the request's Sinkhorn call
+    const int band = (int)(code & ((1u << gwb::kBandBits) - 1));
+    constexpr int R = row_group<NTH, EPT>();
+    constexpr bool GL = row_gl<NTH, EPT>();
+    constexpr bool PF = row_pf<NTH, EPT>();
+    double dup = -1.0;  // exact maxima without the register prefetch, as in k_sk_row
+    if constexpr (PF)
+      dup = pass_shift<NTH>(a.g, tt > 0 ? a.gprev : nullptr, a.N, a.inv_eps,
+                            row_lds<NTH, EPT, R, GL>().dred);
+    const int wf = a.last && j == a.its - 1;
+    if (PF && dup >= 0.0)
+      sk_row_band<NTH, EPT, R, GL, PF, PF>(a.C, a.ldC, a.M, a.N, a.RB, a.cs, a.inv_eps, a.p,
+                                             a.logp, a.g, a.f, a.ms, a.pS, a.pX, a.lse, dup, wf,
+                                             band);
+    else
+      sk_row_band<NTH, EPT, R, GL, PF, false>(a.C, a.ldC, a.M, a.N, a.RB, a.cs, a.inv_eps, a.p,
+                                              a.logp, a.g, a.f, a.ms, a.pS, a.pX, a.lse, 0.0, wf,
+                                              band);
   }
 }
 
@@ -652,9 +820,17 @@ __global__ __launch_bounds__(1024) void k_skb_rowg(const gwb::SkSlot* __restrict
     const gwb::SkSlot& a = slots[code >> gwb::kBandBits];
     if (j >= a.its) continue;
     __syncthreads();
-    sk_rowg_band<8, 2, true>(a.C, a.ldC, a.M, a.N, a.RB, a.cs, a.inv_eps, a.p, a.g, a.f, a.ms,
-                             a.pS, a.pX, a.last && j == a.its - 1,
-                             (int)(code & ((1u << gwb::kBandBits) - 1)));
+    const int tt = a.it0 + j;
+    const int band = (int)(code & ((1u << gwb::kBandBits) - 1));
+    auto& lds = rowg_lds<8, 2>();
+    const double dup = pass_shift<1024>(a.g, tt > 0 ? a.gprev : nullptr, a.N, a.inv_eps, lds.dred);
+    const int wf = a.last && j == a.its - 1;
+    if (dup >= 0.0)
+      sk_rowg_band<8, 2, true, true>(a.C, a.ldC, a.M, a.N, a.RB, a.cs, a.inv_eps, a.p, a.g, a.f,
+                                     a.ms, a.pS, a.pX, a.lse, dup, wf, band);
+    else
+      sk_rowg_band<8, 2, true, false>(a.C, a.ldC, a.M, a.N, a.RB, a.cs, a.inv_eps, a.p, a.g, a.f,
+                                      a.ms, a.pS, a.pX, a.lse, 0.0, wf, band);
   }
 }
 
@@ -668,7 +844,7 @@ __global__ __launch_bounds__(256) void k_skb_col(const gwb::SkSlot* __restrict__
     const gwb::SkSlot& a = slots[code >> gwb::kCBlockBits];
     if (j >= a.its) continue;
     __syncthreads();
-    sk_col_block(a.N, a.nb, a.pS, a.pX, a.q, a.logq, a.eps, a.g, a.status,
+    sk_col_block(a.N, a.nb, a.pS, a.pX, a.q, a.logq, a.eps, a.g, a.status, a.gprev,
                  (int)(code & ((1u << gwb::kCBlockBits) - 1)));
   }
 }
@@ -689,6 +865,8 @@ size_t sinkhorn_ws_bytes(int64_t M, int64_t N) {
   a.take<double>((size_t)nb * N);
   a.take<int>((size_t)nb * N);
   a.take<double>(2 * (size_t)M);
+  a.take<double>(M);  // row bounds
+  a.take<double>(N);  // g before the last merge
   return a.used;
 }
 
@@ -746,6 +924,8 @@ gw_status sinkhorn(const double* C, int64_t ldC, int64_t M, int64_t N, double c_
   double* pS = ws.take<double>((size_t)nb * N);
   int* pX = ws.take<int>((size_t)nb * N);
   double* ms = ws.take<double>(2 * (size_t)M);
+  double* lse = ws.take<double>(M);
+  double* gprev = ws.take<double>(N);
   const double inv_eps = 1.0 / eps;
   gw_status st = sinkhorn_prep(p, q, M, N, init_zero, logp, logq, f, g, s);
   if (st != GW_OK) return st;
@@ -754,23 +934,24 @@ gw_status sinkhorn(const double* C, int64_t ldC, int64_t M, int64_t N, double c_
     {
       gwr::ProfScope ps(gwr::kFamSinkRow, s);
       const int lst = it == iters - 1;
+      const double* gp = it > 0 ? gprev : nullptr;
       switch (gwb::row_class(N)) {
-        case gwb::kClsN256: launch_row<256, 1>(nb, s, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, lst); break;
-        case gwb::kClsN512: launch_row<512, 1>(nb, s, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, lst); break;
-        case gwb::kClsN1024: launch_row<1024, 1>(nb, s, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, lst); break;
-        case gwb::kClsN2048: launch_row<1024, 2>(nb, s, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, lst); break;
-        case gwb::kClsN3072: launch_row<256, 12>(nb, s, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, lst); break;
-        case gwb::kClsN4096: k_sk_rowg<8, 2, true><<<nb, 1024, 0, s>>>(C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, g, f, ms, pS, pX, lst); break;
-        case gwb::kClsN6144: launch_row<512, 12>(nb, s, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, lst); break;
-        case gwb::kClsN8192: launch_row<512, 16>(nb, s, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, lst); break;
-        case gwb::kClsN9216: launch_row<512, 18>(nb, s, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, lst); break;
-        case gwb::kClsN12288: launch_row<512, 24>(nb, s, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, lst); break;
-        default: launch_row<512, 32>(nb, s, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, lst); break;
+        case gwb::kClsN256: launch_row<256, 1>(nb, s, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, lse, gp, lst); break;
+        case gwb::kClsN512: launch_row<512, 1>(nb, s, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, lse, gp, lst); break;
+        case gwb::kClsN1024: launch_row<1024, 1>(nb, s, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, lse, gp, lst); break;
+        case gwb::kClsN2048: launch_row<1024, 2>(nb, s, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, lse, gp, lst); break;
+        case gwb::kClsN3072: launch_row<256, 12>(nb, s, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, lse, gp, lst); break;
+        case gwb::kClsN4096: k_sk_rowg<8, 2, true><<<nb, 1024, 0, s>>>(C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, g, f, ms, pS, pX, lse, gp, lst); break;
+        case gwb::kClsN6144: launch_row<512, 12>(nb, s, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, lse, gp, lst); break;
+        case gwb::kClsN8192: launch_row<512, 16>(nb, s, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, lse, gp, lst); break;
+        case gwb::kClsN9216: launch_row<512, 18>(nb, s, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, lse, gp, lst); break;
+        case gwb::kClsN12288: launch_row<512, 24>(nb, s, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, lse, gp, lst); break;
+        default: launch_row<512, 32>(nb, s, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, lse, gp, lst); break;
       }
     }
     {
       gwr::ProfScope ps(gwr::kFamSinkCol, s);
-      k_sk_col<<<(unsigned)((N + MERGE_COLS - 1) / MERGE_COLS), 256, 0, s>>>(Ni, nb, pS, pX, q, logq, eps, g, status);
+      k_sk_col<<<(unsigned)((N + MERGE_COLS - 1) / MERGE_COLS), 256, 0, s>>>(Ni, nb, pS, pX, q, logq, eps, g, status, gprev);
     }
   }
   return sinkhorn_finish(C, ldC, M, N, c_scale, p, logp, ms, eps, iters, f, g, T, ldT, s, status);
