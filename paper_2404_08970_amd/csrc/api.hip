@@ -115,6 +115,24 @@ void prof_begin(int fam, hipStream_t s) {
   P.open[fam] = e;
 }
 
+void prof_dispatch_events(int fam, hipEvent_t* b, hipEvent_t* e) {
+  *b = *e = nullptr;
+  ProfState& P = prof();
+  if (!(P.mask & (1 << fam))) return;
+  std::lock_guard<std::mutex> g(P.mu);
+  if (P.used[fam] + 2 > (size_t(1) << 20)) drain(P, fam);
+  *b = pool_event(P, fam);
+  *e = pool_event(P, fam);
+  if (!*b || !*e) *b = *e = nullptr;
+}
+
+void prof_dispatch_done(int fam, hipEvent_t b, hipEvent_t e) {
+  if (!b || !e) return;
+  ProfState& P = prof();
+  std::lock_guard<std::mutex> g(P.mu);
+  P.pending[fam].push_back({b, e});
+}
+
 void prof_end(int fam, hipStream_t s) {
   ProfState& P = prof();
   if (!(P.mask & (1 << fam))) return;

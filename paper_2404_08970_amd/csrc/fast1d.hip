@@ -20,6 +20,7 @@
 //       of B; the epilogue writes G.
 // HBM traffic: two reads of T, one write of G, plus O(MN (kx+ky)/64) of
 // moments.
+#include <hip/hip_ext.h>
 #include "common.h"
 #include "runtime.h"
 
@@ -713,9 +714,10 @@ gw_status run_fast1d(const Layout& L, const double* T, int64_t ldT, double* G, i
     }
   }
   {
-    gwr::ProfScope ps(gwr::kFamFastMain, s);
-    k_p3_tile<KX, KY><<<persistent_blocks(k_p3_tile<KX, KY>, ntiles), 256, 0, s>>>(T, ldT, M, N, L.nI, L.nJ, rowmom,
-                                                                   acarry, c1, c2, s2, G, ldG);
+    gwr::ProfDispatch pd(gwr::kFamFastMain);
+    hipExtLaunchKernelGGL(k_p3_tile<KX, KY>, dim3(persistent_blocks(k_p3_tile<KX, KY>, ntiles)),
+                          dim3(256), 0, s, pd.b, pd.e, 0, T, ldT, M, N, L.nI, L.nJ, rowmom, acarry,
+                          c1, c2, s2, G, ldG);
   }
   return gwr::last_launch_status();
 }

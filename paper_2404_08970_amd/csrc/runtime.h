@@ -69,11 +69,25 @@ enum Family {
 void prof_begin(int family, hipStream_t s);
 void prof_end(int family, hipStream_t s);
 
+// Times everything enqueued on `s` during the scope (events recorded before
+// and after: includes the dispatch latency of each launch).
 struct ProfScope {
   int fam;
   hipStream_t s;
   ProfScope(int f, hipStream_t st) : fam(f), s(st) { prof_begin(fam, s); }
   ~ProfScope() { prof_end(fam, s); }
+};
+
+// Times one kernel dispatch by its own begin and end timestamps: pass b and e
+// as the start / stop events of hipExtLaunchKernelGGL.  Both are null (a plain
+// launch) when the family is not being timed.
+void prof_dispatch_events(int family, hipEvent_t* b, hipEvent_t* e);
+void prof_dispatch_done(int family, hipEvent_t b, hipEvent_t e);
+struct ProfDispatch {
+  int fam;
+  hipEvent_t b = nullptr, e = nullptr;
+  explicit ProfDispatch(int f) : fam(f) { prof_dispatch_events(fam, &b, &e); }
+  ~ProfDispatch() { prof_dispatch_done(fam, b, e); }
 };
 
 inline gw_status last_launch_status() {

@@ -36,6 +36,8 @@
 // deterministic.
 #include <limits.h>
 
+#include <hip/hip_ext.h>
+
 #include <type_traits>
 
 #include "batch.h"
@@ -210,11 +212,13 @@ GW_DEV RowLds<NTH, EPT, R, GL>& row_lds() {
 
 template <int EPT, int NG>
 struct RowgLds {
-  double gie[EPT * (1024 / NG)];
+  union {
+    double gie[EPT * (1024 / NG)];                    // g/eps while the rows run
+    double mS[NG > 1 ? NG - 1 : 1][EPT][1024 / NG];  // then the groups' mantissas
+  } u;
+  int mX[NG > 1 ? NG - 1 : 1][EPT][1024 / NG];
   double dred[16][2];
   double red[2][NG][1024 / NG / 64];
-  double mS[NG > 1 ? NG - 1 : 1][1024 / NG];
-  int mX[NG > 1 ? NG - 1 : 1][1024 / NG];
 };
 template <int EPT, int NG>
 GW_DEV RowgLds<EPT, NG>& rowg_lds() {
@@ -415,22 +419,24 @@ __global__ __launch_bounds__(NTH) void k_sk_row(const double* __restrict__ C, in
 // (two reductions, the weight p_i/s_i) is spread over more entries.  g/eps
 // lives in LDS.  The NG groups' column pairs are merged through LDS in group
 // order and written as the block's partial.
+//
+// The rows of a band, given its first row in x (loaded by sk_rowg_band) and
+// g/eps in LDS.
 template <int EPT, int NG, bool PF, bool SHIFT>
-GW_DEV void sk_rowg_band(const double* __restrict__ C, int64_t ldC, int M, int N, int RB,
-                         double cs, double inv_eps, const double* __restrict__ p,
-                         const double* __restrict__ g, double* __restrict__ f,
+GW_DEV void sk_rowg_rows(const double* __restrict__ C, int64_t ldC, int M, int N, int RB,
+                         double csie, const double* __restrict__ p, double* __restrict__ f,
                          double* __restrict__ ms, double* __restrict__ partS,
                          int* __restrict__ partX, double* __restrict__ lse, double dup,
-                         int write_f, int band) {
+                         int write_f, int band, int t, double (&x)[EPT],
+                         const int (&colc)[EPT]) {
   constexpr int GT = 1024 / NG, GW = GT / 64;
   auto& lds = rowg_lds<EPT, NG>();
-  double* gie = lds.gie;
+  const double* gie = lds.u.gie;
   auto& red = lds.red;
-  auto& mS = lds.mS;
-  auto& mX = lds.mX;
-  const int t = opaque_tid(), gi = t / GT, tl = t - gi * GT, wv = tl >> 6, lane = t & 63;
-  const double csie = cs * inv_eps;
-  for (int c = t; c < EPT * GT; c += 1024) gie[c] = c < N ? g[c] * inv_eps : -INFINITY;
+  // group and wave indices are the same in every lane of a wave: kept in
+  // scalar registers, so row addresses are scalar bases
+  const int gi = __builtin_amdgcn_readfirstlane(t / GT), tl = t - gi * GT;
+  const int wv = __builtin_amdgcn_readfirstlane(tl >> 6), lane = t & 63;
   double S[EPT];
   int Xe[EPT];
 #pragma unroll
@@ -440,18 +446,13 @@ GW_DEV void sk_rowg_band(const double* __restrict__ C, int64_t ldC, int M, int N
   }
   const int i0 = band * RB, i1 = min(M, i0 + RB);
   const int nr = (RB + NG - 1) / NG;  // row steps, the same for every group
-  int colc[EPT];                      // column of each entry, clamped into range
-#pragma unroll
-  for (int e = 0; e < EPT; ++e) colc[e] = min(tl + GT * e, N - 1);
-  double x[EPT], nx[EPT];
+  double nx[EPT];
   auto load = [&](double (&dst)[EPT], int j) {
     const int i = min(i0 + j * NG + gi, i1 - 1);
     const double* row = C + (int64_t)i * ldC;
 #pragma unroll
     for (int e = 0; e < EPT; ++e) dst[e] = row[colc[e]];
   };
-  __syncthreads();
-  load(x, 0);
   for (int j = 0; j < nr; ++j) {
     if (PF) load(nx, j + 1);
     const int i = i0 + j * NG + gi;
@@ -522,32 +523,76 @@ GW_DEV void sk_rowg_band(const double* __restrict__ C, int64_t ldC, int M, int N
       load(x, j + 1);
     }
   }
-  // merge the groups' column pairs into group 0, one entry slot at a time
+  // merge the groups' column pairs into group 0 in group order: one exchange
+  // through LDS (the pairs take the place of g/eps, which no row reads any more)
+  if constexpr (NG > 1) {
+    auto& mS = lds.u.mS;
+    auto& mX = lds.mX;
+    __syncthreads();
+    if (gi > 0) {
 #pragma unroll
-  for (int e = 0; e < EPT; ++e) {
-    if (NG > 1) {
-      __syncthreads();
-      if (gi > 0) {
-        mS[gi - 1][tl] = S[e];
-        mX[gi - 1][tl] = Xe[e];
-      }
-      __syncthreads();
-      if (gi == 0) {
-#pragma unroll
-        for (int k = 0; k < NG - 1; ++k) {
-          const int xb = mX[k][tl];
-          const int ne = max(Xe[e], xb);
-          S[e] = ldexp(S[e], Xe[e] - ne) + ldexp(mS[k][tl], xb - ne);
-          Xe[e] = ne;
-        }
+      for (int e = 0; e < EPT; ++e) {
+        mS[gi - 1][e][tl] = S[e];
+        mX[gi - 1][e][tl] = Xe[e];
       }
     }
+    __syncthreads();
+    if (gi > 0) return;
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+#pragma unroll
+      for (int k = 0; k < NG - 1; ++k) {
+        const int xb = mX[k][e][tl];
+        const int ne = max(Xe[e], xb);
+        S[e] = ldexp(S[e], Xe[e] - ne) + ldexp(mS[k][e][tl], xb - ne);
+        Xe[e] = ne;
+      }
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
     const int col = tl + GT * e;
-    if (gi == 0 && col < N) {
+    if (col < N) {
       partS[(int64_t)band * N + col] = S[e];
       partX[(int64_t)band * N + col] = Xe[e];
     }
   }
+}
+
+// One band of the grouped pass: the band's first row is loaded before the
+// move of g is reduced (D+, D-) and g/eps is staged in LDS, so its latency
+// overlaps both; then the rows run with shifted or exact row maxima.
+template <int EPT, int NG, bool PF>
+GW_DEV void sk_rowg_band(const double* __restrict__ C, int64_t ldC, int M, int N, int RB,
+                         double cs, double inv_eps, const double* __restrict__ p,
+                         const double* __restrict__ g, const double* __restrict__ gprev,
+                         double* __restrict__ f, double* __restrict__ ms,
+                         double* __restrict__ partS, int* __restrict__ partX,
+                         double* __restrict__ lse, int write_f, int band) {
+  constexpr int GT = 1024 / NG;
+  auto& lds = rowg_lds<EPT, NG>();
+  const int t = opaque_tid(), gi = __builtin_amdgcn_readfirstlane(t / GT), tl = t - gi * GT;
+  const int i0 = band * RB, i1 = min(M, i0 + RB);
+  int colc[EPT];  // column of each entry, clamped into range
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) colc[e] = min(tl + GT * e, N - 1);
+  double x[EPT];
+  {
+    const double* row = C + (int64_t)min(i0 + gi, i1 - 1) * ldC;
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) x[e] = row[colc[e]];
+  }
+  const double dup = pass_shift<1024>(g, gprev, N, inv_eps, lds.dred);
+  double* gie = lds.u.gie;
+  for (int c = t; c < EPT * GT; c += 1024) gie[c] = c < N ? g[c] * inv_eps : -INFINITY;
+  __syncthreads();
+  const double csie = cs * inv_eps;
+  if (dup >= 0.0)
+    sk_rowg_rows<EPT, NG, PF, true>(C, ldC, M, N, RB, csie, p, f, ms, partS, partX, lse, dup,
+                                    write_f, band, t, x, colc);
+  else
+    sk_rowg_rows<EPT, NG, PF, false>(C, ldC, M, N, RB, csie, p, f, ms, partS, partX, lse, 0.0,
+                                     write_f, band, t, x, colc);
 }
 
 template <int EPT, int NG, bool PF>
@@ -563,14 +608,8 @@ __global__ __launch_bounds__(1024) void k_sk_rowg(const double* __restrict__ C, 
                                                    double* __restrict__ lse,
                                                    const double* __restrict__ gprev,
                                                    int write_f) {
-  auto& lds = rowg_lds<EPT, NG>();
-  const double dup = pass_shift<1024>(g, gprev, N, inv_eps, lds.dred);
-  if (dup >= 0.0)
-    sk_rowg_band<EPT, NG, PF, true>(C, ldC, M, N, RB, cs, inv_eps, p, g, f, ms, partS, partX,
-                                    lse, dup, write_f, blockIdx.x);
-  else
-    sk_rowg_band<EPT, NG, PF, false>(C, ldC, M, N, RB, cs, inv_eps, p, g, f, ms, partS, partX,
-                                     lse, 0.0, write_f, blockIdx.x);
+  sk_rowg_band<EPT, NG, PF>(C, ldC, M, N, RB, cs, inv_eps, p, g, gprev, f, ms, partS, partX,
+                            lse, write_f, blockIdx.x);
 }
 
 // Column merge: a block covers 16 columns x 16 groups of bands; each thread
@@ -761,12 +800,14 @@ constexpr bool row_pf() {
 }
 
 template <int NTH, int EPT>
-void launch_row(int nb, hipStream_t s, const double* C, int64_t ldC, int M, int N, int RB,
-                double cs, double inv_eps, const double* p, const double* logp,
-                const double* g, double* f, double* ms, double* pS, int* pX, double* lse,
-                const double* gprev, int last) {
+void launch_row(int nb, hipStream_t s, hipEvent_t eb, hipEvent_t ee, const double* C,
+                int64_t ldC, int M, int N, int RB, double cs, double inv_eps, const double* p,
+                const double* logp, const double* g, double* f, double* ms, double* pS, int* pX,
+                double* lse, const double* gprev, int last) {
   constexpr int R = row_group<NTH, EPT>();
-  k_sk_row<NTH, EPT, R, row_gl<NTH, EPT>(), row_pf<NTH, EPT>()><<<nb, NTH, 0, s>>>(C, ldC, M, N, RB, cs, inv_eps, p, logp, g, f, ms, pS, pX, lse, gprev, last);
+  hipExtLaunchKernelGGL(k_sk_row<NTH, EPT, R, row_gl<NTH, EPT>(), row_pf<NTH, EPT>()>, dim3(nb),
+                        dim3(NTH), 0, s, eb, ee, 0, C, ldC, M, N, RB, cs, inv_eps, p, logp, g, f,
+                        ms, pS, pX, lse, gprev, last);
 }
 
 // ---------------------------------------------------------------------------
@@ -822,15 +863,9 @@ __global__ __launch_bounds__(1024) void k_skb_rowg(const gwb::SkSlot* __restrict
     __syncthreads();
     const int tt = a.it0 + j;
     const int band = (int)(code & ((1u << gwb::kBandBits) - 1));
-    auto& lds = rowg_lds<8, 2>();
-    const double dup = pass_shift<1024>(a.g, tt > 0 ? a.gprev : nullptr, a.N, a.inv_eps, lds.dred);
-    const int wf = a.last && j == a.its - 1;
-    if (dup >= 0.0)
-      sk_rowg_band<8, 2, true, true>(a.C, a.ldC, a.M, a.N, a.RB, a.cs, a.inv_eps, a.p, a.g, a.f,
-                                     a.ms, a.pS, a.pX, a.lse, dup, wf, band);
-    else
-      sk_rowg_band<8, 2, true, false>(a.C, a.ldC, a.M, a.N, a.RB, a.cs, a.inv_eps, a.p, a.g, a.f,
-                                      a.ms, a.pS, a.pX, a.lse, 0.0, wf, band);
+    sk_rowg_band<8, 2, true>(a.C, a.ldC, a.M, a.N, a.RB, a.cs, a.inv_eps, a.p, a.g,
+                             tt > 0 ? a.gprev : nullptr, a.f, a.ms, a.pS, a.pX, a.lse,
+                             a.last && j == a.its - 1, band);
   }
 }
 
@@ -932,26 +967,29 @@ gw_status sinkhorn(const double* C, int64_t ldC, int64_t M, int64_t N, double c_
   const int Mi = (int)M, Ni = (int)N;
   for (int it = 0; it < iters; ++it) {
     {
-      gwr::ProfScope ps(gwr::kFamSinkRow, s);
+      gwr::ProfDispatch pd(gwr::kFamSinkRow);
+      hipEvent_t eb = pd.b, ee = pd.e;
       const int lst = it == iters - 1;
       const double* gp = it > 0 ? gprev : nullptr;
       switch (gwb::row_class(N)) {
-        case gwb::kClsN256: launch_row<256, 1>(nb, s, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, lse, gp, lst); break;
-        case gwb::kClsN512: launch_row<512, 1>(nb, s, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, lse, gp, lst); break;
-        case gwb::kClsN1024: launch_row<1024, 1>(nb, s, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, lse, gp, lst); break;
-        case gwb::kClsN2048: launch_row<1024, 2>(nb, s, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, lse, gp, lst); break;
-        case gwb::kClsN3072: launch_row<256, 12>(nb, s, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, lse, gp, lst); break;
-        case gwb::kClsN4096: k_sk_rowg<8, 2, true><<<nb, 1024, 0, s>>>(C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, g, f, ms, pS, pX, lse, gp, lst); break;
-        case gwb::kClsN6144: launch_row<512, 12>(nb, s, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, lse, gp, lst); break;
-        case gwb::kClsN8192: launch_row<512, 16>(nb, s, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, lse, gp, lst); break;
-        case gwb::kClsN9216: launch_row<512, 18>(nb, s, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, lse, gp, lst); break;
-        case gwb::kClsN12288: launch_row<512, 24>(nb, s, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, lse, gp, lst); break;
-        default: launch_row<512, 32>(nb, s, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, lse, gp, lst); break;
+        case gwb::kClsN256: launch_row<256, 1>(nb, s, eb, ee, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, lse, gp, lst); break;
+        case gwb::kClsN512: launch_row<512, 1>(nb, s, eb, ee, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, lse, gp, lst); break;
+        case gwb::kClsN1024: launch_row<1024, 1>(nb, s, eb, ee, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, lse, gp, lst); break;
+        case gwb::kClsN2048: launch_row<1024, 2>(nb, s, eb, ee, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, lse, gp, lst); break;
+        case gwb::kClsN3072: launch_row<256, 12>(nb, s, eb, ee, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, lse, gp, lst); break;
+        case gwb::kClsN4096: hipExtLaunchKernelGGL(k_sk_rowg<8, 2, true>, dim3(nb), dim3(1024), 0, s, eb, ee, 0, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, g, f, ms, pS, pX, lse, gp, lst); break;
+        case gwb::kClsN6144: launch_row<512, 12>(nb, s, eb, ee, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, lse, gp, lst); break;
+        case gwb::kClsN8192: launch_row<512, 16>(nb, s, eb, ee, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, lse, gp, lst); break;
+        case gwb::kClsN9216: launch_row<512, 18>(nb, s, eb, ee, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, lse, gp, lst); break;
+        case gwb::kClsN12288: launch_row<512, 24>(nb, s, eb, ee, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, lse, gp, lst); break;
+        default: launch_row<512, 32>(nb, s, eb, ee, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, lse, gp, lst); break;
       }
     }
     {
-      gwr::ProfScope ps(gwr::kFamSinkCol, s);
-      k_sk_col<<<(unsigned)((N + MERGE_COLS - 1) / MERGE_COLS), 256, 0, s>>>(Ni, nb, pS, pX, q, logq, eps, g, status, gprev);
+      gwr::ProfDispatch pd(gwr::kFamSinkCol);
+      hipExtLaunchKernelGGL(k_sk_col, dim3((unsigned)((N + MERGE_COLS - 1) / MERGE_COLS)),
+                            dim3(256), 0, s, pd.b, pd.e, 0, Ni, nb, pS, pX, q, logq, eps, g,
+                            status, gprev);
     }
   }
   return sinkhorn_finish(C, ldC, M, N, c_scale, p, logp, ms, eps, iters, f, g, T, ldT, s, status);

@@ -163,6 +163,24 @@ def test_sinkhorn_matches_oracle(M, N, eps, iters):
     assert err(T.cpu().numpy(), P0) <= TOL
 
 
+def test_sinkhorn_extreme_ratio_exact_then_shifted_passes():
+    """C/eps up to 7000: the first update moves g by more than 600 eps (the
+    next pass takes exact maxima), later ones by a few eps (shifted passes)."""
+    gw, torch = _gw()
+    rng = inputs.rng_for(206)
+    M, N = 90, 70
+    C = rng.uniform(0, 4, size=(M, N))
+    C[:, 5] += 3.0
+    p, q = inputs.dirichlet(M, rng), inputs.dirichlet(N, rng)
+    eps = 1e-3
+    f0, g0 = O.sinkhorn(C, p, q, eps, 6)
+    f, g, T = gw.sinkhorn(_to_dev(torch, C), _to_dev(torch, p), _to_dev(torch, q), eps, 6, plan=True)
+    torch.cuda.synchronize()
+    assert err(f.cpu().numpy(), f0) <= TOL
+    assert err(g.cpu().numpy(), g0) <= TOL
+    assert err(T.cpu().numpy(), O.plan(C, f0, g0, eps)) <= TOL
+
+
 def test_sinkhorn_zero_mass_and_extreme_ratio():
     gw, torch = _gw()
     rng = inputs.rng_for(206)
