@@ -102,4 +102,25 @@ GW_DEV double ipow(double d, int k) {
   return v;
 }
 
+// Masked stores without a branch: a raw buffer resource over `base` (a
+// wave-uniform address) covering kRsrcBytes, and a store that every lane
+// issues; lanes whose byte offset is kOffDrop or above fall outside the
+// resource's range and are dropped by the hardware.  With no branch around
+// stores, the number of memory operations in flight is the same on every
+// path, so later waits for loads are not widened to cover the stores.
+// In-range offsets must stay below kRsrcBytes.
+constexpr int kRsrcBytes = 1 << 16;
+constexpr int kOffDrop = 1 << 30;
+typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
+
+GW_DEV __amdgpu_buffer_rsrc_t buffer_rsrc(const void* base) {
+  // 0x00020000: the raw-buffer data format word of the gfx9 family
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, kRsrcBytes,
+                                           0x00020000);
+}
+
+GW_DEV void buffer_store_f64(double v, __amdgpu_buffer_rsrc_t r, int byte_off) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, v), r, byte_off, 0, 0);
+}
+
 }  // namespace gwk

@@ -133,7 +133,8 @@ __global__ __launch_bounds__(256) void k_p1_moments(const double* __restrict__ T
   constexpr int KM = (KX > KY ? KX : KY) + 1;
   __shared__ double X[TS][LDS_STRIDE];
   __shared__ double part[2][NSEG][TS][2 * KM];
-  const int t = threadIdx.x, lane = t & (TS - 1), seg = t >> 6;
+  // seg is the wave index: kept in a scalar register, so row addresses are scalar
+  const int t = threadIdx.x, lane = t & (TS - 1), seg = __builtin_amdgcn_readfirstlane(t >> 6);
   const int ntiles = nI * nJ;
   // Two tiles in flight: the tile processed now was requested two tiles ago.
   double pfa[SEG], pfb[SEG];
@@ -147,7 +148,11 @@ __global__ __launch_bounds__(256) void k_p1_moments(const double* __restrict__ T
     }
   };
   const int stride = gridDim.x;
-  auto body = [&](double (&pf)[SEG], int tile) {
+  // tile_in >= ntiles: a pass over the last tile whose stores are dropped, so
+  // that both bodies of the loop run on every iteration
+  auto body = [&](double (&pf)[SEG], int tile_in) {
+    const bool live = tile_in < ntiles;
+    const int tile = min(tile_in, ntiles - 1);
     const int I = tile / nJ, J = tile - I * nJ;
     const int js = I * TS, qs = J * TS;
     const int h = min(TS, M - js), w = min(TS, N - qs);
@@ -179,38 +184,76 @@ __global__ __launch_bounds__(256) void k_p1_moments(const double* __restrict__ T
       }
     }
     __syncthreads();
-    if (t < TS) {
-      if (t < h) {
-        double a[KY + 1], b[KY + 1];
-        combine_segments<KY, KM, TS>(part[0], t, a, b);
+    // wave 0 writes the row moments of the tile's rows, wave 1 the column
+    // moments of its columns; every wave issues the same KM x 2 stores (the
+    // others and the unused ones dropped by the buffer range check), so no
+    // branch surrounds a store
+    {
+      double a[KM], b[KM];
+#pragma unroll
+      for (int r = 0; r < KM; ++r) a[r] = b[r] = 0.0;
+      bool ok = false;
+      if (seg == 0) {
+        double ra[KY + 1], rb[KY + 1];
+        combine_segments<KY, KM, TS>(part[0], lane, ra, rb);
 #pragma unroll
         for (int r = 0; r <= KY; ++r) {
-          rowmom[((size_t)(0 * nJ + J) * (KY + 1) + r) * M + js + t] = a[r];
-          rowmom[((size_t)(1 * nJ + J) * (KY + 1) + r) * M + js + t] = b[r];
+          a[r] = ra[r];
+          b[r] = rb[r];
         }
-      }
-    } else if (t < 2 * TS) {
-      const int c = t - TS;
-      if (c < w) {
-        double a[KX + 1], b[KX + 1];
-        combine_segments<KX, KM, TS>(part[1], c, a, b);
+        ok = live && lane < h;
+      } else if (seg == 1) {
+        double ca[KX + 1], cb[KX + 1];
+        combine_segments<KX, KM, TS>(part[1], lane, ca, cb);
 #pragma unroll
         for (int r = 0; r <= KX; ++r) {
-          colmom[((size_t)(0 * nI + I) * (KX + 1) + r) * N + qs + c] = a[r];
-          colmom[((size_t)(1 * nI + I) * (KX + 1) + r) * N + qs + c] = b[r];
+          a[r] = ca[r];
+          b[r] = cb[r];
         }
+        ok = live && lane < w;
+      }
+#pragma unroll
+      for (int r = 0; r < KM; ++r) {
+        // moment row (direction, tile, r) of the wave's array, at the tile's first line
+        const double* pa;
+        const double* pb;
+        bool okr;
+        if (seg == 0) {
+          okr = ok && r <= KY;
+          const int rr = min(r, KY);
+          pa = rowmom + ((size_t)(0 * nJ + J) * (KY + 1) + rr) * M + js;
+          pb = rowmom + ((size_t)(1 * nJ + J) * (KY + 1) + rr) * M + js;
+        } else {
+          okr = seg == 1 && ok && r <= KX;
+          const int rr = min(r, KX);
+          pa = colmom + ((size_t)(0 * nI + I) * (KX + 1) + rr) * N + qs;
+          pb = colmom + ((size_t)(1 * nI + I) * (KX + 1) + rr) * N + qs;
+        }
+        const int off = okr ? lane * 8 : gwk::kOffDrop;
+        gwk::buffer_store_f64(a[r], gwk::buffer_rsrc(pa), off);
+        gwk::buffer_store_f64(b[r], gwk::buffer_rsrc(pb), off);
       }
     }
     __syncthreads();
   };
   int tile = blockIdx.x;
   if (tile < ntiles) {
+    // the prologue issues the same memory operations between the two
+    // prefetches as a loop iteration (its stores dropped, at distinct and
+    // non-adjacent offsets so that none is merged with another), so the waits
+    // for a prefetched tile do not also cover the stores that follow it
     load_tile(pfa, tile);
+#pragma unroll
+    for (int u = 0; u < 2 * KM; ++u)
+      gwk::buffer_store_f64(0.0, gwk::buffer_rsrc(rowmom), gwk::kOffDrop + 64 * u);
     load_tile(pfb, min(tile + stride, ntiles - 1));
+#pragma unroll
+    for (int u = 0; u < 2 * KM; ++u)
+      gwk::buffer_store_f64(0.0, gwk::buffer_rsrc(rowmom), gwk::kOffDrop + 64 * u);
   }
   for (; tile < ntiles; tile += 2 * stride) {
     body(pfa, tile);
-    if (tile + stride < ntiles) body(pfb, tile + stride);
+    body(pfb, tile + stride);
   }
 }
 
@@ -239,15 +282,22 @@ GW_DEV void scan_lines(double* base, size_t stride, int line, bool valid, int nt
   constexpr int PF = 8;  // tiles loaded ahead of the recurrence
   const int cs = (ntiles + CH - 1) / CH;
   const int s0 = ch * cs, s1 = min(ntiles, s0 + cs);
+  // Loads are unconditional (the tile index clamped into this chunk), so all
+  // PF tiles are in flight at once; entries past the chunk are zeroed after.
   auto load = [&](const double* db, double (&buf)[PF][K + 1], int sb, int dir) {
 #pragma unroll
     for (int u = 0; u < PF; ++u) {
-      const int sidx = sb + u;
+      const int sidx = min(sb + u, s1 - 1);
       const int tt = dir == 0 ? sidx : ntiles - 1 - sidx;
 #pragma unroll
-      for (int r = 0; r <= K; ++r)
-        buf[u][r] = (valid && sidx < s1) ? db[((size_t)tt * (K + 1) + r) * stride] : 0.0;
+      for (int r = 0; r <= K; ++r) buf[u][r] = db[((size_t)tt * (K + 1) + r) * stride];
     }
+#pragma unroll
+    for (int u = 0; u < PF; ++u)
+      if (!(valid && sb + u < s1)) {
+#pragma unroll
+        for (int r = 0; r <= K; ++r) buf[u][r] = 0.0;
+      }
   };
   // pass 1: chunk aggregates and spans in both directions
 #pragma unroll
@@ -372,11 +422,13 @@ __global__ __launch_bounds__(256) void k_p2c(int N, int nJ, const double* __rest
   const int nround = (nJ + P2C_TILES - 1) / P2C_TILES;
   const int sb = tl * TS + seg * SEG;  // segment start within a round
   auto stage_in = [&](int e0) {
+    double v[P2C_ROUND / 256];  // all loads issued before any is used (indices clamped)
+#pragma unroll
+    for (int c = 0; c < P2C_ROUND / 256; ++c) v[c] = vec[min(e0 + t + 256 * c, N - 1)];
 #pragma unroll
     for (int c = 0; c < P2C_ROUND / 256; ++c) {
       const int i = t + 256 * c;
-      const int p = e0 + i;
-      stg[stg_index(i)] = p < N ? vec[p] : 0.0;
+      stg[stg_index(i)] = e0 + i < N ? v[c] : 0.0;
     }
   };
   auto summaries = [&](double (&x)[SEG]) {
@@ -550,7 +602,8 @@ __global__ __launch_bounds__(256) void k_p3_tile(const double* __restrict__ T, i
   constexpr int KM = (KX > KY ? KX : KY) + 1;
   __shared__ double X[TS][LDS_STRIDE];
   __shared__ double sums[2][NSEG][TS][KM];  // [pre/suf][seg][line][r]
-  const int t = threadIdx.x, lane = t & (TS - 1), seg = t >> 6;
+  // seg is the wave index: kept in a scalar register, so row addresses are scalar
+  const int t = threadIdx.x, lane = t & (TS - 1), seg = __builtin_amdgcn_readfirstlane(t >> 6);
   const int ntiles = nI * nJ;
   double pf[SEG];  // the next tile, requested while this one is processed
   auto load_tile = [&](double (&dst)[SEG], int tile) {
@@ -567,20 +620,18 @@ __global__ __launch_bounds__(256) void k_p3_tile(const double* __restrict__ T, i
     const int I = tile / nJ, J = tile - I * nJ;
     const int js = I * TS, qs = J * TS;
     const int h = min(TS, M - js), w = min(TS, N - qs);
-    double x[SEG];
-#pragma unroll
-    for (int i = 0; i < SEG; ++i) x[i] = (seg * SEG + i < h && lane < w) ? pf[i] : 0.0;
-    load_tile(pf, min(tile + stride, ntiles - 1));
     // carries for this tile: row carries of the thread's row, A's column
-    // carries of its column (loaded now, used after the barriers)
+    // carries of its column, and c2 of its column (used after the barriers).
+    // They are requested before the next tile: loads complete in issue order,
+    // so waiting for them then leaves the next tile's loads in flight.
     double ra[KY + 1], rb[KY + 1], ca[KX + 1], cb[KX + 1];
+    const double c2v = c2[min(qs + lane, N - 1)];
     {
       const int row = min(js + lane, M - 1);
-      const double keep = lane < h ? 1.0 : 0.0;
 #pragma unroll
       for (int r = 0; r <= KY; ++r) {
-        ra[r] = keep * rowmom[((size_t)(0 * nJ + J) * (KY + 1) + r) * M + row];
-        rb[r] = keep * rowmom[((size_t)(1 * nJ + J) * (KY + 1) + r) * M + row];
+        ra[r] = rowmom[((size_t)(0 * nJ + J) * (KY + 1) + r) * M + row];
+        rb[r] = rowmom[((size_t)(1 * nJ + J) * (KY + 1) + r) * M + row];
       }
       const int col = min(qs + lane, N - 1);
 #pragma unroll
@@ -589,8 +640,16 @@ __global__ __launch_bounds__(256) void k_p3_tile(const double* __restrict__ T, i
         cb[r] = acarry[((size_t)(1 * nI + I) * (KX + 1) + r) * N + col];
       }
     }
+    // the tile goes to LDS straight from the prefetch registers, which then
+    // take the next tile (the same registers in every iteration)
 #pragma unroll
-    for (int i = 0; i < SEG; ++i) X[seg * SEG + i][lane] = x[i];
+    for (int i = 0; i < SEG; ++i) X[seg * SEG + i][lane] = (seg * SEG + i < h && lane < w) ? pf[i] : 0.0;
+    load_tile(pf, min(tile + stride, ntiles - 1));
+    if (lane >= h) {  // rows past the matrix carry nothing
+#pragma unroll
+      for (int r = 0; r <= KY; ++r) ra[r] = rb[r] = 0.0;
+    }
+    double x[SEG];
     __syncthreads();
     // ---- row phase
 #pragma unroll
@@ -646,17 +705,27 @@ __global__ __launch_bounds__(256) void k_p3_tile(const double* __restrict__ T, i
       for (int r = 0; r <= KX; ++r) cb[r] += sums[1][sg][lane][r];
     }
     seg_sweep<KX>(x, ca, cb, out);
-    if (lane < w) {
-      const double c2v = c2[qs + lane];
+    // every lane stores (rows and columns past the matrix are dropped by the
+    // buffer range check): no branch around the stores
 #pragma unroll
-      for (int i = 0; i < SEG; ++i) {
-        const int r = seg * SEG + i;
-        if (r < h) G[(int64_t)(js + r) * ldG + qs + lane] = (c1[js + r] + c2v) - s2 * out[i];
-      }
+    for (int i = 0; i < SEG; ++i) {
+      const int r = seg * SEG + i;  // wave-uniform
+      const int row = min(js + r, M - 1);
+      const double v = (c1[row] + c2v) - s2 * out[i];
+      gwk::buffer_store_f64(v, gwk::buffer_rsrc(G + (int64_t)row * ldG + qs),
+                            (r < h && lane < w) ? lane * 8 : gwk::kOffDrop);
     }
     __syncthreads();
   };
-  if ((int)blockIdx.x < ntiles) load_tile(pf, blockIdx.x);
+  if ((int)blockIdx.x < ntiles) {
+    load_tile(pf, blockIdx.x);
+    // as many (dropped) stores after the first prefetch as a tile issues after
+    // its prefetch, so the wait for a prefetched tile never covers the stores
+    // (distinct, non-adjacent offsets: identical stores would be merged into
+    // one, adjacent ones into wider stores)
+#pragma unroll
+    for (int u = 0; u < SEG; ++u) gwk::buffer_store_f64(0.0, gwk::buffer_rsrc(G), gwk::kOffDrop + 64 * u);
+  }
   for (int tile = blockIdx.x; tile < ntiles; tile += stride) body(tile);
 }
 

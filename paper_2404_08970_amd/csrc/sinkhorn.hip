@@ -64,8 +64,8 @@ GW_DEV double shift_from_spread(double up, double dn) {
 
 // D+ for the pass (or -1: exact maxima) from g and g before the last merge
 // (gprev, null in the first iteration of a call), reduced over all columns by
-// the block; every block computes the same value.
-template <int NT>
+// the block; every block computes the same value.  N <= NT * NC.
+template <int NT, int NC>
 GW_DEV double pass_shift(const double* __restrict__ g, const double* __restrict__ gprev, int N,
                          double inv_eps, double (*red2)[2]);
 
@@ -79,12 +79,22 @@ GW_DEV void fold_move(double gn, double go, double& up, double& dn) {
   }
 }
 
-template <int NT>
+template <int NT, int NC>
 GW_DEV double pass_shift(const double* __restrict__ g, const double* __restrict__ gprev, int N,
                          double inv_eps, double (*red2)[2]) {
   if (gprev == nullptr) return -1.0;
+  // every load is issued before any is used (indices clamped into range)
+  double gn[NC], go[NC];
+#pragma unroll
+  for (int k = 0; k < NC; ++k) {
+    const int c = min((int)threadIdx.x + NT * k, N - 1);
+    gn[k] = g[c];
+    go[k] = gprev[c];
+  }
   double up = 0.0, dn = 0.0;
-  for (int c = threadIdx.x; c < N; c += NT) fold_move(g[c], gprev[c], up, dn);
+#pragma unroll
+  for (int k = 0; k < NC; ++k)
+    if ((int)threadIdx.x + NT * k < N) fold_move(gn[k], go[k], up, dn);
   up = gwk::wave_max(up) * inv_eps;
   dn = gwk::wave_max(dn) * inv_eps;
   const int w = threadIdx.x >> 6;
@@ -248,14 +258,41 @@ GW_DEV void sk_row_band(const double* __restrict__ C, int64_t ldC, int M, int N,
   double S[EPT];
   int Xe[EPT];
   double gir[GL ? 1 : EPT];  // g_p / eps
+  if constexpr (GL && EPT > 24) {
+    // g/eps to LDS one entry at a time (the longest rows have no registers to
+    // spare for a batch of loads)
 #pragma unroll
-  for (int e = 0; e < EPT; ++e) {
-    const int col = t + NTH * e;
-    S[e] = 0.0;
-    Xe[e] = EXP_SENTINEL;
-    const double gv = col < N ? g[col] * inv_eps : -INFINITY;
-    if constexpr (GL) gls[t + NTH * e] = gv;
-    else gir[e] = gv;
+    for (int e = 0; e < EPT; ++e) {
+      const int col = t + NTH * e;
+      S[e] = 0.0;
+      Xe[e] = EXP_SENTINEL;
+      gls[t + NTH * e] = col < N ? g[col] * inv_eps : -INFINITY;
+    }
+  } else if constexpr (GL) {
+    // g/eps to LDS, loads issued 8 at a time before they are used
+#pragma unroll
+    for (int e0 = 0; e0 < EPT; e0 += 8) {
+      double graw[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) graw[u] = g[min(t + NTH * min(e0 + u, EPT - 1), N - 1)];
+#pragma unroll
+      for (int u = 0; u < 8 && e0 + u < EPT; ++u) {
+        const int e = e0 + u, col = t + NTH * e;
+        S[e] = 0.0;
+        Xe[e] = EXP_SENTINEL;
+        gls[col] = col < N ? graw[u] * inv_eps : -INFINITY;
+      }
+    }
+  } else {
+    double graw[EPT];  // all loads issued before any is used (indices clamped)
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) graw[e] = g[min(t + NTH * e, N - 1)];
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      S[e] = 0.0;
+      Xe[e] = EXP_SENTINEL;
+      gir[e] = t + NTH * e < N ? graw[e] * inv_eps : -INFINITY;
+    }
   }
   if constexpr (GL) __syncthreads();
   auto gie = [&](int e) -> double {
@@ -404,7 +441,8 @@ __global__ __launch_bounds__(NTH) void k_sk_row(const double* __restrict__ C, in
   // the longest rows (no register prefetch) always take the exact maxima:
   // their shifted variant spills more registers than it saves
   double dup = -1.0;
-  if constexpr (PF) dup = pass_shift<NTH>(g, gprev, N, inv_eps, row_lds<NTH, EPT, R, GL>().dred);
+  if constexpr (PF)
+    dup = pass_shift<NTH, EPT>(g, gprev, N, inv_eps, row_lds<NTH, EPT, R, GL>().dred);
   if (PF && dup >= 0.0)
     sk_row_band<NTH, EPT, R, GL, PF, PF>(C, ldC, M, N, RB, cs, inv_eps, p, logp, g, f, ms,
                                          partS, partX, lse, dup, write_f, blockIdx.x);
@@ -582,9 +620,19 @@ GW_DEV void sk_rowg_band(const double* __restrict__ C, int64_t ldC, int M, int N
 #pragma unroll
     for (int e = 0; e < EPT; ++e) x[e] = row[colc[e]];
   }
-  const double dup = pass_shift<1024>(g, gprev, N, inv_eps, lds.dred);
+  const double dup = pass_shift<1024, EPT * GT / 1024>(g, gprev, N, inv_eps, lds.dred);
   double* gie = lds.u.gie;
-  for (int c = t; c < EPT * GT; c += 1024) gie[c] = c < N ? g[c] * inv_eps : -INFINITY;
+  {
+    constexpr int NF = EPT * GT / 1024;
+    double gv[NF];  // all loads issued before any is used (indices clamped)
+#pragma unroll
+    for (int k = 0; k < NF; ++k) gv[k] = g[min(t + 1024 * k, N - 1)];
+#pragma unroll
+    for (int k = 0; k < NF; ++k) {
+      const int c = t + 1024 * k;
+      gie[c] = c < N ? gv[k] * inv_eps : -INFINITY;
+    }
+  }
   __syncthreads();
   const double csie = cs * inv_eps;
   if (dup >= 0.0)
@@ -836,8 +884,8 @@ __global__ __launch_bounds__(NTH) void k_skb_row(const gwb::SkSlot* __restrict__
     constexpr bool PF = row_pf<NTH, EPT>();
     double dup = -1.0;  // exact maxima without the register prefetch, as in k_sk_row
     if constexpr (PF)
-      dup = pass_shift<NTH>(a.g, tt > 0 ? a.gprev : nullptr, a.N, a.inv_eps,
-                            row_lds<NTH, EPT, R, GL>().dred);
+      dup = pass_shift<NTH, EPT>(a.g, tt > 0 ? a.gprev : nullptr, a.N, a.inv_eps,
+                                 row_lds<NTH, EPT, R, GL>().dred);
     const int wf = a.last && j == a.its - 1;
     if (PF && dup >= 0.0)
       sk_row_band<NTH, EPT, R, GL, PF, PF>(a.C, a.ldC, a.M, a.N, a.RB, a.cs, a.inv_eps, a.p,
