@@ -120,6 +120,8 @@ GW_DEV void combine_segments(const double (*part)[LINES][2 * KM], int line, doub
 }
 
 // ---------------------------------------------------------------- P1 moments
+constexpr int P1_DEPTH = 2;  // tiles in flight per block (3 measured no faster)
+
 // Persistent blocks of 256 threads walk the tiles; thread (line, seg) holds a
 // 16-entry column segment of the tile in registers (loaded one tile ahead),
 // sums it for the column moments, and sums a row segment (through LDS) for
@@ -136,8 +138,9 @@ __global__ __launch_bounds__(256) void k_p1_moments(const double* __restrict__ T
   // seg is the wave index: kept in a scalar register, so row addresses are scalar
   const int t = threadIdx.x, lane = t & (TS - 1), seg = __builtin_amdgcn_readfirstlane(t >> 6);
   const int ntiles = nI * nJ;
-  // Two tiles in flight: the tile processed now was requested two tiles ago.
-  double pfa[SEG], pfb[SEG];
+  // P1_DEPTH tiles in flight: the tile processed now was requested P1_DEPTH
+  // tiles ago.
+  double pf3[P1_DEPTH][SEG];
   auto load_tile = [&](double (&pf)[SEG], int tile) {
     const int I = tile / nJ, J = tile - (tile / nJ) * nJ;
     const int col = min(J * TS + lane, N - 1);
@@ -159,7 +162,7 @@ __global__ __launch_bounds__(256) void k_p1_moments(const double* __restrict__ T
     double x[SEG];
 #pragma unroll
     for (int i = 0; i < SEG; ++i) x[i] = (seg * SEG + i < h && lane < w) ? pf[i] : 0.0;
-    load_tile(pf, min(tile + 2 * stride, ntiles - 1));
+    load_tile(pf, min(tile + P1_DEPTH * stride, ntiles - 1));
     {
       double pre[KX + 1], suf[KX + 1];
       seg_summaries<KX>(x, pre, suf);
@@ -238,22 +241,21 @@ __global__ __launch_bounds__(256) void k_p1_moments(const double* __restrict__ T
   };
   int tile = blockIdx.x;
   if (tile < ntiles) {
-    // the prologue issues the same memory operations between the two
+    // the prologue issues the same memory operations between the
     // prefetches as a loop iteration (its stores dropped, at distinct and
     // non-adjacent offsets so that none is merged with another), so the waits
     // for a prefetched tile do not also cover the stores that follow it
-    load_tile(pfa, tile);
 #pragma unroll
-    for (int u = 0; u < 2 * KM; ++u)
-      gwk::buffer_store_f64(0.0, gwk::buffer_rsrc(rowmom), gwk::kOffDrop + 64 * u);
-    load_tile(pfb, min(tile + stride, ntiles - 1));
+    for (int d = 0; d < P1_DEPTH; ++d) {
+      load_tile(pf3[d], min(tile + d * stride, ntiles - 1));
 #pragma unroll
-    for (int u = 0; u < 2 * KM; ++u)
-      gwk::buffer_store_f64(0.0, gwk::buffer_rsrc(rowmom), gwk::kOffDrop + 64 * u);
+      for (int u = 0; u < 2 * KM; ++u)
+        gwk::buffer_store_f64(0.0, gwk::buffer_rsrc(rowmom), gwk::kOffDrop + 64 * u);
+    }
   }
-  for (; tile < ntiles; tile += 2 * stride) {
-    body(pfa, tile);
-    body(pfb, tile + stride);
+  for (; tile < ntiles; tile += P1_DEPTH * stride) {
+#pragma unroll
+    for (int d = 0; d < P1_DEPTH; ++d) body(pf3[d], tile + d * stride);
   }
 }
 

@@ -620,20 +620,46 @@ GW_DEV void sk_rowg_band(const double* __restrict__ C, int64_t ldC, int M, int N
 #pragma unroll
     for (int e = 0; e < EPT; ++e) x[e] = row[colc[e]];
   }
-  const double dup = pass_shift<1024, EPT * GT / 1024>(g, gprev, N, inv_eps, lds.dred);
-  double* gie = lds.u.gie;
+  // g (and g before the last merge) are loaded once: g/eps goes to LDS and
+  // the move of g is reduced over the block, one barrier for both
+  double dup = -1.0;
   {
     constexpr int NF = EPT * GT / 1024;
-    double gv[NF];  // all loads issued before any is used (indices clamped)
+    double* gie = lds.u.gie;
+    double gv[NF], go[NF];  // all loads issued before any is used (indices clamped)
 #pragma unroll
     for (int k = 0; k < NF; ++k) gv[k] = g[min(t + 1024 * k, N - 1)];
+    if (gprev != nullptr) {
+#pragma unroll
+      for (int k = 0; k < NF; ++k) go[k] = gprev[min(t + 1024 * k, N - 1)];
+    }
+    double up = 0.0, dn = 0.0;
 #pragma unroll
     for (int k = 0; k < NF; ++k) {
       const int c = t + 1024 * k;
       gie[c] = c < N ? gv[k] * inv_eps : -INFINITY;
+      if (gprev != nullptr && c < N) fold_move(gv[k], go[k], up, dn);
+    }
+    if (gprev != nullptr) {
+      up = gwk::wave_max(up) * inv_eps;
+      dn = gwk::wave_max(dn) * inv_eps;
+      if ((t & 63) == 63) {
+        lds.dred[t >> 6][0] = up;
+        lds.dred[t >> 6][1] = dn;
+      }
+    }
+    __syncthreads();
+    if (gprev != nullptr) {
+      up = lds.dred[0][0];
+      dn = lds.dred[0][1];
+#pragma unroll
+      for (int w = 1; w < 16; ++w) {
+        up = fmax(up, lds.dred[w][0]);
+        dn = fmax(dn, lds.dred[w][1]);
+      }
+      dup = shift_from_spread(up, dn);
     }
   }
-  __syncthreads();
   const double csie = cs * inv_eps;
   if (dup >= 0.0)
     sk_rowg_rows<EPT, NG, PF, true>(C, ldC, M, N, RB, csie, p, f, ms, partS, partX, lse, dup,
@@ -664,6 +690,7 @@ __global__ __launch_bounds__(1024) void k_sk_rowg(const double* __restrict__ C, 
 // merges its groups' (mantissa, exponent) pairs in band order, then the 16
 // group results of a column are merged in group order.
 constexpr int MERGE_COLS = gwb::kMergeCols, MERGE_GRPS = 16;
+constexpr int MERGE_PER = 16;  // bands per group: nb <= 256 = MERGE_GRPS * MERGE_PER
 
 GW_DEV void sk_col_block(int N, int nb, const double* __restrict__ partS,
                          const int* __restrict__ partX, const double* __restrict__ q,
@@ -675,16 +702,29 @@ GW_DEV void sk_col_block(int N, int nb, const double* __restrict__ partS,
   const int col = cblock * MERGE_COLS + c;
   double S = 0.0;
   int X = EXP_SENTINEL;
-  if (col < N) {
+  {
+    // a group's bands (at most MERGE_PER) are all requested before the first
+    // is merged: indices clamped into range, entries past the group skipped
     const int per = (nb + MERGE_GRPS - 1) / MERGE_GRPS;
     const int b0 = grp * per, b1 = min(nb, b0 + per);
-#pragma unroll 8
-    for (int b = b0; b < b1; ++b) {
-      const double sb = partS[(int64_t)b * N + col];
-      const int xb = partX[(int64_t)b * N + col];
-      const int ne = max(X, xb);
-      S = ldexp(S, X - ne) + ldexp(sb, xb - ne);
-      X = ne;
+    const int colc = min(col, N - 1);
+    double sv[MERGE_PER];
+    int xv[MERGE_PER];
+#pragma unroll
+    for (int u = 0; u < MERGE_PER; ++u) {
+      const int64_t b = min(b0 + u, nb - 1);
+      sv[u] = partS[b * N + colc];
+      xv[u] = partX[b * N + colc];
+    }
+    if (col < N) {
+#pragma unroll
+      for (int u = 0; u < MERGE_PER; ++u) {
+        if (b0 + u < b1) {
+          const int ne = max(X, xv[u]);
+          S = ldexp(S, X - ne) + ldexp(sv[u], xv[u] - ne);
+          X = ne;
+        }
+      }
     }
   }
   ms[grp][c] = S;
