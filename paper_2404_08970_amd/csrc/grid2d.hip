@@ -32,6 +32,77 @@ constexpr int NT = 256;
 // contiguous ranges and their partial sums are added in wave order.
 constexpr int CT_GROUPS = 16;
 
+// Separable form of the same constant term for 2D grids: D^2 / hk^2 is a sum
+// of non-negative terms coef_t |dr|^er_t |dc|^ec_t (squared Euclidean:
+// dr^4 + 2 dr^2 dc^2 + dc^4; (L1)^k: sum_m C(2k, m) |dr|^m |dc|^(2k-m)), so
+// c[(ri, ci)] = hk^2 sum_t coef_t sum_rj |ri - rj|^er_t Z_t[rj][ci] with
+// Z_t[rj][ci] = sum_cj |ci - cj|^ec_t w[rj][cj]: O(N (H + W)) work instead of
+// O(N^2).  A block owns image column ci: the image of w and tables of the
+// powers are staged in LDS, a thread per (term, image row) builds Z_t (summed
+// over cj in order) and then its share of c, and the terms are added in order.
+struct SepConst {
+  int nt;  // number of terms (<= 9)
+  int er[9], ec[9];
+  double coef[9];
+};
+constexpr int CS_MAXT = 9;
+
+size_t const_sep_lds(int H, int W, int nt) {
+  return ((size_t)H * (W + 1) + (size_t)nt * (3 * H + W)) * sizeof(double);
+}
+
+__global__ __launch_bounds__(256) void k_const_sep(SepConst sc, int H, int W, double hk2,
+                                                    const double* __restrict__ w,
+                                                    double* __restrict__ c) {
+  extern __shared__ double sh[];
+  const int nt = sc.nt;
+  double* img = sh;                       // [H][W + 1] (padded rows)
+  double* z = img + (int64_t)H * (W + 1);  // [nt][H]  Z_t[rj] of this block's column
+  double* part = z + nt * H;              // [nt][H]  per-term sums of each row ri
+  double* pwr = part + nt * H;            // [nt][H]  d^er_t, d < H
+  double* pwc = pwr + nt * H;             // [nt][W]  d^ec_t, d < W
+  const int ci = blockIdx.x, n = H * W, tid = threadIdx.x;
+  // the image of w, loads issued 8 at a time before they are stored
+  for (int p0 = 0; p0 < n; p0 += 8 * 256) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = w[min(p0 + tid + u * 256, n - 1)];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int p = p0 + tid + u * 256;
+      if (p < n) img[(p / W) * (W + 1) + p % W] = v[u];
+    }
+  }
+  for (int x = tid; x < nt * H; x += 256) pwr[x] = gwk::ipow((double)(x % H), sc.er[x / H]);
+  for (int x = tid; x < nt * W; x += 256) pwc[x] = gwk::ipow((double)(x % W), sc.ec[x / W]);
+  __syncthreads();
+  // Z_t[rj] = sum_cj |ci - cj|^ec_t w[rj][cj], summed over cj in order
+  for (int x = tid; x < nt * H; x += 256) {
+    const int t = x / H, rj = x % H;
+    const double* pw = pwc + t * W;
+    const double* row = img + rj * (W + 1);
+    double acc = 0.0;
+    for (int cj = 0; cj < W; ++cj) acc = fma(pw[abs(ci - cj)], row[cj], acc);
+    z[x] = acc;
+  }
+  __syncthreads();
+  // per term: sum_rj |ri - rj|^er_t Z_t[rj]
+  for (int x = tid; x < nt * H; x += 256) {
+    const int t = x / H, ri = x % H;
+    const double* pw = pwr + t * H;
+    const double* zt = z + t * H;
+    double st = 0.0;
+    for (int rj = 0; rj < H; ++rj) st = fma(pw[abs(ri - rj)], zt[rj], st);
+    part[x] = st;
+  }
+  __syncthreads();
+  for (int ri = tid; ri < H; ri += 256) {
+    double s = 0.0;
+    for (int t = 0; t < nt; ++t) s = fma(sc.coef[t], part[t * H + ri], s);
+    c[(int64_t)ri * W + ci] = hk2 * s;
+  }
+}
+
 __global__ __launch_bounds__(1024) void k_const_term(int metric, int k, int H, int W, double hk,
                                                       const double* __restrict__ w,
                                                       double* __restrict__ c) {
@@ -316,25 +387,57 @@ struct SepGrid {
 };
 
 // U[i][a'] = sum_{b'} T[i][(a',b')], V[i][b'] = sum_{a'} T[i][(a',b')]; one
-// block per row of T, row staged in LDS.
+// block per row of T, row staged in LDS (loads issued 8 at a time before they
+// are stored).  Each line sum of the image is split into four quarters summed
+// by four adjacent lanes and combined in a fixed order.
+constexpr int RR_Q = 4;
 __global__ __launch_bounds__(NT) void k_sep_rowreduce(const double* __restrict__ T, int64_t ldT,
                                                        int64_t M, int64_t H2, int64_t W2,
                                                        double* __restrict__ U,
                                                        double* __restrict__ V) {
   extern __shared__ double img[];
   const int64_t i = blockIdx.x;
-  const int64_t n2 = H2 * W2;
-  for (int64_t p = threadIdx.x; p < n2; p += NT) img[p] = T[i * ldT + p];
-  __syncthreads();
-  for (int64_t a = threadIdx.x; a < H2; a += NT) {
-    double s = 0.0;
-    for (int64_t b = 0; b < W2; ++b) s += img[a * W2 + b];
-    U[i * H2 + a] = s;
+  const int n2 = (int)(H2 * W2), h2 = (int)H2, w2 = (int)W2;
+  const int t = threadIdx.x;
+  const double* row = T + i * ldT;
+  for (int p0 = 0; p0 < n2; p0 += 8 * NT) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = row[min(p0 + t + u * NT, n2 - 1)];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (p0 + t + u * NT < n2) img[p0 + t + u * NT] = v[u];
   }
-  for (int64_t b = threadIdx.x; b < W2; b += NT) {
+  __syncthreads();
+  // row sums of the image: four adjacent lanes per image row
+  const int q = t & (RR_Q - 1);
+  const int qlen = (w2 + RR_Q - 1) / RR_Q;
+  for (int a0 = 0; a0 < h2; a0 += NT / RR_Q) {
+    const int a = a0 + t / RR_Q;
     double s = 0.0;
-    for (int64_t a = 0; a < H2; ++a) s += img[a * W2 + b];
-    V[i * W2 + b] = s;
+    if (a < h2) {
+      const int b0 = q * qlen, b1 = min(w2, b0 + qlen);
+      for (int b = b0; b < b1; ++b) s += img[a * w2 + b];
+    }
+    const double s1 = __shfl_xor(s, 1);
+    const double s2 = __shfl_xor(s, 2);
+    const double s3 = __shfl_xor(s, 3);
+    // lane q = 0 holds quarter 0; fixed order (q0 + q1) + (q2 + q3)
+    if (q == 0 && a < h2) U[i * H2 + a] = (s + s1) + (s2 + s3);
+  }
+  // column sums: four adjacent lanes per image column, a quarter of the rows each
+  const int hlen = (h2 + RR_Q - 1) / RR_Q;
+  for (int b0 = 0; b0 < w2; b0 += NT / RR_Q) {
+    const int b = b0 + t / RR_Q;
+    double s = 0.0;
+    if (b < w2) {
+      const int a0 = q * hlen, a1 = min(h2, a0 + hlen);
+      for (int a = a0; a < a1; ++a) s += img[a * w2 + b];
+    }
+    const double s1 = __shfl_xor(s, 1);
+    const double s2 = __shfl_xor(s, 2);
+    const double s3 = __shfl_xor(s, 3);
+    if (q == 0 && b < w2) V[i * W2 + b] = (s + s1) + (s2 + s3);
   }
 }
 
@@ -352,53 +455,83 @@ __global__ __launch_bounds__(NT) void k_sep_colreduce(const double* __restrict__
   if (idx < n1) {
     const int64_t a = idx / H2, ap = idx % H2;
     double s = 0.0;
+#pragma unroll 8
     for (int64_t b = 0; b < W1; ++b) s += U[(a * W1 + b) * H2 + ap];
     R1[idx] = s;
   } else if (idx < n1 + n2) {
     const int64_t j = idx - n1, a = j / W2, bp = j % W2;
     double s = 0.0;
+#pragma unroll 8
     for (int64_t b = 0; b < W1; ++b) s += V[(a * W1 + b) * W2 + bp];
     R2[j] = s;
   } else if (idx < n1 + n2 + n3) {
     const int64_t j = idx - n1 - n2, b = j / H2, ap = j % H2;
     double s = 0.0;
+#pragma unroll 8
     for (int64_t a = 0; a < H1; ++a) s += U[(a * W1 + b) * H2 + ap];
     R3[j] = s;
   } else if (idx < n1 + n2 + n3 + n4) {
     const int64_t j = idx - n1 - n2 - n3, b = j / W2, bp = j % W2;
     double s = 0.0;
+#pragma unroll 8
     for (int64_t a = 0; a < H1; ++a) s += V[(a * W1 + b) * W2 + bp];
     R4[j] = s;
   }
 }
 
 // Q = S_x R S_y for the four small matrices (S = |i-j|^m, dense, short axes),
-// scaled by the Kronecker coefficients.  Two stages: P = S_x R, Q = P S_y.
-__global__ __launch_bounds__(NT) void k_sep_left(const double* __restrict__ R, int64_t nx,
-                                                  int64_t ny, int m, double* __restrict__ P) {
-  const int64_t idx = (int64_t)blockIdx.x * NT + threadIdx.x;
-  if (idx >= nx * ny) return;
-  const int64_t i = idx / ny, j = idx % ny;
-  double s = 0.0;
-  for (int64_t l = 0; l < nx; ++l) {
-    const double d = gwk::ipow((double)(i > l ? i - l : l - i), m);
-    s = fma(d, R[l * ny + j], s);
-  }
-  P[idx] = s;
+// scaled by the Kronecker coefficients.  Two launches, each covering all four
+// terms: P = S_x R with one block per (term, column of R), then Q = P S_y with
+// one block per (term, row of P); the line (at most `line` entries, dynamic
+// LDS) is staged once and every thread reads it as a broadcast.
+struct SepTerms {
+  const double* in[4];
+  double* out[4];
+  int nx[4], ny[4];
+  int first[5];  // first block of each term (cumulative line counts)
+  int m;         // exponent of S on this side
+  double coef[4];
+};
+constexpr int SEP_LINE = 128;  // threads of the product kernels
+
+GW_DEV int sep_term(const SepTerms& st) {
+  int t = 0;
+  while (t < 3 && (int)blockIdx.x >= st.first[t + 1]) ++t;
+  return t;
 }
 
-__global__ __launch_bounds__(NT) void k_sep_right(const double* __restrict__ P, int64_t nx,
-                                                   int64_t ny, int m, double coef,
-                                                   double* __restrict__ Q) {
-  const int64_t idx = (int64_t)blockIdx.x * NT + threadIdx.x;
-  if (idx >= nx * ny) return;
-  const int64_t i = idx / ny, j = idx % ny;
-  double s = 0.0;
-  for (int64_t l = 0; l < ny; ++l) {
-    const double d = gwk::ipow((double)(j > l ? j - l : l - j), m);
-    s = fma(P[i * ny + l], d, s);
+__global__ __launch_bounds__(SEP_LINE) void k_sep_left(SepTerms st) {
+  extern __shared__ double col[];
+  const int t = sep_term(st);
+  const int j = blockIdx.x - st.first[t], nx = st.nx[t], ny = st.ny[t];
+  const double* R = st.in[t];
+  for (int i = threadIdx.x; i < nx; i += SEP_LINE) col[i] = R[(int64_t)i * ny + j];
+  __syncthreads();
+  for (int i = threadIdx.x; i < nx; i += SEP_LINE) {
+    double s = 0.0;
+    for (int l = 0; l < nx; ++l) {
+      const double d = gwk::ipow((double)(i > l ? i - l : l - i), st.m);
+      s = fma(d, col[l], s);
+    }
+    st.out[t][(int64_t)i * ny + j] = s;
   }
-  Q[idx] = coef * s;
+}
+
+__global__ __launch_bounds__(SEP_LINE) void k_sep_right(SepTerms st) {
+  extern __shared__ double rowv[];
+  const int t = sep_term(st);
+  const int i = blockIdx.x - st.first[t], ny = st.ny[t];
+  const double* P = st.in[t] + (int64_t)i * ny;
+  for (int j = threadIdx.x; j < ny; j += SEP_LINE) rowv[j] = P[j];
+  __syncthreads();
+  for (int j = threadIdx.x; j < ny; j += SEP_LINE) {
+    double s = 0.0;
+    for (int l = 0; l < ny; ++l) {
+      const double d = gwk::ipow((double)(j > l ? j - l : l - j), st.m);
+      s = fma(rowv[l], d, s);
+    }
+    st.out[t][(int64_t)i * ny + j] = st.coef[t] * s;
+  }
 }
 
 // G[(a,b)][(a',b')] = (c1 + c2) - s2 (Q1[a][a'] + Q2[a][b'] + Q3[b][a'] + Q4[b][b'])
@@ -412,12 +545,25 @@ __global__ __launch_bounds__(NT) void k_sep_write(int64_t H1, int64_t W1, int64_
                                                    double* __restrict__ G, int64_t ldG) {
   const int64_t i = blockIdx.x;
   const int64_t a = i / W1, b = i % W1;
-  const int64_t n2 = H2 * W2;
   const double c1v = c1[i];
-  for (int64_t p = threadIdx.x; p < n2; p += NT) {
-    const int64_t ap = p / W2, bp = p % W2;
-    const double Bv = ((Q1[a * H2 + ap] + Q2[a * W2 + bp]) + Q3[b * H2 + ap]) + Q4[b * W2 + bp];
+  const int w2 = (int)W2, h2 = (int)H2;
+  auto put = [&](int ap, int bp, double q2, double q4) {
+    const int64_t p = (int64_t)ap * W2 + bp;
+    const double Bv = ((Q1[a * H2 + ap] + q2) + Q3[b * H2 + ap]) + q4;
     G[i * ldG + p] = (c1v + c2[p]) - s2 * Bv;
+  };
+  if (w2 <= NT) {
+    // NT / W2 image rows per pass: thread t takes column t % W2 of row t / W2
+    const int rpp = NT / w2, bp = threadIdx.x % w2, ar = threadIdx.x / w2;
+    if (ar < rpp) {
+      const double q2 = Q2[a * W2 + bp], q4 = Q4[b * W2 + bp];
+      for (int ap = ar; ap < h2; ap += rpp) put(ap, bp, q2, q4);
+    }
+  } else {
+    for (int bp = threadIdx.x; bp < w2; bp += NT) {
+      const double q2 = Q2[a * W2 + bp], q4 = Q4[b * W2 + bp];
+      for (int ap = 0; ap < h2; ++ap) put(ap, bp, q2, q4);
+    }
   }
 }
 
@@ -467,6 +613,42 @@ gw_status const_term(const gwr::Grid& g, const double* w, double* c, hipStream_t
   if (const_1d_ok(g)) {
     const ConstJob j = job_of(g, w, c);
     return launch_const_jobs(g.k1d(), 1, (int)n, j, j, s);
+  }
+  if (g.ndim == 2) {
+    SepConst sc{};
+    if (g.metric == GW_METRIC_SQEUCLID) {
+      sc.nt = 3;
+      const int er[3] = {4, 2, 0}, ec[3] = {0, 2, 4};
+      const double cf[3] = {1.0, 2.0, 1.0};
+      for (int t = 0; t < 3; ++t) {
+        sc.er[t] = er[t];
+        sc.ec[t] = ec[t];
+        sc.coef[t] = cf[t];
+      }
+    } else if (2 * g.k + 1 <= CS_MAXT) {
+      sc.nt = 2 * g.k + 1;
+      double binom = 1.0;  // C(2k, m)
+      for (int m = 0; m <= 2 * g.k; ++m) {
+        sc.er[m] = m;
+        sc.ec[m] = 2 * g.k - m;
+        sc.coef[m] = binom;
+        binom = binom * (double)(2 * g.k - m) / (double)(m + 1);
+      }
+    }
+    const size_t shm = const_sep_lds((int)g.H, (int)g.W, sc.nt);
+    if (sc.nt > 0 && shm <= 160 * 1024) {
+      static size_t shm_set = 0;  // dynamic LDS above the default, set once per size
+      if (shm > 64 * 1024 && shm > shm_set) {
+        if (hipFuncSetAttribute(reinterpret_cast<const void*>(&k_const_sep),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm) !=
+            hipSuccess)
+          return GW_EDEVICE;
+        shm_set = shm;
+      }
+      const double hk = g.hk();
+      k_const_sep<<<(unsigned)g.W, 256, shm, s>>>(sc, (int)g.H, (int)g.W, hk * hk, w, c);
+      return gwr::last_launch_status();
+    }
   }
   k_const_term<<<(unsigned)((n + 63) / 64), 1024, 0, s>>>(g.metric, g.k, (int)g.H, (int)g.W, g.hk(), w, c);
   return gwr::last_launch_status();
@@ -566,10 +748,41 @@ gw_status fast_generic(const gwr::Grid& X, const gwr::Grid& Y, const double* p,
     const int64_t ny[4] = {Y.H, Y.W, Y.H, Y.W};
     const double cx[4] = {sx.alpha, sx.alpha, sx.beta, sx.beta};
     const double cy[4] = {sy.alpha, sy.beta, sy.alpha, sy.beta};
+    SepTerms lt{}, rt{};
+    lt.first[0] = rt.first[0] = 0;
+    int64_t lmax = 1, rmax = 1;  // longest line of each launch
     for (int t = 0; t < 4; ++t) {
-      k_sep_left<<<blocks_for(nx[t] * ny[t]), NT, 0, s>>>(R[t], nx[t], ny[t], sx.m, P[t]);
-      k_sep_right<<<blocks_for(nx[t] * ny[t]), NT, 0, s>>>(P[t], nx[t], ny[t], sy.m, cx[t] * cy[t], Q[t]);
+      lmax = nx[t] > lmax ? nx[t] : lmax;
+      rmax = ny[t] > rmax ? ny[t] : rmax;
+      lt.in[t] = R[t];
+      lt.out[t] = P[t];
+      rt.in[t] = P[t];
+      rt.out[t] = Q[t];
+      lt.nx[t] = rt.nx[t] = (int)nx[t];
+      lt.ny[t] = rt.ny[t] = (int)ny[t];
+      lt.first[t + 1] = lt.first[t] + (int)ny[t];  // a block per column of R
+      rt.first[t + 1] = rt.first[t] + (int)nx[t];  // a block per row of P
+      rt.coef[t] = cx[t] * cy[t];
     }
+    lt.m = sx.m;
+    rt.m = sy.m;
+    const size_t lsh = (size_t)lmax * sizeof(double), rsh = (size_t)rmax * sizeof(double);
+    if (lsh > 160 * 1024 || rsh > 160 * 1024) return GW_EUNSUPPORTED;
+    static size_t lset = 0, rset = 0;  // dynamic LDS above the default, set once per size
+    if (lsh > 64 * 1024 && lsh > lset) {
+      if (hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sep_left),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lsh) != hipSuccess)
+        return GW_EDEVICE;
+      lset = lsh;
+    }
+    if (rsh > 64 * 1024 && rsh > rset) {
+      if (hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sep_right),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)rsh) != hipSuccess)
+        return GW_EDEVICE;
+      rset = rsh;
+    }
+    k_sep_left<<<(unsigned)lt.first[4], SEP_LINE, lsh, s>>>(lt);
+    k_sep_right<<<(unsigned)rt.first[4], SEP_LINE, rsh, s>>>(rt);
     k_sep_write<<<(unsigned)M, NT, 0, s>>>(X.H, X.W, Y.H, Y.W, Q[0], Q[1], Q[2], Q[3], c1, c2, s2, G, ldG);
     return gwr::last_launch_status();
   }

@@ -107,6 +107,8 @@ GRAD_2D = [
     ((6, 6), 2, 1, (40,), 2, 0),       # mixed 2D x 1D: generic
     ((33,), 1, 0, (5, 4), 2, 1),       # mixed 1D x 2D
     ((16, 16), 2, 1, (12, 20), 2, 1),  # SQEUCLID H != W
+    ((4, 6), 4, 0, (5, 3), 4, 0),      # l1^4: nine separable constant-term terms
+    ((3, 70), 2, 1, (70, 2), 2, 1),    # SQEUCLID, image sides beyond one wave
 ]
 
 
