@@ -42,7 +42,7 @@ typedef int32_t gw_status;
 #define GW_ENOMEM (-2)        /* workspace too small */
 #define GW_EDEVICE (-3)       /* a HIP runtime call failed */
 #define GW_ENUMERIC (-4)      /* device detected a non-finite value (gw_check_status) */
-#define GW_EUNSUPPORTED (-5)  /* valid request outside what this build implements */
+#define GW_EUNSUPPORTED (-5)  /* valid request outside what this library implements */
 #define GW_EAGAIN (-6)        /* request loop: the result is not ready yet */
 
 /* Distance on a grid (Sec. 2 and Sec. 3.1).

@@ -378,7 +378,7 @@ const char* gw_status_string(gw_status s) {
     case GW_ENOMEM: return "GW_ENOMEM: workspace too small";
     case GW_EDEVICE: return "GW_EDEVICE: HIP runtime error";
     case GW_ENUMERIC: return "GW_ENUMERIC: non-finite value detected on the device";
-    case GW_EUNSUPPORTED: return "GW_EUNSUPPORTED: request outside this build's coverage";
+    case GW_EUNSUPPORTED: return "GW_EUNSUPPORTED: request outside what this library implements";
   }
   return "unknown gw_status";
 }
