@@ -22,6 +22,8 @@ Everything here is written to be read against the paper (arXiv 2404.08970,
 * Pascal recursion for L x ....... Sec. 3, Eq. (1d y), Eq. (1d recursive relation)
 * four-term split of D Gamma D ... Sec. 3, Eq. (Dx)
 * 2D Kronecker expansion ......... Sec. 3.1, Eq. (2D kronecker), Eq. (2d gradient)
+* fused GW (FGW) ................. Remark (Entropic algorithm for FGW): objective
+                                   and gradient decomposition C_2 - 4 theta D Gamma D
 
 Two gradient routines are given.  ``grad_dense`` is the plain definition
 G = c1 1^T + 1 c2^T - 2 D_X T D_Y with explicit distance matrices (the
@@ -41,6 +43,9 @@ Readings where the paper is silent or garbled (each is repeated in the design doc):
 * T^0 = p q^T; Sinkhorn updates f then g, cold start each outer iteration,
   fixed iteration counts; LSE is max-shifted; p_i = 0 gives f_i = -inf.
 * SQEUCLID (h^2 (dr^2 + dc^2)) is supported beside the paper's (l1)^k metric.
+* FGW feature cost c_ip = fa_i - fb_p (its square enters): every FGW workload
+  of the paper has this form (|i - p|, signal-strength and gray-level
+  differences).
 
 Precision: float64 everywhere; no fused multiply-add is requested; sums run in
 index order except where a library primitive (numpy matmul / sum) is used as
@@ -358,3 +363,54 @@ def solve(gx: Grid, gy: Grid, p, q, eps: float, outer: int, inner: int,
     if f is None:
         f, g = np.zeros(p.shape[0]), np.zeros(q.shape[0])
     return T, f, g, objective(gx, gy, T, eps)
+
+
+# ---------------------------------------------------------------------------
+# Fused GW (Remark, Entropic algorithm for FGW)
+# ---------------------------------------------------------------------------
+
+def feature_cost_sq(fa, fb) -> np.ndarray:
+    """c_ip^2 with c_ip = fa_i - fb_p."""
+    fa = np.asarray(fa, dtype=np.float64)
+    fb = np.asarray(fb, dtype=np.float64)
+    d = fa[:, None] - fb[None, :]
+    return d * d
+
+
+def grad_fgw(gx: Grid, gy: Grid, p, q, T, fa, fb, theta: float) -> np.ndarray:
+    """Half of the FGW gradient: the Remark gives
+    grad = (1 - theta) C o C + theta * grad E (C_2 - 4 theta D T D with
+    C_2 = (1 - theta) C o C + 2 theta (constant terms)), and G = grad E / 2, so
+    the value here is theta G + (1 - theta) / 2 C o C."""
+    G = grad_dense(gx, gy, p, q, T)
+    return theta * G + 0.5 * (1.0 - theta) * feature_cost_sq(fa, fb)
+
+
+def objective_fgw(gx: Grid, gy: Grid, T, fa, fb, theta: float, eps: float):
+    """(1 - theta) sum c_ip^2 T_ip + theta E(T) (the Remark's objective), and
+    the same plus eps H(T)."""
+    T = np.asarray(T, dtype=np.float64)
+    E, _ = objective(gx, gy, T, eps)
+    Ef = (1.0 - theta) * float(np.sum(feature_cost_sq(fa, fb) * T)) + theta * E
+    return float(Ef), float(Ef + eps * entropy(T))
+
+
+def solve_fgw(gx: Grid, gy: Grid, p, q, fa, fb, theta: float, eps: float, outer: int,
+              inner: int, warm: bool = False):
+    """Mirror descent of the Remark: the iteration of Eq. (GW sinkhorn) with the
+    FGW gradient as the cost (tau = eps).  T^0 = p q^T.
+    Returns (T, f, g, (E_fgw, E_fgw + eps H))."""
+    p = np.asarray(p, dtype=np.float64)
+    q = np.asarray(q, dtype=np.float64)
+    T = p[:, None] * q[None, :]
+    f = g = None
+    for _ in range(outer):
+        C = 2.0 * grad_fgw(gx, gy, p, q, T, fa, fb, theta)
+        if warm and f is not None:
+            f, g = sinkhorn(C, p, q, eps, inner, f, g)
+        else:
+            f, g = sinkhorn(C, p, q, eps, inner)
+        T = plan(C, f, g, eps)
+    if f is None:
+        f, g = np.zeros(p.shape[0]), np.zeros(q.shape[0])
+    return T, f, g, objective_fgw(gx, gy, T, fa, fb, theta, eps)
