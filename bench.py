@@ -177,6 +177,46 @@ def grid2d_bench(side: int = 64, eps: float = 2e-3, outer: int = 100, inner: int
             "kernel_ms_in_solve": fams, "objective": float(obj[0].item())}
 
 
+def fgw_bench(n: int = 4000, theta: float = 0.5, eps: float = 2e-3, outer: int = 10,
+              inner: int = 100, reps: int = 3):
+    """The 1D random-distribution FGW workload: x_i = y_i = (i-1)/(n-1), k = 1,
+    marginals uniform on [0,1] then normalised, theta = 0.5, feature cost
+    c_ip = |x_i - y_p|, eps = 0.002, 10 mirror-descent steps (each with `inner`
+    Sinkhorn iterations).  Times the FGW solve and the GW solve of the same
+    problem, and the FGW gradient against the GW gradient."""
+    import torch
+    from paper_2404_08970_amd import gw, inputs
+    dev = torch.device("cuda:0")
+    X = gw.unit_grid((n,), 1)
+    rng = inputs.rng_for(11, n)
+    p = torch.tensor(inputs.uniform_marginal(n, rng), device=dev)
+    q = torch.tensor(inputs.uniform_marginal(n, rng), device=dev)
+    x = torch.arange(n, dtype=torch.float64, device=dev) * X.h
+    T = torch.empty((n, n), dtype=torch.float64, device=dev)
+    f = torch.empty(n, dtype=torch.float64, device=dev)
+    g = torch.empty(n, dtype=torch.float64, device=dev)
+    obj = torch.empty(2, dtype=torch.float64, device=dev)
+    ws = gw.workspace(gw.workspace_bytes(X, X, gw.PATH_FAST_F64, gw.OP_SOLVE), dev, key="fgw")
+    fgw = lambda: gw.solve_fgw(X, X, p, q, x, x, theta, eps, outer, inner, T=T, f=f, g=g,
+                               obj=obj, ws=ws)
+    plain = lambda: gw.solve(X, X, p, q, eps, outer, inner, T=T, f=f, g=g, obj=obj, ws=ws)
+    fgw_ms = time_gpu(fgw, reps, torch)
+    E_fgw = float(obj[0].item())
+    gw_ms = time_gpu(plain, reps, torch)
+    gw.check_status(ws)
+    G = torch.empty_like(T)
+    gws = gw.workspace(gw.workspace_bytes(X, X, gw.PATH_FAST_F64, gw.OP_GRAD), dev, key="gfgw")
+    fgw(); torch.cuda.synchronize()
+    gf_ms = time_gpu(lambda: gw.grad_fgw(X, X, p, q, x, x, theta, T, out=G, ws=gws), 20, torch)
+    gg_ms = time_gpu(lambda: gw.grad(X, X, p, q, T, out=G, ws=gws), 20, torch)
+    return {"workload": f"1D FGW n = {n}, k = 1, uniform-random marginals, theta = {theta}, "
+                        f"c_ip = |x_i - y_p|, eps = {eps}, {outer} outer x {inner} Sinkhorn",
+            "fgw_solves_per_s": round(1e3 / fgw_ms, 3), "fgw_ms_per_solve": round(fgw_ms, 2),
+            "gw_ms_per_solve_same_problem": round(gw_ms, 2),
+            "fgw_grad_us": round(gf_ms * 1e3, 1), "gw_grad_us": round(gg_ms * 1e3, 1),
+            "objective_fgw": E_fgw}
+
+
 def precision_study(n: int = 16384, k: int = 2, rows: int = 6):
     """Dense gradient in FP64, FP32, BF16 and split refinements at n = 16384, k = 2,
     Dirichlet(1) marginals, on two plans: p q^T and the plan after one FAST
@@ -326,6 +366,8 @@ def main():
                     help="run the precision study (dense FP64/FP32/BF16/split vs FAST, n=16384) and exit")
     ap.add_argument("--no-serve", action="store_true", help="skip the request-loop measurement")
     ap.add_argument("--no-2d", action="store_true", help="skip the 2D 64x64 solve")
+    ap.add_argument("--no-fgw", action="store_true", help="skip the 1D fused GW solve")
+    ap.add_argument("--only-fgw", action="store_true", help="run only the 1D fused GW solve and exit")
     ap.add_argument("--only-2d", action="store_true", help="run only the 2D 64x64 solve and exit")
     ap.add_argument("--serve-only", action="store_true", help="run only the request loop and exit")
     ap.add_argument("--serve-requests", type=int, default=200)
@@ -334,6 +376,9 @@ def main():
     args = ap.parse_args()
     if args.precision:
         print(json.dumps(precision_study()))
+        return
+    if args.only_fgw:
+        print(json.dumps(fgw_bench()))
         return
     if args.only_2d:
         print(json.dumps(grid2d_bench()))
@@ -454,6 +499,7 @@ def main():
         del Tb, Gb, wsb
 
     grid2d = None if args.no_2d else grid2d_bench()
+    fused = None if args.no_fgw else fgw_bench()
     serving = None
     if not args.no_serve:
         serving = serve_bench(args.serve_requests, args.serve_slots, args.serve_iters)
@@ -480,6 +526,7 @@ def main():
         "n16384": big,
         "objective": objs,
         "grid2d_64x64": grid2d,
+        "fgw_1d_n4000": fused,
         "serving": serving,
     }
     if not args.no_cpu:

@@ -139,6 +139,41 @@ gw_status gw_objective(const gw_grid* X, const gw_grid* Y, const double* T, int6
                        double eps, double* obj, void* ws, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Fused GW (Remark on FGW, Sec. 3): the objective
+ *   E_fgw(T) = (1 - theta) sum_ip c_ip^2 T_ip + theta E(T),  theta in [0, 1],
+ * with the feature cost c_ip = fa_i - fb_p between scalar features fa [M] of
+ * X's points and fb [N] of Y's points (device FP64).  Its gradient is
+ * (1 - theta) C o C + theta grad E, so only the GW part goes through the
+ * gradient paths; the feature term is one extra elementwise pass over G.
+ * Workspace: what gw_workspace_bytes reports for the matching GW operation
+ * (GW_OP_GRAD, GW_OP_SOLVE, GW_OP_OBJECTIVE).  theta outside [0, 1] or not
+ * finite, or a NULL / misaligned fa or fb, is GW_EINVAL.  At theta = 1 the
+ * results are bitwise those of the GW entry points (the feature pass is
+ * skipped).
+ * ------------------------------------------------------------------------ */
+
+/* G = (1 - theta)/2 c o c + theta (c1 1^T + 1 c2^T - 2 D_X T D_Y), half the
+ * FGW gradient, arguments as gw_grad. */
+gw_status gw_grad_fgw(const gw_grid* X, const gw_grid* Y, const double* p, const double* q,
+                      const double* fa, const double* fb, double theta, const double* T,
+                      int64_t ldT, double* G, int64_t ldG, int32_t path, void* ws,
+                      size_t ws_bytes, void* stream);
+
+/* Entropic FGW by mirror descent (Sec. 2.1 with the FGW gradient): as gw_solve
+ * with the Sinkhorn cost 2 G from gw_grad_fgw.  obj[0] = E_fgw(T) (T's own
+ * marginals in E), obj[1] = obj[0] + eps H(T). */
+gw_status gw_solve_fgw(const gw_grid* X, const gw_grid* Y, const double* p, const double* q,
+                       const double* fa, const double* fb, double theta, double eps,
+                       int32_t outer, int32_t inner, int32_t path, int32_t flags, double* T,
+                       int64_t ldT, double* f, double* g, double* obj, void* ws,
+                       size_t ws_bytes, void* stream);
+
+/* obj[0] = E_fgw(T), obj[1] = E_fgw(T) + eps H(T) for a non-negative T. */
+gw_status gw_objective_fgw(const gw_grid* X, const gw_grid* Y, const double* T, int64_t ldT,
+                           const double* fa, const double* fb, double theta, double eps,
+                           double* obj, void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
  * Request loop: continuous batching of gw_solve problems of uneven sizes.
  *
  * Not an operation of the paper; a serving layer that runs the mirror-descent

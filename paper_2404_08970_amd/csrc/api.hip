@@ -206,23 +206,31 @@ namespace gwr {
 
 gw_status run_grad(const Grid& X, const Grid& Y, const double* p, const double* q,
                    const double* T, int64_t ldT, double* G, int64_t ldG, int path, Arena& a,
-                   hipStream_t s, const double* c1, const double* c2) {
+                   hipStream_t s, const double* c1, const double* c2, const Epilogue* epi) {
   if (path == GW_PATH_FAST_F64) {
-    if (X.ndim == 1 && Y.ndim == 1) return gwl::fast1d(X, Y, p, q, T, ldT, G, ldG, a, s, c1, c2);
-    return gwl::fast_generic(X, Y, p, q, T, ldT, G, ldG, a, s, c1, c2);
+    if (X.ndim == 1 && Y.ndim == 1)
+      return gwl::fast1d(X, Y, p, q, T, ldT, G, ldG, a, s, c1, c2, epi);
+    return gwl::fast_generic(X, Y, p, q, T, ldT, G, ldG, a, s, c1, c2, epi);
   }
-  return gwl::dense(X, Y, p, q, T, ldT, G, ldG, path, a, s, c1, c2);
+  gw_status st = gwl::dense(X, Y, p, q, T, ldT, G, ldG, path, a, s, c1, c2);
+  if (st != GW_OK || !epi) return st;
+  return gwl::fgw_blend(G, ldG, X.n(), Y.n(), epi->fa, epi->fb, epi->a, epi->b, s);
 }
 
 gw_status run_objective(const Grid& X, const Grid& Y, const double* T, int64_t ldT, double eps,
                         double* obj, double* Gbuf, Arena& a, hipStream_t s,
-                        gwr::StatusWord* status) {
+                        gwr::StatusWord* status, const Fgw* fgw) {
   const int64_t M = X.n(), N = Y.n();
   double* r = a.take<double>(M);
   double* c = a.take<double>(N);
   gw_status st = gwl::marginals(T, ldT, M, N, r, c, a, s);
   if (st != GW_OK) return st;
-  st = run_grad(X, Y, r, c, T, ldT, Gbuf, N, GW_PATH_FAST_F64, a, s, nullptr, nullptr);
+  // fused objective: sum T (theta G' + (1 - theta) c^2)
+  const bool fused = fgw && fgw->theta != 1.0;
+  const Epilogue epi{fused ? fgw->fa : nullptr, fused ? fgw->fb : nullptr,
+                     fused ? fgw->theta : 1.0, fused ? 1.0 - fgw->theta : 0.0};
+  st = run_grad(X, Y, r, c, T, ldT, Gbuf, N, GW_PATH_FAST_F64, a, s, nullptr, nullptr,
+                fused ? &epi : nullptr);
   if (st != GW_OK) return st;
   return gwl::objective_reduce(Gbuf, N, T, ldT, M, N, eps, obj, a, s, status);
 }
@@ -240,6 +248,113 @@ gw_status clear_status(StatusWord* st, hipStream_t s) {
 namespace {
 using gwr::run_grad;
 using gwr::run_objective;
+
+gw_status check_fgw(const gwr::Fgw& fw) {
+  if (!isfinite(fw.theta) || fw.theta < 0.0 || fw.theta > 1.0) return GW_EINVAL;
+  if (check_vec(fw.fa) != GW_OK || check_vec(fw.fb) != GW_OK) return GW_EINVAL;
+  return GW_OK;
+}
+
+// Gradient (Sec. 2, decomposition of the gradient), GW or fused GW (fgw non-null).
+gw_status grad_impl(const gw_grid* Xp, const gw_grid* Yp, const double* p, const double* q,
+                    const gwr::Fgw* fgw, const double* T, int64_t ldT, double* G, int64_t ldG,
+                    int32_t path, void* ws, size_t ws_bytes, void* stream) {
+  Grid X, Y;
+  gw_status st;
+  if ((st = gwr::to_grid(Xp, &X)) != GW_OK) return st;
+  if ((st = gwr::to_grid(Yp, &Y)) != GW_OK) return st;
+  if (!path_valid(path)) return GW_EINVAL;
+  if (fgw && (st = check_fgw(*fgw)) != GW_OK) return st;
+  const int64_t M = X.n(), N = Y.n();
+  if ((st = check_vec(p)) != GW_OK || (st = check_vec(q)) != GW_OK) return st;
+  if ((st = check_matrix(T, M, N, ldT)) != GW_OK) return st;
+  if ((st = check_matrix(G, M, N, ldG)) != GW_OK) return st;
+  if (overlaps(T, sizeof(double) * ((M - 1) * ldT + N), G, sizeof(double) * ((M - 1) * ldG + N)))
+    return GW_EINVAL;
+  if ((st = check_ws(ws, ws_bytes, grad_need(X, Y, path))) != GW_OK) return st;
+  if (path != GW_PATH_FAST_F64 && (X.ndim != 1 || Y.ndim != 1)) return GW_EUNSUPPORTED;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  Arena a{static_cast<char*>(ws), 0, ws_bytes};
+  a.take<char>(gwr::ws_status_bytes());
+  // fused GW: half gradient theta G + (1 - theta)/2 c^2 (skipped at theta = 1)
+  const bool fused = fgw && fgw->theta != 1.0;
+  const gwr::Epilogue epi{fused ? fgw->fa : nullptr, fused ? fgw->fb : nullptr,
+                          fused ? fgw->theta : 1.0, fused ? 0.5 * (1.0 - fgw->theta) : 0.0};
+  return run_grad(X, Y, p, q, T, ldT, G, ldG, path, a, s, nullptr, nullptr,
+                  fused ? &epi : nullptr);
+}
+
+// Mirror descent (Sec. 2.1), GW or fused GW (fgw non-null).
+gw_status solve_impl(const gw_grid* Xp, const gw_grid* Yp, const double* p, const double* q,
+                     const gwr::Fgw* fgw, double eps, int32_t outer, int32_t inner,
+                     int32_t path, int32_t flags, double* T, int64_t ldT, double* f, double* g,
+                     double* obj, void* ws, size_t ws_bytes, void* stream) {
+  Grid X, Y;
+  gw_status st;
+  if ((st = gwr::to_grid(Xp, &X)) != GW_OK) return st;
+  if ((st = gwr::to_grid(Yp, &Y)) != GW_OK) return st;
+  if (!path_valid(path)) return GW_EINVAL;
+  if (!(eps > 0.0) || !isfinite(eps) || outer < 0 || inner < 0) return GW_EINVAL;
+  if (flags & ~GW_FLAG_WARM_START) return GW_EINVAL;
+  if (fgw && (st = check_fgw(*fgw)) != GW_OK) return st;
+  const int64_t M = X.n(), N = Y.n();
+  if (N > 16384) return GW_EUNSUPPORTED;
+  if ((st = check_vec(p)) != GW_OK || (st = check_vec(q)) != GW_OK) return st;
+  if ((st = check_vec(f)) != GW_OK || (st = check_vec(g)) != GW_OK) return st;
+  if ((st = check_matrix(T, M, N, ldT)) != GW_OK) return st;
+  if (obj && !aligned8(obj)) return GW_EINVAL;
+  if ((st = check_ws(ws, ws_bytes, solve_need(X, Y, path))) != GW_OK) return st;
+  if (path != GW_PATH_FAST_F64 && (X.ndim != 1 || Y.ndim != 1)) return GW_EUNSUPPORTED;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  Arena a{static_cast<char*>(ws), 0, ws_bytes};
+  a.take<char>(gwr::ws_status_bytes());
+  double* G = a.take<double>((size_t)M * N);
+  double* c1 = a.take<double>(M);
+  double* c2 = a.take<double>(N);
+  const size_t mark = a.used;
+  // fused GW: the Sinkhorn cost 2 G becomes (1 - theta) c^2 + theta grad E
+  const bool fused = fgw && fgw->theta != 1.0;
+  const gwr::Epilogue epi{fused ? fgw->fa : nullptr, fused ? fgw->fb : nullptr,
+                          fused ? fgw->theta : 1.0, fused ? 0.5 * (1.0 - fgw->theta) : 0.0};
+  if ((st = gwl::const_terms(X, p, c1, Y, q, c2, s)) != GW_OK) return st;
+  if ((st = gwl::outer_product(p, q, M, N, T, ldT, s)) != GW_OK) return st;
+  if ((st = gwr::clear_status(status_of(ws), s)) != GW_OK) return st;
+  for (int l = 0; l < outer; ++l) {
+    a.used = mark;
+    st = run_grad(X, Y, p, q, T, ldT, G, N, path, a, s, c1, c2, fused ? &epi : nullptr);
+    if (st != GW_OK) return st;
+    a.used = mark;
+    const int cold = (flags & GW_FLAG_WARM_START) && l > 0 ? 0 : 1;
+    st = gwl::sinkhorn(G, N, M, N, 2.0, p, q, eps, inner, cold, f, g, T, ldT, a, s, status_of(ws));
+    if (st != GW_OK) return st;
+  }
+  if (obj) {
+    a.used = mark;
+    return run_objective(X, Y, T, ldT, eps, obj, G, a, s, status_of(ws), fgw);
+  }
+  return gwr::last_launch_status();
+}
+
+gw_status objective_impl(const gw_grid* Xp, const gw_grid* Yp, const double* T, int64_t ldT,
+                         const gwr::Fgw* fgw, double eps, double* obj, void* ws,
+                         size_t ws_bytes, void* stream) {
+  Grid X, Y;
+  gw_status st;
+  if ((st = gwr::to_grid(Xp, &X)) != GW_OK) return st;
+  if ((st = gwr::to_grid(Yp, &Y)) != GW_OK) return st;
+  if (!isfinite(eps) || eps < 0.0) return GW_EINVAL;
+  if (fgw && (st = check_fgw(*fgw)) != GW_OK) return st;
+  const int64_t M = X.n(), N = Y.n();
+  if ((st = check_matrix(T, M, N, ldT)) != GW_OK) return st;
+  if (!obj || !aligned8(obj)) return GW_EINVAL;
+  if ((st = check_ws(ws, ws_bytes, gwr::ws_status_bytes() + gwr::ws_objective_bytes(X, Y))) != GW_OK)
+    return st;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  Arena a{static_cast<char*>(ws), 0, ws_bytes};
+  a.take<char>(gwr::ws_status_bytes());
+  double* Gbuf = a.take<double>((size_t)M * N);
+  return run_objective(X, Y, T, ldT, eps, obj, Gbuf, a, s, status_of(ws), fgw);
+}
 
 }  // namespace
 
@@ -266,23 +381,15 @@ size_t gw_workspace_bytes(const gw_grid* Xp, const gw_grid* Yp, int32_t path, in
 gw_status gw_grad(const gw_grid* Xp, const gw_grid* Yp, const double* p, const double* q,
                   const double* T, int64_t ldT, double* G, int64_t ldG, int32_t path, void* ws,
                   size_t ws_bytes, void* stream) {
-  Grid X, Y;
-  gw_status st;
-  if ((st = gwr::to_grid(Xp, &X)) != GW_OK) return st;
-  if ((st = gwr::to_grid(Yp, &Y)) != GW_OK) return st;
-  if (!path_valid(path)) return GW_EINVAL;
-  const int64_t M = X.n(), N = Y.n();
-  if ((st = check_vec(p)) != GW_OK || (st = check_vec(q)) != GW_OK) return st;
-  if ((st = check_matrix(T, M, N, ldT)) != GW_OK) return st;
-  if ((st = check_matrix(G, M, N, ldG)) != GW_OK) return st;
-  if (overlaps(T, sizeof(double) * ((M - 1) * ldT + N), G, sizeof(double) * ((M - 1) * ldG + N)))
-    return GW_EINVAL;
-  if ((st = check_ws(ws, ws_bytes, grad_need(X, Y, path))) != GW_OK) return st;
-  if (path != GW_PATH_FAST_F64 && (X.ndim != 1 || Y.ndim != 1)) return GW_EUNSUPPORTED;
-  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  Arena a{static_cast<char*>(ws), 0, ws_bytes};
-  a.take<char>(gwr::ws_status_bytes());
-  return run_grad(X, Y, p, q, T, ldT, G, ldG, path, a, s, nullptr, nullptr);
+  return grad_impl(Xp, Yp, p, q, nullptr, T, ldT, G, ldG, path, ws, ws_bytes, stream);
+}
+
+gw_status gw_grad_fgw(const gw_grid* Xp, const gw_grid* Yp, const double* p, const double* q,
+                      const double* fa, const double* fb, double theta, const double* T,
+                      int64_t ldT, double* G, int64_t ldG, int32_t path, void* ws,
+                      size_t ws_bytes, void* stream) {
+  const gwr::Fgw fw{fa, fb, theta};
+  return grad_impl(Xp, Yp, p, q, &fw, T, ldT, G, ldG, path, ws, ws_bytes, stream);
 }
 
 gw_status gw_sinkhorn(const double* C, int64_t ldC, int64_t M, int64_t N, double c_scale,
@@ -311,64 +418,30 @@ gw_status gw_solve(const gw_grid* Xp, const gw_grid* Yp, const double* p, const 
                    double eps, int32_t outer, int32_t inner, int32_t path, int32_t flags,
                    double* T, int64_t ldT, double* f, double* g, double* obj, void* ws,
                    size_t ws_bytes, void* stream) {
-  Grid X, Y;
-  gw_status st;
-  if ((st = gwr::to_grid(Xp, &X)) != GW_OK) return st;
-  if ((st = gwr::to_grid(Yp, &Y)) != GW_OK) return st;
-  if (!path_valid(path)) return GW_EINVAL;
-  if (!(eps > 0.0) || !isfinite(eps) || outer < 0 || inner < 0) return GW_EINVAL;
-  if (flags & ~GW_FLAG_WARM_START) return GW_EINVAL;
-  const int64_t M = X.n(), N = Y.n();
-  if (N > 16384) return GW_EUNSUPPORTED;
-  if ((st = check_vec(p)) != GW_OK || (st = check_vec(q)) != GW_OK) return st;
-  if ((st = check_vec(f)) != GW_OK || (st = check_vec(g)) != GW_OK) return st;
-  if ((st = check_matrix(T, M, N, ldT)) != GW_OK) return st;
-  if (obj && !aligned8(obj)) return GW_EINVAL;
-  if ((st = check_ws(ws, ws_bytes, solve_need(X, Y, path))) != GW_OK) return st;
-  if (path != GW_PATH_FAST_F64 && (X.ndim != 1 || Y.ndim != 1)) return GW_EUNSUPPORTED;
-  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  Arena a{static_cast<char*>(ws), 0, ws_bytes};
-  a.take<char>(gwr::ws_status_bytes());
-  double* G = a.take<double>((size_t)M * N);
-  double* c1 = a.take<double>(M);
-  double* c2 = a.take<double>(N);
-  const size_t mark = a.used;
-  if ((st = gwl::const_terms(X, p, c1, Y, q, c2, s)) != GW_OK) return st;
-  if ((st = gwl::outer_product(p, q, M, N, T, ldT, s)) != GW_OK) return st;
-  if ((st = gwr::clear_status(status_of(ws), s)) != GW_OK) return st;
-  for (int l = 0; l < outer; ++l) {
-    a.used = mark;
-    st = run_grad(X, Y, p, q, T, ldT, G, N, path, a, s, c1, c2);
-    if (st != GW_OK) return st;
-    a.used = mark;
-    const int cold = (flags & GW_FLAG_WARM_START) && l > 0 ? 0 : 1;
-    st = gwl::sinkhorn(G, N, M, N, 2.0, p, q, eps, inner, cold, f, g, T, ldT, a, s, status_of(ws));
-    if (st != GW_OK) return st;
-  }
-  if (obj) {
-    a.used = mark;
-    return run_objective(X, Y, T, ldT, eps, obj, G, a, s, status_of(ws));
-  }
-  return gwr::last_launch_status();
+  return solve_impl(Xp, Yp, p, q, nullptr, eps, outer, inner, path, flags, T, ldT, f, g, obj, ws,
+                    ws_bytes, stream);
+}
+
+gw_status gw_solve_fgw(const gw_grid* Xp, const gw_grid* Yp, const double* p, const double* q,
+                       const double* fa, const double* fb, double theta, double eps,
+                       int32_t outer, int32_t inner, int32_t path, int32_t flags, double* T,
+                       int64_t ldT, double* f, double* g, double* obj, void* ws,
+                       size_t ws_bytes, void* stream) {
+  const gwr::Fgw fw{fa, fb, theta};
+  return solve_impl(Xp, Yp, p, q, &fw, eps, outer, inner, path, flags, T, ldT, f, g, obj, ws,
+                    ws_bytes, stream);
 }
 
 gw_status gw_objective(const gw_grid* Xp, const gw_grid* Yp, const double* T, int64_t ldT,
                        double eps, double* obj, void* ws, size_t ws_bytes, void* stream) {
-  Grid X, Y;
-  gw_status st;
-  if ((st = gwr::to_grid(Xp, &X)) != GW_OK) return st;
-  if ((st = gwr::to_grid(Yp, &Y)) != GW_OK) return st;
-  if (!isfinite(eps) || eps < 0.0) return GW_EINVAL;
-  const int64_t M = X.n(), N = Y.n();
-  if ((st = check_matrix(T, M, N, ldT)) != GW_OK) return st;
-  if (!obj || !aligned8(obj)) return GW_EINVAL;
-  if ((st = check_ws(ws, ws_bytes, gwr::ws_status_bytes() + gwr::ws_objective_bytes(X, Y))) != GW_OK)
-    return st;
-  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  Arena a{static_cast<char*>(ws), 0, ws_bytes};
-  a.take<char>(gwr::ws_status_bytes());
-  double* Gbuf = a.take<double>((size_t)M * N);
-  return run_objective(X, Y, T, ldT, eps, obj, Gbuf, a, s, status_of(ws));
+  return objective_impl(Xp, Yp, T, ldT, nullptr, eps, obj, ws, ws_bytes, stream);
+}
+
+gw_status gw_objective_fgw(const gw_grid* Xp, const gw_grid* Yp, const double* T, int64_t ldT,
+                           const double* fa, const double* fb, double theta, double eps,
+                           double* obj, void* ws, size_t ws_bytes, void* stream) {
+  const gwr::Fgw fw{fa, fb, theta};
+  return objective_impl(Xp, Yp, T, ldT, &fw, eps, obj, ws, ws_bytes, stream);
 }
 
 const char* gw_status_string(gw_status s) {

@@ -592,15 +592,18 @@ __global__ __launch_bounds__(256) void k_p2c(int N, int nJ, const double* __rest
 // row segment; segment summaries pass through LDS and are combined with the
 // tile's row carries, and A overwrites T in LDS.  Column phase: thread
 // (column = lane, seg = wave) does the same along the column with A's column
-// carries, and writes G = (c1 + c2) - s2 B from registers.
-template <int KX, int KY>
+// carries, and writes G = (c1 + c2) - s2 B from registers.  With FG the
+// fused GW feature term is applied on the way out:
+// G = ea ((c1 + c2) - s2 B) + eb (fa_i - fb_p)^2.
+template <int KX, int KY, bool FG>
 __global__ __launch_bounds__(256) void k_p3_tile(const double* __restrict__ T, int64_t ldT, int M,
                                                   int N, int nI, int nJ,
                                                   const double* __restrict__ rowmom,
                                                   const double* __restrict__ acarry,
                                                   const double* __restrict__ c1,
                                                   const double* __restrict__ c2, double s2,
-                                                  double* __restrict__ G, int64_t ldG) {
+                                                  double* __restrict__ G, int64_t ldG,
+                                                  gwr::Epilogue epi) {
   constexpr int KM = (KX > KY ? KX : KY) + 1;
   __shared__ double X[TS][LDS_STRIDE];
   __shared__ double sums[2][NSEG][TS][KM];  // [pre/suf][seg][line][r]
@@ -628,6 +631,8 @@ __global__ __launch_bounds__(256) void k_p3_tile(const double* __restrict__ T, i
     // so waiting for them then leaves the next tile's loads in flight.
     double ra[KY + 1], rb[KY + 1], ca[KX + 1], cb[KX + 1];
     const double c2v = c2[min(qs + lane, N - 1)];
+    double fbv = 0.0;
+    if constexpr (FG) fbv = epi.fb[min(qs + lane, N - 1)];
     {
       const int row = min(js + lane, M - 1);
 #pragma unroll
@@ -713,7 +718,11 @@ __global__ __launch_bounds__(256) void k_p3_tile(const double* __restrict__ T, i
     for (int i = 0; i < SEG; ++i) {
       const int r = seg * SEG + i;  // wave-uniform
       const int row = min(js + r, M - 1);
-      const double v = (c1[row] + c2v) - s2 * out[i];
+      double v = (c1[row] + c2v) - s2 * out[i];
+      if constexpr (FG) {
+        const double d = epi.fa[row] - fbv;
+        v = fma(epi.a, v, epi.b * (d * d));
+      }
       gwk::buffer_store_f64(v, gwk::buffer_rsrc(G + (int64_t)row * ldG + qs),
                             (r < h && lane < w) ? lane * 8 : gwk::kOffDrop);
     }
@@ -758,7 +767,7 @@ int persistent_blocks(K kernel, int ntiles) {
 template <int KX, int KY>
 gw_status run_fast1d(const Layout& L, const double* T, int64_t ldT, double* G, int64_t ldG,
                      const double* c1, const double* c2, double s2, double* rowmom,
-                     double* colmom, double* acarry, hipStream_t s) {
+                     double* colmom, double* acarry, const gwr::Epilogue* epi, hipStream_t s) {
   const int M = (int)L.M, N = (int)L.N;
   const int ntiles = L.nI * L.nJ;
   {
@@ -786,9 +795,16 @@ gw_status run_fast1d(const Layout& L, const double* T, int64_t ldT, double* G, i
   }
   {
     gwr::ProfDispatch pd(gwr::kFamFastMain);
-    hipExtLaunchKernelGGL(k_p3_tile<KX, KY>, dim3(persistent_blocks(k_p3_tile<KX, KY>, ntiles)),
-                          dim3(256), 0, s, pd.b, pd.e, 0, T, ldT, M, N, L.nI, L.nJ, rowmom, acarry,
-                          c1, c2, s2, G, ldG);
+    if (epi)
+      hipExtLaunchKernelGGL(k_p3_tile<KX, KY, true>,
+                            dim3(persistent_blocks(k_p3_tile<KX, KY, true>, ntiles)), dim3(256), 0,
+                            s, pd.b, pd.e, 0, T, ldT, M, N, L.nI, L.nJ, rowmom, acarry, c1, c2, s2,
+                            G, ldG, *epi);
+    else
+      hipExtLaunchKernelGGL(k_p3_tile<KX, KY, false>,
+                            dim3(persistent_blocks(k_p3_tile<KX, KY, false>, ntiles)), dim3(256),
+                            0, s, pd.b, pd.e, 0, T, ldT, M, N, L.nI, L.nJ, rowmom, acarry, c1, c2,
+                            s2, G, ldG, gwr::Epilogue{});
   }
   return gwr::last_launch_status();
 }
@@ -796,12 +812,12 @@ gw_status run_fast1d(const Layout& L, const double* T, int64_t ldT, double* G, i
 template <int KX>
 gw_status dispatch_ky(int ky, const Layout& L, const double* T, int64_t ldT, double* G,
                       int64_t ldG, const double* c1, const double* c2, double s2, double* rm,
-                      double* cm, double* am, hipStream_t s) {
+                      double* cm, double* am, const gwr::Epilogue* epi, hipStream_t s) {
   switch (ky) {
-    case 1: return run_fast1d<KX, 1>(L, T, ldT, G, ldG, c1, c2, s2, rm, cm, am, s);
-    case 2: return run_fast1d<KX, 2>(L, T, ldT, G, ldG, c1, c2, s2, rm, cm, am, s);
-    case 3: return run_fast1d<KX, 3>(L, T, ldT, G, ldG, c1, c2, s2, rm, cm, am, s);
-    case 4: return run_fast1d<KX, 4>(L, T, ldT, G, ldG, c1, c2, s2, rm, cm, am, s);
+    case 1: return run_fast1d<KX, 1>(L, T, ldT, G, ldG, c1, c2, s2, rm, cm, am, epi, s);
+    case 2: return run_fast1d<KX, 2>(L, T, ldT, G, ldG, c1, c2, s2, rm, cm, am, epi, s);
+    case 3: return run_fast1d<KX, 3>(L, T, ldT, G, ldG, c1, c2, s2, rm, cm, am, epi, s);
+    case 4: return run_fast1d<KX, 4>(L, T, ldT, G, ldG, c1, c2, s2, rm, cm, am, epi, s);
   }
   return GW_EUNSUPPORTED;
 }
@@ -823,7 +839,8 @@ size_t fast1d_ws_bytes(const gwr::Grid& X, const gwr::Grid& Y) {
 
 gw_status fast1d(const gwr::Grid& X, const gwr::Grid& Y, const double* p, const double* q,
                  const double* T, int64_t ldT, double* G, int64_t ldG, gwr::Arena& ws,
-                 hipStream_t s, const double* c1_pre, const double* c2_pre) {
+                 hipStream_t s, const double* c1_pre, const double* c2_pre,
+                 const gwr::Epilogue* epi) {
   Layout L = make_layout(X.n(), Y.n(), X.k1d(), Y.k1d());
   double* rm = ws.take<double>(L.rowmom);
   double* cm = ws.take<double>(L.colmom);
@@ -834,10 +851,10 @@ gw_status fast1d(const gwr::Grid& X, const gwr::Grid& Y, const double* p, const 
   if (st != GW_OK) return st;
   const double s2 = 2.0 * (X.hk() * Y.hk());
   switch (L.kx) {
-    case 1: return dispatch_ky<1>(L.ky, L, T, ldT, G, ldG, c1, c2, s2, rm, cm, am, s);
-    case 2: return dispatch_ky<2>(L.ky, L, T, ldT, G, ldG, c1, c2, s2, rm, cm, am, s);
-    case 3: return dispatch_ky<3>(L.ky, L, T, ldT, G, ldG, c1, c2, s2, rm, cm, am, s);
-    case 4: return dispatch_ky<4>(L.ky, L, T, ldT, G, ldG, c1, c2, s2, rm, cm, am, s);
+    case 1: return dispatch_ky<1>(L.ky, L, T, ldT, G, ldG, c1, c2, s2, rm, cm, am, epi, s);
+    case 2: return dispatch_ky<2>(L.ky, L, T, ldT, G, ldG, c1, c2, s2, rm, cm, am, epi, s);
+    case 3: return dispatch_ky<3>(L.ky, L, T, ldT, G, ldG, c1, c2, s2, rm, cm, am, epi, s);
+    case 4: return dispatch_ky<4>(L.ky, L, T, ldT, G, ldG, c1, c2, s2, rm, cm, am, epi, s);
   }
   return GW_EUNSUPPORTED;
 }

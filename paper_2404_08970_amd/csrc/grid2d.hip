@@ -542,15 +542,23 @@ __global__ __launch_bounds__(NT) void k_sep_write(int64_t H1, int64_t W1, int64_
                                                    const double* __restrict__ Q4,
                                                    const double* __restrict__ c1,
                                                    const double* __restrict__ c2, double s2,
-                                                   double* __restrict__ G, int64_t ldG) {
+                                                   double* __restrict__ G, int64_t ldG,
+                                                   gwr::Epilogue epi) {
   const int64_t i = blockIdx.x;
   const int64_t a = i / W1, b = i % W1;
   const double c1v = c1[i];
+  const bool fg = epi.fa != nullptr;  // fused GW feature term (uniform)
+  const double fai = fg ? epi.fa[i] : 0.0;
   const int w2 = (int)W2, h2 = (int)H2;
   auto put = [&](int ap, int bp, double q2, double q4) {
     const int64_t p = (int64_t)ap * W2 + bp;
     const double Bv = ((Q1[a * H2 + ap] + q2) + Q3[b * H2 + ap]) + q4;
-    G[i * ldG + p] = (c1v + c2[p]) - s2 * Bv;
+    double v = (c1v + c2[p]) - s2 * Bv;
+    if (fg) {
+      const double d = fai - epi.fb[p];
+      v = fma(epi.a, v, epi.b * (d * d));
+    }
+    G[i * ldG + p] = v;
   };
   if (w2 <= NT) {
     // NT / W2 image rows per pass: thread t takes column t % W2 of row t / W2
@@ -704,7 +712,7 @@ size_t fast_generic_ws_bytes(const gwr::Grid& X, const gwr::Grid& Y) {
 gw_status fast_generic(const gwr::Grid& X, const gwr::Grid& Y, const double* p,
                        const double* q, const double* T, int64_t ldT, double* G, int64_t ldG,
                        gwr::Arena& ws, hipStream_t s, const double* c1_pre,
-                       const double* c2_pre) {
+                       const double* c2_pre, const gwr::Epilogue* epi) {
   const int64_t M = X.n(), N = Y.n();
   SepGrid sx, sy;
   const bool sep = separable(X, &sx) && separable(Y, &sy);
@@ -783,7 +791,8 @@ gw_status fast_generic(const gwr::Grid& X, const gwr::Grid& Y, const double* p,
     }
     k_sep_left<<<(unsigned)lt.first[4], SEP_LINE, lsh, s>>>(lt);
     k_sep_right<<<(unsigned)rt.first[4], SEP_LINE, rsh, s>>>(rt);
-    k_sep_write<<<(unsigned)M, NT, 0, s>>>(X.H, X.W, Y.H, Y.W, Q[0], Q[1], Q[2], Q[3], c1, c2, s2, G, ldG);
+    k_sep_write<<<(unsigned)M, NT, 0, s>>>(X.H, X.W, Y.H, Y.W, Q[0], Q[1], Q[2], Q[3], c1, c2,
+                                           s2, G, ldG, epi ? *epi : gwr::Epilogue{});
     return gwr::last_launch_status();
   }
   // generic: A = T D^_Y (rows), At = A^T, Bt = At D^_X (rows), G = epilogue(Bt^T)
@@ -793,6 +802,7 @@ gw_status fast_generic(const gwr::Grid& X, const gwr::Grid& Y, const double* p,
   k_rowop<<<(unsigned)N, NT, 0, s>>>(At, M, N, X.ndim, X.k, X.metric, X.H, X.W, A, M, tmp);
   dim3 tg2((unsigned)((M + 31) / 32), (unsigned)((N + 31) / 32));
   k_transpose<<<tg2, NT, 0, s>>>(A, M, N, M, G, ldG, c1, c2, s2);
+  if (epi) return fgw_blend(G, ldG, M, N, epi->fa, epi->fb, epi->a, epi->b, s);
   return gwr::last_launch_status();
 }
 

@@ -101,20 +101,42 @@ struct StatusWord {
 
 gw_status clear_status(StatusWord* st, hipStream_t s);
 
-// Gradient on `path` with optional precomputed constant terms, and the
-// objective of a plan (its own marginals, Gbuf [M x N] as scratch); both take
-// their scratch from `a`.
+// Fused GW terms: feature vectors fa [M], fb [N] (c_ip = fa_i - fb_p) and the
+// weight theta of the GW part.
+struct Fgw {
+  const double* fa;
+  const double* fb;
+  double theta;
+};
+
+// Elementwise step applied to a gradient as it is written:
+// G <- a G + b (fa_i - fb_p)^2 (the fused GW feature term).  Passed by value
+// to kernels.
+struct Epilogue {
+  const double* fa;
+  const double* fb;
+  double a;
+  double b;
+};
+
+// Gradient on `path` with optional precomputed constant terms and optional
+// epilogue, and the objective of a plan (its own marginals, Gbuf [M x N] as
+// scratch; the fused objective when fgw is given); both take their scratch
+// from `a`.
 gw_status run_grad(const Grid& X, const Grid& Y, const double* p, const double* q,
                    const double* T, int64_t ldT, double* G, int64_t ldG, int path, Arena& a,
-                   hipStream_t s, const double* c1, const double* c2);
+                   hipStream_t s, const double* c1, const double* c2,
+                   const Epilogue* epi = nullptr);
 gw_status run_objective(const Grid& X, const Grid& Y, const double* T, int64_t ldT, double eps,
-                        double* obj, double* Gbuf, Arena& a, hipStream_t s, StatusWord* status);
+                        double* obj, double* Gbuf, Arena& a, hipStream_t s, StatusWord* status,
+                        const Fgw* fgw);
 
 }  // namespace gwr
 
 // Launchers implemented in the kernel translation units.
 namespace gwl {
-// c[i] = hk^2 * sum_j d(i,j)^2 w[j] for grid g (recursion in 1D, direct in 2D).
+// c[i] = hk^2 * sum_j d(i,j)^2 w[j] for grid g (recursion in 1D, separable form
+// in 2D).
 gw_status const_term(const gwr::Grid& g, const double* w, double* c, hipStream_t s);
 // c1 for (X, p) and c2 for (Y, q), in one launch when both are 1D with the same
 // exponent.
@@ -125,16 +147,18 @@ gw_status const_terms(const gwr::Grid& X, const double* p, double* c1, const gwr
 gw_status resolve_const_terms(const gwr::Grid& X, const double* p, const double* c1_pre,
                               double** c1, const gwr::Grid& Y, const double* q,
                               const double* c2_pre, double** c2, hipStream_t s);
-// FAST 1D x 1D gradient (tiled recursion).  ws: arena for its scratch.
+// FAST 1D x 1D gradient (tiled recursion).  ws: arena for its scratch; epi
+// (may be null) is applied by the kernel that writes G.
 gw_status fast1d(const gwr::Grid& X, const gwr::Grid& Y, const double* p, const double* q,
                  const double* T, int64_t ldT, double* G, int64_t ldG, gwr::Arena& ws,
-                 hipStream_t s, const double* c1_pre, const double* c2_pre);
+                 hipStream_t s, const double* c1_pre, const double* c2_pre,
+                 const gwr::Epilogue* epi);
 size_t fast1d_ws_bytes(const gwr::Grid& X, const gwr::Grid& Y);
-// Generic FAST gradient for 2D (and mixed 1D/2D) grids.
+// Generic FAST gradient for 2D (and mixed 1D/2D) grids; epi as for fast1d.
 gw_status fast_generic(const gwr::Grid& X, const gwr::Grid& Y, const double* p,
                        const double* q, const double* T, int64_t ldT, double* G, int64_t ldG,
                        gwr::Arena& ws, hipStream_t s, const double* c1_pre,
-                       const double* c2_pre);
+                       const double* c2_pre, const gwr::Epilogue* epi);
 size_t fast_generic_ws_bytes(const gwr::Grid& X, const gwr::Grid& Y);
 // Dense gradient on matrix cores.
 gw_status dense(const gwr::Grid& X, const gwr::Grid& Y, const double* p, const double* q,
@@ -159,4 +183,7 @@ gw_status objective_reduce(const double* G, int64_t ldG, const double* T, int64_
                            int64_t M, int64_t N, double eps, double* obj, gwr::Arena& ws,
                            hipStream_t s, gwr::StatusWord* status);
 size_t objective_reduce_ws_bytes(int64_t M, int64_t N);
+// G <- a G + b (fa_i - fb_p)^2 (fused GW terms).
+gw_status fgw_blend(double* G, int64_t ldG, int64_t M, int64_t N, const double* fa,
+                    const double* fb, double a, double b, hipStream_t s);
 }  // namespace gwl

@@ -185,7 +185,7 @@ gw_status complete(gw_server* sv, Req& q) {
   gw_status st;
   if (q.r.flags & GW_REQ_OBJECTIVE) {
     Arena a{q.tail, 0, q.tail_bytes};
-    if ((st = gwr::run_objective(q.X, q.Y, q.T, q.N, q.r.eps, q.obj, q.G, a, s, q.st)) != GW_OK)
+    if ((st = gwr::run_objective(q.X, q.Y, q.T, q.N, q.r.eps, q.obj, q.G, a, s, q.st, nullptr)) != GW_OK)
       return st;
     if ((st = hip_ok(hipMemcpyAsync(q.rec->obj, q.obj, 2 * sizeof(double),
                                     hipMemcpyDeviceToHost, s))) != GW_OK)

@@ -87,6 +87,13 @@ def _lib():
     lib.gw_solve.restype = I32
     lib.gw_objective.argtypes = [G, G, P, I64, D, P, P, SZ, P]
     lib.gw_objective.restype = I32
+    lib.gw_grad_fgw.argtypes = [G, G, P, P, P, P, D, P, I64, P, I64, I32, P, SZ, P]
+    lib.gw_grad_fgw.restype = I32
+    lib.gw_solve_fgw.argtypes = [G, G, P, P, P, P, D, D, I32, I32, I32, I32, P, I64, P, P, P, P,
+                                 SZ, P]
+    lib.gw_solve_fgw.restype = I32
+    lib.gw_objective_fgw.argtypes = [G, G, P, I64, P, P, D, D, P, P, SZ, P]
+    lib.gw_objective_fgw.restype = I32
     lib.gw_status_string.argtypes = [I32]
     lib.gw_status_string.restype = ctypes.c_char_p
     lib.gw_check_status.argtypes = [P, P]
@@ -289,6 +296,80 @@ def objective(X: Grid, Y: Grid, T, eps: float, ws=None):
     st = _lib().gw_objective(ctypes.byref(xc), ctypes.byref(yc), _ptr(T), T.stride(0), float(eps),
                              _ptr(obj), _ptr(ws), ws.numel(), _stream())
     _raise(st, "gw_objective")
+    return obj
+
+
+def _check_features(fa, fb, M, N):
+    _check_f64("fa", fa, (M,)); _check_f64("fb", fb, (N,))
+
+
+def grad_fgw(X: Grid, Y: Grid, p, q, fa, fb, theta: float, T, path=PATH_FAST_F64, out=None,
+             ws=None):
+    """Half the fused GW gradient, theta (c1 1^T + 1 c2^T - 2 D_X T D_Y)
+    + (1 - theta)/2 (fa_i - fb_p)^2, on the GPU."""
+    path = PATHS.get(path, path)
+    M, N = X.size, Y.size
+    _check_f64("p", p, (M,)); _check_f64("q", q, (N,)); _check_f64("T", T, (M, N))
+    _check_features(fa, fb, M, N)
+    if out is None:
+        out = torch.empty((M, N), dtype=torch.float64, device=T.device)
+    _check_f64("out", out, (M, N))
+    nb = workspace_bytes(X, Y, path, OP_GRAD)
+    if nb == 0:
+        raise GWError(GW_EINVAL, "gw_workspace_bytes")
+    if ws is None:
+        ws = workspace(nb, T.device)
+    xc, yc = X.c(), Y.c()
+    st = _lib().gw_grad_fgw(ctypes.byref(xc), ctypes.byref(yc), _ptr(p), _ptr(q), _ptr(fa),
+                            _ptr(fb), float(theta), _ptr(T), T.stride(0), _ptr(out),
+                            out.stride(0), int(path), _ptr(ws), ws.numel(), _stream())
+    _raise(st, "gw_grad_fgw")
+    return out
+
+
+def solve_fgw(X: Grid, Y: Grid, p, q, fa, fb, theta: float, eps: float, outer: int, inner: int,
+              path=PATH_FAST_F64, warm: bool = False, objective: bool = True, T=None, f=None,
+              g=None, obj=None, ws=None):
+    """Entropic fused GW mirror descent on the GPU; returns (T, f, g, obj[2] or None)."""
+    path = PATHS.get(path, path)
+    M, N = X.size, Y.size
+    _check_f64("p", p, (M,)); _check_f64("q", q, (N,))
+    _check_features(fa, fb, M, N)
+    dev = p.device
+    T = torch.empty((M, N), dtype=torch.float64, device=dev) if T is None else T
+    f = torch.empty(M, dtype=torch.float64, device=dev) if f is None else f
+    g = torch.empty(N, dtype=torch.float64, device=dev) if g is None else g
+    if objective and obj is None:
+        obj = torch.empty(2, dtype=torch.float64, device=dev)
+    nb = workspace_bytes(X, Y, path, OP_SOLVE)
+    if nb == 0:
+        raise GWError(GW_EINVAL, "gw_workspace_bytes")
+    if ws is None:
+        ws = workspace(nb, dev, key="solve")
+    xc, yc = X.c(), Y.c()
+    st = _lib().gw_solve_fgw(ctypes.byref(xc), ctypes.byref(yc), _ptr(p), _ptr(q), _ptr(fa),
+                             _ptr(fb), float(theta), float(eps), int(outer), int(inner),
+                             int(path), FLAG_WARM_START if warm else 0, _ptr(T), T.stride(0),
+                             _ptr(f), _ptr(g), _ptr(obj if objective else None), _ptr(ws),
+                             ws.numel(), _stream())
+    _raise(st, "gw_solve_fgw")
+    return T, f, g, (obj if objective else None)
+
+
+def objective_fgw(X: Grid, Y: Grid, T, fa, fb, theta: float, eps: float, ws=None):
+    """(E_fgw(T), E_fgw(T) + eps H(T)) as a device tensor of 2 doubles."""
+    M, N = X.size, Y.size
+    _check_f64("T", T, (M, N))
+    _check_features(fa, fb, M, N)
+    obj = torch.empty(2, dtype=torch.float64, device=T.device)
+    nb = workspace_bytes(X, Y, PATH_FAST_F64, OP_OBJECTIVE)
+    if ws is None:
+        ws = workspace(nb, T.device, key="objective")
+    xc, yc = X.c(), Y.c()
+    st = _lib().gw_objective_fgw(ctypes.byref(xc), ctypes.byref(yc), _ptr(T), T.stride(0),
+                                 _ptr(fa), _ptr(fb), float(theta), float(eps), _ptr(obj),
+                                 _ptr(ws), ws.numel(), _stream())
+    _raise(st, "gw_objective_fgw")
     return obj
 
 

@@ -1,0 +1,167 @@
+"""GPU parity of the fused GW entry points (Remark on FGW) against the oracle.
+
+Same bar as the GW paths: err(X) = max|X - X*| / max|X*| <= 1e-10 for FP64;
+theta = 1 is bitwise the GW entry point (the feature pass is skipped)."""
+import numpy as np
+import pytest
+
+from oracle import gw_oracle as O
+from paper_2404_08970_amd import inputs
+
+from test_gpu_parity import TOL, _gw, _to_dev, err, ogrid
+
+pytestmark = pytest.mark.gpu
+
+
+def _features(M, N, rng):
+    return rng.normal(size=M), rng.normal(size=N)
+
+
+GRAD_CASES = [((1,), (1,), 1, 1, 0.5), ((65,), (63,), 1, 2, 0.0), ((130,), (70,), 2, 1, 0.3),
+              ((257,), (129,), 1, 1, 0.5), ((200,), (300,), 3, 2, 0.9)]
+
+
+@pytest.mark.parametrize("sx,sy,kx,ky,theta", GRAD_CASES)
+@pytest.mark.parametrize("path", ["fast", "dense"])
+def test_grad_fgw_1d_matches_oracle(sx, sy, kx, ky, theta, path):
+    gw, torch = _gw()
+    print(f"grad_fgw {sx} {sy} theta={theta} {path}", flush=True)
+    X, Y = gw.unit_grid(sx, kx), gw.unit_grid(sy, ky)
+    rng = inputs.rng_for(801, X.size, Y.size, kx, ky)
+    T = inputs.random_plan(X.size, Y.size, rng)
+    p, q = inputs.dirichlet(X.size, rng), inputs.dirichlet(Y.size, rng)
+    fa, fb = _features(X.size, Y.size, rng)
+    ref = O.grad_fgw(ogrid(X), ogrid(Y), p, q, T, fa, fb, theta)
+    d = lambda a: _to_dev(torch, a)
+    G = gw.grad_fgw(X, Y, d(p), d(q), d(fa), d(fb), theta, d(T), path=path)
+    torch.cuda.synchronize()
+    assert err(G.cpu().numpy(), ref) <= TOL
+
+
+@pytest.mark.parametrize("sx,sy,kx,ky,mx,my,theta", [
+    ((12, 17), (9, 23), 1, 2, 0, 0, 0.5), ((16, 16), (20, 12), 2, 1, 1, 0, 0.1),
+    ((33, 40), (70,), 1, 1, 0, 0, 0.7)])
+def test_grad_fgw_2d_matches_oracle(sx, sy, kx, ky, mx, my, theta):
+    gw, torch = _gw()
+    print(f"grad_fgw 2d {sx} {sy} theta={theta}", flush=True)
+    X, Y = gw.unit_grid(sx, kx, mx), gw.unit_grid(sy, ky, my)
+    rng = inputs.rng_for(802, X.size, Y.size)
+    T = inputs.random_plan(X.size, Y.size, rng)
+    p, q = inputs.dirichlet(X.size, rng), inputs.dirichlet(Y.size, rng)
+    fa, fb = rng.uniform(0, 1, X.size), rng.uniform(0, 1, Y.size)  # gray levels
+    ref = O.grad_fgw(ogrid(X), ogrid(Y), p, q, T, fa, fb, theta)
+    d = lambda a: _to_dev(torch, a)
+    G = gw.grad_fgw(X, Y, d(p), d(q), d(fa), d(fb), theta, d(T))
+    torch.cuda.synchronize()
+    assert err(G.cpu().numpy(), ref) <= TOL
+
+
+SOLVE_CASES = [((96,), (80,), 1, 1, 0.5, 0.02, 3, 30, "fast"),
+               ((150,), (129,), 1, 2, 0.3, 0.01, 4, 25, "dense"),
+               ((64,), (200,), 2, 1, 0.0, 0.05, 2, 40, "fast"),
+               ((10, 12), (11, 9), 1, 1, 0.1, 0.05, 3, 30, "fast")]
+
+
+@pytest.mark.parametrize("sx,sy,kx,ky,theta,eps,outer,inner,path", SOLVE_CASES)
+def test_solve_fgw_matches_oracle(sx, sy, kx, ky, theta, eps, outer, inner, path):
+    gw, torch = _gw()
+    print(f"solve_fgw {sx} {sy} theta={theta} eps={eps} {outer}x{inner} {path}", flush=True)
+    X, Y = gw.unit_grid(sx, kx), gw.unit_grid(sy, ky)
+    rng = inputs.rng_for(803, X.size, Y.size)
+    if len(sx) == 1:
+        p, q = inputs.gauss_mixture_1d(X.size, rng), inputs.gauss_mixture_1d(Y.size, rng)
+        # the 1D feature cost of the random-distribution workload: grid coordinates
+        fa, fb = np.arange(X.size) * X.h, np.arange(Y.size) * Y.h
+    else:
+        p = inputs.blobs_2d(sx[0], sx[1], rng, floor=1e-6)
+        q = inputs.blobs_2d(sy[0], sy[1], rng, floor=1e-6)
+        fa, fb = rng.uniform(0, 1, X.size), rng.uniform(0, 1, Y.size)
+    T0, f0, g0, (E0, R0) = O.solve_fgw(ogrid(X), ogrid(Y), p, q, fa, fb, theta, eps, outer, inner)
+    d = lambda a: _to_dev(torch, a)
+    T, f, g, obj = gw.solve_fgw(X, Y, d(p), d(q), d(fa), d(fb), theta, eps, outer, inner,
+                                path=path)
+    torch.cuda.synchronize()
+    assert err(T.cpu().numpy(), T0) <= TOL
+    assert err(f.cpu().numpy(), f0) <= TOL
+    assert err(g.cpu().numpy(), g0) <= TOL
+    o = obj.cpu().numpy()
+    assert abs(o[0] - E0) <= TOL * abs(E0)
+    assert abs(o[1] - R0) <= TOL * max(abs(R0), abs(E0))
+
+
+def test_solve_fgw_warm_start_matches_oracle():
+    gw, torch = _gw()
+    X, Y = gw.unit_grid((120,), 1), gw.unit_grid((100,), 1)
+    rng = inputs.rng_for(804)
+    p, q = inputs.gauss_mixture_1d(120, rng), inputs.gauss_mixture_1d(100, rng)
+    fa, fb = _features(120, 100, rng)
+    T0, f0, g0, _ = O.solve_fgw(ogrid(X), ogrid(Y), p, q, fa, fb, 0.5, 0.02, 4, 15, warm=True)
+    d = lambda a: _to_dev(torch, a)
+    T, f, g, _ = gw.solve_fgw(X, Y, d(p), d(q), d(fa), d(fb), 0.5, 0.02, 4, 15, warm=True)
+    torch.cuda.synchronize()
+    assert err(T.cpu().numpy(), T0) <= TOL
+    assert err(f.cpu().numpy(), f0) <= TOL
+
+
+def test_theta_one_is_gw_bitwise():
+    gw, torch = _gw()
+    X, Y = gw.unit_grid((300,), 2), gw.unit_grid((257,), 1)
+    rng = inputs.rng_for(805)
+    p, q = inputs.gauss_mixture_1d(300, rng), inputs.gauss_mixture_1d(257, rng)
+    fa, fb = _features(300, 257, rng)
+    d = lambda a: _to_dev(torch, a)
+    T0, f0, g0, o0 = gw.solve(X, Y, d(p), d(q), 0.01, 3, 20)
+    T1, f1, g1, o1 = gw.solve_fgw(X, Y, d(p), d(q), d(fa), d(fb), 1.0, 0.01, 3, 20)
+    G0 = gw.grad(X, Y, d(p), d(q), T0)
+    G1 = gw.grad_fgw(X, Y, d(p), d(q), d(fa), d(fb), 1.0, T0)
+    torch.cuda.synchronize()
+    for a, b in [(T0, T1), (f0, f1), (g0, g1), (o0, o1), (G0, G1)]:
+        assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("theta", [0.0, 0.25, 1.0])
+def test_objective_fgw_matches_oracle(theta):
+    gw, torch = _gw()
+    X, Y = gw.unit_grid((77,), 1), gw.unit_grid((9, 7), 2)
+    rng = inputs.rng_for(806, int(theta * 4))
+    T = inputs.random_plan(X.size, Y.size, rng)
+    fa, fb = _features(X.size, Y.size, rng)
+    E0, R0 = O.objective_fgw(ogrid(X), ogrid(Y), T, fa, fb, theta, 0.03)
+    d = lambda a: _to_dev(torch, a)
+    o = gw.objective_fgw(X, Y, d(T), d(fa), d(fb), theta, 0.03).cpu().numpy()
+    assert abs(o[0] - E0) <= TOL * abs(E0)
+    assert abs(o[1] - R0) <= TOL * max(abs(R0), abs(E0))
+
+
+def test_grad_fgw_full_size_property():
+    """At the 1D random-distribution size n = 4096 (theta = 0.5, c_ip = |x_i - y_p|)
+    the FGW gradient minus theta times the GW gradient is the feature term
+    (1 - theta)/2 c_ip^2 everywhere, to one rounding of the fused multiply-add."""
+    gw, torch = _gw()
+    n, theta = 4096, 0.5
+    X = gw.unit_grid((n,), 1)
+    rng = inputs.rng_for(807)
+    p, q = inputs.gauss_mixture_1d(n, rng), inputs.gauss_mixture_1d(n, rng)
+    T = inputs.peaked_plan(n, n, rng)
+    x = np.arange(n) * X.h
+    d = lambda a: _to_dev(torch, a)
+    Gg = gw.grad(X, X, d(p), d(q), d(T)).cpu().numpy()
+    Gf = gw.grad_fgw(X, X, d(p), d(q), d(x), d(x), theta, d(T)).cpu().numpy()
+    c2 = (x[:, None] - x[None, :]) ** 2
+    ref = theta * Gg + 0.5 * (1 - theta) * c2
+    scale = np.max(np.abs(ref))
+    assert np.max(np.abs(Gf - ref)) <= 4 * np.finfo(float).eps * scale
+
+
+def test_fgw_rejects_bad_theta():
+    gw, torch = _gw()
+    X = gw.unit_grid((8,), 1)
+    z = torch.full((8,), 1 / 8, dtype=torch.float64, device="cuda")
+    T = torch.full((8, 8), 1 / 64, dtype=torch.float64, device="cuda")
+    for theta in (-0.1, 1.5, float("nan")):
+        with pytest.raises(gw.GWError):
+            gw.grad_fgw(X, X, z, z, z, z, theta, T)
+        with pytest.raises(gw.GWError):
+            gw.solve_fgw(X, X, z, z, z, z, theta, 0.1, 1, 1)
+        with pytest.raises(gw.GWError):
+            gw.objective_fgw(X, X, T, z, z, theta, 0.1)
