@@ -18,7 +18,8 @@ Everything here is written to be read against the paper (arXiv 2404.08970,
 * mirror descent with tau = eps .. Sec. 2.1, Eq. (GW sinkhorn) and the
                                    Remark on tau = eps
 * Sinkhorn ....................... cited by the paper (Cuturi 2013); written
-                                   here in log domain (readings below)
+                                   here in log domain (readings below), with an
+                                   optional tolerance stop
 * Pascal recursion for L x ....... Sec. 3, Eq. (1d y), Eq. (1d recursive relation)
 * four-term split of D Gamma D ... Sec. 3, Eq. (Dx)
 * 2D Kronecker expansion ......... Sec. 3.1, Eq. (2D kronecker), Eq. (2d gradient)
@@ -33,7 +34,7 @@ Both are exact rewrites of one another; the tests pin each of them against
 independent facts (brute-force four-index sums, exact integer arithmetic,
 closed forms, the paper's printed matrices).
 
-Readings where the paper is silent or garbled (each is repeated in the design doc):
+Readings where the paper is silent or garbled:
 
 * G is half of the paper's gradient; the Sinkhorn cost in a solve is 2G.
 * the second constant term uses (D_Y o D_Y) q broadcast along rows.
@@ -46,6 +47,10 @@ Readings where the paper is silent or garbled (each is repeated in the design doc):
 * FGW feature cost c_ip = fa_i - fb_p (its square enters): every FGW workload
   of the paper has this form (|i - p|, signal-strength and gray-level
   differences).
+* optional tolerance stop (the paper fixes iteration counts): every
+  check_every iterations the column-marginal L1 violation of the half-step
+  plan (f_t, g_{t-1}) is measured; the iteration completes and the loop stops
+  once it is <= tol.
 
 Precision: float64 everywhere; no fused multiply-add is requested; sums run in
 index order except where a library primitive (numpy matmul / sum) is used as
@@ -333,6 +338,40 @@ def sinkhorn(C, p, q, eps: float, iters: int, f0=None, g0=None):
     return f, g
 
 
+def sinkhorn_tol(C, p, q, eps: float, max_iters: int, check_every: int, tol: float,
+                 f0=None, g0=None):
+    """Sinkhorn with a stopping rule (the paper runs fixed iteration counts and
+    states none; this is the reading taken for tolerance-based stopping).
+
+    Iteration t (1-based) is the update of ``sinkhorn``.  When t is a multiple
+    of check_every, the plan (f_t, g_{t-1}) of the half-step -- its row sums are
+    p after the f update -- has its column-marginal violation
+    err_t = sum_p |sum_i P_ip - q_p| measured; the g update of iteration t is
+    still applied, and if err_t <= tol the iteration stops there.
+    Returns (f, g, iterations done, last measured err or nan)."""
+    C = np.asarray(C, dtype=np.float64)
+    p = np.asarray(p, dtype=np.float64)
+    q = np.asarray(q, dtype=np.float64)
+    M, N = C.shape
+    f = np.zeros(M) if f0 is None else np.array(f0, dtype=np.float64)
+    g = np.zeros(N) if g0 is None else np.array(g0, dtype=np.float64)
+    with np.errstate(divide="ignore"):
+        logp, logq = np.log(p), np.log(q)
+    err = float("nan")
+    for t in range(1, max_iters + 1):
+        f = eps * logp - eps * _lse_last_axis((g[None, :] - C) / eps)
+        f[p == 0] = -np.inf
+        check = t % check_every == 0
+        if check:
+            col = plan(C, f, g, eps).sum(axis=0)
+            err = float(np.sum(np.abs(col - q)))
+        g = eps * logq - eps * _lse_last_axis(((f[:, None] - C) / eps).T)
+        g[q == 0] = -np.inf
+        if check and err <= tol:
+            return f, g, t, err
+    return f, g, max_iters, err
+
+
 def plan(C, f, g, eps: float) -> np.ndarray:
     """P_ip = exp((f_i + g_p - C_ip)/eps)."""
     C = np.asarray(C, dtype=np.float64)
@@ -363,6 +402,28 @@ def solve(gx: Grid, gy: Grid, p, q, eps: float, outer: int, inner: int,
     if f is None:
         f, g = np.zeros(p.shape[0]), np.zeros(q.shape[0])
     return T, f, g, objective(gx, gy, T, eps)
+
+
+def solve_tol(gx: Grid, gy: Grid, p, q, eps: float, outer: int, max_inner: int,
+              check_every: int, tol: float, warm: bool = False):
+    """``solve`` with each Sinkhorn call stopped by ``sinkhorn_tol``.
+    Returns (T, f, g, (E, E + eps H), inner iterations done per outer step)."""
+    p = np.asarray(p, dtype=np.float64)
+    q = np.asarray(q, dtype=np.float64)
+    T = p[:, None] * q[None, :]
+    f = g = None
+    done = []
+    for _ in range(outer):
+        C = 2.0 * grad_dense(gx, gy, p, q, T)
+        if warm and f is not None:
+            f, g, k, _ = sinkhorn_tol(C, p, q, eps, max_inner, check_every, tol, f, g)
+        else:
+            f, g, k, _ = sinkhorn_tol(C, p, q, eps, max_inner, check_every, tol)
+        done.append(k)
+        T = plan(C, f, g, eps)
+    if f is None:
+        f, g = np.zeros(p.shape[0]), np.zeros(q.shape[0])
+    return T, f, g, objective(gx, gy, T, eps), done
 
 
 # ---------------------------------------------------------------------------
