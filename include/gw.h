@@ -139,6 +139,38 @@ gw_status gw_objective(const gw_grid* X, const gw_grid* Y, const double* T, int6
                        double eps, double* obj, void* ws, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Tolerance-stopped Sinkhorn.  The paper runs fixed iteration counts and
+ * states no stopping rule (Sec. 2.1 and the experiments of Sec. 5); this is
+ * an optional one.  Iteration t (1-based) is gw_sinkhorn's update.  When t is
+ * a multiple of check_every, the column merge of iteration t also measures
+ *   err_t = sum_p | sum_i exp((f_i + g_p - C_eff_ip)/eps) - q_p |
+ * with f after and g before the update of iteration t (the plan whose row
+ * sums are p), the g update is applied, and if err_t <= tol the call stops
+ * there: f, g (and T) are those after iteration t.  The check runs on the
+ * device (no host synchronisation): later launches of the call see a flag and
+ * return at once, so a stopped call still enqueues max_iters launches.
+ * check_every >= 1; tol must not be NaN (tol < 0 never stops).
+ * ------------------------------------------------------------------------ */
+
+/* gw_sinkhorn with a tolerance stop.  iters_done: device int32 (may be NULL),
+ * receives the iterations done (max_iters if no check met tol).  err: device
+ * double (may be NULL), receives the last measured err_t (NaN if none). */
+gw_status gw_sinkhorn_tol(const double* C, int64_t ldC, int64_t M, int64_t N, double c_scale,
+                          const double* p, const double* q, double eps, int32_t max_iters,
+                          int32_t check_every, double tol, int32_t init_zero, double* f,
+                          double* g, double* T, int64_t ldT, int32_t* iters_done, double* err,
+                          void* ws, size_t ws_bytes, void* stream);
+
+/* gw_solve whose Sinkhorn calls stop by tolerance (at most max_inner
+ * iterations each).  inner_done: device int32 [outer] (may be NULL), the
+ * iterations done by each outer step's Sinkhorn call. */
+gw_status gw_solve_tol(const gw_grid* X, const gw_grid* Y, const double* p, const double* q,
+                       double eps, int32_t outer, int32_t max_inner, int32_t check_every,
+                       double tol, int32_t path, int32_t flags, double* T, int64_t ldT, double* f,
+                       double* g, double* obj, int32_t* inner_done, void* ws, size_t ws_bytes,
+                       void* stream);
+
+/* ------------------------------------------------------------------------
  * Fused GW (Remark on FGW, Sec. 3): the objective
  *   E_fgw(T) = (1 - theta) sum_ip c_ip^2 T_ip + theta E(T),  theta in [0, 1],
  * with the feature cost c_ip = fa_i - fb_p between scalar features fa [M] of

@@ -284,11 +284,45 @@ gw_status grad_impl(const gw_grid* Xp, const gw_grid* Yp, const double* p, const
                   fused ? &epi : nullptr);
 }
 
+gw_status check_stop(const gwr::SkStop& so) {
+  if (so.check_every < 1 || isnan(so.tol)) return GW_EINVAL;
+  if (so.iters_out && reinterpret_cast<uintptr_t>(so.iters_out) % alignof(int32_t)) return GW_EINVAL;
+  if (so.err_out && !aligned8(so.err_out)) return GW_EINVAL;
+  return GW_OK;
+}
+
+// Log-domain Sinkhorn (Sec. 2.1), fixed iteration count or tolerance stop (so non-null).
+gw_status sinkhorn_impl(const double* C, int64_t ldC, int64_t M, int64_t N, double c_scale,
+                        const double* p, const double* q, double eps, int32_t iters,
+                        int32_t init_zero, const gwr::SkStop* so, double* f, double* g,
+                        double* T, int64_t ldT, void* ws, size_t ws_bytes, void* stream) {
+  gw_status st;
+  if (M < 1 || N < 1) return GW_EINVAL;
+  if (M > gwr::kMaxExtent || N > gwr::kMaxExtent) return GW_EUNSUPPORTED;
+  if (N > 16384) return GW_EUNSUPPORTED;
+  if (!(eps > 0.0) || !isfinite(eps) || !isfinite(c_scale) || iters < 0) return GW_EINVAL;
+  if (so && (st = check_stop(*so)) != GW_OK) return st;
+  if ((st = check_matrix(C, M, N, ldC)) != GW_OK) return st;
+  if ((st = check_vec(p)) != GW_OK || (st = check_vec(q)) != GW_OK) return st;
+  if ((st = check_vec(f)) != GW_OK || (st = check_vec(g)) != GW_OK) return st;
+  if (T && (st = check_matrix(T, M, N, ldT)) != GW_OK) return st;
+  const size_t need = gwr::ws_status_bytes() + gwr::ws_sinkhorn_bytes(M, N);
+  if ((st = check_ws(ws, ws_bytes, need)) != GW_OK) return st;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  Arena a{static_cast<char*>(ws), 0, ws_bytes};
+  a.take<char>(gwr::ws_status_bytes());
+  return gwl::sinkhorn(C, ldC, M, N, c_scale, p, q, eps, iters, init_zero, f, g, T, ldT, a, s,
+                       status_of(ws), so);
+}
+
 // Mirror descent (Sec. 2.1), GW or fused GW (fgw non-null).
+// With so (non-null), each Sinkhorn call stops by tolerance; its iterations
+// done go to so->iters_out[l] for outer step l (if given).
 gw_status solve_impl(const gw_grid* Xp, const gw_grid* Yp, const double* p, const double* q,
                      const gwr::Fgw* fgw, double eps, int32_t outer, int32_t inner,
                      int32_t path, int32_t flags, double* T, int64_t ldT, double* f, double* g,
-                     double* obj, void* ws, size_t ws_bytes, void* stream) {
+                     double* obj, void* ws, size_t ws_bytes, void* stream,
+                     const gwr::SkStop* so = nullptr) {
   Grid X, Y;
   gw_status st;
   if ((st = gwr::to_grid(Xp, &X)) != GW_OK) return st;
@@ -297,6 +331,7 @@ gw_status solve_impl(const gw_grid* Xp, const gw_grid* Yp, const double* p, cons
   if (!(eps > 0.0) || !isfinite(eps) || outer < 0 || inner < 0) return GW_EINVAL;
   if (flags & ~GW_FLAG_WARM_START) return GW_EINVAL;
   if (fgw && (st = check_fgw(*fgw)) != GW_OK) return st;
+  if (so && (st = check_stop(*so)) != GW_OK) return st;
   const int64_t M = X.n(), N = Y.n();
   if (N > 16384) return GW_EUNSUPPORTED;
   if ((st = check_vec(p)) != GW_OK || (st = check_vec(q)) != GW_OK) return st;
@@ -325,7 +360,11 @@ gw_status solve_impl(const gw_grid* Xp, const gw_grid* Yp, const double* p, cons
     if (st != GW_OK) return st;
     a.used = mark;
     const int cold = (flags & GW_FLAG_WARM_START) && l > 0 ? 0 : 1;
-    st = gwl::sinkhorn(G, N, M, N, 2.0, p, q, eps, inner, cold, f, g, T, ldT, a, s, status_of(ws));
+    gwr::SkStop sl{};
+    if (so) sl = gwr::SkStop{so->check_every, so->tol, so->iters_out ? so->iters_out + l : nullptr,
+                             nullptr};
+    st = gwl::sinkhorn(G, N, M, N, 2.0, p, q, eps, inner, cold, f, g, T, ldT, a, s, status_of(ws),
+                       so ? &sl : nullptr);
     if (st != GW_OK) return st;
   }
   if (obj) {
@@ -396,22 +435,18 @@ gw_status gw_sinkhorn(const double* C, int64_t ldC, int64_t M, int64_t N, double
                       const double* p, const double* q, double eps, int32_t iters,
                       int32_t init_zero, double* f, double* g, double* T, int64_t ldT, void* ws,
                       size_t ws_bytes, void* stream) {
-  gw_status st;
-  if (M < 1 || N < 1) return GW_EINVAL;
-  if (M > gwr::kMaxExtent || N > gwr::kMaxExtent) return GW_EUNSUPPORTED;
-  if (N > 16384) return GW_EUNSUPPORTED;
-  if (!(eps > 0.0) || !isfinite(eps) || !isfinite(c_scale) || iters < 0) return GW_EINVAL;
-  if ((st = check_matrix(C, M, N, ldC)) != GW_OK) return st;
-  if ((st = check_vec(p)) != GW_OK || (st = check_vec(q)) != GW_OK) return st;
-  if ((st = check_vec(f)) != GW_OK || (st = check_vec(g)) != GW_OK) return st;
-  if (T && (st = check_matrix(T, M, N, ldT)) != GW_OK) return st;
-  const size_t need = gwr::ws_status_bytes() + gwr::ws_sinkhorn_bytes(M, N);
-  if ((st = check_ws(ws, ws_bytes, need)) != GW_OK) return st;
-  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  Arena a{static_cast<char*>(ws), 0, ws_bytes};
-  a.take<char>(gwr::ws_status_bytes());
-  return gwl::sinkhorn(C, ldC, M, N, c_scale, p, q, eps, iters, init_zero, f, g, T, ldT, a, s,
-                       status_of(ws));
+  return sinkhorn_impl(C, ldC, M, N, c_scale, p, q, eps, iters, init_zero, nullptr, f, g, T, ldT,
+                       ws, ws_bytes, stream);
+}
+
+gw_status gw_sinkhorn_tol(const double* C, int64_t ldC, int64_t M, int64_t N, double c_scale,
+                          const double* p, const double* q, double eps, int32_t max_iters,
+                          int32_t check_every, double tol, int32_t init_zero, double* f,
+                          double* g, double* T, int64_t ldT, int32_t* iters_done, double* err,
+                          void* ws, size_t ws_bytes, void* stream) {
+  const gwr::SkStop so{check_every, tol, iters_done, err};
+  return sinkhorn_impl(C, ldC, M, N, c_scale, p, q, eps, max_iters, init_zero, &so, f, g, T, ldT,
+                       ws, ws_bytes, stream);
 }
 
 gw_status gw_solve(const gw_grid* Xp, const gw_grid* Yp, const double* p, const double* q,
@@ -420,6 +455,16 @@ gw_status gw_solve(const gw_grid* Xp, const gw_grid* Yp, const double* p, const 
                    size_t ws_bytes, void* stream) {
   return solve_impl(Xp, Yp, p, q, nullptr, eps, outer, inner, path, flags, T, ldT, f, g, obj, ws,
                     ws_bytes, stream);
+}
+
+gw_status gw_solve_tol(const gw_grid* Xp, const gw_grid* Yp, const double* p, const double* q,
+                       double eps, int32_t outer, int32_t max_inner, int32_t check_every,
+                       double tol, int32_t path, int32_t flags, double* T, int64_t ldT, double* f,
+                       double* g, double* obj, int32_t* inner_done, void* ws, size_t ws_bytes,
+                       void* stream) {
+  const gwr::SkStop so{check_every, tol, inner_done, nullptr};
+  return solve_impl(Xp, Yp, p, q, nullptr, eps, outer, max_inner, path, flags, T, ldT, f, g, obj,
+                    ws, ws_bytes, stream, &so);
 }
 
 gw_status gw_solve_fgw(const gw_grid* Xp, const gw_grid* Yp, const double* p, const double* q,

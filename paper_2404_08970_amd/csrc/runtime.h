@@ -119,6 +119,17 @@ struct Epilogue {
   double b;
 };
 
+// Tolerance stop of a Sinkhorn call: every check_every iterations the column
+// violation of the half-step plan is measured; the call stops after the first
+// check with violation <= tol.  iters_out / err_out (device, may be null)
+// receive the iterations done and the last measured violation.
+struct SkStop {
+  int check_every;
+  double tol;
+  int* iters_out;
+  double* err_out;
+};
+
 // Gradient on `path` with optional precomputed constant terms and optional
 // epilogue, and the objective of a plan (its own marginals, Gbuf [M x N] as
 // scratch; the fused objective when fgw is given); both take their scratch
@@ -169,7 +180,7 @@ size_t dense_ws_bytes(const gwr::Grid& X, const gwr::Grid& Y, int path);
 gw_status sinkhorn(const double* C, int64_t ldC, int64_t M, int64_t N, double c_scale,
                    const double* p, const double* q, double eps, int iters, int init_zero,
                    double* f, double* g, double* T, int64_t ldT, gwr::Arena& ws, hipStream_t s,
-                   gwr::StatusWord* status);
+                   gwr::StatusWord* status, const gwr::SkStop* stop = nullptr);
 size_t sinkhorn_ws_bytes(int64_t M, int64_t N);
 gw_status plan(const double* C, int64_t ldC, int64_t M, int64_t N, double c_scale,
                const double* f, const double* g, double eps, double* T, int64_t ldT,

@@ -437,7 +437,8 @@ __global__ __launch_bounds__(NTH) void k_sk_row(const double* __restrict__ C, in
                                                  int* __restrict__ partX,
                                                  double* __restrict__ lse,
                                                  const double* __restrict__ gprev,
-                                                 int write_f) {
+                                                 int write_f, const int* __restrict__ stop) {
+  if (stop != nullptr && *stop) return;  // a tolerance stop has ended the call
   // the longest rows (no register prefetch) always take the exact maxima:
   // their shifted variant spills more registers than it saves
   double dup = -1.0;
@@ -681,7 +682,8 @@ __global__ __launch_bounds__(1024) void k_sk_rowg(const double* __restrict__ C, 
                                                    int* __restrict__ partX,
                                                    double* __restrict__ lse,
                                                    const double* __restrict__ gprev,
-                                                   int write_f) {
+                                                   int write_f, const int* __restrict__ stop) {
+  if (stop != nullptr && *stop) return;  // a tolerance stop has ended the call
   sk_rowg_band<EPT, NG, PF>(C, ldC, M, N, RB, cs, inv_eps, p, g, gprev, f, ms, partS, partX,
                             lse, write_f, blockIdx.x);
 }
@@ -692,10 +694,14 @@ __global__ __launch_bounds__(1024) void k_sk_rowg(const double* __restrict__ C, 
 constexpr int MERGE_COLS = gwb::kMergeCols, MERGE_GRPS = 16;
 constexpr int MERGE_PER = 16;  // bands per group: nb <= 256 = MERGE_GRPS * MERGE_PER
 
+// With errpart (uniform), the block also writes sum |S_p - q_p| over its
+// columns to errpart[cblock]: S_p is the column sum of the plan (f, g before
+// this merge), so the blocks' sums make the half-step's column violation.
 GW_DEV void sk_col_block(int N, int nb, const double* __restrict__ partS,
                          const int* __restrict__ partX, const double* __restrict__ q,
                          const double* __restrict__ logq, double eps, double* __restrict__ g,
-                         gwr::StatusWord* status, double* __restrict__ gprev, int cblock) {
+                         gwr::StatusWord* status, double* __restrict__ gprev, int cblock,
+                         double* __restrict__ errpart) {
   __shared__ double ms[MERGE_GRPS][MERGE_COLS];
   __shared__ int mx[MERGE_GRPS][MERGE_COLS];
   const int c = threadIdx.x & (MERGE_COLS - 1), grp = threadIdx.x / MERGE_COLS;
@@ -730,23 +736,39 @@ GW_DEV void sk_col_block(int N, int nb, const double* __restrict__ partS,
   ms[grp][c] = S;
   mx[grp][c] = X;
   __syncthreads();
-  if (grp != 0 || col >= N) return;
-  for (int k = 1; k < MERGE_GRPS; ++k) {
-    const int ne = max(X, mx[k][c]);
-    S = ldexp(S, X - ne) + ldexp(ms[k][c], mx[k][c] - ne);
-    X = ne;
+  if (errpart == nullptr && (grp != 0 || col >= N)) return;
+  double e = 0.0;
+  if (grp == 0 && col < N) {
+    for (int k = 1; k < MERGE_GRPS; ++k) {
+      const int ne = max(X, mx[k][c]);
+      S = ldexp(S, X - ne) + ldexp(ms[k][c], mx[k][c] - ne);
+      X = ne;
+    }
+    const double qc = q[col];
+    if (errpart != nullptr) e = fabs(ldexp(S, X) - qc);
+    const double gold = g[col];
+    gprev[col] = gold;
+    if (!(qc > 0.0)) {
+      g[col] = -INFINITY;
+    } else {
+      // ln(S 2^X) with X ln 2 split so that X * LN2_HI is exact
+      const double lnS = fma((double)X, LN2_HI, fma((double)X, LN2_LO, log(S)));
+      const double gn = gold + eps * (logq[col] - lnS);
+      g[col] = gn;
+      if (!isfinite(gn)) status->nonfinite = 1;
+    }
   }
-  const double gold = g[col];
-  gprev[col] = gold;
-  if (!(q[col] > 0.0)) {
-    g[col] = -INFINITY;
-    return;
+  if (errpart == nullptr) return;
+  // the block's columns summed in column order (the group-0 threads are lanes
+  // 0..MERGE_COLS-1 of the first wave)
+  __shared__ double es[MERGE_COLS];
+  if (grp == 0) es[c] = e;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int k = 0; k < MERGE_COLS; ++k) t += es[k];
+    errpart[cblock] = t;
   }
-  // ln(S 2^X) with X ln 2 split so that X * LN2_HI is exact
-  const double lnS = fma((double)X, LN2_HI, fma((double)X, LN2_LO, log(S)));
-  const double gn = gold + eps * (logq[col] - lnS);
-  g[col] = gn;
-  if (!isfinite(gn)) status->nonfinite = 1;
 }
 
 __global__ __launch_bounds__(256) void k_sk_col(int N, int nb, const double* __restrict__ partS,
@@ -754,8 +776,48 @@ __global__ __launch_bounds__(256) void k_sk_col(int N, int nb, const double* __r
                                                  const double* __restrict__ q,
                                                  const double* __restrict__ logq, double eps,
                                                  double* __restrict__ g,
-                                                 gwr::StatusWord* status, double* gprev) {
-  sk_col_block(N, nb, partS, partX, q, logq, eps, g, status, gprev, blockIdx.x);
+                                                 gwr::StatusWord* status, double* gprev,
+                                                 const int* __restrict__ stop,
+                                                 double* __restrict__ errpart) {
+  if (stop != nullptr && *stop) return;  // a tolerance stop has ended the call
+  sk_col_block(N, nb, partS, partX, q, logq, eps, g, status, gprev, blockIdx.x, errpart);
+}
+
+// Tolerance stop, state of one call: stop flag, iterations done, last err.
+struct SkCtl {
+  int stop;
+  int done;
+  double err;
+};
+
+__global__ void k_sk_ctl_init(SkCtl* ctl, int iters, int* iters_out, double* err_out) {
+  if (threadIdx.x != 0) return;
+  ctl->stop = 0;
+  ctl->done = iters;
+  ctl->err = NAN;
+  if (iters_out) *iters_out = iters;
+  if (err_out) *err_out = NAN;
+}
+
+// After the merge of iteration `it` (0-based) on a check iteration: err = the
+// column blocks' sums added in block order by one wave; stop if err <= tol.
+__global__ __launch_bounds__(64) void k_sk_check(const double* __restrict__ errpart, int ncb,
+                                                  double tol, int it, SkCtl* ctl,
+                                                  int* iters_out, double* err_out) {
+  if (ctl->stop) return;
+  const int l = threadIdx.x;
+  double t = 0.0;
+  for (int b = l; b < ncb; b += 64) t += errpart[b];
+  // fixed-order tree over the 64 lanes
+  for (int o = 32; o > 0; o >>= 1) t += __shfl_down(t, o, 64);
+  if (l != 0) return;
+  ctl->err = t;
+  if (err_out) *err_out = t;
+  if (t <= tol) {
+    ctl->stop = 1;
+    ctl->done = it + 1;
+    if (iters_out) *iters_out = it + 1;
+  }
 }
 
 // f_i = eps (ln p_i - m_i - ln s_i) from the last row pass's row maximum and
@@ -891,11 +953,11 @@ template <int NTH, int EPT>
 void launch_row(int nb, hipStream_t s, hipEvent_t eb, hipEvent_t ee, const double* C,
                 int64_t ldC, int M, int N, int RB, double cs, double inv_eps, const double* p,
                 const double* logp, const double* g, double* f, double* ms, double* pS, int* pX,
-                double* lse, const double* gprev, int last) {
+                double* lse, const double* gprev, int last, const int* stop) {
   constexpr int R = row_group<NTH, EPT>();
   hipExtLaunchKernelGGL(k_sk_row<NTH, EPT, R, row_gl<NTH, EPT>(), row_pf<NTH, EPT>()>, dim3(nb),
                         dim3(NTH), 0, s, eb, ee, 0, C, ldC, M, N, RB, cs, inv_eps, p, logp, g, f,
-                        ms, pS, pX, lse, gprev, last);
+                        ms, pS, pX, lse, gprev, last, stop);
 }
 
 // ---------------------------------------------------------------------------
@@ -968,7 +1030,7 @@ __global__ __launch_bounds__(256) void k_skb_col(const gwb::SkSlot* __restrict__
     if (j >= a.its) continue;
     __syncthreads();
     sk_col_block(a.N, a.nb, a.pS, a.pX, a.q, a.logq, a.eps, a.g, a.status, a.gprev,
-                 (int)(code & ((1u << gwb::kCBlockBits) - 1)));
+                 (int)(code & ((1u << gwb::kCBlockBits) - 1)), nullptr);
   }
 }
 
@@ -990,6 +1052,8 @@ size_t sinkhorn_ws_bytes(int64_t M, int64_t N) {
   a.take<double>(2 * (size_t)M);
   a.take<double>(M);  // row bounds
   a.take<double>(N);  // g before the last merge
+  a.take<double>(4);  // tolerance-stop state
+  a.take<double>((N + MERGE_COLS - 1) / MERGE_COLS);  // column violation per merge block
   return a.used;
 }
 
@@ -1038,7 +1102,7 @@ gw_status sk_batch_launch(int cls, int j, const gwb::SkSlot* slots, const gwb::S
 gw_status sinkhorn(const double* C, int64_t ldC, int64_t M, int64_t N, double c_scale,
                    const double* p, const double* q, double eps, int iters, int init_zero,
                    double* f, double* g, double* T, int64_t ldT, gwr::Arena& ws, hipStream_t s,
-                   gwr::StatusWord* status) {
+                   gwr::StatusWord* status, const gwr::SkStop* stop_opts) {
   if (N > 16384) return GW_EUNSUPPORTED;
   const int rb = sk_rows_per_block(M);
   const int nb = (int)((M + rb - 1) / rb);
@@ -1049,35 +1113,54 @@ gw_status sinkhorn(const double* C, int64_t ldC, int64_t M, int64_t N, double c_
   double* ms = ws.take<double>(2 * (size_t)M);
   double* lse = ws.take<double>(M);
   double* gprev = ws.take<double>(N);
+  SkCtl* ctl = reinterpret_cast<SkCtl*>(ws.take<double>(4));
+  const int ncb = (int)((N + MERGE_COLS - 1) / MERGE_COLS);
+  double* errpart = ws.take<double>(ncb);
   const double inv_eps = 1.0 / eps;
   gw_status st = sinkhorn_prep(p, q, M, N, init_zero, logp, logq, f, g, s);
   if (st != GW_OK) return st;
+  // tolerance stop: every `every` iterations the merge measures the column
+  // violation and k_sk_check may raise the flag that the later launches of
+  // this call test first
+  const int every = stop_opts ? stop_opts->check_every : 0;
+  const int* stop = stop_opts ? &ctl->stop : nullptr;
+  if (stop_opts) {
+    gwr::ProfScope ps(gwr::kFamOther, s);
+    k_sk_ctl_init<<<1, 64, 0, s>>>(ctl, iters, stop_opts->iters_out, stop_opts->err_out);
+  }
   const int Mi = (int)M, Ni = (int)N;
   for (int it = 0; it < iters; ++it) {
+    const bool check = every > 0 && (it + 1) % every == 0;
     {
       gwr::ProfDispatch pd(gwr::kFamSinkRow);
       hipEvent_t eb = pd.b, ee = pd.e;
-      const int lst = it == iters - 1;
+      // a pass that may be the last one leaves (m_i, s_i) for k_sk_f
+      const int lst = it == iters - 1 || check;
       const double* gp = it > 0 ? gprev : nullptr;
       switch (gwb::row_class(N)) {
-        case gwb::kClsN256: launch_row<256, 1>(nb, s, eb, ee, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, lse, gp, lst); break;
-        case gwb::kClsN512: launch_row<512, 1>(nb, s, eb, ee, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, lse, gp, lst); break;
-        case gwb::kClsN1024: launch_row<1024, 1>(nb, s, eb, ee, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, lse, gp, lst); break;
-        case gwb::kClsN2048: launch_row<1024, 2>(nb, s, eb, ee, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, lse, gp, lst); break;
-        case gwb::kClsN3072: launch_row<256, 12>(nb, s, eb, ee, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, lse, gp, lst); break;
-        case gwb::kClsN4096: hipExtLaunchKernelGGL(k_sk_rowg<8, 2, true>, dim3(nb), dim3(1024), 0, s, eb, ee, 0, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, g, f, ms, pS, pX, lse, gp, lst); break;
-        case gwb::kClsN6144: launch_row<512, 12>(nb, s, eb, ee, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, lse, gp, lst); break;
-        case gwb::kClsN8192: launch_row<512, 16>(nb, s, eb, ee, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, lse, gp, lst); break;
-        case gwb::kClsN9216: launch_row<512, 18>(nb, s, eb, ee, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, lse, gp, lst); break;
-        case gwb::kClsN12288: launch_row<512, 24>(nb, s, eb, ee, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, lse, gp, lst); break;
-        default: launch_row<512, 32>(nb, s, eb, ee, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, lse, gp, lst); break;
+        case gwb::kClsN256: launch_row<256, 1>(nb, s, eb, ee, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, lse, gp, lst, stop); break;
+        case gwb::kClsN512: launch_row<512, 1>(nb, s, eb, ee, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, lse, gp, lst, stop); break;
+        case gwb::kClsN1024: launch_row<1024, 1>(nb, s, eb, ee, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, lse, gp, lst, stop); break;
+        case gwb::kClsN2048: launch_row<1024, 2>(nb, s, eb, ee, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, lse, gp, lst, stop); break;
+        case gwb::kClsN3072: launch_row<256, 12>(nb, s, eb, ee, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, lse, gp, lst, stop); break;
+        case gwb::kClsN4096: hipExtLaunchKernelGGL(k_sk_rowg<8, 2, true>, dim3(nb), dim3(1024), 0, s, eb, ee, 0, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, g, f, ms, pS, pX, lse, gp, lst, stop); break;
+        case gwb::kClsN6144: launch_row<512, 12>(nb, s, eb, ee, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, lse, gp, lst, stop); break;
+        case gwb::kClsN8192: launch_row<512, 16>(nb, s, eb, ee, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, lse, gp, lst, stop); break;
+        case gwb::kClsN9216: launch_row<512, 18>(nb, s, eb, ee, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, lse, gp, lst, stop); break;
+        case gwb::kClsN12288: launch_row<512, 24>(nb, s, eb, ee, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, lse, gp, lst, stop); break;
+        default: launch_row<512, 32>(nb, s, eb, ee, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, lse, gp, lst, stop); break;
       }
     }
     {
       gwr::ProfDispatch pd(gwr::kFamSinkCol);
-      hipExtLaunchKernelGGL(k_sk_col, dim3((unsigned)((N + MERGE_COLS - 1) / MERGE_COLS)),
-                            dim3(256), 0, s, pd.b, pd.e, 0, Ni, nb, pS, pX, q, logq, eps, g,
-                            status, gprev);
+      hipExtLaunchKernelGGL(k_sk_col, dim3((unsigned)ncb), dim3(256), 0, s, pd.b, pd.e, 0, Ni,
+                            nb, pS, pX, q, logq, eps, g, status, gprev, stop,
+                            check ? errpart : nullptr);
+    }
+    if (check) {
+      gwr::ProfScope ps(gwr::kFamOther, s);
+      k_sk_check<<<1, 64, 0, s>>>(errpart, ncb, stop_opts->tol, it, ctl, stop_opts->iters_out,
+                                   stop_opts->err_out);
     }
   }
   return sinkhorn_finish(C, ldC, M, N, c_scale, p, logp, ms, eps, iters, f, g, T, ldT, s, status);

@@ -87,6 +87,12 @@ def _lib():
     lib.gw_solve.restype = I32
     lib.gw_objective.argtypes = [G, G, P, I64, D, P, P, SZ, P]
     lib.gw_objective.restype = I32
+    lib.gw_sinkhorn_tol.argtypes = [P, I64, I64, I64, D, P, P, D, I32, I32, D, I32, P, P, P, I64,
+                                    P, P, P, SZ, P]
+    lib.gw_sinkhorn_tol.restype = I32
+    lib.gw_solve_tol.argtypes = [G, G, P, P, D, I32, I32, I32, D, I32, I32, P, I64, P, P, P, P, P,
+                                 SZ, P]
+    lib.gw_solve_tol.restype = I32
     lib.gw_grad_fgw.argtypes = [G, G, P, P, P, P, D, P, I64, P, I64, I32, P, SZ, P]
     lib.gw_grad_fgw.restype = I32
     lib.gw_solve_fgw.argtypes = [G, G, P, P, P, P, D, D, I32, I32, I32, I32, P, I64, P, P, P, P,
@@ -256,6 +262,64 @@ def sinkhorn(C, p, q, eps: float, iters: int, c_scale: float = 1.0, f=None, g=No
                             T.stride(0) if T is not None else N, _ptr(ws), ws.numel(), _stream())
     _raise(st, "gw_sinkhorn")
     return (f, g, T) if plan else (f, g)
+
+
+def sinkhorn_tol(C, p, q, eps: float, max_iters: int, check_every: int, tol: float,
+                 c_scale: float = 1.0, f=None, g=None, plan: bool = False, ws=None):
+    """Sinkhorn stopped once the column violation of the half-step plan, measured
+    every check_every iterations, is <= tol.  Returns (f, g, iters_done, err) or
+    (f, g, T, iters_done, err); iters_done (int32) and err are device tensors."""
+    M, N = C.shape
+    _check_f64("C", C, (M, N)); _check_f64("p", p, (M,)); _check_f64("q", q, (N,))
+    init_zero = 1 if (f is None and g is None) else 0
+    if f is None:
+        f = torch.zeros(M, dtype=torch.float64, device=C.device)
+    if g is None:
+        g = torch.zeros(N, dtype=torch.float64, device=C.device)
+    T = torch.empty((M, N), dtype=torch.float64, device=C.device) if plan else None
+    done = torch.empty(1, dtype=torch.int32, device=C.device)
+    err = torch.empty(1, dtype=torch.float64, device=C.device)
+    gx, gy = Grid((M,), 1.0, 1), Grid((N,), 1.0, 1)
+    nb = workspace_bytes(gx, gy, PATH_FAST_F64, OP_SINKHORN)
+    if ws is None:
+        ws = workspace(nb, C.device)
+    st = _lib().gw_sinkhorn_tol(_ptr(C), C.stride(0), M, N, float(c_scale), _ptr(p), _ptr(q),
+                                float(eps), int(max_iters), int(check_every), float(tol),
+                                init_zero, _ptr(f), _ptr(g), _ptr(T),
+                                T.stride(0) if T is not None else N, _ptr(done), _ptr(err),
+                                _ptr(ws), ws.numel(), _stream())
+    _raise(st, "gw_sinkhorn_tol")
+    return (f, g, T, done, err) if plan else (f, g, done, err)
+
+
+def solve_tol(X: Grid, Y: Grid, p, q, eps: float, outer: int, max_inner: int, check_every: int,
+              tol: float, path=PATH_FAST_F64, warm: bool = False, objective: bool = True,
+              T=None, f=None, g=None, obj=None, ws=None):
+    """Entropic GW mirror descent whose Sinkhorn calls stop by tolerance; returns
+    (T, f, g, obj[2] or None, inner_done[outer] int32 device tensor)."""
+    path = PATHS.get(path, path)
+    M, N = X.size, Y.size
+    _check_f64("p", p, (M,)); _check_f64("q", q, (N,))
+    dev = p.device
+    T = torch.empty((M, N), dtype=torch.float64, device=dev) if T is None else T
+    f = torch.empty(M, dtype=torch.float64, device=dev) if f is None else f
+    g = torch.empty(N, dtype=torch.float64, device=dev) if g is None else g
+    if objective and obj is None:
+        obj = torch.empty(2, dtype=torch.float64, device=dev)
+    done = torch.empty(max(int(outer), 1), dtype=torch.int32, device=dev)
+    nb = workspace_bytes(X, Y, path, OP_SOLVE)
+    if nb == 0:
+        raise GWError(GW_EINVAL, "gw_workspace_bytes")
+    if ws is None:
+        ws = workspace(nb, dev, key="solve")
+    xc, yc = X.c(), Y.c()
+    st = _lib().gw_solve_tol(ctypes.byref(xc), ctypes.byref(yc), _ptr(p), _ptr(q), float(eps),
+                             int(outer), int(max_inner), int(check_every), float(tol), int(path),
+                             FLAG_WARM_START if warm else 0, _ptr(T), T.stride(0), _ptr(f),
+                             _ptr(g), _ptr(obj if objective else None), _ptr(done), _ptr(ws),
+                             ws.numel(), _stream())
+    _raise(st, "gw_solve_tol")
+    return T, f, g, (obj if objective else None), done[:outer]
 
 
 def solve(X: Grid, Y: Grid, p, q, eps: float, outer: int, inner: int, path=PATH_FAST_F64,
