@@ -217,6 +217,36 @@ def fgw_bench(n: int = 4000, theta: float = 0.5, eps: float = 2e-3, outer: int =
             "objective_fgw": E_fgw}
 
 
+def tolerance_bench(tol: float = 1e-4, every: int = 10):
+    """The 1D n = 4096 solves (k = 1, 2, 3; eps = 1e-3; 100 outer steps) with
+    warm-started Sinkhorn: at most 100 inner iterations, fixed count vs stopped
+    once the half-step column violation (checked every `every` iterations) is
+    <= tol.  Reports time, inner iterations run and the objective change."""
+    import torch
+    from paper_2404_08970_amd import gw
+    dev = torch.device("cuda:0")
+    out = {"workload": f"1D n = {N}, k in {{1,2,3}}, eps = {EPS}, {OUTER} outer, warm start, "
+                       f"<= {INNER} Sinkhorn iterations, tol = {tol} checked every {every}"}
+    for k in KS:
+        X = gw.unit_grid((N,), k)
+        p, q = (torch.tensor(v, device=dev) for v in marginals(N, k))
+        gw.solve(X, X, p, q, EPS, 1, 5, warm=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, _, _, o1 = gw.solve(X, X, p, q, EPS, OUTER, INNER, warm=True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, _, _, o2, done = gw.solve_tol(X, X, p, q, EPS, OUTER, INNER, every, tol, warm=True)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        e1, e2 = float(o1[0].item()), float(o2[0].item())
+        out[f"k{k}"] = {"fixed_ms": round((t1 - t0) * 1e3, 1), "tol_ms": round((t2 - t1) * 1e3, 1),
+                        "inner_iters_fixed": OUTER * INNER,
+                        "inner_iters_tol": int(done.sum().item()),
+                        "objective_rel_change": abs(e2 - e1) / abs(e1)}
+    return out
+
+
 def precision_study(n: int = 16384, k: int = 2, rows: int = 6):
     """Dense gradient in FP64, FP32, BF16 and split refinements at n = 16384, k = 2,
     Dirichlet(1) marginals, on two plans: p q^T and the plan after one FAST
@@ -367,6 +397,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the request-loop measurement")
     ap.add_argument("--no-2d", action="store_true", help="skip the 2D 64x64 solve")
     ap.add_argument("--no-fgw", action="store_true", help="skip the 1D fused GW solve")
+    ap.add_argument("--no-tol", action="store_true", help="skip the tolerance-stop comparison")
+    ap.add_argument("--only-tol", action="store_true", help="run only the tolerance-stop comparison")
     ap.add_argument("--only-fgw", action="store_true", help="run only the 1D fused GW solve and exit")
     ap.add_argument("--only-2d", action="store_true", help="run only the 2D 64x64 solve and exit")
     ap.add_argument("--serve-only", action="store_true", help="run only the request loop and exit")
@@ -376,6 +408,9 @@ def main():
     args = ap.parse_args()
     if args.precision:
         print(json.dumps(precision_study()))
+        return
+    if args.only_tol:
+        print(json.dumps(tolerance_bench()))
         return
     if args.only_fgw:
         print(json.dumps(fgw_bench()))
@@ -500,6 +535,7 @@ def main():
 
     grid2d = None if args.no_2d else grid2d_bench()
     fused = None if args.no_fgw else fgw_bench()
+    stopped = None if args.no_tol else tolerance_bench()
     serving = None
     if not args.no_serve:
         serving = serve_bench(args.serve_requests, args.serve_slots, args.serve_iters)
@@ -527,6 +563,7 @@ def main():
         "objective": objs,
         "grid2d_64x64": grid2d,
         "fgw_1d_n4000": fused,
+        "tolerance_stop": stopped,
         "serving": serving,
     }
     if not args.no_cpu:
