@@ -23,6 +23,8 @@ Everything here is written to be read against the paper (arXiv 2404.08970,
 * Pascal recursion for L x ....... Sec. 3, Eq. (1d y), Eq. (1d recursive relation)
 * four-term split of D Gamma D ... Sec. 3, Eq. (Dx)
 * 2D Kronecker expansion ......... Sec. 3.1, Eq. (2D kronecker), Eq. (2d gradient)
+* 3D grids ....................... Sec. 3.1's expansion with a third factor (the
+                                   section states higher dimensions work alike)
 * fused GW (FGW) ................. Remark (Entropic algorithm for FGW): objective
                                    and gradient decomposition C_2 - 4 theta D Gamma D
 
@@ -44,6 +46,8 @@ Readings where the paper is silent or garbled:
 * T^0 = p q^T; Sinkhorn updates f then g, cold start each outer iteration,
   fixed iteration counts; LSE is max-shifted; p_i = 0 gives f_i = -inf.
 * SQEUCLID (h^2 (dr^2 + dc^2)) is supported beside the paper's (l1)^k metric.
+* 3D grids: (|dd|+|dr|+|dc|)^k or squared Euclidean, flattened row-major
+  (flat = (d * H + r) * W + c).
 * FGW feature cost c_ip = fa_i - fb_p (its square enters): every FGW workload
   of the paper has this form (|i - p|, signal-strength and gray-level
   differences).
@@ -69,10 +73,12 @@ METRIC_SQEUCLID = 1
 
 @dataclass(frozen=True)
 class Grid:
-    """A uniform grid: 1D with ``shape=(n,)`` or 2D with ``shape=(H, W)``.
+    """A uniform grid: 1D with ``shape=(n,)``, 2D with ``shape=(H, W)`` or 3D
+    with ``shape=(D, H, W)`` (the extension of Sec. 3.1 to one more axis).
 
     ``h`` is the spacing, ``k`` the exponent of the distance (Sec. 2 and
-    Sec. 3.1) and ``metric`` selects (|dr|+|dc|)^k (the paper's 2D metric) or
+    Sec. 3.1) and ``metric`` selects the l1 distance to the power k,
+    (|dr|+|dc|)^k in 2D (the paper's metric) and (|dd|+|dr|+|dc|)^k in 3D, or
     the squared Euclidean distance (k must be 2)."""
 
     shape: tuple
@@ -101,13 +107,32 @@ def h_power(g: Grid) -> float:
     return v
 
 
+def _axis_coords(g: Grid, flat) -> list:
+    """Row-major coordinates of flat indices, one array per axis."""
+    coords, rest = [], np.asarray(flat, dtype=np.int64)
+    for ext in reversed(g.shape):
+        coords.append(rest % ext)
+        rest = rest // ext
+    return coords[::-1]
+
+
+def _distance_from_axes(g: Grid, diffs) -> np.ndarray:
+    if g.metric == METRIC_SQEUCLID:
+        return sum(d * d for d in diffs)
+    return sum(diffs) ** g.k
+
+
 def integer_distance(g: Grid) -> np.ndarray:
     """Unscaled integer distance matrix (int64), Eq. (1d distance matrices) /
-    Eq. (2d Dx).  2D grids are flattened row-major."""
+    Eq. (2d Dx) and its 3D analogue.  Multi-dimensional grids are flattened
+    row-major."""
     if g.ndim == 1:
         idx = np.arange(g.shape[0], dtype=np.int64)
         d = np.abs(idx[:, None] - idx[None, :])
         return d ** g.k
+    if g.ndim == 3:
+        co = _axis_coords(g, np.arange(g.size))
+        return _distance_from_axes(g, [np.abs(c[:, None] - c[None, :]) for c in co])
     H, W = g.shape
     flat = np.arange(H * W, dtype=np.int64)
     r, c = flat // W, flat % W
@@ -130,6 +155,9 @@ def integer_distance_rows(g: Grid, rows) -> np.ndarray:
     if g.ndim == 1:
         idx = np.arange(g.shape[0], dtype=np.int64)
         return np.abs(rows[:, None] - idx[None, :]) ** g.k
+    if g.ndim == 3:
+        ca, cb = _axis_coords(g, rows), _axis_coords(g, np.arange(g.size))
+        return _distance_from_axes(g, [np.abs(a[:, None] - b[None, :]) for a, b in zip(ca, cb)])
     H, W = g.shape
     flat = np.arange(H * W, dtype=np.int64)
     r, c = flat // W, flat % W
@@ -235,6 +263,8 @@ def grid_apply(g: Grid, X: np.ndarray) -> np.ndarray:
     D^{o2} mat(x) J + J mat(x) D^{o2}."""
     if g.ndim == 1:
         return toeplitz_apply(X, g.k)
+    if g.ndim == 3:
+        return _grid_apply_3d(g, X)
     H, W = g.shape
     L = X.shape[1]
     img = X.reshape(H, W, L)
@@ -252,6 +282,31 @@ def grid_apply(g: Grid, X: np.ndarray) -> np.ndarray:
         t = toeplitz_apply(t, mr)
         out = out + coef * t
     return out.reshape(H * W, L)
+
+
+def _grid_apply_3d(g: Grid, X: np.ndarray) -> np.ndarray:
+    """3D: the Kronecker expansion of Sec. 3.1 with three factors.  (l1)^k:
+    (d1 + d2 + d3)^k = sum over a + b + c = k of k!/(a! b! c!) d1^a d2^b d3^c,
+    so D = sum k!/(a! b! c!) D_1^{oa} (x) D_1^{ob} (x) D_1^{oc} (D_1^{o0} = J);
+    SQEUCLID: D_1^{o2} (x) J (x) J + J (x) D_1^{o2} (x) J + J (x) J (x) D_1^{o2}.
+    Each factor acts along its own axis of the reshaped vector."""
+    D0, H, W = g.shape
+    L = X.shape[1]
+    img = X.reshape(D0, H, W, L)
+    if g.metric == METRIC_SQEUCLID:
+        terms = [(1, (2, 0, 0)), (1, (0, 2, 0)), (1, (0, 0, 2))]
+    else:
+        k = g.k
+        terms = [(math.factorial(k) // (math.factorial(a) * math.factorial(b) *
+                                        math.factorial(k - a - b)), (a, b, k - a - b))
+                 for a in range(k + 1) for b in range(k + 1 - a)]
+    out = np.zeros(img.shape, dtype=np.float64)
+    for coef, ms in terms:
+        t = img
+        for axis in (2, 1, 0):
+            t = np.moveaxis(toeplitz_apply(np.moveaxis(t, axis, 0), ms[axis]), 0, axis)
+        out = out + coef * t
+    return out.reshape(D0 * H * W, L)
 
 
 def grad_pascal(gx: Grid, gy: Grid, p, q, T) -> np.ndarray:
