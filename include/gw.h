@@ -78,15 +78,19 @@ typedef int32_t gw_status;
 /* gw_solve flags */
 #define GW_FLAG_WARM_START 1  /* Sinkhorn starts from the previous outer step's potentials */
 
-/* A uniform grid (Sec. 2; Sec. 3.1).  ndim = 1: shape = {n, 1}; ndim = 2:
- * shape = {H, W}, points flattened row-major (flat = r * W + c).  h > 0 is the
+/* A uniform grid (Sec. 2; Sec. 3.1, which states that more axes work alike).
+ * ndim = 1: shape = {n, 1, 1}; ndim = 2: shape = {H, W, 1}, points flattened
+ * row-major (flat = r * W + c); ndim = 3: shape = {D, H, W},
+ * flat = (d * H + r) * W + c, distance (|dd| + |dr| + |dc|)^k (L1POW) or
+ * dd^2 + dr^2 + dc^2 (SQEUCLID), times h^k.  3D grids run on GW_PATH_FAST_F64
+ * only (the dense paths are 1D).  h > 0 is the
  * spacing, k in [1, GW_KMAX] the exponent, metric one of GW_METRIC_*. */
 typedef struct gw_grid {
   int32_t ndim;
   int32_t k;
   int32_t metric;
   int32_t reserved; /* must be 0 */
-  int64_t shape[2];
+  int64_t shape[3];
   double h;
 } gw_grid;
 

@@ -15,26 +15,33 @@ static const int64_t kMaxExtent = 65535;
 gw_status to_grid(const gw_grid* g, Grid* out) {
   if (!g) return GW_EINVAL;
   if (g->reserved != 0) return GW_EINVAL;
-  if (g->ndim != 1 && g->ndim != 2) return GW_EINVAL;
+  if (g->ndim < 1 || g->ndim > 3) return GW_EINVAL;
   if (g->metric != GW_METRIC_L1POW && g->metric != GW_METRIC_SQEUCLID) return GW_EINVAL;
   if (g->k < 1 || g->k > GW_KMAX) return GW_EINVAL;
   if (g->metric == GW_METRIC_SQEUCLID && g->k != 2) return GW_EINVAL;
   if (!(g->h > 0.0) || !isfinite(g->h)) return GW_EINVAL;
-  if (g->shape[0] < 1 || g->shape[1] < 1) return GW_EINVAL;
+  if (g->shape[0] < 1 || g->shape[1] < 1 || g->shape[2] < 1) return GW_EINVAL;
   if (g->ndim == 1 && g->shape[1] != 1) return GW_EINVAL;
+  if (g->ndim <= 2 && g->shape[2] != 1) return GW_EINVAL;
   Grid r;
   r.ndim = g->ndim;
   r.k = g->k;
   r.metric = g->metric;
   r.h = g->h;
+  r.Z = 1;
   if (g->ndim == 1) {
     r.H = 1;
     r.W = g->shape[0];
-  } else {
+  } else if (g->ndim == 2) {
     r.H = g->shape[0];
     r.W = g->shape[1];
+  } else {
+    r.Z = g->shape[0];
+    r.H = g->shape[1];
+    r.W = g->shape[2];
   }
-  if (r.H > kMaxExtent || r.W > kMaxExtent || r.n() > kMaxExtent) return GW_EUNSUPPORTED;
+  if (r.Z > kMaxExtent || r.H > kMaxExtent || r.W > kMaxExtent) return GW_EUNSUPPORTED;
+  if (r.Z * r.H > kMaxExtent || r.n() > kMaxExtent) return GW_EUNSUPPORTED;
   *out = r;
   return GW_OK;
 }

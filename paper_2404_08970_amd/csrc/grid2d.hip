@@ -144,6 +144,53 @@ __global__ __launch_bounds__(1024) void k_const_term(int metric, int k, int H, i
   }
 }
 
+// 3D grids: c_i = sum_j (hk d(i,j))^2 w_j directly, d the (l1)^k or squared
+// Euclidean distance of the (z, r, c) coordinates; 64 outputs per block, the
+// j range split over 16 groups summed in group order.
+__global__ __launch_bounds__(1024) void k_const_term3(int metric, int k, int Z, int H, int W,
+                                                       double hk, const double* __restrict__ w,
+                                                       double* __restrict__ c) {
+  __shared__ double part[CT_GROUPS][64];
+  const int hw = H * W, n = Z * hw;
+  const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
+  const int i = blockIdx.x * 64 + lane;
+  double acc = 0.0;
+  if (i < n) {
+    const int zi = i / hw, ri = (i % hw) / W, ci = i % W;
+    const int chunk = (n + CT_GROUPS - 1) / CT_GROUPS;
+    const int j0 = grp * chunk, j1 = min(n, j0 + chunk);
+    int zj = j0 / hw, rj = (j0 % hw) / W, cj = j0 % W;
+    for (int j = j0; j < j1; ++j) {
+      const int dz = abs(zi - zj), dr = abs(ri - rj), dc = abs(ci - cj);
+      double d;
+      if (metric == GW_METRIC_SQEUCLID) {
+        d = (double)(dz * dz + dr * dr + dc * dc);
+      } else {
+        const double e = (double)(dz + dr + dc);
+        d = e;
+        for (int u = 1; u < k; ++u) d *= e;
+      }
+      const double D = hk * d;
+      acc = fma(D * D, w[j], acc);
+      if (++cj == W) {
+        cj = 0;
+        if (++rj == H) {
+          rj = 0;
+          ++zj;
+        }
+      }
+    }
+  }
+  part[grp][lane] = acc;
+  __syncthreads();
+  if (grp == 0 && i < n) {
+    double s = part[0][lane];
+#pragma unroll
+    for (int g = 1; g < CT_GROUPS; ++g) s += part[g][lane];
+    c[i] = s;
+  }
+}
+
 // 1D grids: c = hk^2 [|i-j|^{2k}] w by the recursion with exponent K2 = 2k,
 // one block per vector (up to two vectors per launch: blockIdx.x selects the
 // job).  Thread t owns entries [16 t, 16 t + 16).  Segment summaries (prefix
@@ -335,20 +382,70 @@ __device__ void line_op(int m, const double* x, int64_t xs, double* y, int64_t y
   }
 }
 
-// Apply the (unscaled) grid operator to each row of `in` (rows x n, n = H*W)
-// treating the row as an H x W image; one block per row.  `tmp` is a rows x n
-// scratch.  1D grids (H = 1) use a single sequential line per row.
+// Apply the (unscaled) grid operator to each row of `in` (rows x n,
+// n = Z*H*W) treating the row as a Z x H x W array; one block per row.  `tmp`
+// (and `tmp2` for 3D) are rows x n scratch.  1D grids use a single sequential
+// line per row.
 __global__ __launch_bounds__(NT) void k_rowop(const double* __restrict__ in, int64_t ldi,
                                                int64_t rows, int ndim, int k, int metric,
-                                               int64_t H, int64_t W, double* __restrict__ out,
-                                               int64_t ldo, double* __restrict__ tmp) {
+                                               int64_t Z, int64_t H, int64_t W,
+                                               double* __restrict__ out, int64_t ldo,
+                                               double* __restrict__ tmp,
+                                               double* __restrict__ tmp2) {
   const int64_t row = blockIdx.x;
   const double* x = in + row * ldi;
   double* y = out + row * ldo;
-  double* t = tmp + row * (H * W);
+  const int64_t hw = H * W;
+  double* t = tmp + row * (Z * hw);
   const int tid = threadIdx.x;
   if (ndim == 1) {
     if (tid == 0) line_op(metric == GW_METRIC_SQEUCLID ? 2 : k, x, 1, y, 1, W, 1.0, false);
+    return;
+  }
+  if (ndim == 3) {
+    // (l1)^k: (dz + dr + dc)^k = sum over a + b + c = k of k!/(a! b! c!) dz^a dr^b dc^c,
+    // one Kronecker term per (a, b, c); SQEUCLID: the three squared axes
+    constexpr int MAXT = (GW_KMAX + 1) * (GW_KMAX + 2) / 2;
+    int nterms = 0;
+    int coefs[MAXT], mz[MAXT], mh[MAXT], mw[MAXT];
+    if (metric == GW_METRIC_SQEUCLID) {
+      for (int ax = 0; ax < 3; ++ax) {
+        coefs[ax] = 1;
+        mz[ax] = ax == 0 ? 2 : 0;
+        mh[ax] = ax == 1 ? 2 : 0;
+        mw[ax] = ax == 2 ? 2 : 0;
+      }
+      nterms = 3;
+    } else {
+      int fact[GW_KMAX + 1];
+      fact[0] = 1;
+      for (int u = 1; u <= k; ++u) fact[u] = fact[u - 1] * u;
+      for (int a = 0; a <= k; ++a)
+        for (int b = 0; a + b <= k; ++b) {
+          coefs[nterms] = fact[k] / (fact[a] * fact[b] * fact[k - a - b]);
+          mz[nterms] = a;
+          mh[nterms] = b;
+          mw[nterms] = k - a - b;
+          ++nterms;
+        }
+    }
+    double* t2 = tmp2 + row * (Z * hw);
+    for (int term = 0; term < nterms; ++term) {
+      // along W: the Z*H lines of length W
+      for (int64_t l = tid; l < Z * H; l += NT)
+        line_op(mw[term], x + l * W, 1, t + l * W, 1, W, 1.0, false);
+      __syncthreads();
+      // along H: the Z*W lines of stride W
+      for (int64_t l = tid; l < Z * W; l += NT) {
+        const int64_t off = (l / W) * hw + l % W;
+        line_op(mh[term], t + off, W, t2 + off, W, H, 1.0, false);
+      }
+      __syncthreads();
+      // along Z: the H*W lines of stride H*W, accumulated into y
+      for (int64_t e = tid; e < hw; e += NT)
+        line_op(mz[term], t2 + e, hw, y + e, hw, Z, (double)coefs[term], term > 0);
+      __syncthreads();
+    }
     return;
   }
   int nterms;
@@ -658,7 +755,12 @@ gw_status const_term(const gwr::Grid& g, const double* w, double* c, hipStream_t
       return gwr::last_launch_status();
     }
   }
-  k_const_term<<<(unsigned)((n + 63) / 64), 1024, 0, s>>>(g.metric, g.k, (int)g.H, (int)g.W, g.hk(), w, c);
+  if (g.ndim == 3)
+    k_const_term3<<<(unsigned)((n + 63) / 64), 1024, 0, s>>>(g.metric, g.k, (int)g.Z, (int)g.H,
+                                                             (int)g.W, g.hk(), w, c);
+  else
+    k_const_term<<<(unsigned)((n + 63) / 64), 1024, 0, s>>>(g.metric, g.k, (int)g.H, (int)g.W,
+                                                            g.hk(), w, c);
   return gwr::last_launch_status();
 }
 
@@ -703,6 +805,7 @@ size_t fast_generic_ws_bytes(const gwr::Grid& X, const gwr::Grid& Y) {
     a.take<double>((size_t)M * N);
     a.take<double>((size_t)M * N);
     a.take<double>((size_t)M * N);
+    if (X.ndim == 3 || Y.ndim == 3) a.take<double>((size_t)M * N);
   }
   a.take<double>(M);
   a.take<double>(N);
@@ -717,7 +820,7 @@ gw_status fast_generic(const gwr::Grid& X, const gwr::Grid& Y, const double* p,
   SepGrid sx, sy;
   const bool sep = separable(X, &sx) && separable(Y, &sy);
   double *U = nullptr, *V = nullptr, *R[4] = {}, *P[4] = {}, *Q[4] = {};
-  double *A = nullptr, *At = nullptr, *tmp = nullptr;
+  double *A = nullptr, *At = nullptr, *tmp = nullptr, *tmp2 = nullptr;
   if (sep) {
     U = ws.take<double>(M * Y.H);
     V = ws.take<double>(M * Y.W);
@@ -732,6 +835,7 @@ gw_status fast_generic(const gwr::Grid& X, const gwr::Grid& Y, const double* p,
     A = ws.take<double>((size_t)M * N);
     At = ws.take<double>((size_t)M * N);
     tmp = ws.take<double>((size_t)M * N);
+    if (X.ndim == 3 || Y.ndim == 3) tmp2 = ws.take<double>((size_t)M * N);
   }
   double* c1 = ws.take<double>(M);
   double* c2 = ws.take<double>(N);
@@ -796,10 +900,12 @@ gw_status fast_generic(const gwr::Grid& X, const gwr::Grid& Y, const double* p,
     return gwr::last_launch_status();
   }
   // generic: A = T D^_Y (rows), At = A^T, Bt = At D^_X (rows), G = epilogue(Bt^T)
-  k_rowop<<<(unsigned)M, NT, 0, s>>>(T, ldT, M, Y.ndim, Y.k, Y.metric, Y.H, Y.W, A, N, tmp);
+  k_rowop<<<(unsigned)M, NT, 0, s>>>(T, ldT, M, Y.ndim, Y.k, Y.metric, Y.Z, Y.H, Y.W, A, N, tmp,
+                                     tmp2);
   dim3 tg1((unsigned)((N + 31) / 32), (unsigned)((M + 31) / 32));
   k_transpose<<<tg1, NT, 0, s>>>(A, N, M, N, At, M, nullptr, nullptr, 0.0);
-  k_rowop<<<(unsigned)N, NT, 0, s>>>(At, M, N, X.ndim, X.k, X.metric, X.H, X.W, A, M, tmp);
+  k_rowop<<<(unsigned)N, NT, 0, s>>>(At, M, N, X.ndim, X.k, X.metric, X.Z, X.H, X.W, A, M, tmp,
+                                     tmp2);
   dim3 tg2((unsigned)((M + 31) / 32), (unsigned)((N + 31) / 32));
   k_transpose<<<tg2, NT, 0, s>>>(A, M, N, M, G, ldG, c1, c2, s2);
   if (epi) return fgw_blend(G, ldG, M, N, epi->fa, epi->fb, epi->a, epi->b, s);

@@ -14,9 +14,9 @@ struct Grid {
   int ndim;
   int k;
   int metric;
-  int64_t H, W;  // 1D: H = 1, W = n
+  int64_t Z, H, W;  // 1D: Z = H = 1, W = n; 2D: Z = 1
   double h;
-  int64_t n() const { return H * W; }
+  int64_t n() const { return Z * H * W; }
   // h^k as k left-to-right products (h^2 for SQEUCLID).
   double hk() const {
     int kk = metric == GW_METRIC_SQEUCLID ? 2 : k;

@@ -48,7 +48,7 @@ class GWError(RuntimeError):
 
 class c_grid(ctypes.Structure):
     _fields_ = [("ndim", ctypes.c_int32), ("k", ctypes.c_int32), ("metric", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("shape", ctypes.c_int64 * 2), ("h", ctypes.c_double)]
+                ("reserved", ctypes.c_int32), ("shape", ctypes.c_int64 * 3), ("h", ctypes.c_double)]
 
 
 class c_request(ctypes.Structure):
@@ -140,7 +140,8 @@ def library():
 
 @dataclass(frozen=True)
 class Grid:
-    """Uniform grid: ``shape=(n,)`` (1D) or ``(H, W)`` (2D, row-major)."""
+    """Uniform grid: ``shape=(n,)`` (1D), ``(H, W)`` (2D) or ``(D, H, W)`` (3D),
+    flattened row-major."""
     shape: tuple
     h: float
     k: int
@@ -164,13 +165,15 @@ class Grid:
         g.metric = self.metric
         g.reserved = 0
         g.shape[0] = int(self.shape[0])
-        g.shape[1] = int(self.shape[1]) if self.ndim == 2 else 1
+        g.shape[1] = int(self.shape[1]) if self.ndim >= 2 else 1
+        g.shape[2] = int(self.shape[2]) if self.ndim == 3 else 1
         g.h = float(self.h)
         return g
 
 
 def unit_grid(shape, k: int, metric: int = METRIC_L1POW) -> Grid:
-    """Grid on [0,1] (or [0,1]^2) with h = 1/(n-1)."""
+    """Grid on [0,1] along its first axis (the other axes share the spacing),
+    h = 1/(n-1)."""
     shape = tuple(int(s) for s in shape)
     h = 1.0 / max(shape[0] - 1, 1)
     return Grid(shape, h, k, metric)
