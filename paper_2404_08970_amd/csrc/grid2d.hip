@@ -145,38 +145,51 @@ __global__ __launch_bounds__(1024) void k_const_term(int metric, int k, int H, i
 }
 
 // 3D grids: c_i = sum_j (hk d(i,j))^2 w_j directly, d the (l1)^k or squared
-// Euclidean distance of the (z, r, c) coordinates; 64 outputs per block, the
-// j range split over 16 groups summed in group order.
+// Euclidean distance of the (z, r, c) coordinates.  A block of 1024 threads
+// owns CT3_OUT outputs (lane) and splits j over 64 groups; w passes through
+// LDS in chunks, each chunk split into 64 contiguous group ranges; a group's
+// partial runs over its ranges in chunk order and the groups' partials are
+// added in group order.
+constexpr int CT3_OUT = 16, CT3_GRP = 64, CT3_CHUNK = 8192;
 __global__ __launch_bounds__(1024) void k_const_term3(int metric, int k, int Z, int H, int W,
                                                        double hk, const double* __restrict__ w,
                                                        double* __restrict__ c) {
-  __shared__ double part[CT_GROUPS][64];
+  __shared__ double wc[CT3_CHUNK];
+  __shared__ double part[CT3_GRP][CT3_OUT];
   const int hw = H * W, n = Z * hw;
-  const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
-  const int i = blockIdx.x * 64 + lane;
+  const int lane = threadIdx.x & (CT3_OUT - 1), grp = threadIdx.x / CT3_OUT;
+  const int i = blockIdx.x * CT3_OUT + lane;
+  const int ii = min(i, n - 1);
+  const int zi = ii / hw, ri = (ii % hw) / W, ci = ii % W;
   double acc = 0.0;
-  if (i < n) {
-    const int zi = i / hw, ri = (i % hw) / W, ci = i % W;
-    const int chunk = (n + CT_GROUPS - 1) / CT_GROUPS;
-    const int j0 = grp * chunk, j1 = min(n, j0 + chunk);
-    int zj = j0 / hw, rj = (j0 % hw) / W, cj = j0 % W;
-    for (int j = j0; j < j1; ++j) {
-      const int dz = abs(zi - zj), dr = abs(ri - rj), dc = abs(ci - cj);
-      double d;
-      if (metric == GW_METRIC_SQEUCLID) {
-        d = (double)(dz * dz + dr * dr + dc * dc);
-      } else {
-        const double e = (double)(dz + dr + dc);
-        d = e;
-        for (int u = 1; u < k; ++u) d *= e;
-      }
-      const double D = hk * d;
-      acc = fma(D * D, w[j], acc);
-      if (++cj == W) {
-        cj = 0;
-        if (++rj == H) {
-          rj = 0;
-          ++zj;
+  for (int j0 = 0; j0 < n; j0 += CT3_CHUNK) {
+    const int len = min(CT3_CHUNK, n - j0);
+    __syncthreads();
+    for (int e = threadIdx.x; e < len; e += 1024) wc[e] = w[j0 + e];
+    __syncthreads();
+    const int glen = (len + CT3_GRP - 1) / CT3_GRP;
+    const int a0 = grp * glen, a1 = min(len, a0 + glen);
+    if (a0 < a1) {
+      const int j = j0 + a0;
+      int zj = j / hw, rj = (j % hw) / W, cj = j % W;
+      for (int a = a0; a < a1; ++a) {
+        const int dz = abs(zi - zj), dr = abs(ri - rj), dc = abs(ci - cj);
+        double d;
+        if (metric == GW_METRIC_SQEUCLID) {
+          d = (double)(dz * dz + dr * dr + dc * dc);
+        } else {
+          const double e = (double)(dz + dr + dc);
+          d = e;
+          for (int u = 1; u < k; ++u) d *= e;
+        }
+        const double D = hk * d;
+        acc = fma(D * D, wc[a], acc);
+        if (++cj == W) {
+          cj = 0;
+          if (++rj == H) {
+            rj = 0;
+            ++zj;
+          }
         }
       }
     }
@@ -185,8 +198,7 @@ __global__ __launch_bounds__(1024) void k_const_term3(int metric, int k, int Z, 
   __syncthreads();
   if (grp == 0 && i < n) {
     double s = part[0][lane];
-#pragma unroll
-    for (int g = 1; g < CT_GROUPS; ++g) s += part[g][lane];
+    for (int g = 1; g < CT3_GRP; ++g) s += part[g][lane];
     c[i] = s;
   }
 }
@@ -687,6 +699,286 @@ bool separable(const gwr::Grid& g, SepGrid* s) {
 
 unsigned blocks_for(int64_t n) { return (unsigned)((n + NT - 1) / NT); }
 
+// --------------------------------------------------- axis-separable path
+// Grids whose distance is a sum of per-axis terms, d(i, j) = sum_a |x_a(i) -
+// x_a(j)|^m (1D: one axis, m = k; 2D/3D squared Euclidean: m = 2; 2D/3D
+// (l1)^1: m = 1), so D = sum_a J (x) .. (x) D_a^{om} (x) .. (x) J (the
+// Kronecker expansion of Sec. 3.1 without cross terms).  Then
+//   (D_X T D_Y)[i][p] = sum_{u, v} Q_uv[x_u(i)][y_v(p)],
+//   Q_uv = D_u^{om} R_uv D_v^{om},  R_uv[x][y] = sum of T over the rows with
+//   x_u = x and the columns with y_v = y,
+// so T is reduced once to small matrices, the 1D operators act on those, and
+// the write pass gathers one value per axis pair.  Used for 3D grids and for
+// mixed 1D/2D pairs; 1D x 1D and 2D x 2D have their own paths.
+struct AxGrid {
+  int na;             // number of axes (leading axis first)
+  int n[3];           // extents
+  int64_t stride[3];  // flat-index strides
+  int m;              // exponent of every per-axis term
+};
+constexpr int AX_MAXP = 9;  // axis pairs
+
+struct AxPlan {
+  AxGrid x, y;
+  int offy[3];               // offset of Y axis v in a row of U (sum of the Y extents before it)
+  int sy;                    // sum of the Y extents
+  const double* U;           // M x sy row sums (T itself when Y has one axis)
+  int64_t ldU;
+  const double* R[AX_MAXP];  // R_uv, nx_u x ny_v, leading dimension ldR (a view of U
+  int64_t ldR[AX_MAXP];      // when X has one axis)
+  double* Rw[AX_MAXP];       // where k_ax_colreduce writes R_uv
+  double* P[AX_MAXP];        // D_u R_uv
+  double* Q[AX_MAXP];        // P_uv D_v
+  int first_left[AX_MAXP + 1], first_right[AX_MAXP + 1];  // thread ranges of the line kernels
+  int first_elem[AX_MAXP + 1];  // cumulative nx_u ny_v: entry ranges of the dense kernels
+};
+
+GW_DEV int ax_coord(const AxGrid& g, int a, int64_t flat) {
+  return (int)((flat / g.stride[a]) % g.n[a]);
+}
+
+// Row sums for a Y grid of two or three axes, seen as Zy x H x W (Zy = 1 in
+// 2D): U[i][offy_v + y] = sum over the columns p of row i with y_v(p) = y.
+// One block per row, the row staged in LDS; the plane P[r][c] = sum_z row is
+// formed first (a thread per (r, c)), the H and W sums come from P, and the
+// slab sums over z (3D) are split into `qs` contiguous parts added in order.
+__global__ __launch_bounds__(NT) void k_ax_rowreduce(const double* __restrict__ T, int64_t ldT,
+                                                      int N, AxGrid ay, int qs,
+                                                      double* __restrict__ U, int sy) {
+  extern __shared__ double lds[];
+  const int na = ay.na;
+  const int Zy = na == 3 ? ay.n[0] : 1, H = ay.n[na - 2], W = ay.n[na - 1], hw = H * W;
+  double* row = lds;
+  double* P = lds + N;
+  double* part = P + hw;
+  const int64_t i = blockIdx.x;
+  const int t = threadIdx.x;
+  const double* src = T + i * ldT;
+  for (int p0 = 0; p0 < N; p0 += 8 * NT) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = src[min(p0 + t + u * NT, N - 1)];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (p0 + t + u * NT < N) row[p0 + t + u * NT] = v[u];
+  }
+  __syncthreads();
+  for (int rc = t; rc < hw; rc += NT) {
+    double acc = row[rc];
+    for (int z = 1; z < Zy; ++z) acc += row[z * hw + rc];
+    P[rc] = acc;
+  }
+  if (na == 3) {
+    const int len = (hw + qs - 1) / qs;
+    for (int w = t; w < Zy * qs; w += NT) {
+      const int z = w / qs, q = w - z * qs;
+      const int e0 = q * len, e1 = min(hw, e0 + len);
+      double acc = 0.0;
+      for (int e = e0; e < e1; ++e) acc += row[z * hw + e];
+      part[w] = acc;
+    }
+  }
+  __syncthreads();
+  double* out = U + i * sy;
+  const int offH = na == 3 ? Zy : 0, offW = offH + H;
+  for (int r = t; r < H; r += NT) {
+    double acc = P[r * W];
+    for (int c = 1; c < W; ++c) acc += P[r * W + c];
+    out[offH + r] = acc;
+  }
+  for (int c = t; c < W; c += NT) {
+    double acc = P[c];
+    for (int r = 1; r < H; ++r) acc += P[r * W + c];
+    out[offW + c] = acc;
+  }
+  if (na == 3) {
+    for (int z = t; z < Zy; z += NT) {
+      double acc = part[z * qs];
+      for (int q = 1; q < qs; ++q) acc += part[z * qs + q];
+      out[z] = acc;
+    }
+  }
+}
+
+// R_uv[x][y] = sum over the rows i with x_u(i) = x of U[i][offy_v + y]; one
+// block per (pair, x).  With nv < NT each sum is split into NT / nv parts
+// (rows in index order within a part) added in part order.
+__global__ __launch_bounds__(NT) void k_ax_colreduce(AxPlan pl, int M) {
+  __shared__ double part[NT];
+  int b = blockIdx.x, pr = 0;
+  while (b >= pl.first_right[pr + 1] - pl.first_right[pr]) {
+    b -= pl.first_right[pr + 1] - pl.first_right[pr];
+    ++pr;
+  }
+  const int u = pr / pl.y.na, v = pr % pl.y.na, x = b;
+  const int nv = pl.y.n[v], nu = pl.x.n[u];
+  const int su = (int)pl.x.stride[u];
+  const int cnt = M / nu;
+  const int K = nv >= NT ? 1 : NT / nv;
+  const int len = (cnt + K - 1) / K;
+  const int t = threadIdx.x;
+  const double* Ub = pl.U + pl.offy[v];
+  for (int y0 = 0; y0 < nv; y0 += NT) {
+    const int y = y0 + t % min(nv, NT), k = t / min(nv, NT);
+    double acc = 0.0;
+    if (k < K && y < nv) {
+      const int o0 = k * len, o1 = min(cnt, o0 + len);
+      int lo = o0 % su;
+      int64_t i = (int64_t)(o0 / su) * (su * nu) + (int64_t)x * su + lo;
+      for (int o = o0; o < o1; ++o) {
+        acc += Ub[i * pl.ldU + y];
+        ++i;
+        if (++lo == su) {
+          lo = 0;
+          i += (int64_t)su * (nu - 1);
+        }
+      }
+    }
+    if (K > 1) {
+      part[t] = acc;
+      __syncthreads();
+      if (t < nv) {
+        double r = part[t];
+        for (int kk = 1; kk < K; ++kk) r += part[kk * nv + t];
+        pl.Rw[pr][(int64_t)x * nv + t] = r;
+      }
+      __syncthreads();
+    } else if (y < nv) {
+      pl.Rw[pr][(int64_t)x * nv + y] = acc;
+    }
+  }
+}
+
+// P_uv = D_u^{om} R_uv: one thread per (pair, column y), the recursion along x.
+__global__ __launch_bounds__(NT) void k_ax_left(AxPlan pl) {
+  const int tid = blockIdx.x * NT + threadIdx.x;
+  const int npairs = pl.x.na * pl.y.na;
+  if (tid >= pl.first_left[npairs]) return;
+  int pr = 0;
+  while (tid >= pl.first_left[pr + 1]) ++pr;
+  const int u = pr / pl.y.na, v = pr % pl.y.na;
+  const int y = tid - pl.first_left[pr], nv = pl.y.n[v];
+  line_op(pl.x.m, pl.R[pr] + y, pl.ldR[pr], pl.P[pr] + y, nv, pl.x.n[u], 1.0, false);
+}
+
+// Short axes: the same products densely, one thread per entry of P (or Q).
+GW_DEV double small_pow(int d, int e) {
+  double v = 1.0;
+  for (int u = 0; u < e; ++u) v *= (double)d;
+  return v;
+}
+
+GW_DEV int ax_pair_of(const AxPlan& pl, int e) {
+  int pr = 0;
+  while (e >= pl.first_elem[pr + 1]) ++pr;
+  return pr;
+}
+
+__global__ __launch_bounds__(NT) void k_ax_left_dense(AxPlan pl) {
+  const int e = blockIdx.x * NT + threadIdx.x;
+  if (e >= pl.first_elem[pl.x.na * pl.y.na]) return;
+  const int pr = ax_pair_of(pl, e), u = pr / pl.y.na, v = pr % pl.y.na;
+  const int nv = pl.y.n[v], nu = pl.x.n[u], r = e - pl.first_elem[pr];
+  const int x = r / nv, y = r - x * nv;
+  const double* R = pl.R[pr] + y;
+  const int64_t ld = pl.ldR[pr];
+  double s = 0.0;
+#pragma unroll 4
+  for (int l = 0; l < nu; ++l) s = fma(small_pow(abs(x - l), pl.x.m), R[l * ld], s);
+  pl.P[pr][r] = s;
+}
+
+__global__ __launch_bounds__(NT) void k_ax_right_dense(AxPlan pl) {
+  const int e = blockIdx.x * NT + threadIdx.x;
+  if (e >= pl.first_elem[pl.x.na * pl.y.na]) return;
+  const int pr = ax_pair_of(pl, e), v = pr % pl.y.na;
+  const int nv = pl.y.n[v], r = e - pl.first_elem[pr];
+  const int x = r / nv, y = r - x * nv;
+  const double* Pr = pl.P[pr] + (int64_t)x * nv;
+  double s = 0.0;
+#pragma unroll 4
+  for (int l = 0; l < nv; ++l) s = fma(Pr[l], small_pow(abs(l - y), pl.y.m), s);
+  pl.Q[pr][r] = s;
+}
+
+// Q_uv = P_uv D_v^{om}: one thread per (pair, row x), the recursion along y.
+__global__ __launch_bounds__(NT) void k_ax_right(AxPlan pl) {
+  const int tid = blockIdx.x * NT + threadIdx.x;
+  const int npairs = pl.x.na * pl.y.na;
+  if (tid >= pl.first_right[npairs]) return;
+  int pr = 0;
+  while (tid >= pl.first_right[pr + 1]) ++pr;
+  const int v = pr % pl.y.na;
+  const int x = tid - pl.first_right[pr], nv = pl.y.n[v];
+  line_op(pl.y.m, pl.P[pr] + (int64_t)x * nv, 1, pl.Q[pr] + (int64_t)x * nv, 1, nv, 1.0, false);
+}
+
+// G[i][p] = (c1_i + c2_p) - s2 sum_v V_v[y_v(p)], V_v[y] = sum_u Q_uv[x_u(i)][y]
+// (u, v in axis order); V in LDS, one block per row, the column coordinates
+// stepped in mixed radix.  With epi.fa the fused GW feature term follows.
+template <int NA>
+__global__ __launch_bounds__(NT) void k_ax_write(AxPlan pl, int N, const double* __restrict__ c1,
+                                                  const double* __restrict__ c2, double s2,
+                                                  double* __restrict__ G, int64_t ldG,
+                                                  gwr::Epilogue epi) {
+  extern __shared__ double V[];
+  const int64_t i = blockIdx.x;
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int v = 0; v < NA; ++v) {
+    const int nv = pl.y.n[v];
+    for (int y = t; y < nv; y += NT) {
+      double acc = 0.0;
+      for (int u = 0; u < pl.x.na; ++u)
+        acc += pl.Q[u * NA + v][(int64_t)ax_coord(pl.x, u, i) * nv + y];
+      V[pl.offy[v] + y] = acc;
+    }
+  }
+  __syncthreads();
+  const double c1v = c1[i];
+  const bool fg = epi.fa != nullptr;
+  const double fai = fg ? epi.fa[i] : 0.0;
+  // mixed-radix digits (last axis fastest) of the thread's first column and
+  // of the step NT; the leading digit is unbounded
+  int d[3] = {0, 0, 0}, st[3] = {0, 0, 0};
+  {
+    int a = t, b = NT;
+#pragma unroll
+    for (int v = NA - 1; v >= 1; --v) {
+      d[v] = a % pl.y.n[v];
+      a /= pl.y.n[v];
+      st[v] = b % pl.y.n[v];
+      b /= pl.y.n[v];
+    }
+    d[0] = a;
+    st[0] = b;
+  }
+  double* grow = G + i * ldG;
+  const int o1 = pl.offy[1], o2 = pl.offy[2];
+  for (int p = t; p < N; p += NT) {
+    double B = V[d[0]];
+    if constexpr (NA > 1) B += V[o1 + d[1]];
+    if constexpr (NA > 2) B += V[o2 + d[2]];
+    double val = (c1v + c2[p]) - s2 * B;
+    if (fg) {
+      const double df = fai - epi.fb[p];
+      val = fma(epi.a, val, epi.b * (df * df));
+    }
+    grow[p] = val;
+    // advance by NT: each digit and step digit is below its extent, so one
+    // subtraction and a carry of at most one per axis
+    int carry = 0;
+#pragma unroll
+    for (int v = NA - 1; v >= 1; --v) {
+      d[v] += st[v] + carry;
+      carry = d[v] >= pl.y.n[v] ? 1 : 0;
+      if (carry) d[v] -= pl.y.n[v];
+    }
+    d[0] += st[0] + carry;
+  }
+}
+
+
 // One launch for up to two 1D vectors of the same exponent (job 1 may be
 // empty: nblocks = 1).
 bool const_1d_ok(const gwr::Grid& g) { return g.ndim == 1 && g.n() <= (int64_t)1024 * C1_SEG; }
@@ -755,10 +1047,10 @@ gw_status const_term(const gwr::Grid& g, const double* w, double* c, hipStream_t
       return gwr::last_launch_status();
     }
   }
-  if (g.ndim == 3)
-    k_const_term3<<<(unsigned)((n + 63) / 64), 1024, 0, s>>>(g.metric, g.k, (int)g.Z, (int)g.H,
-                                                             (int)g.W, g.hk(), w, c);
-  else
+  if (g.ndim == 3) {
+    k_const_term3<<<(unsigned)((n + CT3_OUT - 1) / CT3_OUT), 1024, 0, s>>>(
+        g.metric, g.k, (int)g.Z, (int)g.H, (int)g.W, g.hk(), w, c);
+  } else
     k_const_term<<<(unsigned)((n + 63) / 64), 1024, 0, s>>>(g.metric, g.k, (int)g.H, (int)g.W,
                                                             g.hk(), w, c);
   return gwr::last_launch_status();
@@ -788,6 +1080,72 @@ gw_status resolve_const_terms(const gwr::Grid& X, const double* p, const double*
   return st;
 }
 
+bool axis_separable(const gwr::Grid& g, AxGrid* a) {
+  *a = AxGrid{};
+  if (g.ndim == 1) {
+    a->na = 1;
+    a->n[0] = (int)g.W;
+    a->stride[0] = 1;
+    a->m = g.k1d();
+    return true;
+  }
+  if (g.metric == GW_METRIC_SQEUCLID) a->m = 2;
+  else if (g.k == 1) a->m = 1;
+  else return false;
+  if (g.ndim == 2) {
+    a->na = 2;
+    a->n[0] = (int)g.H;
+    a->n[1] = (int)g.W;
+    a->stride[0] = g.W;
+    a->stride[1] = 1;
+  } else {
+    a->na = 3;
+    a->n[0] = (int)g.Z;
+    a->n[1] = (int)g.H;
+    a->n[2] = (int)g.W;
+    a->stride[0] = g.H * g.W;
+    a->stride[1] = g.W;
+    a->stride[2] = 1;
+  }
+  return true;
+}
+
+int ax_extent_sum(const AxGrid& a) {
+  int s = 0;
+  for (int v = 0; v < a.na; ++v) s += a.n[v];
+  return s;
+}
+
+// parts per slab sum of the row reduction (3D Y): enough work items for the block
+int ax_parts(const AxGrid& ay) {
+  if (ay.na != 3) return 1;
+  const int q = NT / ay.n[0];
+  return q < 1 ? 1 : (q > 16 ? 16 : q);
+}
+
+size_t ax_row_lds(int64_t N, const AxGrid& ay) {
+  const int64_t hw = (int64_t)ay.n[ay.na - 2] * ay.n[ay.na - 1];
+  const int64_t zs = ay.na == 3 ? (int64_t)ay.n[0] * ax_parts(ay) : 0;
+  return (size_t)(N + hw + zs) * sizeof(double);
+}
+
+int64_t ax_pair_elems(const AxGrid& ax, const AxGrid& ay) {
+  int64_t t = 0;
+  for (int u = 0; u < ax.na; ++u)
+    for (int v = 0; v < ay.na; ++v) t += (int64_t)ax.n[u] * ay.n[v];
+  return t;
+}
+
+// The axis-separable path serves 3D grids and mixed 1D/2D pairs whose two
+// distances are sums of per-axis terms, when its LDS stages fit.
+bool ax_path(const gwr::Grid& X, const gwr::Grid& Y, AxGrid* ax, AxGrid* ay) {
+  if (X.ndim == Y.ndim && X.ndim < 3) return false;
+  if (!axis_separable(X, ax) || !axis_separable(Y, ay)) return false;
+  if (ay->na > 1 && ax_row_lds(Y.n(), *ay) > 160 * 1024) return false;
+  if ((size_t)ax_extent_sum(*ay) * sizeof(double) > 160 * 1024) return false;
+  return true;
+}
+
 size_t fast_generic_ws_bytes(const gwr::Grid& X, const gwr::Grid& Y) {
   const int64_t M = X.n(), N = Y.n();
   gwr::Arena a{nullptr, 0, 0};
@@ -801,6 +1159,12 @@ size_t fast_generic_ws_bytes(const gwr::Grid& X, const gwr::Grid& Y) {
       a.take<double>(X.W * Y.H);
       a.take<double>(X.W * Y.W);
     }
+  } else if (AxGrid ax, ay; ax_path(X, Y, &ax, &ay)) {
+    if (ay.na > 1) a.take<double>((size_t)M * ax_extent_sum(ay));
+    const int64_t pe = ax_pair_elems(ax, ay);
+    if (ax.na > 1) a.take<double>(pe);
+    a.take<double>(pe);
+    a.take<double>(pe);
   } else {
     a.take<double>((size_t)M * N);
     a.take<double>((size_t)M * N);
@@ -821,6 +1185,9 @@ gw_status fast_generic(const gwr::Grid& X, const gwr::Grid& Y, const double* p,
   const bool sep = separable(X, &sx) && separable(Y, &sy);
   double *U = nullptr, *V = nullptr, *R[4] = {}, *P[4] = {}, *Q[4] = {};
   double *A = nullptr, *At = nullptr, *tmp = nullptr, *tmp2 = nullptr;
+  AxGrid ax{}, ay{};
+  const bool axp = !sep && ax_path(X, Y, &ax, &ay);
+  double *aU = nullptr, *aR = nullptr, *aP = nullptr, *aQ = nullptr;
   if (sep) {
     U = ws.take<double>(M * Y.H);
     V = ws.take<double>(M * Y.W);
@@ -831,6 +1198,12 @@ gw_status fast_generic(const gwr::Grid& X, const gwr::Grid& Y, const double* p,
       sets[t][2] = ws.take<double>(X.W * Y.H);
       sets[t][3] = ws.take<double>(X.W * Y.W);
     }
+  } else if (axp) {
+    if (ay.na > 1) aU = ws.take<double>((size_t)M * ax_extent_sum(ay));
+    const int64_t pe = ax_pair_elems(ax, ay);
+    if (ax.na > 1) aR = ws.take<double>(pe);
+    aP = ws.take<double>(pe);
+    aQ = ws.take<double>(pe);
   } else {
     A = ws.take<double>((size_t)M * N);
     At = ws.take<double>((size_t)M * N);
@@ -897,6 +1270,83 @@ gw_status fast_generic(const gwr::Grid& X, const gwr::Grid& Y, const double* p,
     k_sep_right<<<(unsigned)rt.first[4], SEP_LINE, rsh, s>>>(rt);
     k_sep_write<<<(unsigned)M, NT, 0, s>>>(X.H, X.W, Y.H, Y.W, Q[0], Q[1], Q[2], Q[3], c1, c2,
                                            s2, G, ldG, epi ? *epi : gwr::Epilogue{});
+    return gwr::last_launch_status();
+  }
+  if (axp) {
+    AxPlan pl{};
+    pl.x = ax;
+    pl.y = ay;
+    int off = 0;
+    for (int v = 0; v < ay.na; ++v) {
+      pl.offy[v] = off;
+      off += ay.n[v];
+    }
+    pl.sy = off;
+    if (ay.na == 1) {  // one axis: the row sums are T itself
+      pl.U = T;
+      pl.ldU = ldT;
+    } else {
+      const int qs = ax_parts(ay);
+      const size_t shm = ax_row_lds(N, ay);
+      static bool rr_set = false;
+      if (!rr_set) {
+        if (hipFuncSetAttribute(reinterpret_cast<const void*>(&k_ax_rowreduce),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) !=
+            hipSuccess)
+          return GW_EDEVICE;
+        rr_set = true;
+      }
+      k_ax_rowreduce<<<(unsigned)M, NT, shm, s>>>(T, ldT, (int)N, ay, qs, aU, off);
+      pl.U = aU;
+      pl.ldU = off;
+    }
+    int64_t roff = 0;
+    for (int u = 0; u < ax.na; ++u)
+      for (int v = 0; v < ay.na; ++v) {
+        const int pr = u * ay.na + v;
+        if (ax.na == 1) {  // one axis: R_0v is a view of U
+          pl.R[pr] = pl.U + pl.offy[v];
+          pl.ldR[pr] = pl.ldU;
+        } else {
+          pl.Rw[pr] = aR + roff;
+          pl.R[pr] = pl.Rw[pr];
+          pl.ldR[pr] = ay.n[v];
+        }
+        pl.P[pr] = aP + roff;
+        pl.Q[pr] = aQ + roff;
+        roff += (int64_t)ax.n[u] * ay.n[v];
+        pl.first_left[pr + 1] = pl.first_left[pr] + ay.n[v];
+        pl.first_right[pr + 1] = pl.first_right[pr] + ax.n[u];
+        pl.first_elem[pr + 1] = pl.first_elem[pr] + ax.n[u] * ay.n[v];
+      }
+    const int npairs = ax.na * ay.na;
+    if (ax.na > 1) k_ax_colreduce<<<(unsigned)pl.first_right[npairs], NT, 0, s>>>(pl, (int)M);
+    // dense products on axes of up to 64 points, the recursion on longer ones
+    int lx = 0, ly = 0;
+    for (int u = 0; u < ax.na; ++u) lx = ax.n[u] > lx ? ax.n[u] : lx;
+    for (int v = 0; v < ay.na; ++v) ly = ay.n[v] > ly ? ay.n[v] : ly;
+    if (lx <= 64) k_ax_left_dense<<<blocks_for(roff), NT, 0, s>>>(pl);
+    else k_ax_left<<<blocks_for(pl.first_left[npairs]), NT, 0, s>>>(pl);
+    if (ly <= 64) k_ax_right_dense<<<blocks_for(roff), NT, 0, s>>>(pl);
+    else k_ax_right<<<blocks_for(pl.first_right[npairs]), NT, 0, s>>>(pl);
+    const size_t wsh = (size_t)pl.sy * sizeof(double);
+    const gwr::Epilogue e = epi ? *epi : gwr::Epilogue{};
+    static bool w_set = false;  // dynamic LDS above the default, allowed once
+    if (!w_set) {
+      const void* fns[3] = {reinterpret_cast<const void*>(&k_ax_write<1>),
+                            reinterpret_cast<const void*>(&k_ax_write<2>),
+                            reinterpret_cast<const void*>(&k_ax_write<3>)};
+      for (const void* fn : fns)
+        if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) !=
+            hipSuccess)
+          return GW_EDEVICE;
+      w_set = true;
+    }
+    switch (ay.na) {
+      case 1: k_ax_write<1><<<(unsigned)M, NT, wsh, s>>>(pl, (int)N, c1, c2, s2, G, ldG, e); break;
+      case 2: k_ax_write<2><<<(unsigned)M, NT, wsh, s>>>(pl, (int)N, c1, c2, s2, G, ldG, e); break;
+      default: k_ax_write<3><<<(unsigned)M, NT, wsh, s>>>(pl, (int)N, c1, c2, s2, G, ldG, e); break;
+    }
     return gwr::last_launch_status();
   }
   // generic: A = T D^_Y (rows), At = A^T, Bt = At D^_X (rows), G = epilogue(Bt^T)
