@@ -177,6 +177,42 @@ def grid2d_bench(side: int = 64, eps: float = 2e-3, outer: int = 100, inner: int
             "kernel_ms_in_solve": fams, "objective": float(obj[0].item())}
 
 
+def grid3d_bench(side: int = 16, eps: float = 2e-3, outer: int = 100, inner: int = 100):
+    """3D grids side^3 vs side^3 (N = side^3), squared Euclidean cost, marginals
+    = normalised volumes of 1-5 seeded Gaussian blobs plus a 1e-6 floor, FAST
+    FP64 gradient (axis-separable path) and log-domain Sinkhorn: one full solve
+    timed after a short warm-up, and the 3D gradient timed alone."""
+    import torch
+    from paper_2404_08970_amd import gw, inputs
+    dev = torch.device("cuda:0")
+    X = gw.unit_grid((side, side, side), 2, gw.METRIC_SQEUCLID)
+    p = torch.tensor(inputs.blobs_3d(side, side, side, inputs.rng_for(12, 0), floor=1e-6),
+                     device=dev)
+    q = torch.tensor(inputs.blobs_3d(side, side, side, inputs.rng_for(12, 1), floor=1e-6),
+                     device=dev)
+    n = X.size
+    T = torch.empty((n, n), dtype=torch.float64, device=dev)
+    f = torch.empty(n, dtype=torch.float64, device=dev)
+    g = torch.empty(n, dtype=torch.float64, device=dev)
+    obj = torch.empty(2, dtype=torch.float64, device=dev)
+    ws = gw.workspace(gw.workspace_bytes(X, X, gw.PATH_FAST_F64, gw.OP_SOLVE), dev, key="bench3d")
+    gw.solve(X, X, p, q, eps, 2, 5, T=T, f=f, g=g, obj=obj, ws=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gw.solve(X, X, p, q, eps, outer, inner, T=T, f=f, g=g, obj=obj, ws=ws)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    gw.check_status(ws)
+    G = torch.empty_like(T)
+    gws = gw.workspace(gw.workspace_bytes(X, X, gw.PATH_FAST_F64, gw.OP_GRAD), dev, key="g3d")
+    grad_ms = time_gpu(lambda: gw.grad(X, X, p, q, T, path="fast", out=G, ws=gws), 20, torch)
+    return {"workload": f"3D {side}^3 vs {side}^3 (N = {n}), squared Euclidean, blob marginals "
+                        f"+ 1e-6 floor, eps = {eps}, {outer} outer x {inner} Sinkhorn",
+            "solves_per_s": round(1.0 / dt, 4), "ms_per_solve": round(dt * 1e3, 1),
+            "fast_grad_us": round(grad_ms * 1e3, 1), "fast_grads_per_s": round(1e3 / grad_ms, 1),
+            "objective": float(obj[0].item())}
+
+
 def fgw_bench(n: int = 4000, theta: float = 0.5, eps: float = 2e-3, outer: int = 10,
               inner: int = 100, reps: int = 3):
     """The 1D random-distribution FGW workload: x_i = y_i = (i-1)/(n-1), k = 1,
@@ -397,6 +433,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the request-loop measurement")
     ap.add_argument("--no-2d", action="store_true", help="skip the 2D 64x64 solve")
     ap.add_argument("--no-fgw", action="store_true", help="skip the 1D fused GW solve")
+    ap.add_argument("--no-3d", action="store_true", help="skip the 3D 16^3 solve")
+    ap.add_argument("--only-3d", action="store_true", help="run only the 3D 16^3 solve and exit")
     ap.add_argument("--no-tol", action="store_true", help="skip the tolerance-stop comparison")
     ap.add_argument("--only-tol", action="store_true", help="run only the tolerance-stop comparison")
     ap.add_argument("--only-fgw", action="store_true", help="run only the 1D fused GW solve and exit")
@@ -408,6 +446,9 @@ def main():
     args = ap.parse_args()
     if args.precision:
         print(json.dumps(precision_study()))
+        return
+    if args.only_3d:
+        print(json.dumps(grid3d_bench()))
         return
     if args.only_tol:
         print(json.dumps(tolerance_bench()))
@@ -535,6 +576,7 @@ def main():
 
     grid2d = None if args.no_2d else grid2d_bench()
     fused = None if args.no_fgw else fgw_bench()
+    grid3d = None if args.no_3d else grid3d_bench()
     stopped = None if args.no_tol else tolerance_bench()
     serving = None
     if not args.no_serve:
@@ -563,6 +605,7 @@ def main():
         "objective": objs,
         "grid2d_64x64": grid2d,
         "fgw_1d_n4000": fused,
+        "grid3d_16cube": grid3d,
         "tolerance_stop": stopped,
         "serving": serving,
     }

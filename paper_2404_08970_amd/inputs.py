@@ -70,6 +70,25 @@ def blobs_2d(H: int, W: int, rng: np.random.Generator, floor: float = 0.0,
     return img.reshape(-1)
 
 
+def blobs_3d(D: int, H: int, W: int, rng: np.random.Generator, floor: float = 0.0,
+             nblobs=None, mean_range=(0.1, 0.9), sigma_range=(0.05, 0.2)) -> np.ndarray:
+    """Flattened row-major D*H*W volume of isotropic Gaussian blobs, normalised."""
+    if nblobs is None:
+        nblobs = int(rng.integers(1, 6))
+    axes = [np.arange(e, dtype=np.float64) / max(e - 1, 1) for e in (D, H, W)]
+    Z, R, Cc = np.meshgrid(*axes, indexing="ij")
+    vol = np.zeros((D, H, W))
+    for _ in range(nblobs):
+        mz, mr, mc = rng.uniform(*mean_range, size=3)
+        s = rng.uniform(*sigma_range)
+        vol += np.exp(-0.5 * (((Z - mz) / s) ** 2 + ((R - mr) / s) ** 2 + ((Cc - mc) / s) ** 2))
+    vol = vol / vol.sum()
+    if floor > 0:
+        vol = vol + floor
+        vol = vol / vol.sum()
+    return vol.reshape(-1)
+
+
 def dirichlet(n: int, rng: np.random.Generator, alpha: float = 1.0) -> np.ndarray:
     return rng.dirichlet(np.full(n, alpha))
 
