@@ -27,6 +27,10 @@ Everything here is written to be read against the paper (arXiv 2404.08970,
                                    section states higher dimensions work alike)
 * fused GW (FGW) ................. Remark (Entropic algorithm for FGW): objective
                                    and gradient decomposition C_2 - 4 theta D Gamma D
+* unbalanced GW (UGW) ............ Remark (Entropic algorithm for UGW): divergence and
+                                   sub-problem; its scalar term, its unbalanced
+                                   Sinkhorn and the mass rescaling follow the cited
+                                   UGW work (readings in that section)
 
 Two gradient routines are given.  ``grad_dense`` is the plain definition
 G = c1 1^T + 1 c2^T - 2 D_X T D_Y with explicit distance matrices (the
@@ -530,3 +534,111 @@ def solve_fgw(gx: Grid, gy: Grid, p, q, fa, fb, theta: float, eps: float, outer:
     if f is None:
         f, g = np.zeros(p.shape[0]), np.zeros(q.shape[0])
     return T, f, g, objective_fgw(gx, gy, T, fa, fb, theta, eps)
+
+
+# ---------------------------------------------------------------------------
+# Unbalanced GW (Remark, Entropic algorithm for UGW)
+# ---------------------------------------------------------------------------
+# The Remark fixes the divergence and the sub-problem solved at each step,
+#   min_{T >= 0} < G(Th) + g(Th), T > + m(Th) (rho KL(T 1 | u) + rho KL(T^T 1 | v)
+#                                            + eps KL(T | u (x) v)),
+# with G(Th) = grad E(Th) / 2 taken with Th's own marginals, but not the scalar
+# g(Th) nor the solver of the sub-problem; both are read from the UGW work the
+# Remark cites (alternate minimisation of its bi-convex relaxation):
+#   g(Th) = rho <log(a/u), a> + rho <log(b/v), b> + eps <log(Th/(u (x) v)), Th>,
+#           a = Th 1, b = Th^T 1;
+#   the sub-problem by unbalanced Sinkhorn on the dual potentials,
+#           f = -tau e LSE_p((g_p - C_ip)/e + ln v_p),
+#           g = -tau e LSE_i((f_i - C_ip)/e + ln u_i),
+#           tau = r / (r + e),  r = m(Th) rho,  e = m(Th) eps,
+#           T_ip = exp((f_i + g_p - C_ip)/e) u_i v_p;
+#   then the mass is rescaled, T <- sqrt(m(Th) / m(T)) T, and
+#   T^0 = u (x) v / sqrt(m(u) m(v)).
+# KL is the divergence of positive measures, KL(a|b) = sum a log(a/b) - m(a) + m(b),
+# and the quadratic one KL(a (x) a | b (x) b) = 2 m(a) KL(a|b) + (m(a) - m(b))^2.
+
+def mass(a) -> float:
+    return float(np.sum(np.asarray(a, dtype=np.float64)))
+
+
+def kl(a, b) -> float:
+    """KL(a|b) = sum a log(a/b) - m(a) + m(b) for non-negative a, b (0 log 0 = 0)."""
+    a = np.asarray(a, dtype=np.float64).ravel()
+    b = np.asarray(b, dtype=np.float64).ravel()
+    pos = a > 0
+    return float(np.sum(a[pos] * np.log(a[pos] / b[pos])) - a.sum() + b.sum())
+
+
+def quad_kl(a, b) -> float:
+    """KL(a (x) a | b (x) b), by the identity 2 m(a) KL(a|b) + (m(a) - m(b))^2."""
+    return 2.0 * mass(a) * kl(a, b) + (mass(a) - mass(b)) ** 2
+
+
+def ugw_shift(T, u, v, rho: float, eps: float) -> float:
+    """g(T) = rho <log(a/u), a> + rho <log(b/v), b> + eps <log(T/(u (x) v)), T>."""
+    T = np.asarray(T, dtype=np.float64)
+    u = np.asarray(u, dtype=np.float64)
+    v = np.asarray(v, dtype=np.float64)
+    a, b = T.sum(axis=1), T.sum(axis=0)
+
+    def xlogy(x, y):
+        pos = x > 0
+        return float(np.sum(x[pos] * np.log(x[pos] / y[pos])))
+
+    return (rho * xlogy(a, u) + rho * xlogy(b, v)
+            + eps * xlogy(T, u[:, None] * v[None, :]))
+
+
+def uot_sinkhorn(C, u, v, rho: float, eps: float, iters: int, f0=None, g0=None):
+    """Unbalanced entropic OT, min <C, T> + rho KL(T1|u) + rho KL(T^T 1|v)
+    + eps KL(T|u (x) v), by the log-domain potential updates (f then g).
+    Returns (f, g)."""
+    C = np.asarray(C, dtype=np.float64)
+    u = np.asarray(u, dtype=np.float64)
+    v = np.asarray(v, dtype=np.float64)
+    M, N = C.shape
+    tau = rho / (rho + eps)
+    with np.errstate(divide="ignore"):
+        lu, lv = np.log(u), np.log(v)
+    f = np.zeros(M) if f0 is None else np.array(f0, dtype=np.float64)
+    g = np.zeros(N) if g0 is None else np.array(g0, dtype=np.float64)
+    for _ in range(iters):
+        f = -tau * eps * _lse_last_axis((g[None, :] - C) / eps + lv[None, :])
+        g = -tau * eps * _lse_last_axis(((f[:, None] - C) / eps + lu[:, None]).T)
+    return f, g
+
+
+def uot_plan(C, f, g, u, v, eps: float) -> np.ndarray:
+    """T_ip = exp((f_i + g_p - C_ip)/eps) u_i v_p."""
+    C = np.asarray(C, dtype=np.float64)
+    return (np.exp((np.asarray(f)[:, None] + np.asarray(g)[None, :] - C) / eps)
+            * np.asarray(u, dtype=np.float64)[:, None] * np.asarray(v, dtype=np.float64)[None, :])
+
+
+def objective_ugw(gx: Grid, gy: Grid, T, u, v, rho: float, eps: float):
+    """The Remark's divergence E(T) + rho KL(a (x) a|u (x) u) + rho KL(b (x) b|v (x) v)
+    (E with T's own marginals), and the same plus eps KL(T (x) T|(u (x) v) (x) (u (x) v))."""
+    T = np.asarray(T, dtype=np.float64)
+    u = np.asarray(u, dtype=np.float64)
+    v = np.asarray(v, dtype=np.float64)
+    E, _ = objective(gx, gy, T, 0.0)
+    U = E + rho * quad_kl(T.sum(axis=1), u) + rho * quad_kl(T.sum(axis=0), v)
+    return float(U), float(U + eps * quad_kl(T, u[:, None] * v[None, :]))
+
+
+def solve_ugw(gx: Grid, gy: Grid, u, v, rho: float, eps: float, outer: int, inner: int):
+    """Entropic UGW by the Remark's iteration (readings above).
+    Returns (T, f, g, objective_ugw(T))."""
+    u = np.asarray(u, dtype=np.float64)
+    v = np.asarray(v, dtype=np.float64)
+    T = u[:, None] * v[None, :] / math.sqrt(mass(u) * mass(v))
+    f, g = np.zeros(u.shape[0]), np.zeros(v.shape[0])
+    for _ in range(outer):
+        m = mass(T)
+        a, b = T.sum(axis=1), T.sum(axis=0)
+        C = grad_dense(gx, gy, a, b, T) + ugw_shift(T, u, v, rho, eps)
+        e = m * eps
+        f, g = uot_sinkhorn(C, u, v, m * rho, e, inner)
+        P = uot_plan(C, f, g, u, v, e)
+        T = math.sqrt(m / mass(P)) * P
+    return T, f, g, objective_ugw(gx, gy, T, u, v, rho, eps)
