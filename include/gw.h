@@ -74,6 +74,8 @@ typedef int32_t gw_status;
 #define GW_OP_SINKHORN 1
 #define GW_OP_SOLVE 2
 #define GW_OP_OBJECTIVE 3
+#define GW_OP_UOT_SINKHORN 4
+#define GW_OP_SOLVE_UGW 5
 
 /* gw_solve flags */
 #define GW_FLAG_WARM_START 1  /* Sinkhorn starts from the previous outer step's potentials */
@@ -173,6 +175,42 @@ gw_status gw_solve_tol(const gw_grid* X, const gw_grid* Y, const double* p, cons
                        double tol, int32_t path, int32_t flags, double* T, int64_t ldT, double* f,
                        double* g, double* obj, int32_t* inner_done, void* ws, size_t ws_bytes,
                        void* stream);
+
+/* ------------------------------------------------------------------------
+ * Unbalanced GW (Remark on UGW, Sec. 3): for positive measures u [M], v [N]
+ * (device FP64, not necessarily of mass 1) and rho > 0 the divergence
+ *   E(T) + rho KL(T1 (x) T1 | u (x) u) + rho KL(T^T 1 (x) T^T 1 | v (x) v),
+ * KL(a|b) = sum a log(a/b) - m(a) + m(b), minimised with the entropic term
+ * eps KL(T (x) T | (u (x) v) (x) (u (x) v)).  The Remark gives the step
+ *   T = argmin <G(Th) + g(Th), T> + m(Th) (rho KL(T1|u) + rho KL(T^T 1|v)
+ *                                          + eps KL(T|u (x) v)),
+ * G(Th) the half gradient at Th's own marginals; the scalar g(Th), the solver
+ * of the step and the mass rescaling are those of the UGW work it cites:
+ *   g(Th) = rho <log(a/u), a> + rho <log(b/v), b> + eps <log(Th/(u (x) v)), Th>,
+ *   unbalanced Sinkhorn with tau = rho / (rho + eps) and e = m(Th) eps,
+ *   T <- sqrt(m(Th) / m(T)) T after each step, T^0 = u (x) v / sqrt(m(u) m(v)).
+ * Workspace: gw_workspace_bytes with GW_OP_UOT_SINKHORN / GW_OP_SOLVE_UGW.
+ * ------------------------------------------------------------------------ */
+
+/* Unbalanced entropic OT on C_eff = C + c_shift:
+ *   min <C_eff, T> + rho KL(T1|u) + rho KL(T^T 1|v) + eps KL(T|u (x) v).
+ * One iteration: f_i = -tau eps LSE_p((g_p - C_eff_ip)/eps + ln v_p), then
+ * g_p = -tau eps LSE_i((f_i - C_eff_ip)/eps + ln u_i), tau = rho/(rho+eps).
+ * init_zero: start from f = g = 0 (else from the given f, g).  T (may be
+ * NULL) receives exp((f_i + g_p - C_eff_ip)/eps) u_i v_p.  N <= 16384. */
+gw_status gw_uot_sinkhorn(const double* C, int64_t ldC, int64_t M, int64_t N, double c_shift,
+                          const double* u, const double* v, double rho, double eps,
+                          int32_t iters, int32_t init_zero, double* f, double* g, double* T,
+                          int64_t ldT, void* ws, size_t ws_bytes, void* stream);
+
+/* Entropic UGW: `outer` steps, each `inner` unbalanced Sinkhorn iterations
+ * from zero potentials.  T [M x N]: the plan; f, g: the last step's
+ * potentials (0 if outer = 0); obj (may be NULL): obj[0] = the divergence at
+ * T, obj[1] = obj[0] + its entropic term.  The gradient runs on `path`. */
+gw_status gw_solve_ugw(const gw_grid* X, const gw_grid* Y, const double* u, const double* v,
+                       double rho, double eps, int32_t outer, int32_t inner, int32_t path,
+                       double* T, int64_t ldT, double* f, double* g, double* obj, void* ws,
+                       size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
  * Fused GW (Remark on FGW, Sec. 3): the objective

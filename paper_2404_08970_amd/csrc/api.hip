@@ -192,6 +192,33 @@ size_t grad_need(const Grid& X, const Grid& Y, int path) {
 
 bool path_valid(int path) { return path >= GW_PATH_FAST_F64 && path <= GW_PATH_DENSE_F32_SPLIT; }
 
+// UGW solve: scalars, a, b, row partials, G, E, then the larger of the UOT
+// scratch, the gradient's and the objective's.
+size_t ugw_need(const Grid& X, const Grid& Y, int path) {
+  const int64_t M = X.n(), N = Y.n();
+  Arena a{nullptr, 0, 0};
+  a.take<char>(gwr::ws_status_bytes());
+  a.take<char>(gwl::uot_scalars_bytes());
+  a.take<double>(M);              // a = T 1
+  a.take<double>(N);              // b = T^T 1
+  a.take<double>(M);              // row partials
+  a.take<double>((size_t)M * N);  // G
+  a.take<double>(2);              // E
+  size_t tail = gwr::ws_grad_bytes(X, Y, path);
+  const size_t uo = gwl::uot_ws_bytes(M, N);
+  if (uo > tail) tail = uo;
+  const size_t ob = gwr::ws_objective_tail_bytes(X, Y);
+  if (ob > tail) tail = ob;
+  return a.used + tail;
+}
+
+size_t uot_need(int64_t M, int64_t N) {
+  Arena a{nullptr, 0, 0};
+  a.take<char>(gwr::ws_status_bytes());
+  a.take<char>(gwl::uot_scalars_bytes());
+  return a.used + gwl::uot_ws_bytes(M, N);
+}
+
 size_t solve_need(const Grid& X, const Grid& Y, int path) {
   const int64_t M = X.n(), N = Y.n();
   Arena a{nullptr, 0, 0};
@@ -420,6 +447,11 @@ size_t gw_workspace_bytes(const gw_grid* Xp, const gw_grid* Yp, int32_t path, in
       return solve_need(X, Y, path);
     case GW_OP_OBJECTIVE:
       return gwr::ws_status_bytes() + gwr::ws_objective_bytes(X, Y);
+    case GW_OP_UOT_SINKHORN:
+      return uot_need(X.n(), Y.n());
+    case GW_OP_SOLVE_UGW:
+      if (!path_valid(path)) return 0;
+      return ugw_need(X, Y, path);
   }
   return 0;
 }
@@ -472,6 +504,90 @@ gw_status gw_solve_tol(const gw_grid* Xp, const gw_grid* Yp, const double* p, co
   const gwr::SkStop so{check_every, tol, inner_done, nullptr};
   return solve_impl(Xp, Yp, p, q, nullptr, eps, outer, max_inner, path, flags, T, ldT, f, g, obj,
                     ws, ws_bytes, stream, &so);
+}
+
+gw_status gw_uot_sinkhorn(const double* C, int64_t ldC, int64_t M, int64_t N, double c_shift,
+                          const double* u, const double* v, double rho, double eps,
+                          int32_t iters, int32_t init_zero, double* f, double* g, double* T,
+                          int64_t ldT, void* ws, size_t ws_bytes, void* stream) {
+  gw_status st;
+  if (M < 1 || N < 1) return GW_EINVAL;
+  if (M > gwr::kMaxExtent || N > gwr::kMaxExtent) return GW_EUNSUPPORTED;
+  if (N > 16384) return GW_EUNSUPPORTED;
+  if (!(eps > 0.0) || !isfinite(eps) || !(rho > 0.0) || !isfinite(rho) || !isfinite(c_shift) ||
+      iters < 0)
+    return GW_EINVAL;
+  if ((st = check_matrix(C, M, N, ldC)) != GW_OK) return st;
+  if ((st = check_vec(u)) != GW_OK || (st = check_vec(v)) != GW_OK) return st;
+  if ((st = check_vec(f)) != GW_OK || (st = check_vec(g)) != GW_OK) return st;
+  if (T && (st = check_matrix(T, M, N, ldT)) != GW_OK) return st;
+  if ((st = check_ws(ws, ws_bytes, uot_need(M, N))) != GW_OK) return st;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  Arena a{static_cast<char*>(ws), 0, ws_bytes};
+  a.take<char>(gwr::ws_status_bytes());
+  void* scal = a.take<char>(gwl::uot_scalars_bytes());
+  if ((st = gwl::uot_set_scalars(scal, c_shift, eps, rho / (rho + eps), s)) != GW_OK) return st;
+  return gwl::uot_sinkhorn(C, ldC, M, N, u, v, iters, init_zero, f, g, T, ldT, false, scal, a, s);
+}
+
+gw_status gw_solve_ugw(const gw_grid* Xp, const gw_grid* Yp, const double* u, const double* v,
+                       double rho, double eps, int32_t outer, int32_t inner, int32_t path,
+                       double* T, int64_t ldT, double* f, double* g, double* obj, void* ws,
+                       size_t ws_bytes, void* stream) {
+  Grid X, Y;
+  gw_status st;
+  if ((st = gwr::to_grid(Xp, &X)) != GW_OK) return st;
+  if ((st = gwr::to_grid(Yp, &Y)) != GW_OK) return st;
+  if (!path_valid(path)) return GW_EINVAL;
+  if (!(eps > 0.0) || !isfinite(eps) || !(rho > 0.0) || !isfinite(rho) || outer < 0 || inner < 0)
+    return GW_EINVAL;
+  const int64_t M = X.n(), N = Y.n();
+  if (N > 16384) return GW_EUNSUPPORTED;
+  if ((st = check_vec(u)) != GW_OK || (st = check_vec(v)) != GW_OK) return st;
+  if ((st = check_vec(f)) != GW_OK || (st = check_vec(g)) != GW_OK) return st;
+  if ((st = check_matrix(T, M, N, ldT)) != GW_OK) return st;
+  if (obj && !aligned8(obj)) return GW_EINVAL;
+  if ((st = check_ws(ws, ws_bytes, ugw_need(X, Y, path))) != GW_OK) return st;
+  if (path != GW_PATH_FAST_F64 && (X.ndim != 1 || Y.ndim != 1)) return GW_EUNSUPPORTED;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  Arena ar{static_cast<char*>(ws), 0, ws_bytes};
+  ar.take<char>(gwr::ws_status_bytes());
+  void* scal = ar.take<char>(gwl::uot_scalars_bytes());
+  double* a = ar.take<double>(M);
+  double* b = ar.take<double>(N);
+  double* rowpart = ar.take<double>(M);
+  double* G = ar.take<double>((size_t)M * N);
+  double* eobj = ar.take<double>(2);
+  const size_t mark = ar.used;
+  if ((st = gwr::clear_status(status_of(ws), s)) != GW_OK) return st;
+  if ((st = gwl::ugw_init(u, v, M, N, T, ldT, scal, s)) != GW_OK) return st;
+  for (int l = 0; l < outer; ++l) {
+    ar.used = mark;
+    // the step at Th = T: marginals, scalars, the half gradient at T's own marginals
+    if ((st = gwl::marginals(T, ldT, M, N, a, b, ar, s)) != GW_OK) return st;
+    if ((st = gwl::ugw_step_scalars(T, ldT, M, N, a, b, u, v, rho, eps, rowpart, scal, s)) !=
+        GW_OK)
+      return st;
+    if ((st = run_grad(X, Y, a, b, T, ldT, G, N, path, ar, s, nullptr, nullptr)) != GW_OK)
+      return st;
+    ar.used = mark;
+    st = gwl::uot_sinkhorn(G, N, M, N, u, v, inner, 1, f, g, T, ldT, true, scal, ar, s);
+    if (st != GW_OK) return st;
+  }
+  if (outer == 0) {  // potentials of no step: zero
+    ar.used = mark;
+    if ((st = gwl::uot_sinkhorn(G, N, M, N, u, v, 0, 1, f, g, nullptr, ldT, false, scal, ar, s)) !=
+        GW_OK)
+      return st;
+  }
+  if (obj) {
+    ar.used = mark;
+    if ((st = run_objective(X, Y, T, ldT, 0.0, eobj, G, ar, s, status_of(ws), nullptr)) != GW_OK)
+      return st;
+    if ((st = gwl::marginals(T, ldT, M, N, a, b, ar, s)) != GW_OK) return st;
+    return gwl::ugw_objective(T, ldT, M, N, a, b, u, v, rho, eps, rowpart, scal, eobj, obj, s);
+  }
+  return gwr::last_launch_status();
 }
 
 gw_status gw_solve_fgw(const gw_grid* Xp, const gw_grid* Yp, const double* p, const double* q,

@@ -194,6 +194,24 @@ gw_status objective_reduce(const double* G, int64_t ldG, const double* T, int64_
                            int64_t M, int64_t N, double eps, double* obj, gwr::Arena& ws,
                            hipStream_t s, gwr::StatusWord* status);
 size_t objective_reduce_ws_bytes(int64_t M, int64_t N);
+// Unbalanced GW: step scalars (device block of uot_scalars_bytes()), the
+// unbalanced Sinkhorn and the solve's set-up / step / objective pieces.
+size_t uot_scalars_bytes();
+size_t uot_ws_bytes(int64_t M, int64_t N);
+gw_status uot_set_scalars(void* scal, double shift, double e, double tau, hipStream_t s);
+gw_status uot_sinkhorn(const double* C, int64_t ldC, int64_t M, int64_t N, const double* u,
+                       const double* v, int iters, int init_zero, double* f, double* g,
+                       double* T, int64_t ldT, bool rescale, void* scal, gwr::Arena& ws,
+                       hipStream_t s);
+gw_status ugw_init(const double* u, const double* v, int64_t M, int64_t N, double* T,
+                   int64_t ldT, void* scal, hipStream_t s);
+gw_status ugw_step_scalars(const double* T, int64_t ldT, int64_t M, int64_t N, const double* a,
+                           const double* b, const double* u, const double* v, double rho,
+                           double eps, double* rowpart, void* scal, hipStream_t s);
+gw_status ugw_objective(const double* T, int64_t ldT, int64_t M, int64_t N, const double* a,
+                        const double* b, const double* u, const double* v, double rho,
+                        double eps, double* rowpart, const void* scal, const double* eobj,
+                        double* obj, hipStream_t s);
 // G <- a G + b (fa_i - fb_p)^2 (fused GW terms).
 gw_status fgw_blend(double* G, int64_t ldG, int64_t M, int64_t N, const double* fa,
                     const double* fb, double a, double b, hipStream_t s);

@@ -1,0 +1,446 @@
+// Unbalanced GW (Remark, Entropic algorithm for UGW).  Each step solves
+//   min_{T >= 0} <G(Th) + g(Th), T> + m(Th) (rho KL(T1|u) + rho KL(T^T 1|v) + eps KL(T|u (x) v))
+// with G(Th) the half gradient at Th's own marginals (the FAST paths), then
+// rescales the plan's mass.  The Remark leaves the scalar g(Th) and the
+// solver of this sub-problem to the UGW work it cites; taken from there:
+//   g(Th) = rho <log(a/u), a> + rho <log(b/v), b> + eps <log(Th/(u (x) v)), Th>,
+//   f = -tau e LSE_p((g_p - C_ip)/e + ln v_p),  g = -tau e LSE_i((f_i - C_ip)/e + ln u_i),
+//   tau = rho / (rho + eps), e = m(Th) eps,  T = exp((f + g - C)/e) u (x) v,
+//   T <- sqrt(m(Th) / m(T)) T,  T^0 = u (x) v / sqrt(m(u) m(v)).
+// The scalars of a step (m, the shift g(Th), e, tau, the rescale factor) stay
+// in device memory, so a solve needs no host synchronisation.
+//
+// Kernels: the row update is one block per row (each thread holds its entries
+// of the row, block max then block sum of the exponentials); the column update
+// runs an online log-sum-exp over row chunks (a block per 64 columns x chunk,
+// 16 waves splitting the chunk) and merges the chunks per column in order.
+// Every reduction has a fixed order.  This path is not tuned like the balanced
+// Sinkhorn: it reads C twice per iteration.
+#include "common.h"
+#include "runtime.h"
+
+namespace {
+
+struct UgwScal {
+  double m;       // m(Th)
+  double shift;   // g(Th), added to every cost entry
+  double e;       // m(Th) eps
+  double tau;     // rho / (rho + eps)
+  double factor;  // mass rescale of the last plan
+  double mu, mv;  // m(u), m(v)
+  double pad;
+};
+
+constexpr int UR_NT = 1024;                  // row update threads
+constexpr int UC_COLS = 64, UC_WAVES = 16;   // column update block shape
+constexpr int UC_MAX_CHUNKS = 64;
+
+// Fixed-order block reductions (butterfly inside a wave, waves in order).
+template <int NTH>
+GW_DEV double block_max(double v, double* red) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double r = red[0];
+#pragma unroll
+  for (int w = 1; w < NTH / 64; ++w) r = fmax(r, red[w]);
+  return r;
+}
+
+template <int NTH>
+GW_DEV double block_sum(double v, double* red) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double r = red[0];
+#pragma unroll
+  for (int w = 1; w < NTH / 64; ++w) r += red[w];
+  return r;
+}
+
+// (m, s) pairs of a log-sum-exp: the value is m + log(s); m = -inf is empty.
+GW_DEV void lse_merge(double& m, double& s, double m2, double s2) {
+  const double mx = fmax(m, m2);
+  if (mx == -INFINITY) return;
+  s = s * exp(m - mx) + s2 * exp(m2 - mx);
+  m = mx;
+}
+
+__global__ __launch_bounds__(256) void k_uot_logs(const double* __restrict__ u,
+                                                  const double* __restrict__ v, int M, int N,
+                                                  double* __restrict__ lu,
+                                                  double* __restrict__ lv, double* __restrict__ f,
+                                                  double* __restrict__ g, int zero) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < M) {
+    lu[i] = u[i] > 0.0 ? log(u[i]) : -INFINITY;
+    if (zero) f[i] = 0.0;
+  }
+  if (i < N) {
+    lv[i] = v[i] > 0.0 ? log(v[i]) : -INFINITY;
+    if (zero) g[i] = 0.0;
+  }
+}
+
+__global__ void k_uot_set(UgwScal* sc, double shift, double e, double tau) {
+  if (threadIdx.x != 0) return;
+  sc->m = 1.0;
+  sc->shift = shift;
+  sc->e = e;
+  sc->tau = tau;
+  sc->factor = 1.0;
+}
+
+// f_i = -tau e LSE_p((g_p - C_ip - shift)/e + ln v_p): one block per row.
+template <int EPT>
+__global__ __launch_bounds__(UR_NT) void k_uot_row(const double* __restrict__ C, int64_t ldC,
+                                                   int N, const double* __restrict__ g,
+                                                   const double* __restrict__ lv,
+                                                   const UgwScal* __restrict__ sc,
+                                                   double* __restrict__ f) {
+  __shared__ double red[UR_NT / 64];
+  const int64_t i = blockIdx.x;
+  const int t = threadIdx.x;
+  const double* row = C + i * ldC;
+  const double shift = sc->shift, ie = 1.0 / sc->e;
+  double z[EPT];
+#pragma unroll
+  for (int k = 0; k < EPT; ++k) {
+    const int p = t + k * UR_NT, pc = min(p, N - 1);
+    const double zz = (g[pc] - row[pc] - shift) * ie + lv[pc];
+    z[k] = p < N ? zz : -INFINITY;
+  }
+  double mx = z[0];
+#pragma unroll
+  for (int k = 1; k < EPT; ++k) mx = fmax(mx, z[k]);
+  mx = block_max<UR_NT>(mx, red);
+  double s = 0.0;
+  if (mx != -INFINITY) {
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) s += exp(z[k] - mx);
+  }
+  s = block_sum<UR_NT>(s, red);
+  if (t == 0) {
+    const double L = mx == -INFINITY ? -INFINITY : mx + log(s);
+    f[i] = -sc->tau * sc->e * L;
+  }
+}
+
+// Column update, first stage: (m, s) of LSE_i((f_i - C_ip - shift)/e + ln u_i)
+// over the rows of chunk blockIdx.y, for 64 columns; each wave takes a
+// contiguous part of the chunk, the waves are merged in order.
+__global__ __launch_bounds__(UC_COLS * UC_WAVES) void k_uot_colpart(
+    const double* __restrict__ C, int64_t ldC, int M, int N, int rows_per_chunk,
+    const double* __restrict__ f, const double* __restrict__ lu, const UgwScal* __restrict__ sc,
+    double* __restrict__ pm, double* __restrict__ ps) {
+  __shared__ double sm[UC_WAVES][UC_COLS], ss[UC_WAVES][UC_COLS];
+  const int lane = threadIdx.x & (UC_COLS - 1), wv = threadIdx.x / UC_COLS;
+  const int col = blockIdx.x * UC_COLS + lane, colc = min(col, N - 1);
+  const int r0 = blockIdx.y * rows_per_chunk, r1 = min(M, r0 + rows_per_chunk);
+  const int len = (r1 - r0 + UC_WAVES - 1) / UC_WAVES;
+  const int a0 = r0 + wv * len, a1 = min(r1, a0 + len);
+  const double shift = sc->shift, ie = 1.0 / sc->e;
+  double m = -INFINITY, s = 0.0;
+  for (int i = a0; i < a1; ++i) {
+    const double z = (f[i] - C[(int64_t)i * ldC + colc] - shift) * ie + lu[i];
+    if (z > m) {
+      s = s * exp(m - z) + 1.0;
+      m = z;
+    } else if (z > -INFINITY) {
+      s += exp(z - m);
+    }
+  }
+  sm[wv][lane] = m;
+  ss[wv][lane] = s;
+  __syncthreads();
+  if (wv != 0 || col >= N) return;
+  for (int w = 1; w < UC_WAVES; ++w) lse_merge(m, s, sm[w][lane], ss[w][lane]);
+  pm[(int64_t)blockIdx.y * N + col] = m;
+  ps[(int64_t)blockIdx.y * N + col] = s;
+}
+
+// Column update, second stage: merge the chunks in order, g_p = -tau e LSE.
+__global__ __launch_bounds__(256) void k_uot_colmerge(int N, int R, const double* __restrict__ pm,
+                                                      const double* __restrict__ ps,
+                                                      const UgwScal* __restrict__ sc,
+                                                      double* __restrict__ g) {
+  const int col = blockIdx.x * 256 + threadIdx.x;
+  if (col >= N) return;
+  double m = pm[col], s = ps[col];
+  for (int r = 1; r < R; ++r) lse_merge(m, s, pm[(int64_t)r * N + col], ps[(int64_t)r * N + col]);
+  const double L = m == -INFINITY ? -INFINITY : m + log(s);
+  g[col] = -sc->tau * sc->e * L;
+}
+
+// T_ip = exp((f_i + g_p - C_ip - shift)/e) u_i v_p; with rowsum, each row's sum.
+__global__ __launch_bounds__(256) void k_uot_plan(const double* __restrict__ C, int64_t ldC,
+                                                  int N, const double* __restrict__ f,
+                                                  const double* __restrict__ g,
+                                                  const double* __restrict__ u,
+                                                  const double* __restrict__ v,
+                                                  const UgwScal* __restrict__ sc,
+                                                  double* __restrict__ T, int64_t ldT,
+                                                  double* __restrict__ rowsum) {
+  __shared__ double red[4];
+  const int64_t i = blockIdx.x;
+  const double fi = f[i], ui = u[i], shift = sc->shift, ie = 1.0 / sc->e;
+  double acc = 0.0;
+  for (int p = threadIdx.x; p < N; p += 256) {
+    const double val = exp((fi + g[p] - C[i * ldC + p] - shift) * ie) * ui * v[p];
+    T[i * ldT + p] = val;
+    acc += val;
+  }
+  acc = block_sum<256>(acc, red);
+  if (rowsum != nullptr && threadIdx.x == 0) rowsum[i] = acc;
+}
+
+// rowpart[i] = sum_p T_ip log T_ip (0 log 0 = 0).
+__global__ __launch_bounds__(256) void k_ugw_tlogt(const double* __restrict__ T, int64_t ldT,
+                                                   int N, double* __restrict__ rowpart) {
+  __shared__ double red[4];
+  const int64_t i = blockIdx.x;
+  double acc = 0.0;
+  for (int p = threadIdx.x; p < N; p += 256) {
+    const double x = T[i * ldT + p];
+    if (x > 0.0) acc += x * log(x);
+  }
+  acc = block_sum<256>(acc, red);
+  if (threadIdx.x == 0) rowpart[i] = acc;
+}
+
+// Sums of a step (one block, fixed order): m = sum a, the shift g(Th), e, tau.
+struct UgwSums {
+  double m, alogau, blogbv, tlogt, alogu, blogv;
+};
+
+GW_DEV UgwSums ugw_sums(const double* a, const double* b, const double* u, const double* v,
+                        const double* rowpart, int M, int N, double* red) {
+  double m = 0.0, au = 0.0, al = 0.0, tl = 0.0;
+  double bv = 0.0, bl = 0.0;
+  for (int i = threadIdx.x; i < M; i += 256) {
+    const double x = a[i];
+    m += x;
+    tl += rowpart[i];
+    if (x > 0.0) {
+      au += x * log(x / u[i]);
+      al += x * log(u[i]);
+    }
+  }
+  for (int p = threadIdx.x; p < N; p += 256) {
+    const double x = b[p];
+    if (x > 0.0) {
+      bv += x * log(x / v[p]);
+      bl += x * log(v[p]);
+    }
+  }
+  UgwSums r;
+  r.m = block_sum<256>(m, red);
+  r.alogau = block_sum<256>(au, red);
+  r.blogbv = block_sum<256>(bv, red);
+  r.tlogt = block_sum<256>(tl, red);
+  r.alogu = block_sum<256>(al, red);
+  r.blogv = block_sum<256>(bl, red);
+  return r;
+}
+
+__global__ __launch_bounds__(256) void k_ugw_scalars(const double* __restrict__ a,
+                                                     const double* __restrict__ b,
+                                                     const double* __restrict__ u,
+                                                     const double* __restrict__ v,
+                                                     const double* __restrict__ rowpart, int M,
+                                                     int N, double rho, double eps,
+                                                     UgwScal* __restrict__ sc) {
+  __shared__ double red[4];
+  const UgwSums S = ugw_sums(a, b, u, v, rowpart, M, N, red);
+  if (threadIdx.x != 0) return;
+  sc->m = S.m;
+  sc->shift = rho * S.alogau + rho * S.blogbv + eps * ((S.tlogt - S.alogu) - S.blogv);
+  sc->e = S.m * eps;
+  sc->tau = rho / (rho + eps);
+}
+
+// m(u), m(v) and the initial plan's factor 1 / sqrt(m(u) m(v)).
+__global__ __launch_bounds__(256) void k_ugw_masses(const double* __restrict__ u,
+                                                    const double* __restrict__ v, int M, int N,
+                                                    UgwScal* __restrict__ sc) {
+  __shared__ double red[4];
+  double su = 0.0, sv = 0.0;
+  for (int i = threadIdx.x; i < M; i += 256) su += u[i];
+  for (int p = threadIdx.x; p < N; p += 256) sv += v[p];
+  su = block_sum<256>(su, red);
+  sv = block_sum<256>(sv, red);
+  if (threadIdx.x == 0) {
+    sc->mu = su;
+    sc->mv = sv;
+    sc->factor = 1.0 / sqrt(su * sv);
+  }
+}
+
+// T_ip = factor u_i v_p.
+__global__ __launch_bounds__(256) void k_ugw_outer(const double* __restrict__ u,
+                                                   const double* __restrict__ v, int N,
+                                                   const UgwScal* __restrict__ sc,
+                                                   double* __restrict__ T, int64_t ldT) {
+  const int64_t i = blockIdx.y;
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  if (p < N) T[i * ldT + p] = sc->factor * u[i] * v[p];
+}
+
+// factor = sqrt(m(Th) / m(T)) from the plan's row sums; then T *= factor.
+__global__ __launch_bounds__(256) void k_ugw_rescale(const double* __restrict__ rowsum, int M,
+                                                     UgwScal* __restrict__ sc) {
+  __shared__ double red[4];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < M; i += 256) s += rowsum[i];
+  s = block_sum<256>(s, red);
+  if (threadIdx.x == 0) sc->factor = sqrt(sc->m / s);
+}
+
+__global__ __launch_bounds__(256) void k_ugw_scale(double* __restrict__ T, int64_t ldT, int N,
+                                                   const UgwScal* __restrict__ sc) {
+  const int64_t i = blockIdx.y;
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  if (p < N) T[i * ldT + p] *= sc->factor;
+}
+
+// obj[0] = E + rho (KL(a(x)a|u(x)u) + KL(b(x)b|v(x)v)),
+// obj[1] = obj[0] + eps KL(T(x)T|(u(x)v)(x)(u(x)v)),
+// KL(x(x)x|y(x)y) = 2 m(x) KL(x|y) + (m(x) - m(y))^2.
+__global__ __launch_bounds__(256) void k_ugw_objective(const double* __restrict__ a,
+                                                       const double* __restrict__ b,
+                                                       const double* __restrict__ u,
+                                                       const double* __restrict__ v,
+                                                       const double* __restrict__ rowpart, int M,
+                                                       int N, double rho, double eps,
+                                                       const UgwScal* __restrict__ sc,
+                                                       const double* __restrict__ eobj,
+                                                       double* __restrict__ obj) {
+  __shared__ double red[4];
+  const UgwSums S = ugw_sums(a, b, u, v, rowpart, M, N, red);
+  if (threadIdx.x != 0) return;
+  const double mT = S.m, mu = sc->mu, mv = sc->mv;
+  const double kla = S.alogau - mT + mu, klb = S.blogbv - mT + mv;
+  const double klt = ((S.tlogt - S.alogu) - S.blogv) - mT + mu * mv;
+  const double qa = 2.0 * mT * kla + (mT - mu) * (mT - mu);
+  const double qb = 2.0 * mT * klb + (mT - mv) * (mT - mv);
+  const double qt = 2.0 * mT * klt + (mT - mu * mv) * (mT - mu * mv);
+  const double U = eobj[0] + rho * (qa + qb);
+  obj[0] = U;
+  obj[1] = U + eps * qt;
+}
+
+int uot_chunks(int64_t M) {
+  const int64_t r = (M + 63) / 64;
+  return (int)(r < 1 ? 1 : (r > UC_MAX_CHUNKS ? UC_MAX_CHUNKS : r));
+}
+
+gw_status launch_uot_row(const double* C, int64_t ldC, int64_t M, int64_t N, const double* g,
+                         const double* lv, const UgwScal* sc, double* f, hipStream_t s) {
+  const int ept = (int)((N + UR_NT - 1) / UR_NT);
+  if (ept <= 1) k_uot_row<1><<<(unsigned)M, UR_NT, 0, s>>>(C, ldC, (int)N, g, lv, sc, f);
+  else if (ept <= 2) k_uot_row<2><<<(unsigned)M, UR_NT, 0, s>>>(C, ldC, (int)N, g, lv, sc, f);
+  else if (ept <= 4) k_uot_row<4><<<(unsigned)M, UR_NT, 0, s>>>(C, ldC, (int)N, g, lv, sc, f);
+  else if (ept <= 8) k_uot_row<8><<<(unsigned)M, UR_NT, 0, s>>>(C, ldC, (int)N, g, lv, sc, f);
+  else if (ept <= 16) k_uot_row<16><<<(unsigned)M, UR_NT, 0, s>>>(C, ldC, (int)N, g, lv, sc, f);
+  else return GW_EUNSUPPORTED;
+  return GW_OK;
+}
+
+}  // namespace
+
+namespace gwl {
+
+size_t uot_scalars_bytes() { return gwr::align_up(sizeof(UgwScal), 256); }
+
+size_t uot_ws_bytes(int64_t M, int64_t N) {
+  gwr::Arena a{nullptr, 0, 0};
+  a.take<double>(M);  // ln u
+  a.take<double>(N);  // ln v
+  const int R = uot_chunks(M);
+  a.take<double>((size_t)R * N);
+  a.take<double>((size_t)R * N);
+  a.take<double>(M);  // row sums of the plan
+  return a.used;
+}
+
+gw_status uot_set_scalars(void* scal, double shift, double e, double tau, hipStream_t s) {
+  k_uot_set<<<1, 64, 0, s>>>(static_cast<UgwScal*>(scal), shift, e, tau);
+  return gwr::last_launch_status();
+}
+
+// Unbalanced Sinkhorn on C + shift with the step scalars in `scal`; with T the
+// plan, and with rescale its mass set to m (scal) times sqrt(m / m(plan)).
+gw_status uot_sinkhorn(const double* C, int64_t ldC, int64_t M, int64_t N, const double* u,
+                       const double* v, int iters, int init_zero, double* f, double* g,
+                       double* T, int64_t ldT, bool rescale, void* scal, gwr::Arena& ws,
+                       hipStream_t s) {
+  if (N > 16 * UR_NT) return GW_EUNSUPPORTED;
+  UgwScal* sc = static_cast<UgwScal*>(scal);
+  double* lu = ws.take<double>(M);
+  double* lv = ws.take<double>(N);
+  const int R = uot_chunks(M);
+  double* pm = ws.take<double>((size_t)R * N);
+  double* ps = ws.take<double>((size_t)R * N);
+  double* rowsum = ws.take<double>(M);
+  gwr::ProfScope prof(gwr::kFamOther, s);
+  const int64_t mx = M > N ? M : N;
+  k_uot_logs<<<(unsigned)((mx + 255) / 256), 256, 0, s>>>(u, v, (int)M, (int)N, lu, lv, f, g,
+                                                          init_zero);
+  const int rpc = (int)((M + R - 1) / R);
+  const dim3 cgrid((unsigned)((N + UC_COLS - 1) / UC_COLS), (unsigned)R);
+  for (int it = 0; it < iters; ++it) {
+    gw_status st = launch_uot_row(C, ldC, M, N, g, lv, sc, f, s);
+    if (st != GW_OK) return st;
+    k_uot_colpart<<<cgrid, UC_COLS * UC_WAVES, 0, s>>>(C, ldC, (int)M, (int)N, rpc, f, lu, sc,
+                                                       pm, ps);
+    k_uot_colmerge<<<(unsigned)((N + 255) / 256), 256, 0, s>>>((int)N, R, pm, ps, sc, g);
+  }
+  if (T) {
+    k_uot_plan<<<(unsigned)M, 256, 0, s>>>(C, ldC, (int)N, f, g, u, v, sc, T, ldT,
+                                           rescale ? rowsum : nullptr);
+    if (rescale) {
+      k_ugw_rescale<<<1, 256, 0, s>>>(rowsum, (int)M, sc);
+      const dim3 sg((unsigned)((N + 255) / 256), (unsigned)M);
+      k_ugw_scale<<<sg, 256, 0, s>>>(T, ldT, (int)N, sc);
+    }
+  }
+  return gwr::last_launch_status();
+}
+
+// Set-up of a UGW solve: m(u), m(v) into the step scalars and T^0.
+gw_status ugw_init(const double* u, const double* v, int64_t M, int64_t N, double* T,
+                   int64_t ldT, void* scal, hipStream_t s) {
+  gwr::ProfScope prof(gwr::kFamOther, s);
+  UgwScal* sc = static_cast<UgwScal*>(scal);
+  k_ugw_masses<<<1, 256, 0, s>>>(u, v, (int)M, (int)N, sc);
+  const dim3 grid((unsigned)((N + 255) / 256), (unsigned)M);
+  k_ugw_outer<<<grid, 256, 0, s>>>(u, v, (int)N, sc, T, ldT);
+  return gwr::last_launch_status();
+}
+
+// The step scalars from T (its marginals a, b already in place): m, g(T), e, tau.
+gw_status ugw_step_scalars(const double* T, int64_t ldT, int64_t M, int64_t N, const double* a,
+                           const double* b, const double* u, const double* v, double rho,
+                           double eps, double* rowpart, void* scal, hipStream_t s) {
+  gwr::ProfScope prof(gwr::kFamOther, s);
+  k_ugw_tlogt<<<(unsigned)M, 256, 0, s>>>(T, ldT, (int)N, rowpart);
+  k_ugw_scalars<<<1, 256, 0, s>>>(a, b, u, v, rowpart, (int)M, (int)N, rho, eps,
+                                  static_cast<UgwScal*>(scal));
+  return gwr::last_launch_status();
+}
+
+// obj from E (device, eobj[0]) and T's marginals a, b.
+gw_status ugw_objective(const double* T, int64_t ldT, int64_t M, int64_t N, const double* a,
+                        const double* b, const double* u, const double* v, double rho,
+                        double eps, double* rowpart, const void* scal, const double* eobj,
+                        double* obj, hipStream_t s) {
+  gwr::ProfScope prof(gwr::kFamOther, s);
+  k_ugw_tlogt<<<(unsigned)M, 256, 0, s>>>(T, ldT, (int)N, rowpart);
+  k_ugw_objective<<<1, 256, 0, s>>>(a, b, u, v, rowpart, (int)M, (int)N, rho, eps,
+                                    static_cast<const UgwScal*>(scal), eobj, obj);
+  return gwr::last_launch_status();
+}
+
+}  // namespace gwl

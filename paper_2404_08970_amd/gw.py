@@ -22,7 +22,7 @@ GW_EAGAIN = -6
 METRIC_L1POW, METRIC_SQEUCLID = 0, 1
 PATH_FAST_F64, PATH_DENSE_F64, PATH_DENSE_F32, PATH_DENSE_BF16 = 0, 1, 2, 3
 PATH_DENSE_BF16_SPLIT, PATH_DENSE_F32_SPLIT = 4, 5
-OP_GRAD, OP_SINKHORN, OP_SOLVE, OP_OBJECTIVE = 0, 1, 2, 3
+OP_GRAD, OP_SINKHORN, OP_SOLVE, OP_OBJECTIVE, OP_UOT_SINKHORN, OP_SOLVE_UGW = 0, 1, 2, 3, 4, 5
 FLAG_WARM_START = 1
 REQ_OBJECTIVE = 2
 REQ_QUEUED, REQ_RUNNING, REQ_DONE = 0, 1, 2
@@ -93,6 +93,11 @@ def _lib():
     lib.gw_solve_tol.argtypes = [G, G, P, P, D, I32, I32, I32, D, I32, I32, P, I64, P, P, P, P, P,
                                  SZ, P]
     lib.gw_solve_tol.restype = I32
+    lib.gw_uot_sinkhorn.argtypes = [P, I64, I64, I64, D, P, P, D, D, I32, I32, P, P, P, I64, P,
+                                    SZ, P]
+    lib.gw_uot_sinkhorn.restype = I32
+    lib.gw_solve_ugw.argtypes = [G, G, P, P, D, D, I32, I32, I32, P, I64, P, P, P, P, SZ, P]
+    lib.gw_solve_ugw.restype = I32
     lib.gw_grad_fgw.argtypes = [G, G, P, P, P, P, D, P, I64, P, I64, I32, P, SZ, P]
     lib.gw_grad_fgw.restype = I32
     lib.gw_solve_fgw.argtypes = [G, G, P, P, P, P, D, D, I32, I32, I32, I32, P, I64, P, P, P, P,
@@ -364,6 +369,57 @@ def objective(X: Grid, Y: Grid, T, eps: float, ws=None):
                              _ptr(obj), _ptr(ws), ws.numel(), _stream())
     _raise(st, "gw_objective")
     return obj
+
+
+def uot_sinkhorn(C, u, v, rho: float, eps: float, iters: int, c_shift: float = 0.0, f=None,
+                 g=None, plan: bool = False, ws=None):
+    """Unbalanced entropic OT on C + c_shift (log-domain potentials); returns
+    (f, g) or (f, g, T)."""
+    M, N = C.shape
+    _check_f64("C", C, (M, N)); _check_f64("u", u, (M,)); _check_f64("v", v, (N,))
+    init_zero = 1 if (f is None and g is None) else 0
+    if f is None:
+        f = torch.zeros(M, dtype=torch.float64, device=C.device)
+    if g is None:
+        g = torch.zeros(N, dtype=torch.float64, device=C.device)
+    T = torch.empty((M, N), dtype=torch.float64, device=C.device) if plan else None
+    gx, gy = Grid((M,), 1.0, 1), Grid((N,), 1.0, 1)
+    nb = workspace_bytes(gx, gy, PATH_FAST_F64, OP_UOT_SINKHORN)
+    if ws is None:
+        ws = workspace(nb, C.device, key="uot")
+    st = _lib().gw_uot_sinkhorn(_ptr(C), C.stride(0), M, N, float(c_shift), _ptr(u), _ptr(v),
+                                float(rho), float(eps), int(iters), init_zero, _ptr(f), _ptr(g),
+                                _ptr(T), T.stride(0) if T is not None else N, _ptr(ws),
+                                ws.numel(), _stream())
+    _raise(st, "gw_uot_sinkhorn")
+    return (f, g, T) if plan else (f, g)
+
+
+def solve_ugw(X: Grid, Y: Grid, u, v, rho: float, eps: float, outer: int, inner: int,
+              path=PATH_FAST_F64, objective: bool = True, T=None, f=None, g=None, obj=None,
+              ws=None):
+    """Entropic unbalanced GW on the GPU; returns (T, f, g, obj[2] or None)."""
+    path = PATHS.get(path, path)
+    M, N = X.size, Y.size
+    _check_f64("u", u, (M,)); _check_f64("v", v, (N,))
+    dev = u.device
+    T = torch.empty((M, N), dtype=torch.float64, device=dev) if T is None else T
+    f = torch.empty(M, dtype=torch.float64, device=dev) if f is None else f
+    g = torch.empty(N, dtype=torch.float64, device=dev) if g is None else g
+    if objective and obj is None:
+        obj = torch.empty(2, dtype=torch.float64, device=dev)
+    nb = workspace_bytes(X, Y, path, OP_SOLVE_UGW)
+    if nb == 0:
+        raise GWError(GW_EINVAL, "gw_workspace_bytes")
+    if ws is None:
+        ws = workspace(nb, dev, key="ugw")
+    xc, yc = X.c(), Y.c()
+    st = _lib().gw_solve_ugw(ctypes.byref(xc), ctypes.byref(yc), _ptr(u), _ptr(v), float(rho),
+                             float(eps), int(outer), int(inner), int(path), _ptr(T), T.stride(0),
+                             _ptr(f), _ptr(g), _ptr(obj if objective else None), _ptr(ws),
+                             ws.numel(), _stream())
+    _raise(st, "gw_solve_ugw")
+    return T, f, g, (obj if objective else None)
 
 
 def _check_features(fa, fb, M, N):
