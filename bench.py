@@ -213,6 +213,37 @@ def grid3d_bench(side: int = 16, eps: float = 2e-3, outer: int = 100, inner: int
             "objective": float(obj[0].item())}
 
 
+def ugw_bench(n: int = 4096, rho: float = 1.0, eps: float = 2e-3, outer: int = 10,
+              inner: int = 100, reps: int = 2):
+    """Unbalanced GW on the 1D grid of the headline size: k = 1, u and v
+    3-Gaussian-mixture marginals of masses 1 and 1.5, rho = 1, eps = 2e-3,
+    10 outer x 100 unbalanced Sinkhorn iterations; also the unbalanced
+    Sinkhorn iteration alone (row and column update) at this size."""
+    import torch
+    from paper_2404_08970_amd import gw, inputs
+    dev = torch.device("cuda:0")
+    X = gw.unit_grid((n,), 1)
+    rng = inputs.rng_for(13, n)
+    u = torch.tensor(inputs.gauss_mixture_1d(n, rng), device=dev)
+    v = torch.tensor(1.5 * inputs.gauss_mixture_1d(n, rng), device=dev)
+    T = torch.empty((n, n), dtype=torch.float64, device=dev)
+    f = torch.empty(n, dtype=torch.float64, device=dev)
+    g = torch.empty(n, dtype=torch.float64, device=dev)
+    obj = torch.empty(2, dtype=torch.float64, device=dev)
+    ws = gw.workspace(gw.workspace_bytes(X, X, gw.PATH_FAST_F64, gw.OP_SOLVE_UGW), dev, key="ugw")
+    run = lambda: gw.solve_ugw(X, X, u, v, rho, eps, outer, inner, T=T, f=f, g=g, obj=obj, ws=ws)
+    ms = time_gpu(run, reps, torch)
+    gw.check_status(ws)
+    C = gw.grad(X, X, u, v, T)
+    it_ms = time_gpu(lambda: gw.uot_sinkhorn(C, u, v, rho, eps, 20, f=f, g=g), 3, torch) / 20
+    return {"workload": f"1D UGW n = {n}, k = 1, mixture marginals of mass 1 and 1.5, rho = {rho}, "
+                        f"eps = {eps}, {outer} outer x {inner} unbalanced Sinkhorn",
+            "solves_per_s": round(1e3 / ms, 3), "ms_per_solve": round(ms, 2),
+            "uot_iteration_us": round(it_ms * 1e3, 1),
+            "uot_GBps_at_16B_per_entry": round(16.0 * n * n / (it_ms * 1e-3) / 1e9, 1),
+            "objective": float(obj[0].item()), "plan_mass": float(T.sum().item())}
+
+
 def fgw_bench(n: int = 4000, theta: float = 0.5, eps: float = 2e-3, outer: int = 10,
               inner: int = 100, reps: int = 3):
     """The 1D random-distribution FGW workload: x_i = y_i = (i-1)/(n-1), k = 1,
@@ -434,6 +465,8 @@ def main():
     ap.add_argument("--no-2d", action="store_true", help="skip the 2D 64x64 solve")
     ap.add_argument("--no-fgw", action="store_true", help="skip the 1D fused GW solve")
     ap.add_argument("--no-3d", action="store_true", help="skip the 3D 16^3 solve")
+    ap.add_argument("--no-ugw", action="store_true", help="skip the 1D unbalanced GW solve")
+    ap.add_argument("--only-ugw", action="store_true", help="run only the 1D unbalanced GW solve")
     ap.add_argument("--only-3d", action="store_true", help="run only the 3D 16^3 solve and exit")
     ap.add_argument("--no-tol", action="store_true", help="skip the tolerance-stop comparison")
     ap.add_argument("--only-tol", action="store_true", help="run only the tolerance-stop comparison")
@@ -446,6 +479,9 @@ def main():
     args = ap.parse_args()
     if args.precision:
         print(json.dumps(precision_study()))
+        return
+    if args.only_ugw:
+        print(json.dumps(ugw_bench()))
         return
     if args.only_3d:
         print(json.dumps(grid3d_bench()))
@@ -577,6 +613,7 @@ def main():
     grid2d = None if args.no_2d else grid2d_bench()
     fused = None if args.no_fgw else fgw_bench()
     grid3d = None if args.no_3d else grid3d_bench()
+    unbalanced = None if args.no_ugw else ugw_bench()
     stopped = None if args.no_tol else tolerance_bench()
     serving = None
     if not args.no_serve:
@@ -606,6 +643,7 @@ def main():
         "grid2d_64x64": grid2d,
         "fgw_1d_n4000": fused,
         "grid3d_16cube": grid3d,
+        "ugw_1d_n4096": unbalanced,
         "tolerance_stop": stopped,
         "serving": serving,
     }

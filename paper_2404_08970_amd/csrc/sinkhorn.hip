@@ -866,21 +866,29 @@ __global__ __launch_bounds__(256) void k_rowsum(const double* __restrict__ T, in
   if (threadIdx.x == 0) r[i] = s;
 }
 
-// column sums: block of 256 threads covers 64 columns x 4 row-quarters
-__global__ __launch_bounds__(256) void k_colsum(const double* __restrict__ T, int64_t ldT, int M,
-                                                 int N, double* __restrict__ c) {
-  __shared__ double part[4][64];
-  const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
-  const int col = blockIdx.x * 64 + lane;
+// column sums: a block of 1024 threads covers 16 columns x 64 row groups
+// (contiguous row ranges), the groups' sums added in group order
+constexpr int CS_COLS = 16, CS_GRPS = 64;
+__global__ __launch_bounds__(CS_COLS * CS_GRPS) void k_colsum(const double* __restrict__ T,
+                                                              int64_t ldT, int M, int N,
+                                                              double* __restrict__ c) {
+  __shared__ double part[CS_GRPS][CS_COLS];
+  const int lane = threadIdx.x & (CS_COLS - 1), grp = threadIdx.x / CS_COLS;
+  const int col = blockIdx.x * CS_COLS + lane;
   double s = 0.0;
   if (col < N) {
-    const int chunk = (M + 3) / 4;
+    const int chunk = (M + CS_GRPS - 1) / CS_GRPS;
     const int r0 = grp * chunk, r1 = min(M, r0 + chunk);
+#pragma unroll 8
     for (int i = r0; i < r1; ++i) s += T[(int64_t)i * ldT + col];
   }
   part[grp][lane] = s;
   __syncthreads();
-  if (grp == 0 && col < N) c[col] = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
+  if (grp == 0 && col < N) {
+    double r = part[0][lane];
+    for (int g = 1; g < CS_GRPS; ++g) r += part[g][lane];
+    c[col] = r;
+  }
 }
 
 // partial sums of G*T and T (ln T - 1) per block (rows band), fixed order
@@ -1187,7 +1195,8 @@ gw_status marginals(const double* T, int64_t ldT, int64_t M, int64_t N, double* 
                     gwr::Arena&, hipStream_t s) {
   gwr::ProfScope ps(gwr::kFamOther, s);
   k_rowsum<<<(unsigned)M, 256, 0, s>>>(T, ldT, (int)N, r);
-  k_colsum<<<(unsigned)((N + 63) / 64), 256, 0, s>>>(T, ldT, (int)M, (int)N, c);
+  k_colsum<<<(unsigned)((N + CS_COLS - 1) / CS_COLS), CS_COLS * CS_GRPS, 0, s>>>(T, ldT, (int)M,
+                                                                                (int)N, c);
   return gwr::last_launch_status();
 }
 

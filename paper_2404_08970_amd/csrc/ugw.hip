@@ -94,13 +94,13 @@ __global__ void k_uot_set(UgwScal* sc, double shift, double e, double tau) {
 }
 
 // f_i = -tau e LSE_p((g_p - C_ip - shift)/e + ln v_p): one block per row.
-template <int EPT>
-__global__ __launch_bounds__(UR_NT) void k_uot_row(const double* __restrict__ C, int64_t ldC,
-                                                   int N, const double* __restrict__ g,
-                                                   const double* __restrict__ lv,
-                                                   const UgwScal* __restrict__ sc,
-                                                   double* __restrict__ f) {
-  __shared__ double red[UR_NT / 64];
+template <int NTH, int EPT>
+__global__ __launch_bounds__(NTH) void k_uot_row(const double* __restrict__ C, int64_t ldC,
+                                                 int N, const double* __restrict__ g,
+                                                 const double* __restrict__ lv,
+                                                 const UgwScal* __restrict__ sc,
+                                                 double* __restrict__ f) {
+  __shared__ double red[NTH / 64];
   const int64_t i = blockIdx.x;
   const int t = threadIdx.x;
   const double* row = C + i * ldC;
@@ -108,20 +108,20 @@ __global__ __launch_bounds__(UR_NT) void k_uot_row(const double* __restrict__ C,
   double z[EPT];
 #pragma unroll
   for (int k = 0; k < EPT; ++k) {
-    const int p = t + k * UR_NT, pc = min(p, N - 1);
+    const int p = t + k * NTH, pc = min(p, N - 1);
     const double zz = (g[pc] - row[pc] - shift) * ie + lv[pc];
     z[k] = p < N ? zz : -INFINITY;
   }
   double mx = z[0];
 #pragma unroll
   for (int k = 1; k < EPT; ++k) mx = fmax(mx, z[k]);
-  mx = block_max<UR_NT>(mx, red);
+  mx = block_max<NTH>(mx, red);
   double s = 0.0;
   if (mx != -INFINITY) {
 #pragma unroll
     for (int k = 0; k < EPT; ++k) s += exp(z[k] - mx);
   }
-  s = block_sum<UR_NT>(s, red);
+  s = block_sum<NTH>(s, red);
   if (t == 0) {
     const double L = mx == -INFINITY ? -INFINITY : mx + log(s);
     f[i] = -sc->tau * sc->e * L;
@@ -161,15 +161,24 @@ __global__ __launch_bounds__(UC_COLS * UC_WAVES) void k_uot_colpart(
   ps[(int64_t)blockIdx.y * N + col] = s;
 }
 
-// Column update, second stage: merge the chunks in order, g_p = -tau e LSE.
+// Column update, second stage: a wave per column, lane r holding chunk r
+// (R <= 64), merged by a butterfly (a fixed order), g_p = -tau e LSE.
 __global__ __launch_bounds__(256) void k_uot_colmerge(int N, int R, const double* __restrict__ pm,
                                                       const double* __restrict__ ps,
                                                       const UgwScal* __restrict__ sc,
                                                       double* __restrict__ g) {
-  const int col = blockIdx.x * 256 + threadIdx.x;
-  if (col >= N) return;
-  double m = pm[col], s = ps[col];
-  for (int r = 1; r < R; ++r) lse_merge(m, s, pm[(int64_t)r * N + col], ps[(int64_t)r * N + col]);
+  const int col = blockIdx.x * 4 + (threadIdx.x >> 6), r = threadIdx.x & 63;
+  const int cc = min(col, N - 1);
+  double m = -INFINITY, s = 0.0;
+  if (r < R) {
+    m = pm[(int64_t)r * N + cc];
+    s = ps[(int64_t)r * N + cc];
+  }
+  for (int o = 1; o < 64; o <<= 1) {
+    const double m2 = __shfl_xor(m, o, 64), s2 = __shfl_xor(s, o, 64);
+    lse_merge(m, s, m2, s2);
+  }
+  if (r != 0 || col >= N) return;
   const double L = m == -INFINITY ? -INFINITY : m + log(s);
   g[col] = -sc->tau * sc->e * L;
 }
@@ -332,18 +341,21 @@ __global__ __launch_bounds__(256) void k_ugw_objective(const double* __restrict_
 }
 
 int uot_chunks(int64_t M) {
-  const int64_t r = (M + 63) / 64;
+  const int64_t r = (M + 255) / 256;
   return (int)(r < 1 ? 1 : (r > UC_MAX_CHUNKS ? UC_MAX_CHUNKS : r));
 }
 
 gw_status launch_uot_row(const double* C, int64_t ldC, int64_t M, int64_t N, const double* g,
                          const double* lv, const UgwScal* sc, double* f, hipStream_t s) {
-  const int ept = (int)((N + UR_NT - 1) / UR_NT);
-  if (ept <= 1) k_uot_row<1><<<(unsigned)M, UR_NT, 0, s>>>(C, ldC, (int)N, g, lv, sc, f);
-  else if (ept <= 2) k_uot_row<2><<<(unsigned)M, UR_NT, 0, s>>>(C, ldC, (int)N, g, lv, sc, f);
-  else if (ept <= 4) k_uot_row<4><<<(unsigned)M, UR_NT, 0, s>>>(C, ldC, (int)N, g, lv, sc, f);
-  else if (ept <= 8) k_uot_row<8><<<(unsigned)M, UR_NT, 0, s>>>(C, ldC, (int)N, g, lv, sc, f);
-  else if (ept <= 16) k_uot_row<16><<<(unsigned)M, UR_NT, 0, s>>>(C, ldC, (int)N, g, lv, sc, f);
+  // rows up to 4096 entries: 256 threads (cheaper block reductions), longer: 1024
+  const unsigned m = (unsigned)M;
+  const int n = (int)N;
+  if (N <= 256) k_uot_row<256, 1><<<m, 256, 0, s>>>(C, ldC, n, g, lv, sc, f);
+  else if (N <= 1024) k_uot_row<256, 4><<<m, 256, 0, s>>>(C, ldC, n, g, lv, sc, f);
+  else if (N <= 2048) k_uot_row<256, 8><<<m, 256, 0, s>>>(C, ldC, n, g, lv, sc, f);
+  else if (N <= 4096) k_uot_row<256, 16><<<m, 256, 0, s>>>(C, ldC, n, g, lv, sc, f);
+  else if (N <= 8192) k_uot_row<UR_NT, 8><<<m, UR_NT, 0, s>>>(C, ldC, n, g, lv, sc, f);
+  else if (N <= 16384) k_uot_row<UR_NT, 16><<<m, UR_NT, 0, s>>>(C, ldC, n, g, lv, sc, f);
   else return GW_EUNSUPPORTED;
   return GW_OK;
 }
@@ -395,7 +407,7 @@ gw_status uot_sinkhorn(const double* C, int64_t ldC, int64_t M, int64_t N, const
     if (st != GW_OK) return st;
     k_uot_colpart<<<cgrid, UC_COLS * UC_WAVES, 0, s>>>(C, ldC, (int)M, (int)N, rpc, f, lu, sc,
                                                        pm, ps);
-    k_uot_colmerge<<<(unsigned)((N + 255) / 256), 256, 0, s>>>((int)N, R, pm, ps, sc, g);
+    k_uot_colmerge<<<(unsigned)((N + 3) / 4), 256, 0, s>>>((int)N, R, pm, ps, sc, g);
   }
   if (T) {
     k_uot_plan<<<(unsigned)M, 256, 0, s>>>(C, ldC, (int)N, f, g, u, v, sc, T, ldT,
