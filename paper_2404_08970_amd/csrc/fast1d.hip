@@ -126,15 +126,19 @@ constexpr int P1_DEPTH = 2;  // tiles in flight per block (3 measured no faster)
 // 16-entry column segment of the tile in registers (loaded one tile ahead),
 // sums it for the column moments, and sums a row segment (through LDS) for
 // the row moments.  Entries beyond the matrix are zero, so every tile is
-// handled at its nominal size.
+// handled at its nominal size.  The segment summaries reuse the tile's LDS
+// once every thread has read its row segment (one LDS buffer per block: more
+// resident blocks).
 template <int KX, int KY>
 __global__ __launch_bounds__(256) void k_p1_moments(const double* __restrict__ T, int64_t ldT,
                                                      int M, int N, int nI, int nJ,
                                                      double* __restrict__ rowmom,
                                                      double* __restrict__ colmom) {
   constexpr int KM = (KX > KY ? KX : KY) + 1;
-  __shared__ double X[TS][LDS_STRIDE];
-  __shared__ double part[2][NSEG][TS][2 * KM];
+  constexpr int XW = TS * LDS_STRIDE, PW = 2 * NSEG * TS * 2 * KM;
+  __shared__ double lds1[XW > PW ? XW : PW];
+  auto X = reinterpret_cast<double (*)[LDS_STRIDE]>(lds1);          // the tile
+  auto part = reinterpret_cast<double (*)[NSEG][TS][2 * KM]>(lds1);  // then the summaries
   // seg is the wave index: kept in a scalar register, so row addresses are scalar
   const int t = threadIdx.x, lane = t & (TS - 1), seg = __builtin_amdgcn_readfirstlane(t >> 6);
   const int ntiles = nI * nJ;
@@ -163,28 +167,24 @@ __global__ __launch_bounds__(256) void k_p1_moments(const double* __restrict__ T
 #pragma unroll
     for (int i = 0; i < SEG; ++i) x[i] = (seg * SEG + i < h && lane < w) ? pf[i] : 0.0;
     load_tile(pf, min(tile + P1_DEPTH * stride, ntiles - 1));
-    {
-      double pre[KX + 1], suf[KX + 1];
-      seg_summaries<KX>(x, pre, suf);
+    double cpre[KX + 1], csuf[KX + 1], rpre[KY + 1], rsuf[KY + 1];
+    seg_summaries<KX>(x, cpre, csuf);
 #pragma unroll
-      for (int r = 0; r <= KX; ++r) {
-        part[1][seg][lane][r] = pre[r];
-        part[1][seg][lane][KM + r] = suf[r];
-      }
-#pragma unroll
-      for (int i = 0; i < SEG; ++i) X[seg * SEG + i][lane] = x[i];
-    }
+    for (int i = 0; i < SEG; ++i) X[seg * SEG + i][lane] = x[i];
     __syncthreads();
-    {
 #pragma unroll
-      for (int c = 0; c < SEG; ++c) x[c] = X[lane][seg * SEG + c];
-      double pre[KY + 1], suf[KY + 1];
-      seg_summaries<KY>(x, pre, suf);
+    for (int c = 0; c < SEG; ++c) x[c] = X[lane][seg * SEG + c];
+    seg_summaries<KY>(x, rpre, rsuf);
+    __syncthreads();  // every row segment has been read: the summaries take the LDS
 #pragma unroll
-      for (int r = 0; r <= KY; ++r) {
-        part[0][seg][lane][r] = pre[r];
-        part[0][seg][lane][KM + r] = suf[r];
-      }
+    for (int r = 0; r <= KY; ++r) {
+      part[0][seg][lane][r] = rpre[r];
+      part[0][seg][lane][KM + r] = rsuf[r];
+    }
+#pragma unroll
+    for (int r = 0; r <= KX; ++r) {
+      part[1][seg][lane][r] = cpre[r];
+      part[1][seg][lane][KM + r] = csuf[r];
     }
     __syncthreads();
     // wave 0 writes the row moments of the tile's rows, wave 1 the column
