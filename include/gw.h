@@ -190,6 +190,10 @@ gw_status gw_solve_tol(const gw_grid* X, const gw_grid* Y, const double* p, cons
  *   unbalanced Sinkhorn with tau = rho / (rho + eps) and e = m(Th) eps,
  *   T <- sqrt(m(Th) / m(T)) T after each step, T^0 = u (x) v / sqrt(m(u) m(v)).
  * Workspace: gw_workspace_bytes with GW_OP_UOT_SINKHORN / GW_OP_SOLVE_UGW.
+ * u and v must have positive mass; a non-finite potential or rescale factor
+ * (e.g. from an empty measure) sets the workspace status (gw_check_status ->
+ * GW_ENUMERIC).  gw_solve_ugw clears the status first; gw_uot_sinkhorn, like
+ * gw_sinkhorn, leaves an earlier flag in place.
  * ------------------------------------------------------------------------ */
 
 /* Unbalanced entropic OT on C_eff = C + c_shift:

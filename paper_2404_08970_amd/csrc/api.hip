@@ -527,7 +527,8 @@ gw_status gw_uot_sinkhorn(const double* C, int64_t ldC, int64_t M, int64_t N, do
   a.take<char>(gwr::ws_status_bytes());
   void* scal = a.take<char>(gwl::uot_scalars_bytes());
   if ((st = gwl::uot_set_scalars(scal, c_shift, eps, rho / (rho + eps), s)) != GW_OK) return st;
-  return gwl::uot_sinkhorn(C, ldC, M, N, u, v, iters, init_zero, f, g, T, ldT, false, scal, a, s);
+  return gwl::uot_sinkhorn(C, ldC, M, N, u, v, iters, init_zero, f, g, T, ldT, false, scal, a, s,
+                           status_of(ws));
 }
 
 gw_status gw_solve_ugw(const gw_grid* Xp, const gw_grid* Yp, const double* u, const double* v,
@@ -571,13 +572,14 @@ gw_status gw_solve_ugw(const gw_grid* Xp, const gw_grid* Yp, const double* u, co
     if ((st = run_grad(X, Y, a, b, T, ldT, G, N, path, ar, s, nullptr, nullptr)) != GW_OK)
       return st;
     ar.used = mark;
-    st = gwl::uot_sinkhorn(G, N, M, N, u, v, inner, 1, f, g, T, ldT, true, scal, ar, s);
+    st = gwl::uot_sinkhorn(G, N, M, N, u, v, inner, 1, f, g, T, ldT, true, scal, ar, s,
+                           status_of(ws));
     if (st != GW_OK) return st;
   }
   if (outer == 0) {  // potentials of no step: zero
     ar.used = mark;
-    if ((st = gwl::uot_sinkhorn(G, N, M, N, u, v, 0, 1, f, g, nullptr, ldT, false, scal, ar, s)) !=
-        GW_OK)
+    if ((st = gwl::uot_sinkhorn(G, N, M, N, u, v, 0, 1, f, g, nullptr, ldT, false, scal, ar, s,
+                                status_of(ws))) != GW_OK)
       return st;
   }
   if (obj) {

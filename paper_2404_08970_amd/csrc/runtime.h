@@ -202,7 +202,7 @@ gw_status uot_set_scalars(void* scal, double shift, double e, double tau, hipStr
 gw_status uot_sinkhorn(const double* C, int64_t ldC, int64_t M, int64_t N, const double* u,
                        const double* v, int iters, int init_zero, double* f, double* g,
                        double* T, int64_t ldT, bool rescale, void* scal, gwr::Arena& ws,
-                       hipStream_t s);
+                       hipStream_t s, gwr::StatusWord* status);
 gw_status ugw_init(const double* u, const double* v, int64_t M, int64_t N, double* T,
                    int64_t ldT, void* scal, hipStream_t s);
 gw_status ugw_step_scalars(const double* T, int64_t ldT, int64_t M, int64_t N, const double* a,

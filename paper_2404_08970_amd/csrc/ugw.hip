@@ -166,7 +166,8 @@ __global__ __launch_bounds__(UC_COLS * UC_WAVES) void k_uot_colpart(
 __global__ __launch_bounds__(256) void k_uot_colmerge(int N, int R, const double* __restrict__ pm,
                                                       const double* __restrict__ ps,
                                                       const UgwScal* __restrict__ sc,
-                                                      double* __restrict__ g) {
+                                                      double* __restrict__ g,
+                                                      gwr::StatusWord* status) {
   const int col = blockIdx.x * 4 + (threadIdx.x >> 6), r = threadIdx.x & 63;
   const int cc = min(col, N - 1);
   double m = -INFINITY, s = 0.0;
@@ -180,7 +181,9 @@ __global__ __launch_bounds__(256) void k_uot_colmerge(int N, int R, const double
   }
   if (r != 0 || col >= N) return;
   const double L = m == -INFINITY ? -INFINITY : m + log(s);
-  g[col] = -sc->tau * sc->e * L;
+  const double gn = -sc->tau * sc->e * L;
+  g[col] = gn;
+  if (isnan(gn)) status->nonfinite = 1;
 }
 
 // T_ip = exp((f_i + g_p - C_ip - shift)/e) u_i v_p; with rowsum, each row's sum.
@@ -299,12 +302,17 @@ __global__ __launch_bounds__(256) void k_ugw_outer(const double* __restrict__ u,
 
 // factor = sqrt(m(Th) / m(T)) from the plan's row sums; then T *= factor.
 __global__ __launch_bounds__(256) void k_ugw_rescale(const double* __restrict__ rowsum, int M,
-                                                     UgwScal* __restrict__ sc) {
+                                                     UgwScal* __restrict__ sc,
+                                                     gwr::StatusWord* status) {
   __shared__ double red[4];
   double s = 0.0;
   for (int i = threadIdx.x; i < M; i += 256) s += rowsum[i];
   s = block_sum<256>(s, red);
-  if (threadIdx.x == 0) sc->factor = sqrt(sc->m / s);
+  if (threadIdx.x == 0) {
+    const double fct = sqrt(sc->m / s);
+    sc->factor = fct;
+    if (!isfinite(fct)) status->nonfinite = 1;  // an empty plan or a non-finite step
+  }
 }
 
 __global__ __launch_bounds__(256) void k_ugw_scale(double* __restrict__ T, int64_t ldT, int N,
@@ -387,7 +395,7 @@ gw_status uot_set_scalars(void* scal, double shift, double e, double tau, hipStr
 gw_status uot_sinkhorn(const double* C, int64_t ldC, int64_t M, int64_t N, const double* u,
                        const double* v, int iters, int init_zero, double* f, double* g,
                        double* T, int64_t ldT, bool rescale, void* scal, gwr::Arena& ws,
-                       hipStream_t s) {
+                       hipStream_t s, gwr::StatusWord* status) {
   if (N > 16 * UR_NT) return GW_EUNSUPPORTED;
   UgwScal* sc = static_cast<UgwScal*>(scal);
   double* lu = ws.take<double>(M);
@@ -407,13 +415,13 @@ gw_status uot_sinkhorn(const double* C, int64_t ldC, int64_t M, int64_t N, const
     if (st != GW_OK) return st;
     k_uot_colpart<<<cgrid, UC_COLS * UC_WAVES, 0, s>>>(C, ldC, (int)M, (int)N, rpc, f, lu, sc,
                                                        pm, ps);
-    k_uot_colmerge<<<(unsigned)((N + 3) / 4), 256, 0, s>>>((int)N, R, pm, ps, sc, g);
+    k_uot_colmerge<<<(unsigned)((N + 3) / 4), 256, 0, s>>>((int)N, R, pm, ps, sc, g, status);
   }
   if (T) {
     k_uot_plan<<<(unsigned)M, 256, 0, s>>>(C, ldC, (int)N, f, g, u, v, sc, T, ldT,
                                            rescale ? rowsum : nullptr);
     if (rescale) {
-      k_ugw_rescale<<<1, 256, 0, s>>>(rowsum, (int)M, sc);
+      k_ugw_rescale<<<1, 256, 0, s>>>(rowsum, (int)M, sc, status);
       const dim3 sg((unsigned)((N + 255) / 256), (unsigned)M);
       k_ugw_scale<<<sg, 256, 0, s>>>(T, ldT, (int)N, sc);
     }

@@ -123,3 +123,18 @@ def test_ugw_rejects_bad_arguments():
         with pytest.raises(gw.GWError):
             gw.uot_sinkhorn(torch.zeros((4, 4), dtype=torch.float64, device="cuda"), z, z, rho,
                             eps, 1)
+
+
+def test_ugw_empty_measure_flags_numeric_status():
+    """u = 0 has no plan to rescale: the non-finite step is reported through the
+    workspace status (GW_ENUMERIC), not silently returned."""
+    gw, torch = _gw()
+    X = gw.unit_grid((16,), 1)
+    u = torch.zeros(16, dtype=torch.float64, device="cuda")
+    v = torch.full((16,), 1 / 16, dtype=torch.float64, device="cuda")
+    ws = gw.workspace(gw.workspace_bytes(X, X, gw.PATH_FAST_F64, gw.OP_SOLVE_UGW), "cuda",
+                      key="ugw_status")
+    gw.solve_ugw(X, X, u, v, 1.0, 0.05, 2, 5, ws=ws)
+    with pytest.raises(gw.GWError) as e:
+        gw.check_status(ws)
+    assert e.value.status == gw.GW_ENUMERIC
