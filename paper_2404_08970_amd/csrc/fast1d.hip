@@ -822,6 +822,106 @@ gw_status dispatch_ky(int ky, const Layout& L, const double* T, int64_t ldT, dou
   return GW_EUNSUPPORTED;
 }
 
+// ------------------------------------------------ image operator (2D rows)
+// For 2D grids whose image fits one 64 x 64 tile: each row of `in` is an
+// H x W image (zero padded to the tile) and receives
+//   sum_t coef_t  D_H^{o mh_t} X D_W^{o mw_t}   (D^{o0} = J, the diagonal included),
+// the Kronecker expansion of Sec. 3.1 applied to one image.  A block of 256
+// threads owns one row: thread (line, seg) applies the recursion to a 16-entry
+// segment of a line, with the carries of the other segments combined through
+// LDS (as the tile sweep does), first along the image rows (exponent mw), the
+// result staged in LDS, then along the image columns (exponent mh), summed over
+// the terms in registers.  The thread keeps its row segment of the image in
+// registers for every term.
+struct ImgTerms {
+  int n;
+  int coef[GW_KMAX + 1], mh[GW_KMAX + 1], mw[GW_KMAX + 1];
+};
+
+template <int K>
+GW_DEV void img_line(const double (&x)[SEG], double (&out)[SEG],
+                     double (*sums)[NSEG][TS][GW_KMAX + 1], int lane, int seg) {
+  double pre[K + 1], suf[K + 1];
+  seg_summaries<K>(x, pre, suf);
+#pragma unroll
+  for (int r = 0; r <= K; ++r) {
+    sums[0][seg][lane][r] = pre[r];
+    sums[1][seg][lane][r] = suf[r];
+  }
+  __syncthreads();
+  double a[K + 1], b[K + 1];
+#pragma unroll
+  for (int r = 0; r <= K; ++r) a[r] = b[r] = 0.0;
+  for (int sg = 0; sg < seg; ++sg) {
+    gwk::pascal_shift<K>(a, (double)SEG);
+#pragma unroll
+    for (int r = 0; r <= K; ++r) a[r] += sums[0][sg][lane][r];
+  }
+  for (int sg = NSEG - 1; sg > seg; --sg) {
+    gwk::pascal_shift<K>(b, (double)SEG);
+#pragma unroll
+    for (int r = 0; r <= K; ++r) b[r] += sums[1][sg][lane][r];
+  }
+  seg_sweep<K>(x, a, b, out);
+  if constexpr (K == 0) {  // J: the entry itself belongs to the line sum
+#pragma unroll
+    for (int c = 0; c < SEG; ++c) out[c] += x[c];
+  }
+  __syncthreads();  // the summaries are read before the next line pass writes them
+}
+
+GW_DEV void img_line_m(int m, const double (&x)[SEG], double (&out)[SEG],
+                       double (*sums)[NSEG][TS][GW_KMAX + 1], int lane, int seg) {
+  switch (m) {
+    case 0: img_line<0>(x, out, sums, lane, seg); break;
+    case 1: img_line<1>(x, out, sums, lane, seg); break;
+    case 2: img_line<2>(x, out, sums, lane, seg); break;
+    case 3: img_line<3>(x, out, sums, lane, seg); break;
+    default: img_line<4>(x, out, sums, lane, seg); break;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_img_rowop(const double* __restrict__ in, int64_t ldi,
+                                                   int H, int W, ImgTerms terms,
+                                                   double* __restrict__ out, int64_t ldo) {
+  __shared__ double Y[TS][LDS_STRIDE];
+  __shared__ double sums[2][NSEG][TS][GW_KMAX + 1];
+  const int t = threadIdx.x, lane = t & (TS - 1), seg = __builtin_amdgcn_readfirstlane(t >> 6);
+  const int64_t row = blockIdx.x;
+  const double* src = in + row * ldi;
+  // the thread's row segment of the image: image row `lane`, columns seg*SEG + c
+  double xr[SEG];
+#pragma unroll
+  for (int c = 0; c < SEG; ++c) {
+    const int col = seg * SEG + c;
+    xr[c] = (lane < H && col < W) ? src[lane * W + col] : 0.0;
+  }
+  double acc[SEG];
+#pragma unroll
+  for (int i = 0; i < SEG; ++i) acc[i] = 0.0;
+  double o[SEG], x[SEG];
+  for (int tm = 0; tm < terms.n; ++tm) {
+    // along the image rows: Y[r][.] = (row r) D_W^{o mw}
+    img_line_m(terms.mw[tm], xr, o, sums, lane, seg);
+#pragma unroll
+    for (int c = 0; c < SEG; ++c) Y[lane][seg * SEG + c] = o[c];
+    __syncthreads();
+    // along the image columns: column `lane`, rows seg*SEG + i
+#pragma unroll
+    for (int i = 0; i < SEG; ++i) x[i] = Y[seg * SEG + i][lane];
+    img_line_m(terms.mh[tm], x, o, sums, lane, seg);
+    const double cf = (double)terms.coef[tm];
+#pragma unroll
+    for (int i = 0; i < SEG; ++i) acc[i] = fma(cf, o[i], acc[i]);
+  }
+  double* dst = out + row * ldo;
+#pragma unroll
+  for (int i = 0; i < SEG; ++i) {
+    const int r = seg * SEG + i;
+    if (r < H && lane < W) dst[r * W + lane] = acc[i];
+  }
+}
+
 }  // namespace
 
 namespace gwl {
@@ -857,6 +957,30 @@ gw_status fast1d(const gwr::Grid& X, const gwr::Grid& Y, const double* p, const 
     case 4: return dispatch_ky<4>(L.ky, L, T, ldT, G, ldG, c1, c2, s2, rm, cm, am, epi, s);
   }
   return GW_EUNSUPPORTED;
+}
+
+// The image operator on every row of `in` for a 2D grid of at most 64 x 64
+// points (GW_EUNSUPPORTED otherwise).
+gw_status img_rowop(const double* in, int64_t ldi, int64_t rows, const gwr::Grid& g,
+                    double* out, int64_t ldo, hipStream_t s) {
+  if (g.ndim != 2 || g.H > TS || g.W > TS) return GW_EUNSUPPORTED;
+  ImgTerms tm{};
+  if (g.metric == GW_METRIC_SQEUCLID) {
+    tm.n = 2;
+    tm.coef[0] = 1; tm.mh[0] = 2; tm.mw[0] = 0;
+    tm.coef[1] = 1; tm.mh[1] = 0; tm.mw[1] = 2;
+  } else {
+    tm.n = g.k + 1;
+    int cb = 1;  // C(k, r)
+    for (int r = 0; r <= g.k; ++r) {
+      tm.coef[r] = cb;
+      tm.mh[r] = g.k - r;
+      tm.mw[r] = r;
+      cb = cb * (g.k - r) / (r + 1);
+    }
+  }
+  k_img_rowop<<<(unsigned)rows, 256, 0, s>>>(in, ldi, (int)g.H, (int)g.W, tm, out, ldo);
+  return gwr::last_launch_status();
 }
 
 }  // namespace gwl

@@ -108,6 +108,9 @@ GRAD_2D = [
     ((33,), 1, 0, (5, 4), 2, 1),       # mixed 1D x 2D
     ((16, 16), 2, 1, (12, 20), 2, 1),  # SQEUCLID H != W
     ((4, 6), 4, 0, (5, 3), 4, 0),      # l1^4: nine separable constant-term terms
+    ((64, 64), 2, 0, (17, 40), 3, 0),  # l1^k image operator: a full 64 x 64 tile, a padded one
+    ((1, 50), 2, 0, (63, 1), 4, 0),    # image operator on one-line images
+    ((20, 64), 3, 0, (64, 9), 2, 0),   # image operator, H != W at the tile edge
     ((3, 70), 2, 1, (70, 2), 2, 1),    # SQEUCLID, image sides beyond one wave
 ]
 
@@ -328,3 +331,18 @@ def test_dense_low_precision_within_bound(n, k):
         assert e <= lp_bound(path, n)
     assert errs["dense_f32_split"] < errs["dense_f32"]
     assert errs["dense_bf16_split"] < errs["dense_bf16"]
+
+
+@pytest.mark.parametrize("sx,kx,sy,ky", [((10, 12), 2, (9, 7), 3), ((64, 5), 2, (8, 64), 2)])
+def test_grad_2d_image_operator_integer_bit_exact(sx, kx, sy, ky):
+    """(l1)^k image operator on integer inputs (h = 1): every intermediate is an
+    integer below 2^53, so the result equals the oracle's exactly."""
+    gw, torch = _gw()
+    X, Y = gw.Grid(sx, 1.0, kx), gw.Grid(sy, 1.0, ky)
+    rng = inputs.rng_for(209, X.size, Y.size)
+    T = inputs.integer_plan(X.size, Y.size, rng, hi=4)
+    p = rng.integers(0, 3, size=X.size).astype(np.float64)
+    q = rng.integers(0, 3, size=Y.size).astype(np.float64)
+    ref = O.grad_dense(ogrid(X), ogrid(Y), p, q, T)
+    assert np.max(np.abs(ref)) < 2.0 ** 53
+    assert np.array_equal(_grad(gw, torch, X, Y, p, q, T), ref)
