@@ -886,31 +886,102 @@ __global__ __launch_bounds__(256) void k_img_rowop(const double* __restrict__ in
                                                    double* __restrict__ out, int64_t ldo) {
   __shared__ double Y[TS][LDS_STRIDE];
   __shared__ double sums[2][NSEG][TS][GW_KMAX + 1];
+  __shared__ double vec[4][TS];  // row sums, column sums, D^m (row sums), (column sums) D^m
   const int t = threadIdx.x, lane = t & (TS - 1), seg = __builtin_amdgcn_readfirstlane(t >> 6);
   const int64_t row = blockIdx.x;
   const double* src = in + row * ldi;
-  // the thread's row segment of the image: image row `lane`, columns seg*SEG + c
+  // the image into LDS (zero padded to the tile; consecutive threads read
+  // consecutive entries of an image row), then the thread's row segment: image
+  // row `lane`, columns seg*SEG + c
+  {
+    // all loads issued before any is used (indices clamped into the image)
+    constexpr int PER = TS * TS / 256;
+    double v[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = t + 256 * u, r = e / TS, c = e % TS;
+      v[u] = src[min(r, H - 1) * W + min(c, W - 1)];
+    }
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = t + 256 * u, r = e / TS, c = e % TS;
+      Y[r][c] = (r < H && c < W) ? v[u] : 0.0;
+    }
+  }
+  __syncthreads();
   double xr[SEG];
 #pragma unroll
-  for (int c = 0; c < SEG; ++c) {
-    const int col = seg * SEG + c;
-    xr[c] = (lane < H && col < W) ? src[lane * W + col] : 0.0;
-  }
+  for (int c = 0; c < SEG; ++c) xr[c] = Y[lane][seg * SEG + c];
   double acc[SEG];
 #pragma unroll
   for (int i = 0; i < SEG; ++i) acc[i] = 0.0;
   double o[SEG], x[SEG];
+  // Terms with a J factor act on the image's line sums only:
+  //   D_H^{o m} X J = (D^{o m} X 1) 1^T,   J X D_W^{o m} = 1 (1^T X D^{o m}).
+  // Row and column sums first (segments, then the segments in order).
+  {
+    double rp = 0.0;
+#pragma unroll
+    for (int c = 0; c < SEG; ++c) rp += xr[c];
+    sums[0][seg][lane][0] = rp;
+    double cp = 0.0;
+#pragma unroll
+    for (int i = 0; i < SEG; ++i) cp += Y[seg * SEG + i][lane];
+    sums[1][seg][lane][0] = cp;
+    __syncthreads();
+    if (seg < 2) {
+      double v = sums[seg][0][lane][0];
+#pragma unroll
+      for (int sg = 1; sg < NSEG; ++sg) v += sums[seg][sg][lane][0];
+      vec[seg][lane] = v;
+    }
+    __syncthreads();
+  }
   for (int tm = 0; tm < terms.n; ++tm) {
-    // along the image rows: Y[r][.] = (row r) D_W^{o mw}
-    img_line_m(terms.mw[tm], xr, o, sums, lane, seg);
+    const int mh = terms.mh[tm], mw = terms.mw[tm];
+    const double cf = (double)terms.coef[tm];
+    if (mw == 0 || mh == 0) {
+      // one line operator on a vector of line sums: vec[2] = D^{mh} rowsums
+      // (mw = 0), vec[3] = colsums D^{mw} (mh = 0); then broadcast
+      const int m = mw == 0 ? mh : mw;
+      const int which = mw == 0 ? 0 : 1;
+      {
+        // output `lane`: thread (lane, seg) sums the segment's 16 sums, the
+        // segments are added in order
+        double v = 0.0;
+#pragma unroll
+        for (int jj = 0; jj < SEG; ++jj) {
+          const int j = seg * SEG + jj;
+          const int d = lane > j ? lane - j : j - lane;
+          double w = 1.0;
+          for (int u = 0; u < m; ++u) w *= (double)d;
+          v = fma(w, vec[which][j], v);
+        }
+        sums[0][seg][lane][0] = v;
+      }
+      __syncthreads();
+      if (seg == 0) {
+        double v = sums[0][0][lane][0];
+#pragma unroll
+        for (int sg = 1; sg < NSEG; ++sg) v += sums[0][sg][lane][0];
+        vec[2 + which][lane] = v;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < SEG; ++i)
+        acc[i] = fma(cf, which == 0 ? vec[2][seg * SEG + i] : vec[3][lane], acc[i]);
+      __syncthreads();  // vec[2 + which] is rewritten by the next such term
+      continue;
+    }
+    // cross terms: along the image rows: Y[r][.] = (row r) D_W^{o mw}
+    img_line_m(mw, xr, o, sums, lane, seg);
 #pragma unroll
     for (int c = 0; c < SEG; ++c) Y[lane][seg * SEG + c] = o[c];
     __syncthreads();
     // along the image columns: column `lane`, rows seg*SEG + i
 #pragma unroll
     for (int i = 0; i < SEG; ++i) x[i] = Y[seg * SEG + i][lane];
-    img_line_m(terms.mh[tm], x, o, sums, lane, seg);
-    const double cf = (double)terms.coef[tm];
+    img_line_m(mh, x, o, sums, lane, seg);
 #pragma unroll
     for (int i = 0; i < SEG; ++i) acc[i] = fma(cf, o[i], acc[i]);
   }
