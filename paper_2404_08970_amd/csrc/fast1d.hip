@@ -993,6 +993,108 @@ __global__ __launch_bounds__(256) void k_img_rowop(const double* __restrict__ in
   }
 }
 
+// ------------------------------------------------ 3D image operator
+// For 3D grids with every axis of at most SEG points: each row of `in` is a
+// Z x H x W array receiving sum_t coef_t (A_z^{a_t} (x) A_r^{b_t} (x) A_c^{c_t}) x,
+// A^{e} = [|i-j|^e] (A^0 = J), one multinomial term per (a, b, c) (squared
+// Euclidean: the three squared axes).  One block per row: the array and one
+// temporary in LDS (line stride W + 1); a thread per line loads the line (at
+// most SEG entries) into registers, applies the recursion of one segment with
+// zero carries and writes the line back (the second pass in place: the lines
+// of a pass are disjoint); the last axis' results are summed over the terms in
+// registers.
+struct Img3Terms {
+  int n;
+  int coef[15], ez[15], eh[15], ew[15];
+};
+
+template <int K>
+GW_DEV void line16(const double (&x)[SEG], double (&out)[SEG]) {
+  double a[K + 1], b[K + 1];
+#pragma unroll
+  for (int r = 0; r <= K; ++r) a[r] = b[r] = 0.0;
+  seg_sweep<K>(x, a, b, out);
+  if constexpr (K == 0) {  // J: the entry itself belongs to the line sum
+#pragma unroll
+    for (int c = 0; c < SEG; ++c) out[c] += x[c];
+  }
+}
+
+GW_DEV void line16_m(int m, const double (&x)[SEG], double (&out)[SEG]) {
+  switch (m) {
+    case 0: line16<0>(x, out); break;
+    case 1: line16<1>(x, out); break;
+    case 2: line16<2>(x, out); break;
+    case 3: line16<3>(x, out); break;
+    default: line16<4>(x, out); break;
+  }
+}
+
+constexpr int I3_NT = 256;
+
+__global__ __launch_bounds__(I3_NT) void k_img3_rowop(const double* __restrict__ in, int64_t ldi,
+                                                      int Z, int H, int W, Img3Terms terms,
+                                                      double* __restrict__ out, int64_t ldo) {
+  extern __shared__ double l3[];
+  const int Wp = W + 1, hwp = H * Wp, np = Z * hwp, hw = H * W, n = Z * hw;
+  double* xs = l3;
+  double* t1 = l3 + np;
+  const int tid = threadIdx.x;
+  const int64_t row = blockIdx.x;
+  const double* src = in + row * ldi;
+  for (int e = tid; e < n; e += I3_NT) {
+    const int z = e / hw, rem = e - z * hw, r = rem / W, c = rem - r * W;
+    xs[z * hwp + r * Wp + c] = src[e];
+  }
+  // the Z-line (r, c) = tid of the last pass is the thread's output (hw <= I3_NT)
+  double acc[SEG];
+#pragma unroll
+  for (int i = 0; i < SEG; ++i) acc[i] = 0.0;
+  double x[SEG], o[SEG];
+  __syncthreads();
+  for (int tm = 0; tm < terms.n; ++tm) {
+    // along W: the Z*H lines (z, r), contiguous
+    for (int l = tid; l < Z * H; l += I3_NT) {
+      const int base = (l / H) * hwp + (l % H) * Wp;
+#pragma unroll
+      for (int c = 0; c < SEG; ++c) x[c] = c < W ? xs[base + c] : 0.0;
+      line16_m(terms.ew[tm], x, o);
+#pragma unroll
+      for (int c = 0; c < SEG; ++c)
+        if (c < W) t1[base + c] = o[c];
+    }
+    __syncthreads();
+    // along H: the Z*W lines (z, c), stride W + 1
+    for (int l = tid; l < Z * W; l += I3_NT) {
+      const int base = (l / W) * hwp + (l % W);
+#pragma unroll
+      for (int r = 0; r < SEG; ++r) x[r] = r < H ? t1[base + r * Wp] : 0.0;
+      line16_m(terms.eh[tm], x, o);
+#pragma unroll
+      for (int r = 0; r < SEG; ++r)
+        if (r < H) t1[base + r * Wp] = o[r];
+    }
+    __syncthreads();
+    // along Z: the H*W lines (r, c), stride H (W + 1), summed over the terms
+    if (tid < hw) {
+      const int base = (tid / W) * Wp + (tid % W);
+#pragma unroll
+      for (int z = 0; z < SEG; ++z) x[z] = z < Z ? t1[base + z * hwp] : 0.0;
+      line16_m(terms.ez[tm], x, o);
+      const double cf = (double)terms.coef[tm];
+#pragma unroll
+      for (int z = 0; z < SEG; ++z) acc[z] = fma(cf, o[z], acc[z]);
+    }
+    __syncthreads();  // t1 is rewritten by the next term
+  }
+  if (tid < hw) {
+    double* dst = out + row * ldo;
+#pragma unroll
+    for (int z = 0; z < SEG; ++z)
+      if (z < Z) dst[z * hw + tid] = acc[z];
+  }
+}
+
 }  // namespace
 
 namespace gwl {
@@ -1051,6 +1153,46 @@ gw_status img_rowop(const double* in, int64_t ldi, int64_t rows, const gwr::Grid
     }
   }
   k_img_rowop<<<(unsigned)rows, 256, 0, s>>>(in, ldi, (int)g.H, (int)g.W, tm, out, ldo);
+  return gwr::last_launch_status();
+}
+
+// The 3D grid operator on every row of `in`, for arrays whose axes have at
+// most 16 points (GW_EUNSUPPORTED otherwise).
+gw_status img3_rowop(const double* in, int64_t ldi, int64_t rows, const gwr::Grid& g,
+                     double* out, int64_t ldo, hipStream_t s) {
+  if (g.ndim != 3 || g.Z > SEG || g.H > SEG || g.W > SEG) return GW_EUNSUPPORTED;
+  Img3Terms tm{};
+  if (g.metric == GW_METRIC_SQEUCLID) {
+    tm.n = 3;
+    for (int ax = 0; ax < 3; ++ax) {
+      tm.coef[ax] = 1;
+      tm.ez[ax] = ax == 0 ? 2 : 0;
+      tm.eh[ax] = ax == 1 ? 2 : 0;
+      tm.ew[ax] = ax == 2 ? 2 : 0;
+    }
+  } else {
+    int fact[GW_KMAX + 1];
+    fact[0] = 1;
+    for (int u = 1; u <= g.k; ++u) fact[u] = fact[u - 1] * u;
+    for (int a = 0; a <= g.k; ++a)
+      for (int b = 0; a + b <= g.k; ++b) {
+        tm.coef[tm.n] = fact[g.k] / (fact[a] * fact[b] * fact[g.k - a - b]);
+        tm.ez[tm.n] = a;
+        tm.eh[tm.n] = b;
+        tm.ew[tm.n] = g.k - a - b;
+        ++tm.n;
+      }
+  }
+  const size_t shm = 2 * (size_t)(g.Z * g.H * (g.W + 1)) * sizeof(double);
+  static bool set = false;  // dynamic LDS above the default, allowed once
+  if (!set) {
+    if (hipFuncSetAttribute(reinterpret_cast<const void*>(&k_img3_rowop),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) != hipSuccess)
+      return GW_EDEVICE;
+    set = true;
+  }
+  k_img3_rowop<<<(unsigned)rows, I3_NT, shm, s>>>(in, ldi, (int)g.Z, (int)g.H, (int)g.W, tm, out,
+                                                  ldo);
   return gwr::last_launch_status();
 }
 

@@ -1350,13 +1350,15 @@ gw_status fast_generic(const gwr::Grid& X, const gwr::Grid& Y, const double* p,
     return gwr::last_launch_status();
   }
   // generic: A = T D^_Y (rows), At = A^T, Bt = At D^_X (rows), G = epilogue(Bt^T)
-  // images of up to 64 x 64 points: the tile recursion (one block per row)
-  if (gwl::img_rowop(T, ldT, M, Y, A, N, s) == GW_EUNSUPPORTED)
+  // images of up to 64 x 64 points (3D: 16 per axis): the LDS kernels, one block per row
+  if (gwl::img_rowop(T, ldT, M, Y, A, N, s) == GW_EUNSUPPORTED &&
+      gwl::img3_rowop(T, ldT, M, Y, A, N, s) == GW_EUNSUPPORTED)
     k_rowop<<<(unsigned)M, NT, 0, s>>>(T, ldT, M, Y.ndim, Y.k, Y.metric, Y.Z, Y.H, Y.W, A, N, tmp,
                                        tmp2);
   dim3 tg1((unsigned)((N + 31) / 32), (unsigned)((M + 31) / 32));
   k_transpose<<<tg1, NT, 0, s>>>(A, N, M, N, At, M, nullptr, nullptr, 0.0);
-  if (gwl::img_rowop(At, M, N, X, A, M, s) == GW_EUNSUPPORTED)
+  if (gwl::img_rowop(At, M, N, X, A, M, s) == GW_EUNSUPPORTED &&
+      gwl::img3_rowop(At, M, N, X, A, M, s) == GW_EUNSUPPORTED)
     k_rowop<<<(unsigned)N, NT, 0, s>>>(At, M, N, X.ndim, X.k, X.metric, X.Z, X.H, X.W, A, M, tmp,
                                        tmp2);
   dim3 tg2((unsigned)((M + 31) / 32), (unsigned)((N + 31) / 32));

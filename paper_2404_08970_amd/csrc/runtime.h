@@ -169,6 +169,9 @@ size_t fast1d_ws_bytes(const gwr::Grid& X, const gwr::Grid& Y);
 // at most 64 x 64 points; GW_EUNSUPPORTED otherwise.
 gw_status img_rowop(const double* in, int64_t ldi, int64_t rows, const gwr::Grid& g,
                     double* out, int64_t ldo, hipStream_t s);
+// The same for 3D grids with every axis of at most 16 points.
+gw_status img3_rowop(const double* in, int64_t ldi, int64_t rows, const gwr::Grid& g,
+                     double* out, int64_t ldo, hipStream_t s);
 // Generic FAST gradient for 2D (and mixed 1D/2D) grids; epi as for fast1d.
 gw_status fast_generic(const gwr::Grid& X, const gwr::Grid& Y, const double* p,
                        const double* q, const double* T, int64_t ldT, double* G, int64_t ldG,

@@ -50,7 +50,7 @@ def test_grad_3d_integer_inputs_bit_exact(sx, sy, k, metric):
     assert np.array_equal(G.cpu().numpy(), ref)
 
 
-@pytest.mark.parametrize("metric,k", [(1, 2), (0, 1)])
+@pytest.mark.parametrize("metric,k", [(1, 2), (0, 1), (0, 2), (0, 3)])
 def test_grad_3d_16cube_sampled_rows(metric, k):
     """16 x 16 x 16 vs 16 x 16 x 16 (n = 4096): sampled rows against the
     oracle's row-wise definition."""
