@@ -34,8 +34,11 @@ def _case(gw, torch, seed, xshape, yshape, k, metric=0, ky=None):
     Y = gw.unit_grid(yshape, ky if ky is not None else k, metric)
 
     def marg(shape):
-        return inputs.gauss_mixture_1d(shape[0], rng) if len(shape) == 1 else \
-            inputs.blobs_2d(shape[0], shape[1], rng)
+        if len(shape) == 1:
+            return inputs.gauss_mixture_1d(shape[0], rng)
+        if len(shape) == 2:
+            return inputs.blobs_2d(shape[0], shape[1], rng)
+        return inputs.blobs_3d(*shape, rng, floor=1e-6)
     return X, Y, _dev(torch, marg(xshape)), _dev(torch, marg(yshape))
 
 
@@ -82,6 +85,9 @@ CLASS_CASES = [
     ((2500,), (2500,), 1, 0, 3e-3, 1, 5, False, False),
     ((96, 96), (96, 96), 2, 0, 4e-3, 1, 4, True, True),
     ((128, 128), (128, 128), 1, 0, 6e-3, 1, 3, False, False),
+    ((12, 12, 12), (10, 10, 10), 2, 1, 3e-3, 2, 5, False, True),  # 3D, axis-separable
+    ((8, 8, 8), (7, 9, 6), 2, 0, 5e-3, 2, 4, True, True),         # 3D (l1)^2, 3D image operator
+    ((40, 50), (64, 64), 2, 0, 4e-3, 2, 4, False, True),          # 2D (l1)^2, image operator
 ]
 
 
