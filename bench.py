@@ -14,7 +14,7 @@ solves (saturated throughput, then Poisson arrivals at 0.8x of it: p50/p99
 latency and solves/s).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-big]
-                       [--no-serve] [--serve-requests R] [--serve-only]
+                       [--no-serve] [--serve-requests R] [--serve-only] [--serve-boost B]
 """
 from __future__ import annotations
 
@@ -366,13 +366,15 @@ def precision_study(n: int = 16384, k: int = 2, rows: int = 6):
 
 
 def serve_bench(n_req: int = 200, slots: int = 32, iters: int = 10, load: float = 0.8,
-                arena_gb: float = 48.0, outer: int = 10, inner: int = 100):
+                arena_gb: float = 48.0, outer: int = 10, inner: int = 100, boost: int = 4):
     """Request loop on the serving stream: 70% 1D n ~ U{128..8192}, 30% 2D
     s ~ U{16..96} (L1POW), k ~ U{1,2}, eps ~ U[1e-3,1e-2], mixture / blob
     marginals, 10 outer x 100 Sinkhorn iterations each.  The `n_req` requests
     all submitted at t = 0 give the saturated rate; the same requests with
     Poisson arrivals at `load` x that rate give p50/p99 of completion minus
-    arrival.  Completion times come from each request's HIP completion event."""
+    arrival.  Completion times come from each request's HIP completion event.
+    Both are measured with equal iteration quotas and with size quotas
+    (`boost`), the Poisson runs on the same arrival times."""
     import numpy as np
     import torch
     from oracle import gw_oracle as O
@@ -418,6 +420,11 @@ def serve_bench(n_req: int = 200, slots: int = 32, iters: int = 10, load: float 
     rate = load * sat
     arr = np.array([r["arrival"] for r in reqs])
     arr = (arr - arr[0]) / rate
+    lat_eq, fin_eq, steps_eq = run(dreqs, arr.tolist(), outer, inner)
+    sv.set_boost(boost)
+    run(dreqs[:24], [0.0] * 24, 1, iters)
+    torch.cuda.synchronize()
+    lat_satb, fin_satb, _ = run(dreqs, [0.0] * n_req, outer, inner)
     lat, fin, steps = run(dreqs, arr.tolist(), outer, inner)
 
     # accuracy: the smallest 1D request of the stream against the oracle (the
@@ -439,14 +446,23 @@ def serve_bench(n_req: int = 200, slots: int = 32, iters: int = 10, load: float 
         "workload": (f"{n_req} requests, Poisson arrivals at {load}x the saturated rate; "
                      f"{n1} 1D n~U{{128..8192}}, {n_req - n1} 2D s~U{{16..96}} (L1POW); "
                      f"k~U{{1,2}}, eps~U[1e-3,1e-2]; {outer} outer x {inner} Sinkhorn iterations"),
-        "saturated_solves_per_s": round(sat, 2),
-        "saturated_p50_ms": round(float(np.percentile(lat_sat, 50)) * 1e3, 1),
+        "size_quota_boost": boost,
+        "saturated_solves_per_s": round(n_req / float(fin_satb.max()), 2),
+        "saturated_p50_ms": round(float(np.percentile(lat_satb, 50)) * 1e3, 1),
         "offered_rate_per_s": round(rate, 2),
         "solves_per_s": round(n_req / float(fin.max()), 2),
         "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 1),
         "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 1),
         "mean_ms": round(float(lat.mean()) * 1e3, 1),
         "steps": steps,
+        "equal_quotas": {
+            "saturated_solves_per_s": round(sat, 2),
+            "saturated_p50_ms": round(float(np.percentile(lat_sat, 50)) * 1e3, 1),
+            "solves_per_s": round(n_req / float(fin_eq.max()), 2),
+            "p50_ms": round(float(np.percentile(lat_eq, 50)) * 1e3, 1),
+            "p99_ms": round(float(np.percentile(lat_eq, 99)) * 1e3, 1),
+            "mean_ms": round(float(lat_eq.mean()) * 1e3, 1),
+            "steps": steps_eq},
         "max_slots": slots, "iters_per_step": iters, "arena_GB": arena_gb,
         "accuracy": {"request_n": reqs[ic]["shape"][0], "k": X.k, "eps": round(eps, 6),
                      "rel_err_T_vs_oracle": acc,
@@ -481,6 +497,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--serve-slots", type=int, default=32)
     ap.add_argument("--serve-iters", type=int, default=10)
+    ap.add_argument("--serve-boost", type=int, default=4,
+                    help="size quotas of the request loop (1 = equal quotas)")
     args = ap.parse_args()
     if args.precision:
         print(json.dumps(precision_study()))
@@ -501,7 +519,7 @@ def main():
         print(json.dumps(grid2d_bench()))
         return
     if args.serve_only:
-        print(json.dumps(serve_bench(args.serve_requests, args.serve_slots, args.serve_iters)))
+        print(json.dumps(serve_bench(args.serve_requests, args.serve_slots, args.serve_iters, boost=args.serve_boost)))
         return
     if args.profile_target:
         profile_target(args.profile_target, args.reps)
@@ -622,7 +640,7 @@ def main():
     stopped = None if args.no_tol else tolerance_bench()
     serving = None
     if not args.no_serve:
-        serving = serve_bench(args.serve_requests, args.serve_slots, args.serve_iters)
+        serving = serve_bench(args.serve_requests, args.serve_slots, args.serve_iters, boost=args.serve_boost)
 
     out = {
         "metric": METRIC,

@@ -267,7 +267,8 @@ gw_status gw_objective_fgw(const gw_grid* X, const gw_grid* Y, const double* T, 
  *   2. for each request at the start of an outer iteration: its gradient and
  *      Sinkhorn set-up (per-request launches);
  *   3. one replay of a captured HIP graph that runs `iters_per_step` Sinkhorn
- *      iterations of every request in its Sinkhorn phase: persistent batched
+ *      iterations of every request in its Sinkhorn phase (a multiple of it for
+ *      small requests under size quotas, gw_server_set_boost): persistent batched
  *      kernels read a device work table (per request: sizes, pointers and
  *      how many of the step's iterations it takes) that the host rewrites
  *      between replays, so request shapes are data, not launch shapes;
@@ -338,6 +339,19 @@ size_t gw_server_table_bytes(int32_t max_slots);
  * device memory.  stream: the hipStream_t all work goes to. */
 gw_status gw_server_create(void* arena, size_t arena_bytes, int32_t max_slots,
                            int32_t iters_per_step, void* stream, gw_server** out);
+
+/* Size-aware iteration quotas (a scheduling policy of the request loop, not
+ * an operation of the paper).  With max_boost b > 1 (1, 2, 4 or 8), a request
+ * in its Sinkhorn phase whose problem has at most M N / 2^m entries, where
+ * M N is the largest among the requests in their Sinkhorn phase in that
+ * step, takes 2^m iters_per_step iterations in the step (2^m <= b); the
+ * largest take iters_per_step.  Small requests finish in fewer steps while
+ * the step time grows only by their extra (small) work.  Results do not
+ * change: every request still runs its iterations in order with the same
+ * arithmetic.  Default 1 (every request takes iters_per_step).  GW_EINVAL if
+ * b is not one of 1, 2, 4, 8 or iters_per_step * b > 1000.  Host-only; may be
+ * called between steps. */
+gw_status gw_server_set_boost(gw_server* sv, int32_t max_boost);
 
 /* Queue a request; *id receives its handle.  GW_ENOMEM if its footprint can
  * never fit the arena.  Nothing is launched. */

@@ -31,6 +31,10 @@ enum Phase { kQueued, kGrad, kSink, kDone };
 
 constexpr int kMaxSlots = 4096;
 constexpr int kMaxItersPerStep = 1000;
+constexpr int kMaxBoost = 8;
+constexpr int kLevels = 4;  // iteration ranges of a step: [0, S), [S, 2S), [2S, 4S), [4S, 8S)
+static_assert(kLevels * gwb::kNumRowCls <= 64, "graph key holds a class mask per range");
+static_assert(kMaxBoost == 1 << (kLevels - 1), "one iteration range per doubling");
 constexpr int64_t kMaxRows = 65535;
 constexpr int64_t kMaxCols = 16384;
 
@@ -140,6 +144,7 @@ struct gw_server {
   TableLayout L{};
   RangeAllocator alloc;
   int max_slots = 0, S = 0;
+  int boost = 1;  // largest iteration share of a small request (power of two, <= kMaxBoost)
   std::vector<int> free_slots;
   std::deque<int64_t> queue;
   std::map<int64_t, Req> reqs;
@@ -147,7 +152,7 @@ struct gw_server {
   char* h_stage[2] = {nullptr, nullptr};
   hipEvent_t stage_ev[2] = {nullptr, nullptr};
   bool stage_used[2] = {false, false};
-  std::map<uint32_t, hipGraphExec_t> graphs;
+  std::map<uint64_t, hipGraphExec_t> graphs;  // by the class masks of the step's iteration ranges
   std::vector<uint32_t> lists[gwb::kNumLists];
   std::vector<HostRecord*> rec_free;
   std::vector<void*> rec_chunks;
@@ -243,8 +248,17 @@ gw_status admit(gw_server* sv, Req& q) {
   return GW_OK;
 }
 
-gw_status graph_for(gw_server* sv, uint32_t mask, hipGraphExec_t* out) {
-  auto it = sv->graphs.find(mask);
+// Row classes launched in iteration range l of a step (see kLevels), packed
+// 11 bits per range: the ranges are nested (a request that takes iterations
+// of range l takes every earlier one), so the first empty range ends the step.
+uint32_t level_mask(uint64_t key, int l) {
+  return (uint32_t)(key >> (l * gwb::kNumRowCls)) & ((1u << gwb::kNumRowCls) - 1u);
+}
+
+int level_start(int S, int l) { return l == 0 ? 0 : S << (l - 1); }
+
+gw_status graph_for(gw_server* sv, uint64_t key, hipGraphExec_t* out) {
+  auto it = sv->graphs.find(key);
   if (it != sv->graphs.end()) {
     *out = it->second;
     return GW_OK;
@@ -255,10 +269,14 @@ gw_status graph_for(gw_server* sv, uint32_t mask, hipGraphExec_t* out) {
   if (hipStreamBeginCapture(sv->cap, hipStreamCaptureModeThreadLocal) != hipSuccess)
     return GW_EDEVICE;
   gw_status st = GW_OK;
-  for (int j = 0; j < sv->S && st == GW_OK; ++j) {
-    for (int c = 0; c < gwb::kNumRowCls && st == GW_OK; ++c)
-      if (mask & (1u << c)) st = gwl::sk_batch_launch(c, j, slots, head, items, sv->cap);
-    if (st == GW_OK) st = gwl::sk_batch_launch(gwb::kClsCol, j, slots, head, items, sv->cap);
+  for (int l = 0; l < kLevels && st == GW_OK; ++l) {
+    const uint32_t mask = level_mask(key, l);
+    if (!mask) break;
+    for (int j = level_start(sv->S, l); j < level_start(sv->S, l + 1) && st == GW_OK; ++j) {
+      for (int c = 0; c < gwb::kNumRowCls && st == GW_OK; ++c)
+        if (mask & (1u << c)) st = gwl::sk_batch_launch(c, j, slots, head, items, sv->cap);
+      if (st == GW_OK) st = gwl::sk_batch_launch(gwb::kClsCol, j, slots, head, items, sv->cap);
+    }
   }
   hipGraph_t g = nullptr;
   const hipError_t ec = hipStreamEndCapture(sv->cap, &g);
@@ -270,22 +288,37 @@ gw_status graph_for(gw_server* sv, uint32_t mask, hipGraphExec_t* out) {
   const hipError_t ei = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
   (void)hipGraphDestroy(g);
   if (ei != hipSuccess) return GW_EDEVICE;
-  sv->graphs[mask] = exec;
+  sv->graphs[key] = exec;
   *out = exec;
   return GW_OK;
 }
 
+// Iterations a request in its Sinkhorn phase takes in a step: S, or with size
+// quotas b S for the largest power of two b <= boost with b M N at most the
+// largest M N in the Sinkhorn phase (never more than the call has left).
+int step_quota(const gw_server* sv, const Req& q, int64_t wmax) {
+  int b = 1;
+  while (b < sv->boost && 2 * b * (q.M * q.N) <= wmax) b *= 2;
+  const int quota = b * sv->S;
+  return q.inner_left < quota ? q.inner_left : quota;
+}
+
 // Write the work table for the requests in their Sinkhorn phase into the
-// staging buffer; returns the class mask (0: nothing to run) and the bytes to
-// upload.
-uint32_t build_table(gw_server* sv, char* stage, size_t* upload) {
+// staging buffer; returns the graph key (the class masks of the iteration
+// ranges, 0: nothing to run) and the bytes to upload.
+uint64_t build_table(gw_server* sv, char* stage, size_t* upload) {
   for (auto& l : sv->lists) l.clear();
   auto* slots = reinterpret_cast<gwb::SkSlot*>(stage + sv->L.slots);
-  uint32_t mask = 0;
+  int64_t wmax = 0;
+  for (int64_t id : sv->running) {
+    const Req& q = sv->reqs[id];
+    if (q.phase == kSink && q.M * q.N > wmax) wmax = q.M * q.N;
+  }
+  uint64_t key = 0;
   for (int64_t id : sv->running) {
     Req& q = sv->reqs[id];
     if (q.phase != kSink) continue;
-    q.its = q.inner_left < sv->S ? q.inner_left : sv->S;
+    q.its = step_quota(sv, q, wmax);
     gwb::SkSlot& d = slots[q.slot];
     d.C = q.G;
     d.ldC = q.N;
@@ -309,11 +342,12 @@ uint32_t build_table(gw_server* sv, char* stage, size_t* upload) {
     d.RB = q.rb;
     d.nb = q.nb;
     d.its = q.its;
-    d.last = q.inner_left <= sv->S ? 1 : 0;
+    d.last = q.inner_left == q.its ? 1 : 0;
     d.it0 = q.r.inner - q.inner_left;
     d.pad = 0;
     const int cls = gwb::row_class(q.N);
-    mask |= 1u << cls;
+    for (int l = 0; l < kLevels; ++l)
+      if (q.its > level_start(sv->S, l)) key |= (uint64_t)(1u << cls) << (l * gwb::kNumRowCls);
     for (int b = 0; b < q.nb; ++b)
       sv->lists[cls].push_back(((uint32_t)q.slot << gwb::kBandBits) | (uint32_t)b);
     const int ncb = (int)((q.N + gwb::kMergeCols - 1) / gwb::kMergeCols);
@@ -329,7 +363,7 @@ uint32_t build_table(gw_server* sv, char* stage, size_t* upload) {
     for (uint32_t v : sv->lists[c]) items[n++] = v;
   }
   *upload = sv->L.items + n * sizeof(uint32_t);
-  return mask;
+  return key;
 }
 
 gw_status step(gw_server* sv, int32_t* active, int32_t* queued) {
@@ -356,10 +390,10 @@ gw_status step(gw_server* sv, int32_t* active, int32_t* queued) {
   }
   // 3. the batched Sinkhorn iterations
   size_t upload = 0;
-  const uint32_t mask = build_table(sv, sv->h_stage[b], &upload);
-  if (mask) {
+  const uint64_t key = build_table(sv, sv->h_stage[b], &upload);
+  if (key) {
     hipGraphExec_t exec = nullptr;
-    if ((st = graph_for(sv, mask, &exec)) != GW_OK) return st;
+    if ((st = graph_for(sv, key, &exec)) != GW_OK) return st;
     if ((st = hip_ok(hipMemcpyAsync(sv->arena, sv->h_stage[b], upload, hipMemcpyHostToDevice,
                                     sv->s))) != GW_OK)
       return st;
@@ -438,6 +472,14 @@ gw_status gw_server_create(void* arena, size_t arena_bytes, int32_t max_slots,
   }
   sv->ready = true;
   *out = sv;
+  return GW_OK;
+}
+
+gw_status gw_server_set_boost(gw_server* sv, int32_t max_boost) {
+  if (!sv) return GW_EINVAL;
+  if (max_boost < 1 || max_boost > kMaxBoost || (max_boost & (max_boost - 1))) return GW_EINVAL;
+  if ((int64_t)sv->S * max_boost > kMaxItersPerStep) return GW_EINVAL;
+  sv->boost = max_boost;
   return GW_OK;
 }
 

@@ -122,6 +122,8 @@ def _lib():
     lib.gw_server_table_bytes.restype = SZ
     lib.gw_server_create.argtypes = [P, SZ, I32, I32, P, PS]
     lib.gw_server_create.restype = I32
+    lib.gw_server_set_boost.argtypes = [P, I32]
+    lib.gw_server_set_boost.restype = I32
     lib.gw_server_submit.argtypes = [P, R, ctypes.POINTER(I64)]
     lib.gw_server_submit.restype = I32
     lib.gw_server_step.argtypes = [P, ctypes.POINTER(I32), ctypes.POINTER(I32)]
@@ -557,7 +559,7 @@ class Server:
     alive here until release."""
 
     def __init__(self, arena_bytes: int, max_slots: int = 64, iters_per_step: int = 10,
-                 device=None, stream=None):
+                 device=None, stream=None, boost: int = 1):
         dev = torch.device("cuda") if device is None else torch.device(device)
         self.device = dev
         self._arena = torch.empty(int(arena_bytes) + 256, dtype=torch.uint8, device=dev)
@@ -572,6 +574,14 @@ class Server:
         self.t0 = time.perf_counter()
         self._h = h
         self._keep = {}
+        if boost != 1:
+            self.set_boost(boost)
+
+    def set_boost(self, max_boost: int):
+        """Size-aware iteration quotas: a request with at most 1/2^m of the
+        largest Sinkhorn-phase problem's entries takes 2^m x iters_per_step
+        iterations per step (2^m <= max_boost in {1, 2, 4, 8})."""
+        _raise(_lib().gw_server_set_boost(self._h, int(max_boost)), "gw_server_set_boost")
 
     def submit(self, X: Grid, Y: Grid, p, q, eps: float, outer: int, inner: int,
                warm: bool = False, objective: bool = False) -> int:

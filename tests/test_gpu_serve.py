@@ -160,6 +160,50 @@ def test_mix_equals_alone():
     sv.close()
 
 
+def test_size_quotas_keep_results():
+    """Size quotas (boost 8, 3 iterations per step): requests with at most
+    1/2, 1/4, 1/8 of the largest problem take 6, 12, 24 iterations a step,
+    calls whose remainder is below the quota take the remainder; every result
+    is still gw_solve's bits, and the smallest request needs fewer steps than
+    the largest."""
+    gw, torch = _gw()
+    specs = [((4000,), 1, 2e-3, 2, 23, False, True), ((128,), 2, 5e-3, 3, 23, True, True),
+             ((30, 30), 1, 4e-3, 2, 17, False, False), ((1000,), 2, 3e-3, 2, 23, False, True),
+             ((2000,), 1, 6e-3, 1, 9, True, False), ((2900,), 2, 2e-3, 1, 14, False, False)]
+    cases, refs = [], []
+    for i, (shape, k, eps, outer, inner, warm, obj) in enumerate(specs):
+        X, Y, p, q = _case(gw, torch, 950 + i, shape, shape, k)
+        cases.append((X, Y, p, q, eps, outer, inner, warm, obj))
+        refs.append(_reference(gw, torch, X, Y, p, q, eps, outer, inner, warm, obj))
+    sv = gw.Server(6 * GB, max_slots=8, iters_per_step=3, boost=8)
+    ids = [sv.submit(X, Y, p, q, eps, outer, inner, warm=warm, objective=obj)
+           for X, Y, p, q, eps, outer, inner, warm, obj in cases]
+    finished = {}
+    for n in range(1, 10000):
+        sv.step()
+        for rid in ids:
+            if rid not in finished and sv.poll(rid) == 2:
+                finished[rid] = n
+        if len(finished) == len(ids):
+            break
+    for rid, ref, c in zip(ids, refs, cases):
+        print(f"quota request {rid} shape={c[0].shape} finished at step {finished[rid]}", flush=True)
+        _assert_same(torch, sv.result(rid), ref, c[8])
+    assert finished[ids[1]] < finished[ids[0]]
+    for b in (0, 3, 16, -2):
+        with pytest.raises(gw.GWError):
+            sv.set_boost(b)
+    sv.set_boost(1)
+    for rid in ids:
+        sv.release(rid)
+    sv.close()
+    sv2 = gw.Server(gw.server_table_bytes(1) + 4096, max_slots=1, iters_per_step=200)
+    sv2.set_boost(4)
+    with pytest.raises(gw.GWError):
+        sv2.set_boost(8)       # 200 x 8 iterations exceed a step's 1000
+    sv2.close()
+
+
 def test_admission_by_footprint():
     gw, torch = _gw()
     X, Y, p, q = _case(gw, torch, 31, (1000,), (1000,), 2)

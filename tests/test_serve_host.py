@@ -179,6 +179,7 @@ def test_server_calls_reject_null_handle():
     r = gw.make_request(X, X, None, None, 1e-2, 1, 1)
     assert lib.gw_server_submit(None, ctypes.byref(r), ctypes.byref(rid)) == gw.GW_EINVAL
     assert lib.gw_server_step(None, None, None) == gw.GW_EINVAL
+    assert lib.gw_server_set_boost(None, 2) == gw.GW_EINVAL
     assert lib.gw_server_poll(None, 1, ctypes.byref(s)) == gw.GW_EINVAL
     assert lib.gw_server_result(None, 1, ctypes.byref(res)) == gw.GW_EINVAL
     assert lib.gw_server_release(None, 1) == gw.GW_EINVAL
