@@ -32,6 +32,7 @@ enum Phase { kQueued, kGrad, kSink, kDone };
 constexpr int kMaxSlots = 4096;
 constexpr int kMaxItersPerStep = 1000;
 constexpr int kMaxBoost = 8;
+constexpr size_t kMaxGraphs = 256;  // step graphs kept; least recently used ones go first
 constexpr int kLevels = 4;  // iteration ranges of a step: [0, S), [S, 2S), [2S, 4S), [4S, 8S)
 static_assert(kLevels * gwb::kNumRowCls <= 64, "graph key holds a class mask per range");
 static_assert(kMaxBoost == 1 << (kLevels - 1), "one iteration range per doubling");
@@ -152,7 +153,11 @@ struct gw_server {
   char* h_stage[2] = {nullptr, nullptr};
   hipEvent_t stage_ev[2] = {nullptr, nullptr};
   bool stage_used[2] = {false, false};
-  std::map<uint64_t, hipGraphExec_t> graphs;  // by the class masks of the step's iteration ranges
+  struct CachedGraph {
+    hipGraphExec_t exec;
+    int64_t last_step;  // step whose replay used it last
+  };
+  std::map<uint64_t, CachedGraph> graphs;  // by the class masks of the step's iteration ranges
   std::vector<uint32_t> lists[gwb::kNumLists];
   std::vector<HostRecord*> rec_free;
   std::vector<void*> rec_chunks;
@@ -257,12 +262,27 @@ uint32_t level_mask(uint64_t key, int l) {
 
 int level_start(int S, int l) { return l == 0 ? 0 : S << (l - 1); }
 
+// Destroy the least recently used graph if it last ran two or more steps ago
+// (the step's wait on its staging event has then seen that replay finish).
+void evict_graph(gw_server* sv) {
+  auto victim = sv->graphs.end();
+  for (auto it = sv->graphs.begin(); it != sv->graphs.end(); ++it)
+    if (it->second.last_step <= sv->steps - 2 &&
+        (victim == sv->graphs.end() || it->second.last_step < victim->second.last_step))
+      victim = it;
+  if (victim == sv->graphs.end()) return;
+  (void)hipGraphExecDestroy(victim->second.exec);
+  sv->graphs.erase(victim);
+}
+
 gw_status graph_for(gw_server* sv, uint64_t key, hipGraphExec_t* out) {
   auto it = sv->graphs.find(key);
   if (it != sv->graphs.end()) {
-    *out = it->second;
+    it->second.last_step = sv->steps;
+    *out = it->second.exec;
     return GW_OK;
   }
+  if (sv->graphs.size() >= kMaxGraphs) evict_graph(sv);
   const gwb::SkTableHead* head = reinterpret_cast<const gwb::SkTableHead*>(sv->arena + sv->L.head);
   const gwb::SkSlot* slots = reinterpret_cast<const gwb::SkSlot*>(sv->arena + sv->L.slots);
   const uint32_t* items = reinterpret_cast<const uint32_t*>(sv->arena + sv->L.items);
@@ -288,7 +308,7 @@ gw_status graph_for(gw_server* sv, uint64_t key, hipGraphExec_t* out) {
   const hipError_t ei = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
   (void)hipGraphDestroy(g);
   if (ei != hipSuccess) return GW_EDEVICE;
-  sv->graphs[key] = exec;
+  sv->graphs[key] = {exec, sv->steps};
   *out = exec;
   return GW_OK;
 }
@@ -568,7 +588,7 @@ gw_status gw_server_destroy(gw_server* sv) {
   if (sv->ready) st = hip_ok(hipStreamSynchronize(sv->s));
   for (auto& kv : sv->reqs)
     if (kv.second.done) (void)hipEventDestroy(kv.second.done);
-  for (auto& kv : sv->graphs) (void)hipGraphExecDestroy(kv.second);
+  for (auto& kv : sv->graphs) (void)hipGraphExecDestroy(kv.second.exec);
   for (int i = 0; i < 2; ++i) {
     if (sv->h_stage[i]) (void)hipHostFree(sv->h_stage[i]);
     if (sv->stage_ev[i]) (void)hipEventDestroy(sv->stage_ev[i]);
