@@ -119,8 +119,11 @@ GW_DEV __amdgpu_buffer_rsrc_t buffer_rsrc(const void* base) {
                                            0x00020000);
 }
 
+// AUX: cache policy bits of the store (0 default; 2 non-temporal, for output
+// that is streamed out and not read back soon).
+template <int AUX = 0>
 GW_DEV void buffer_store_f64(double v, __amdgpu_buffer_rsrc_t r, int byte_off) {
-  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, v), r, byte_off, 0, 0);
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, v), r, byte_off, 0, AUX);
 }
 
 }  // namespace gwk

@@ -592,7 +592,8 @@ __global__ __launch_bounds__(256) void k_p2c(int N, int nJ, const double* __rest
 // row segment; segment summaries pass through LDS and are combined with the
 // tile's row carries, and A overwrites T in LDS.  Column phase: thread
 // (column = lane, seg = wave) does the same along the column with A's column
-// carries, and writes G = (c1 + c2) - s2 B from registers.  With FG the
+// carries, and writes G = (c1 + c2) - s2 B from registers (non-temporal
+// stores: G is streamed out, not read back by this gradient).  With FG the
 // fused GW feature term is applied on the way out:
 // G = ea ((c1 + c2) - s2 B) + eb (fa_i - fb_p)^2.
 template <int KX, int KY, bool FG>
@@ -723,7 +724,7 @@ __global__ __launch_bounds__(256) void k_p3_tile(const double* __restrict__ T, i
         const double d = epi.fa[row] - fbv;
         v = fma(epi.a, v, epi.b * (d * d));
       }
-      gwk::buffer_store_f64(v, gwk::buffer_rsrc(G + (int64_t)row * ldG + qs),
+      gwk::buffer_store_f64<2>(v, gwk::buffer_rsrc(G + (int64_t)row * ldG + qs),
                             (r < h && lane < w) ? lane * 8 : gwk::kOffDrop);
     }
     __syncthreads();
