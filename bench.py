@@ -387,7 +387,10 @@ def serve_bench(n_req: int = 200, slots: int = 32, iters: int = 10, load: float 
         dreqs.append((X, torch.tensor(r["p"], device=dev), torch.tensor(r["q"], device=dev), r["eps"]))
     sv = gw.Server(int(arena_gb * GB), max_slots=slots, iters_per_step=iters)
 
-    def run(batch, arrivals, n_outer, n_inner):
+    def run(batch, arrivals, n_outer, n_inner, label=""):
+        # long streams report every 100 finished requests (stderr), so a
+        # multi-minute run shows its progress
+        report = len(batch) >= 500
         t_start = time.perf_counter()
         nxt, live, lat, fin = 0, {}, [], []
         steps = 0
@@ -410,22 +413,25 @@ def serve_bench(n_req: int = 200, slots: int = 32, iters: int = 10, load: float 
                     lat.append(res["done_t"] - (t_start + live.pop(rid)))
                     fin.append(res["done_t"] - t_start)
                     sv.release(rid)
+                    if report and len(lat) % 100 == 0:
+                        print(f"serve {label}: {len(lat)}/{len(batch)} done", file=sys.stderr,
+                              flush=True)
         return np.array(lat), np.array(fin), steps
 
     # warm-up (not timed): one short solve of each request shape class in the stream
     run(dreqs[:24], [0.0] * 24, 1, iters)
     torch.cuda.synchronize()
-    lat_sat, fin_sat, steps_sat = run(dreqs, [0.0] * n_req, outer, inner)
+    lat_sat, fin_sat, steps_sat = run(dreqs, [0.0] * n_req, outer, inner, "saturated, equal quotas")
     sat = n_req / float(fin_sat.max())
     rate = load * sat
     arr = np.array([r["arrival"] for r in reqs])
     arr = (arr - arr[0]) / rate
-    lat_eq, fin_eq, steps_eq = run(dreqs, arr.tolist(), outer, inner)
+    lat_eq, fin_eq, steps_eq = run(dreqs, arr.tolist(), outer, inner, "Poisson, equal quotas")
     sv.set_boost(boost)
     run(dreqs[:24], [0.0] * 24, 1, iters)
     torch.cuda.synchronize()
-    lat_satb, fin_satb, _ = run(dreqs, [0.0] * n_req, outer, inner)
-    lat, fin, steps = run(dreqs, arr.tolist(), outer, inner)
+    lat_satb, fin_satb, _ = run(dreqs, [0.0] * n_req, outer, inner, "saturated, size quotas")
+    lat, fin, steps = run(dreqs, arr.tolist(), outer, inner, "Poisson, size quotas")
 
     # accuracy: the smallest 1D request of the stream against the oracle (the
     # result of a request is the same in any mix, so it is solved alone here)
@@ -628,9 +634,20 @@ def main():
         wsb = gw.workspace(gw.workspace_bytes(Xb, Xb, gw.PATH_DENSE_F64, gw.OP_GRAD), dev, key="big")
         fast_ms = time_gpu(lambda: gw.grad(Xb, Xb, pb, pb, Tb, path="fast", out=Gb, ws=wsb), 10, torch)
         dense_ms = time_gpu(lambda: gw.grad(Xb, Xb, pb, pb, Tb, path="dense", out=Gb, ws=wsb), 1, torch)
+        gw.profile_enable([gw.FAM_FAST_MAIN, gw.FAM_FAST_CARRY])
+        gw.grad(Xb, Xb, pb, pb, Tb, path="fast", out=Gb, ws=wsb)
+        torch.cuda.synchronize()
+        main_ms, _ = gw.profile_read(gw.FAM_FAST_MAIN)
+        carry_ms, _ = gw.profile_read(gw.FAM_FAST_CARRY)
+        gw.profile_enable([])
+        tile_gbs = 16.0 * nb * nb / (main_ms * 1e-3) / 1e9  # one read of T, one write of G
         big = {"n": nb, "k": 2, "fast_ms": round(fast_ms, 3), "dense_f64_ms": round(dense_ms, 1),
                "speedup": round(dense_ms / fast_ms, 1), "target_speedup": nb / 64,
-               "fast_GBps_at_24B_per_entry": round(24.0 * nb * nb / (fast_ms * 1e-3) / 1e9, 1)}
+               "fast_GBps_at_24B_per_entry": round(24.0 * nb * nb / (fast_ms * 1e-3) / 1e9, 1),
+               "fast_tile_kernel_ms": round(main_ms, 3),
+               "fast_tile_kernel_GBps_at_16B_per_entry": round(tile_gbs, 1),
+               "fast_tile_kernel_hbm_frac": round(tile_gbs / HBM_PEAK_GBS, 4),
+               "fast_moment_kernels_ms": round(carry_ms, 3)}
         del Tb, Gb, wsb
 
     grid2d = None if args.no_2d else grid2d_bench()
