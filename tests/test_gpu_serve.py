@@ -204,6 +204,39 @@ def test_size_quotas_keep_results():
     sv2.close()
 
 
+def test_graph_cache_eviction_keeps_results():
+    """More distinct step graphs than the server keeps (256): each step runs a
+    different set of row-length classes (pairs, triples and quadruples of the
+    11 classes, one 2 x N request per class), so the least recently used
+    graphs are destroyed and, when a class set comes back, captured again.
+    Every result equals the request's gw_solve bit for bit."""
+    import itertools
+    gw, torch = _gw()
+    Ns = [200, 400, 900, 1800, 2900, 3900, 5000, 7000, 9000, 11000, 15000]  # one per class
+    X = gw.unit_grid((2,), 1)
+    p = torch.tensor([0.3, 0.7], dtype=torch.float64, device="cuda")
+    rng = inputs.rng_for(960)
+    cls = []
+    for n in Ns:
+        Y = gw.unit_grid((n,), 2)
+        q = _dev(torch, inputs.gauss_mixture_1d(n, rng))
+        cls.append((Y, q, _reference(gw, torch, X, Y, p, q, 4e-3, 1, 3, False, False)))
+    subsets = (list(itertools.combinations(range(11), 2)) +
+               list(itertools.combinations(range(11), 3)) +
+               list(itertools.combinations(range(11), 4))[:60])
+    assert len(subsets) > 256
+    sv = gw.Server(GB, max_slots=8, iters_per_step=3)
+    for n_set, sub in enumerate(subsets + subsets[:5]):  # the first sets again, after eviction
+        ids = [sv.submit(X, cls[c][0], p, cls[c][1], 4e-3, 1, 3) for c in sub]
+        done = _run_until_done(sv, ids)
+        for rid, c in zip(ids, sub):
+            _assert_same(torch, done[rid], cls[c][2], False)
+            sv.release(rid)
+        if n_set % 50 == 0:
+            print(f"class set {n_set}: {sub}", flush=True)
+    sv.close()
+
+
 def test_admission_by_footprint():
     gw, torch = _gw()
     X, Y, p, q = _case(gw, torch, 31, (1000,), (1000,), 2)
