@@ -3,7 +3,9 @@
 #include <math.h>
 #include <string.h>
 
+#include <map>
 #include <mutex>
+#include <utility>
 #include <vector>
 
 #include "runtime.h"
@@ -11,6 +13,21 @@
 namespace gwr {
 
 static const int64_t kMaxExtent = 65535;
+
+gw_status allow_dyn_lds(const void* kernel, size_t bytes) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return GW_EDEVICE;
+  static std::mutex mu;
+  static std::map<std::pair<int, const void*>, size_t> set;  // largest size set so far
+  std::lock_guard<std::mutex> lock(mu);
+  size_t& cur = set[{dev, kernel}];
+  if (bytes <= cur) return GW_OK;
+  if (hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) !=
+      hipSuccess)
+    return GW_EDEVICE;
+  cur = bytes;
+  return GW_OK;
+}
 
 gw_status to_grid(const gw_grid* g, Grid* out) {
   if (!g) return GW_EINVAL;

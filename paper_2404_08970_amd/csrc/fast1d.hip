@@ -742,14 +742,13 @@ __global__ __launch_bounds__(256) void k_p3_tile(const double* __restrict__ T, i
 }
 
 int cu_count() {
-  static int ncu = 0;
-  if (ncu == 0) {
-    int dev = 0;
+  static const int ncu = [] {  // thread-safe one-time initialisation
+    int dev = 0, n = 0;
     hipDeviceProp_t prop;
     if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
-      ncu = prop.multiProcessorCount;
-    if (ncu <= 0) ncu = 256;
-  }
+      n = prop.multiProcessorCount;
+    return n > 0 ? n : 256;
+  }();
   return ncu;
 }
 
@@ -784,13 +783,9 @@ gw_status run_fast1d(const Layout& L, const double* T, int64_t ldT, double* G, i
     if (L.nJ <= 4 * P2C_TILES) {
       k_p2c<KX, KY, 4><<<nvec, 256, shm, s>>>(N, L.nJ, colmom, acarry);
     } else {
-      static size_t shm_set = 0;  // dynamic LDS above the default limit, set once per size
-      if (shm > shm_set) {
-        if (hipFuncSetAttribute(reinterpret_cast<const void*>(&k_p2c<KX, KY, 0>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm) != hipSuccess)
-          return GW_EDEVICE;
-        shm_set = shm;
-      }
+      // dynamic LDS above the default limit
+      if (gwr::allow_dyn_lds(reinterpret_cast<const void*>(&k_p2c<KX, KY, 0>), shm) != GW_OK)
+        return GW_EDEVICE;
       k_p2c<KX, KY, 0><<<nvec, 256, shm, s>>>(N, L.nJ, colmom, acarry);
     }
   }
@@ -1185,13 +1180,9 @@ gw_status img3_rowop(const double* in, int64_t ldi, int64_t rows, const gwr::Gri
       }
   }
   const size_t shm = 2 * (size_t)(g.Z * g.H * (g.W + 1)) * sizeof(double);
-  static bool set = false;  // dynamic LDS above the default, allowed once
-  if (!set) {
-    if (hipFuncSetAttribute(reinterpret_cast<const void*>(&k_img3_rowop),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) != hipSuccess)
-      return GW_EDEVICE;
-    set = true;
-  }
+  // dynamic LDS above the default
+  if (gwr::allow_dyn_lds(reinterpret_cast<const void*>(&k_img3_rowop), 160 * 1024) != GW_OK)
+    return GW_EDEVICE;
   k_img3_rowop<<<(unsigned)rows, I3_NT, shm, s>>>(in, ldi, (int)g.Z, (int)g.H, (int)g.W, tm, out,
                                                   ldo);
   return gwr::last_launch_status();

@@ -1034,14 +1034,10 @@ gw_status const_term(const gwr::Grid& g, const double* w, double* c, hipStream_t
     }
     const size_t shm = const_sep_lds((int)g.H, (int)g.W, sc.nt);
     if (sc.nt > 0 && shm <= 160 * 1024) {
-      static size_t shm_set = 0;  // dynamic LDS above the default, set once per size
-      if (shm > 64 * 1024 && shm > shm_set) {
-        if (hipFuncSetAttribute(reinterpret_cast<const void*>(&k_const_sep),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm) !=
-            hipSuccess)
-          return GW_EDEVICE;
-        shm_set = shm;
-      }
+      // dynamic LDS above the default
+      if (shm > 64 * 1024 &&
+          gwr::allow_dyn_lds(reinterpret_cast<const void*>(&k_const_sep), shm) != GW_OK)
+        return GW_EDEVICE;
       const double hk = g.hk();
       k_const_sep<<<(unsigned)g.W, 256, shm, s>>>(sc, (int)g.H, (int)g.W, hk * hk, w, c);
       return gwr::last_launch_status();
@@ -1219,12 +1215,8 @@ gw_status fast_generic(const gwr::Grid& X, const gwr::Grid& Y, const double* p,
   if (sep) {
     const size_t shm = (size_t)N * sizeof(double);
     if (shm > 160 * 1024) return GW_EUNSUPPORTED;
-    static bool attr_set = false;
-    if (!attr_set) {
-      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sep_rowreduce),
-                          hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-      attr_set = true;
-    }
+    if (gwr::allow_dyn_lds(reinterpret_cast<const void*>(&k_sep_rowreduce), 160 * 1024) != GW_OK)
+      return GW_EDEVICE;
     k_sep_rowreduce<<<(unsigned)M, NT, shm, s>>>(T, ldT, M, Y.H, Y.W, U, V);
     const int64_t ntot = X.H * Y.H + X.H * Y.W + X.W * Y.H + X.W * Y.W;
     k_sep_colreduce<<<blocks_for(ntot), NT, 0, s>>>(U, V, X.H, X.W, Y.H, Y.W, R[0], R[1], R[2], R[3]);
@@ -1253,19 +1245,13 @@ gw_status fast_generic(const gwr::Grid& X, const gwr::Grid& Y, const double* p,
     rt.m = sy.m;
     const size_t lsh = (size_t)lmax * sizeof(double), rsh = (size_t)rmax * sizeof(double);
     if (lsh > 160 * 1024 || rsh > 160 * 1024) return GW_EUNSUPPORTED;
-    static size_t lset = 0, rset = 0;  // dynamic LDS above the default, set once per size
-    if (lsh > 64 * 1024 && lsh > lset) {
-      if (hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sep_left),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lsh) != hipSuccess)
-        return GW_EDEVICE;
-      lset = lsh;
-    }
-    if (rsh > 64 * 1024 && rsh > rset) {
-      if (hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sep_right),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)rsh) != hipSuccess)
-        return GW_EDEVICE;
-      rset = rsh;
-    }
+    // dynamic LDS above the default
+    if (lsh > 64 * 1024 &&
+        gwr::allow_dyn_lds(reinterpret_cast<const void*>(&k_sep_left), lsh) != GW_OK)
+      return GW_EDEVICE;
+    if (rsh > 64 * 1024 &&
+        gwr::allow_dyn_lds(reinterpret_cast<const void*>(&k_sep_right), rsh) != GW_OK)
+      return GW_EDEVICE;
     k_sep_left<<<(unsigned)lt.first[4], SEP_LINE, lsh, s>>>(lt);
     k_sep_right<<<(unsigned)rt.first[4], SEP_LINE, rsh, s>>>(rt);
     k_sep_write<<<(unsigned)M, NT, 0, s>>>(X.H, X.W, Y.H, Y.W, Q[0], Q[1], Q[2], Q[3], c1, c2,
@@ -1288,14 +1274,9 @@ gw_status fast_generic(const gwr::Grid& X, const gwr::Grid& Y, const double* p,
     } else {
       const int qs = ax_parts(ay);
       const size_t shm = ax_row_lds(N, ay);
-      static bool rr_set = false;
-      if (!rr_set) {
-        if (hipFuncSetAttribute(reinterpret_cast<const void*>(&k_ax_rowreduce),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) !=
-            hipSuccess)
-          return GW_EDEVICE;
-        rr_set = true;
-      }
+      if (gwr::allow_dyn_lds(reinterpret_cast<const void*>(&k_ax_rowreduce), 160 * 1024) !=
+          GW_OK)
+        return GW_EDEVICE;
       k_ax_rowreduce<<<(unsigned)M, NT, shm, s>>>(T, ldT, (int)N, ay, qs, aU, off);
       pl.U = aU;
       pl.ldU = off;
@@ -1331,16 +1312,12 @@ gw_status fast_generic(const gwr::Grid& X, const gwr::Grid& Y, const double* p,
     else k_ax_right<<<blocks_for(pl.first_right[npairs]), NT, 0, s>>>(pl);
     const size_t wsh = (size_t)pl.sy * sizeof(double);
     const gwr::Epilogue e = epi ? *epi : gwr::Epilogue{};
-    static bool w_set = false;  // dynamic LDS above the default, allowed once
-    if (!w_set) {
+    {  // dynamic LDS above the default
       const void* fns[3] = {reinterpret_cast<const void*>(&k_ax_write<1>),
                             reinterpret_cast<const void*>(&k_ax_write<2>),
                             reinterpret_cast<const void*>(&k_ax_write<3>)};
       for (const void* fn : fns)
-        if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) !=
-            hipSuccess)
-          return GW_EDEVICE;
-      w_set = true;
+        if (gwr::allow_dyn_lds(fn, 160 * 1024) != GW_OK) return GW_EDEVICE;
     }
     switch (ay.na) {
       case 1: k_ax_write<1><<<(unsigned)M, NT, wsh, s>>>(pl, (int)N, c1, c2, s2, G, ldG, e); break;

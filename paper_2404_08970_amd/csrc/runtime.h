@@ -90,6 +90,11 @@ struct ProfDispatch {
   ~ProfDispatch() { prof_dispatch_done(fam, b, e); }
 };
 
+// Raise a kernel's dynamic LDS limit on the current device to at least
+// `bytes` (hipFuncSetAttribute once per kernel, device and larger size;
+// thread-safe).  GW_EDEVICE if the runtime refuses.
+gw_status allow_dyn_lds(const void* kernel, size_t bytes);
+
 inline gw_status last_launch_status() {
   return hipGetLastError() == hipSuccess ? GW_OK : GW_EDEVICE;
 }
