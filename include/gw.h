@@ -152,9 +152,17 @@ gw_status gw_objective(const gw_grid* X, const gw_grid* Y, const double* T, int6
  *   err_t = sum_p | sum_i exp((f_i + g_p - C_eff_ip)/eps) - q_p |
  * with f after and g before the update of iteration t (the plan whose row
  * sums are p), the g update is applied, and if err_t <= tol the call stops
- * there: f, g (and T) are those after iteration t.  The check runs on the
- * device (no host synchronisation): later launches of the call see a flag and
- * return at once, so a stopped call still enqueues max_iters launches.
+ * there: f, g (and T) are those after iteration t.  The decision is taken on
+ * the device: later launches of the call see a flag and return at once.  The
+ * host follows it one check behind: after enqueueing check c it waits for
+ * check c - 1 to finish on the device (a 4-byte copy of the flag to pinned
+ * host memory) and enqueues nothing more once a check has stopped the call,
+ * so these calls return only when the device has reached the stopping check
+ * (or the last one), and a stopped call enqueues at most two check periods
+ * past its stop.  On a stream being captured into a graph the host does not
+ * wait: all max_iters launches are enqueued (stopped ones return at once).
+ * Results are the same either way.  The pinned flags and events are pooled
+ * per device (host memory, allocated on first use).
  * check_every >= 1; tol must not be NaN (tol < 0 never stops).
  * ------------------------------------------------------------------------ */
 

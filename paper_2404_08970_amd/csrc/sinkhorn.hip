@@ -38,7 +38,10 @@
 
 #include <hip/hip_ext.h>
 
+#include <mutex>
+#include <new>
 #include <type_traits>
+#include <vector>
 
 #include "batch.h"
 #include "common.h"
@@ -1045,6 +1048,77 @@ __global__ __launch_bounds__(256) void k_skb_col(const gwb::SkSlot* __restrict__
 // Persistent grids: enough blocks to fill the chip at the class's occupancy.
 constexpr unsigned kBatchBlocks256 = 2048, kBatchBlocks512 = 1024, kBatchBlocks1024 = 512;
 
+// Host view of a tolerance stop: after each check the device's stop flag is
+// copied to pinned host memory, so the host can stop enqueueing iterations
+// once a check has stopped the call (the launches it no longer enqueues
+// would return at once: results are unchanged).  Probes are pooled per
+// device and reused; a probe is taken only after its previous user's copies
+// have landed.
+constexpr int kProbeSlots = 2;
+
+struct StopProbe {
+  int dev = -1;
+  int* flag = nullptr;  // pinned, kProbeSlots flags
+  hipEvent_t ev[kProbeSlots] = {};
+};
+
+std::mutex g_probe_mu;
+std::vector<StopProbe*> g_probe_free;
+
+void probe_destroy(StopProbe* pr) {
+  for (hipEvent_t e : pr->ev)
+    if (e) (void)hipEventDestroy(e);
+  if (pr->flag) (void)hipHostFree(pr->flag);
+  delete pr;
+}
+
+// nullptr if no probe can be had (the call then enqueues every iteration).
+StopProbe* probe_take() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  StopProbe* pr = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_probe_mu);
+    for (size_t i = 0; i < g_probe_free.size(); ++i)
+      if (g_probe_free[i]->dev == dev) {
+        pr = g_probe_free[i];
+        g_probe_free.erase(g_probe_free.begin() + (ptrdiff_t)i);
+        break;
+      }
+  }
+  if (!pr) {
+    pr = new (std::nothrow) StopProbe();
+    if (!pr) return nullptr;
+    pr->dev = dev;
+    bool ok = hipHostMalloc(reinterpret_cast<void**>(&pr->flag), kProbeSlots * sizeof(int),
+                            hipHostMallocDefault) == hipSuccess;
+    for (int i = 0; i < kProbeSlots && ok; ++i)
+      ok = hipEventCreateWithFlags(&pr->ev[i], hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
+      probe_destroy(pr);
+      return nullptr;
+    }
+    return pr;
+  }
+  for (hipEvent_t e : pr->ev)
+    if (hipEventSynchronize(e) != hipSuccess) {
+      probe_destroy(pr);
+      return nullptr;
+    }
+  return pr;
+}
+
+void probe_give(StopProbe* pr) {
+  if (!pr) return;
+  std::lock_guard<std::mutex> lock(g_probe_mu);
+  g_probe_free.push_back(pr);
+}
+
+bool stream_capturing(hipStream_t s) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  return hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone;
+}
+
 }  // namespace
 
 namespace gwl {
@@ -1136,6 +1210,10 @@ gw_status sinkhorn(const double* C, int64_t ldC, int64_t M, int64_t N, double c_
     gwr::ProfScope ps(gwr::kFamOther, s);
     k_sk_ctl_init<<<1, 64, 0, s>>>(ctl, iters, stop_opts->iters_out, stop_opts->err_out);
   }
+  // the host follows the checks one period behind (not while the stream is
+  // captured into a graph, which cannot wait on the host)
+  StopProbe* probe = every > 0 && !stream_capturing(s) ? probe_take() : nullptr;
+  int nchecks = 0;
   const int Mi = (int)M, Ni = (int)N;
   for (int it = 0; it < iters; ++it) {
     const bool check = every > 0 && (it + 1) % every == 0;
@@ -1166,11 +1244,36 @@ gw_status sinkhorn(const double* C, int64_t ldC, int64_t M, int64_t N, double c_
                             check ? errpart : nullptr);
     }
     if (check) {
-      gwr::ProfScope ps(gwr::kFamOther, s);
-      k_sk_check<<<1, 64, 0, s>>>(errpart, ncb, stop_opts->tol, it, ctl, stop_opts->iters_out,
-                                   stop_opts->err_out);
+      {
+        gwr::ProfScope ps(gwr::kFamOther, s);
+        k_sk_check<<<1, 64, 0, s>>>(errpart, ncb, stop_opts->tol, it, ctl, stop_opts->iters_out,
+                                     stop_opts->err_out);
+      }
+      if (probe) {
+        // this check's flag to the host; then wait for the previous check's
+        // (the device still has this period queued) and stop enqueueing if
+        // it stopped the call.  The slot written now held the flag of two
+        // checks ago, whose copy was waited for one check ago.
+        const int slot = nchecks % kProbeSlots;
+        if (hipMemcpyAsync(&probe->flag[slot], &ctl->stop, sizeof(int), hipMemcpyDeviceToHost,
+                           s) != hipSuccess ||
+            hipEventRecord(probe->ev[slot], s) != hipSuccess) {
+          probe_give(probe);
+          return GW_EDEVICE;
+        }
+        ++nchecks;
+        if (nchecks >= 2) {
+          const int prev = (nchecks - 2) % kProbeSlots;
+          if (hipEventSynchronize(probe->ev[prev]) != hipSuccess) {
+            probe_give(probe);
+            return GW_EDEVICE;
+          }
+          if (probe->flag[prev]) break;
+        }
+      }
     }
   }
+  probe_give(probe);
   return sinkhorn_finish(C, ldC, M, N, c_scale, p, logp, ms, eps, iters, f, g, T, ldT, s, status);
 }
 
