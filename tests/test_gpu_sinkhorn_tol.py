@@ -75,6 +75,39 @@ def test_sinkhorn_tol_unmet_equals_fixed_count():
     assert torch.equal(f, f2) and torch.equal(g, g2)
 
 
+def test_sinkhorn_tol_graph_replays_equal_eager():
+    """Captured into a HIP graph the call waits for nothing on the host: every
+    launch is recorded and the ones after the stop return at once.  Three
+    replays, with eager Sinkhorn work between them, each equal the eager call
+    bit for bit (potentials, plan, iterations done)."""
+    gw, torch = _gw()
+    rng = inputs.rng_for(915)
+    M, N = 120, 900
+    C = _to_dev(torch, rng.uniform(0, 1, size=(M, N)))
+    p = _to_dev(torch, inputs.dirichlet(M, rng))
+    q = _to_dev(torch, inputs.dirichlet(N, rng))
+    f0, g0, T0, d0, _ = gw.sinkhorn_tol(C, p, q, 0.05, 200, 10, 1e-9, plan=True)
+    torch.cuda.synchronize()
+    n0 = int(d0.item())
+    assert 0 < n0 < 200
+    nb = gw.workspace_bytes(gw.unit_grid((M,), 1), gw.unit_grid((N,), 1), gw.PATH_FAST_F64,
+                            gw.OP_SINKHORN)
+    ws = gw.workspace(nb, "cuda", key="capture")
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=side):
+        f, g, T, d, _ = gw.sinkhorn_tol(C, p, q, 0.05, 200, 10, 1e-9, plan=True, ws=ws)
+    for r in range(3):
+        print(f"replay {r}", flush=True)
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(f, f0) and torch.equal(g, g0) and torch.equal(T, T0)
+        assert int(d.item()) == n0
+        gw.sinkhorn(C, p, q, 0.05, 7)  # eager work between the replays
+        torch.cuda.synchronize()
+
+
 def test_sinkhorn_tol_zero_mass_and_warm_start():
     gw, torch = _gw()
     M, N, eps, every = 30, 260, 0.03, 2
