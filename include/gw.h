@@ -17,11 +17,19 @@
  *     dimension in elements.  Pointers marked "device" are device pointers that
  *     must be 8-byte aligned; the workspace must be 256-byte aligned.
  *   - Every call is asynchronous on `stream` (a hipStream_t; NULL = the null
- *     stream).  A return of GW_OK means the arguments were valid and the work
- *     was enqueued.  On any other return nothing was enqueued.
+ *     stream), except the tolerance-stopped calls (see there).  A return of
+ *     GW_OK means the arguments were valid and the work was enqueued.  On any
+ *     other return nothing was enqueued.  Work that does not depend on the
+ *     stream's earlier results beyond the inputs (the constant terms of a FAST
+ *     gradient) may run on a side stream forked from `stream` and joined back
+ *     with events before the results are used, so ordering on `stream` and
+ *     graph capture of `stream` hold as if everything ran on it.
  *   - The caller owns every buffer, including the workspace sized by
  *     gw_workspace_bytes().  The library never frees caller memory and does not
- *     allocate device memory on these calls.
+ *     allocate device memory on these calls.  Per device it creates, on first
+ *     use and never while `stream` is being captured, a small pool of side
+ *     streams (default priority) and events, and pinned host flags for the
+ *     tolerance stop; they live until the process ends.
  *   - Marginals are expected to be non-negative, finite and to sum to 1; zero
  *     entries are allowed (their potential is -inf and their plan row/column
  *     is zero).  These preconditions are documented, not checked per call.

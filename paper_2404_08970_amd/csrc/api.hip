@@ -5,6 +5,7 @@
 
 #include <map>
 #include <mutex>
+#include <new>
 #include <utility>
 #include <vector>
 
@@ -13,6 +14,66 @@
 namespace gwr {
 
 static const int64_t kMaxExtent = 65535;
+
+namespace {
+std::mutex g_side_mu;
+std::vector<SideStream*> g_side_free;
+
+void side_destroy(SideStream* ss) {
+  if (ss->fork_ev) (void)hipEventDestroy(ss->fork_ev);
+  if (ss->join_ev) (void)hipEventDestroy(ss->join_ev);
+  if (ss->side) (void)hipStreamDestroy(ss->side);
+  delete ss;
+}
+
+void side_give(SideStream* ss) {
+  std::lock_guard<std::mutex> lock(g_side_mu);
+  g_side_free.push_back(ss);
+}
+}  // namespace
+
+SideStream* side_take(hipStream_t s) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  SideStream* ss = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_side_mu);
+    for (size_t i = 0; i < g_side_free.size(); ++i)
+      if (g_side_free[i]->dev == dev) {
+        ss = g_side_free[i];
+        g_side_free.erase(g_side_free.begin() + (ptrdiff_t)i);
+        break;
+      }
+  }
+  if (!ss) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
+      return nullptr;
+    ss = new (std::nothrow) SideStream();
+    if (!ss) return nullptr;
+    ss->dev = dev;
+    // default priority, like every stream of this library
+    if (hipStreamCreateWithFlags(&ss->side, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&ss->fork_ev, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&ss->join_ev, hipEventDisableTiming) != hipSuccess) {
+      side_destroy(ss);
+      return nullptr;
+    }
+  }
+  if (hipEventRecord(ss->fork_ev, s) != hipSuccess ||
+      hipStreamWaitEvent(ss->side, ss->fork_ev, 0) != hipSuccess) {
+    side_give(ss);
+    return nullptr;
+  }
+  return ss;
+}
+
+gw_status side_join(SideStream* ss, hipStream_t s) {
+  const bool ok = hipEventRecord(ss->join_ev, ss->side) == hipSuccess &&
+                  hipStreamWaitEvent(s, ss->join_ev, 0) == hipSuccess;
+  side_give(ss);
+  return ok ? GW_OK : GW_EDEVICE;
+}
 
 gw_status allow_dyn_lds(const void* kernel, size_t bytes) {
   int dev = 0;

@@ -767,7 +767,8 @@ int persistent_blocks(K kernel, int ntiles) {
 template <int KX, int KY>
 gw_status run_fast1d(const Layout& L, const double* T, int64_t ldT, double* G, int64_t ldG,
                      const double* c1, const double* c2, double s2, double* rowmom,
-                     double* colmom, double* acarry, const gwr::Epilogue* epi, hipStream_t s) {
+                     double* colmom, double* acarry, const gwr::Epilogue* epi, gwr::SideJoin& sj,
+                     hipStream_t s) {
   const int M = (int)L.M, N = (int)L.N;
   const int ntiles = L.nI * L.nJ;
   {
@@ -789,6 +790,8 @@ gw_status run_fast1d(const Layout& L, const double* T, int64_t ldT, double* G, i
       k_p2c<KX, KY, 0><<<nvec, 256, shm, s>>>(N, L.nJ, colmom, acarry);
     }
   }
+  // the constant terms (maybe on a side stream) are read from here on
+  if (sj.join() != GW_OK) return GW_EDEVICE;
   {
     gwr::ProfDispatch pd(gwr::kFamFastMain);
     if (epi)
@@ -808,12 +811,13 @@ gw_status run_fast1d(const Layout& L, const double* T, int64_t ldT, double* G, i
 template <int KX>
 gw_status dispatch_ky(int ky, const Layout& L, const double* T, int64_t ldT, double* G,
                       int64_t ldG, const double* c1, const double* c2, double s2, double* rm,
-                      double* cm, double* am, const gwr::Epilogue* epi, hipStream_t s) {
+                      double* cm, double* am, const gwr::Epilogue* epi, gwr::SideJoin& sj,
+                      hipStream_t s) {
   switch (ky) {
-    case 1: return run_fast1d<KX, 1>(L, T, ldT, G, ldG, c1, c2, s2, rm, cm, am, epi, s);
-    case 2: return run_fast1d<KX, 2>(L, T, ldT, G, ldG, c1, c2, s2, rm, cm, am, epi, s);
-    case 3: return run_fast1d<KX, 3>(L, T, ldT, G, ldG, c1, c2, s2, rm, cm, am, epi, s);
-    case 4: return run_fast1d<KX, 4>(L, T, ldT, G, ldG, c1, c2, s2, rm, cm, am, epi, s);
+    case 1: return run_fast1d<KX, 1>(L, T, ldT, G, ldG, c1, c2, s2, rm, cm, am, epi, sj, s);
+    case 2: return run_fast1d<KX, 2>(L, T, ldT, G, ldG, c1, c2, s2, rm, cm, am, epi, sj, s);
+    case 3: return run_fast1d<KX, 3>(L, T, ldT, G, ldG, c1, c2, s2, rm, cm, am, epi, sj, s);
+    case 4: return run_fast1d<KX, 4>(L, T, ldT, G, ldG, c1, c2, s2, rm, cm, am, epi, sj, s);
   }
   return GW_EUNSUPPORTED;
 }
@@ -1116,14 +1120,18 @@ gw_status fast1d(const gwr::Grid& X, const gwr::Grid& Y, const double* p, const 
   double* am = ws.take<double>(L.acarry);
   double* c1 = ws.take<double>(X.n());
   double* c2 = ws.take<double>(Y.n());
-  gw_status st = resolve_const_terms(X, p, c1_pre, &c1, Y, q, c2_pre, &c2, s);
+  // the constant terms need only p and q: on a side stream they run beside
+  // the moment and carry passes, joined before the tile pass reads them
+  gwr::SideJoin sj{(!c1_pre || !c2_pre) ? gwr::side_take(s) : nullptr, s};
+  gw_status st =
+      resolve_const_terms(X, p, c1_pre, &c1, Y, q, c2_pre, &c2, sj.ss ? sj.ss->side : s);
   if (st != GW_OK) return st;
   const double s2 = 2.0 * (X.hk() * Y.hk());
   switch (L.kx) {
-    case 1: return dispatch_ky<1>(L.ky, L, T, ldT, G, ldG, c1, c2, s2, rm, cm, am, epi, s);
-    case 2: return dispatch_ky<2>(L.ky, L, T, ldT, G, ldG, c1, c2, s2, rm, cm, am, epi, s);
-    case 3: return dispatch_ky<3>(L.ky, L, T, ldT, G, ldG, c1, c2, s2, rm, cm, am, epi, s);
-    case 4: return dispatch_ky<4>(L.ky, L, T, ldT, G, ldG, c1, c2, s2, rm, cm, am, epi, s);
+    case 1: return dispatch_ky<1>(L.ky, L, T, ldT, G, ldG, c1, c2, s2, rm, cm, am, epi, sj, s);
+    case 2: return dispatch_ky<2>(L.ky, L, T, ldT, G, ldG, c1, c2, s2, rm, cm, am, epi, sj, s);
+    case 3: return dispatch_ky<3>(L.ky, L, T, ldT, G, ldG, c1, c2, s2, rm, cm, am, epi, sj, s);
+    case 4: return dispatch_ky<4>(L.ky, L, T, ldT, G, ldG, c1, c2, s2, rm, cm, am, epi, sj, s);
   }
   return GW_EUNSUPPORTED;
 }

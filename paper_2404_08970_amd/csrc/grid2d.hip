@@ -1208,7 +1208,11 @@ gw_status fast_generic(const gwr::Grid& X, const gwr::Grid& Y, const double* p,
   }
   double* c1 = ws.take<double>(M);
   double* c2 = ws.take<double>(N);
-  gw_status st = resolve_const_terms(X, p, c1_pre, &c1, Y, q, c2_pre, &c2, s);
+  // the constant terms need only p and q: on a side stream they run beside
+  // the reductions and products, joined before the kernel that writes G
+  gwr::SideJoin sj{(!c1_pre || !c2_pre) ? gwr::side_take(s) : nullptr, s};
+  gw_status st =
+      resolve_const_terms(X, p, c1_pre, &c1, Y, q, c2_pre, &c2, sj.ss ? sj.ss->side : s);
   if (st != GW_OK) return st;
   const double s2 = 2.0 * (X.hk() * Y.hk());
   gwr::ProfScope ps(gwr::kFam2D, s);
@@ -1254,6 +1258,7 @@ gw_status fast_generic(const gwr::Grid& X, const gwr::Grid& Y, const double* p,
       return GW_EDEVICE;
     k_sep_left<<<(unsigned)lt.first[4], SEP_LINE, lsh, s>>>(lt);
     k_sep_right<<<(unsigned)rt.first[4], SEP_LINE, rsh, s>>>(rt);
+    if (sj.join() != GW_OK) return GW_EDEVICE;
     k_sep_write<<<(unsigned)M, NT, 0, s>>>(X.H, X.W, Y.H, Y.W, Q[0], Q[1], Q[2], Q[3], c1, c2,
                                            s2, G, ldG, epi ? *epi : gwr::Epilogue{});
     return gwr::last_launch_status();
@@ -1319,6 +1324,7 @@ gw_status fast_generic(const gwr::Grid& X, const gwr::Grid& Y, const double* p,
       for (const void* fn : fns)
         if (gwr::allow_dyn_lds(fn, 160 * 1024) != GW_OK) return GW_EDEVICE;
     }
+    if (sj.join() != GW_OK) return GW_EDEVICE;
     switch (ay.na) {
       case 1: k_ax_write<1><<<(unsigned)M, NT, wsh, s>>>(pl, (int)N, c1, c2, s2, G, ldG, e); break;
       case 2: k_ax_write<2><<<(unsigned)M, NT, wsh, s>>>(pl, (int)N, c1, c2, s2, G, ldG, e); break;
@@ -1339,6 +1345,7 @@ gw_status fast_generic(const gwr::Grid& X, const gwr::Grid& Y, const double* p,
     k_rowop<<<(unsigned)N, NT, 0, s>>>(At, M, N, X.ndim, X.k, X.metric, X.Z, X.H, X.W, A, M, tmp,
                                        tmp2);
   dim3 tg2((unsigned)((M + 31) / 32), (unsigned)((N + 31) / 32));
+  if (sj.join() != GW_OK) return GW_EDEVICE;
   k_transpose<<<tg2, NT, 0, s>>>(A, M, N, M, G, ldG, c1, c2, s2);
   if (epi) return fgw_blend(G, ldG, M, N, epi->fa, epi->fb, epi->a, epi->b, s);
   return gwr::last_launch_status();

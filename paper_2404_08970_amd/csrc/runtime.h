@@ -90,6 +90,33 @@ struct ProfDispatch {
   ~ProfDispatch() { prof_dispatch_done(fam, b, e); }
 };
 
+// A side stream for work that may run beside the caller's stream, pooled per
+// device.  side_take(s) hands one out that waits for what `s` has enqueued so
+// far; side_join makes `s` wait for what was enqueued on it and returns it to
+// the pool.  Both are event waits, so they also hold while `s` is being
+// captured into a graph (where no new side stream is created: nullptr then,
+// and the caller uses `s`).
+struct SideStream {
+  int dev = -1;
+  hipStream_t side = nullptr;
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+};
+SideStream* side_take(hipStream_t s);
+gw_status side_join(SideStream* ss, hipStream_t s);
+
+// Joins a side stream (if any) when the work that needs it is about to be
+// enqueued, or on leaving the scope.
+struct SideJoin {
+  SideStream* ss;
+  hipStream_t s;
+  gw_status join() {
+    SideStream* x = ss;
+    ss = nullptr;
+    return x ? side_join(x, s) : GW_OK;
+  }
+  ~SideJoin() { (void)join(); }
+};
+
 // Raise a kernel's dynamic LDS limit on the current device to at least
 // `bytes` (hipFuncSetAttribute once per kernel, device and larger size;
 // thread-safe).  GW_EDEVICE if the runtime refuses.
