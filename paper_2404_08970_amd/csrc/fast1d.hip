@@ -397,9 +397,10 @@ __global__ __launch_bounds__(SCAN_LINES * CH) void k_p2_scan(int M, int N, int n
 //   pass A  segment summaries -> tile moments (prefix at the tile end, suffix
 //           at its start - 1);
 //   scan    exclusive scans of the tile moments over the tiles: each thread
-//           folds a run of consecutive tiles, an inclusive Hillis-Steele scan
-//           combines the runs (shift over the span between them), and each
-//           thread writes the exclusive states of its run;
+//           folds a run of consecutive tiles, a shuffle scan inside each wave
+//           and the totals of the earlier waves combine the runs (shift over
+//           the span between them), and each thread writes the exclusive
+//           states of its run;
 //   pass B  each segment is swept with its tile's carries advanced over the
 //           segments before (after) it, and the output leaves through LDS.
 constexpr int P2C_TILES = 64;                       // tiles per round
@@ -472,9 +473,9 @@ __global__ __launch_bounds__(256) void k_p2c(int N, int nJ, const double* __rest
       }
     }
   }
-  // scans over the tiles; the Hillis-Steele buffers live in the staging area
+  // scans over the tiles; their buffers live in the staging area
   const int run = (nJ + 255) / 256;  // tiles per thread
-  double* hs = stg;                  // [2 buffers][256][KM]
+  double* hs = stg;                  // [256][KM] inclusive states, then [4][KM] wave totals
 #pragma unroll
   for (int dir = 0; dir < 2; ++dir) {
     __syncthreads();
@@ -490,27 +491,40 @@ __global__ __launch_bounds__(256) void k_p2c(int N, int nJ, const double* __rest
         for (int r = 0; r <= K; ++r) agg[r] += mom[(dir * nJ + J) * KM + r];
       }
     }
-    int cur = 0;
+    // inclusive scan of the run states: inside each wave by shuffles (the
+    // state from lane - d is shifted over the d runs between), then the totals
+    // of the earlier waves, each shifted from its wave's end to this run's end
+    const int lane = t & 63, wv = t >> 6;
+    for (int d = 1; d < 64; d <<= 1) {
+      double o[K + 1];
 #pragma unroll
-    for (int r = 0; r <= K; ++r) hs[(cur * 256 + t) * KM + r] = agg[r];
-    for (int d = 1; d < 256; d <<= 1) {
-      __syncthreads();
-      if (t >= d) {
-        double o[K + 1];
-#pragma unroll
-        for (int r = 0; r <= K; ++r) o[r] = hs[(cur * 256 + t - d) * KM + r];
+      for (int r = 0; r <= K; ++r) o[r] = __shfl_up(agg[r], d, 64);
+      if (lane >= d) {
         gwk::pascal_shift<K>(o, (double)TS * run * d);
 #pragma unroll
         for (int r = 0; r <= K; ++r) agg[r] += o[r];
       }
-      cur ^= 1;
+    }
+    double* wtot = hs + 256 * KM;  // [4][KM]: the waves' totals
+    if (lane == 63) {
 #pragma unroll
-      for (int r = 0; r <= K; ++r) hs[(cur * 256 + t) * KM + r] = agg[r];
+      for (int r = 0; r <= K; ++r) wtot[wv * KM + r] = agg[r];
     }
     __syncthreads();
-    double st[K + 1];
+    for (int w = 0; w < wv; ++w) {
+      double o[K + 1];
 #pragma unroll
-    for (int r = 0; r <= K; ++r) st[r] = t > 0 ? hs[(cur * 256 + t - 1) * KM + r] : 0.0;
+      for (int r = 0; r <= K; ++r) o[r] = wtot[w * KM + r];
+      gwk::pascal_shift<K>(o, (double)TS * run * (t - 64 * w - 63));
+#pragma unroll
+      for (int r = 0; r <= K; ++r) agg[r] += o[r];
+    }
+#pragma unroll
+    for (int r = 0; r <= K; ++r) hs[t * KM + r] = agg[r];
+    __syncthreads();
+    double st[K + 1];  // exclusive: the inclusive state of the run before
+#pragma unroll
+    for (int r = 0; r <= K; ++r) st[r] = t > 0 ? hs[(t - 1) * KM + r] : 0.0;
     for (int u = 0; u < run; ++u) {
       const int pos = t * run + u;
       if (pos < nJ) {
