@@ -648,6 +648,16 @@ def main():
                "fast_tile_kernel_GBps_at_16B_per_entry": round(tile_gbs, 1),
                "fast_tile_kernel_hbm_frac": round(tile_gbs / HBM_PEAK_GBS, 4),
                "fast_moment_kernels_ms": round(carry_ms, 3)}
+        # achieved HBM bandwidth of the tile kernel: the bytes its hardware
+        # counters report per dispatch (T, G and the carries it reads) over
+        # the time measured here
+        tf = os.path.join(ROOT, "profiles", "traffic_fast_tile_n16384.json")
+        if os.path.exists(tf):
+            tb = json.load(open(tf))["bytes_per_launch"]
+            big["fast_tile_kernel_traffic_bytes"] = tb
+            big["fast_tile_kernel_GBps_measured_traffic"] = round(tb / (main_ms * 1e-3) / 1e9, 1)
+            big["fast_tile_kernel_hbm_frac_measured_traffic"] = round(
+                tb / (main_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
         del Tb, Gb, wsb
 
     grid2d = None if args.no_2d else grid2d_bench()
