@@ -666,7 +666,12 @@ __global__ __launch_bounds__(256) void k_p3_tile(const double* __restrict__ T, i
     // take the next tile (the same registers in every iteration)
 #pragma unroll
     for (int i = 0; i < SEG; ++i) X[seg * SEG + i][lane] = (seg * SEG + i < h && lane < w) ? pf[i] : 0.0;
+    // the next tile's loads are issued at raised wave priority, so they go
+    // out ahead of the other resident waves' sweeps (in-kernel wave priority
+    // only; every stream keeps the default priority)
+    __builtin_amdgcn_s_setprio(3);
     load_tile(pf, min(tile + stride, ntiles - 1));
+    __builtin_amdgcn_s_setprio(0);
     if (lane >= h) {  // rows past the matrix carry nothing
 #pragma unroll
       for (int r = 0; r <= KY; ++r) ra[r] = rb[r] = 0.0;
