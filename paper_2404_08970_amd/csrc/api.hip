@@ -30,6 +30,22 @@ void side_give(SideStream* ss) {
   std::lock_guard<std::mutex> lock(g_side_mu);
   g_side_free.push_back(ss);
 }
+
+// A pooled side stream that was forked from a stream under capture stays in
+// that capture until the capture ends, even after it was joined back and
+// returned.  It may only be handed out again to work on a stream of the same
+// capture; eager work, or another capture, must not enqueue on it.
+bool side_usable(SideStream* ss, hipStream_t s) {
+  hipStreamCaptureStatus cs_side = hipStreamCaptureStatusNone;
+  unsigned long long id_side = 0;
+  if (hipStreamGetCaptureInfo(ss->side, &cs_side, &id_side) != hipSuccess) return false;
+  if (cs_side == hipStreamCaptureStatusNone) return true;
+  hipStreamCaptureStatus cs_s = hipStreamCaptureStatusNone;
+  unsigned long long id_s = 0;
+  if (hipStreamGetCaptureInfo(s, &cs_s, &id_s) != hipSuccess) return false;
+  return cs_side == hipStreamCaptureStatusActive && cs_s == hipStreamCaptureStatusActive &&
+         id_s == id_side;
+}
 }  // namespace
 
 SideStream* side_take(hipStream_t s) {
@@ -39,7 +55,7 @@ SideStream* side_take(hipStream_t s) {
   {
     std::lock_guard<std::mutex> lock(g_side_mu);
     for (size_t i = 0; i < g_side_free.size(); ++i)
-      if (g_side_free[i]->dev == dev) {
+      if (g_side_free[i]->dev == dev && side_usable(g_side_free[i], s)) {
         ss = g_side_free[i];
         g_side_free.erase(g_side_free.begin() + (ptrdiff_t)i);
         break;
@@ -426,6 +442,7 @@ gw_status sinkhorn_impl(const double* C, int64_t ldC, int64_t M, int64_t N, doub
   return gwl::sinkhorn(C, ldC, M, N, c_scale, p, q, eps, iters, init_zero, f, g, T, ldT, a, s,
                        status_of(ws), so);
 }
+
 
 // Mirror descent (Sec. 2.1), GW or fused GW (fgw non-null).
 // With so (non-null), each Sinkhorn call stops by tolerance; its iterations

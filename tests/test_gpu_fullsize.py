@@ -122,9 +122,11 @@ def test_solve_n4096_one_outer_full():
     og = O.Grid((n,), X.h, k)
     T0, f0, g0, obj0 = O.solve(og, og, p, q, eps, 1, 5)
     assert _rel(T.cpu().numpy(), T0) <= TOL
+    assert _rel(f.cpu().numpy(), f0) <= TOL
     assert _rel(g.cpu().numpy(), g0) <= TOL
     o = obj.cpu().numpy()
     assert abs(o[0] - obj0[0]) <= TOL * abs(obj0[0])
+    assert abs(o[1] - obj0[1]) <= TOL * max(abs(obj0[1]), abs(obj0[0]))
 
 
 @pytest.mark.parametrize("k", [1, 2, 3])
