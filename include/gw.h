@@ -134,6 +134,25 @@ gw_status gw_sinkhorn(const double* C, int64_t ldC, int64_t M, int64_t N, double
                       int32_t init_zero, double* f, double* g, double* T, int64_t ldT, void* ws,
                       size_t ws_bytes, void* stream);
 
+/* gw_sinkhorn without a workspace argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, results and validation as
+ * gw_sinkhorn; its scratch (band partials, log-marginals, row bounds, status
+ * word) is a static device array of GW_NOALLOC_SCRATCH_BYTES per GPU, held
+ * from the first call on that GPU until the process ends.  Sizes whose
+ * gw_sinkhorn workspace (gw_workspace_bytes with GW_OP_SINKHORN) exceeds it
+ * return GW_ENOMEM before anything is enqueued (about M, N <= 10000 at
+ * M = N).  Calls no allocating routine.  Every call on a GPU shares that GPU's
+ * array: calls that overlap on one GPU (two streams, two threads) race and
+ * must be serialised by the caller.  The status word in the array is cleared
+ * at the start of each call and is not reported by gw_check_status; a
+ * non-finite result shows in f and g. */
+#define GW_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
+gw_status gw_sinkhorn_noalloc(const double* C, int64_t ldC, int64_t M, int64_t N,
+                              double c_scale, const double* p, const double* q, double eps,
+                              int32_t iters, int32_t init_zero, double* f, double* g, double* T,
+                              int64_t ldT, void* stream);
+
 /* Entropic GW by mirror descent with tau = eps (Sec. 2.1): T^0 = p q^T, then
  * `outer` times { G = gw_grad(T); Sinkhorn on the cost 2G with `inner`
  * iterations; T = its plan }.  Afterwards obj[0] = E(T) (the QAP objective of

@@ -423,7 +423,8 @@ gw_status check_stop(const gwr::SkStop& so) {
 gw_status sinkhorn_impl(const double* C, int64_t ldC, int64_t M, int64_t N, double c_scale,
                         const double* p, const double* q, double eps, int32_t iters,
                         int32_t init_zero, const gwr::SkStop* so, double* f, double* g,
-                        double* T, int64_t ldT, void* ws, size_t ws_bytes, void* stream) {
+                        double* T, int64_t ldT, void* ws, size_t ws_bytes, void* stream,
+                        bool clear = false) {
   gw_status st;
   if (M < 1 || N < 1) return GW_EINVAL;
   if (M > gwr::kMaxExtent || N > gwr::kMaxExtent) return GW_EUNSUPPORTED;
@@ -437,12 +438,40 @@ gw_status sinkhorn_impl(const double* C, int64_t ldC, int64_t M, int64_t N, doub
   const size_t need = gwr::ws_status_bytes() + gwr::ws_sinkhorn_bytes(M, N);
   if ((st = check_ws(ws, ws_bytes, need)) != GW_OK) return st;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (clear && (st = gwr::clear_status(status_of(ws), s)) != GW_OK) return st;
   Arena a{static_cast<char*>(ws), 0, ws_bytes};
   a.take<char>(gwr::ws_status_bytes());
   return gwl::sinkhorn(C, ldC, M, N, c_scale, p, q, eps, iters, init_zero, f, g, T, ldT, a, s,
                        status_of(ws), so);
 }
 
+// Scratch of the no-allocation Sinkhorn: a static device array, one copy per
+// GPU, held until the process ends.  Host code never uses the array's name as
+// an address: the device address comes from hipGetSymbolAddress, taken once
+// per device with that device current, and is kept per device.
+constexpr size_t kStaticScratchBytes = GW_NOALLOC_SCRATCH_BYTES;
+}  // namespace
+namespace gwnoalloc {
+__device__ __align__(256) char scratch[kStaticScratchBytes];
+}  // namespace gwnoalloc
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+gw_status static_scratch(void** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return GW_EDEVICE;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev] == nullptr) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(gwnoalloc::scratch)) != hipSuccess || ptr == nullptr)
+      return GW_EDEVICE;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return GW_OK;
+}
 
 // Mirror descent (Sec. 2.1), GW or fused GW (fgw non-null).
 // With so (non-null), each Sinkhorn call stops by tolerance; its iterations
@@ -571,6 +600,21 @@ gw_status gw_sinkhorn(const double* C, int64_t ldC, int64_t M, int64_t N, double
                       size_t ws_bytes, void* stream) {
   return sinkhorn_impl(C, ldC, M, N, c_scale, p, q, eps, iters, init_zero, nullptr, f, g, T, ldT,
                        ws, ws_bytes, stream);
+}
+
+gw_status gw_sinkhorn_noalloc(const double* C, int64_t ldC, int64_t M, int64_t N,
+                              double c_scale, const double* p, const double* q, double eps,
+                              int32_t iters, int32_t init_zero, double* f, double* g, double* T,
+                              int64_t ldT, void* stream) {
+  // sizes the Sinkhorn kernels take but the static scratch does not hold
+  if (M >= 1 && N >= 1 && M <= gwr::kMaxExtent && N <= 16384 &&
+      gwr::ws_status_bytes() + gwr::ws_sinkhorn_bytes(M, N) > kStaticScratchBytes)
+    return GW_ENOMEM;
+  void* ws = nullptr;
+  gw_status st = static_scratch(&ws);
+  if (st != GW_OK) return st;
+  return sinkhorn_impl(C, ldC, M, N, c_scale, p, q, eps, iters, init_zero, nullptr, f, g, T, ldT,
+                       ws, kStaticScratchBytes, stream, /*clear=*/true);
 }
 
 gw_status gw_sinkhorn_tol(const double* C, int64_t ldC, int64_t M, int64_t N, double c_scale,

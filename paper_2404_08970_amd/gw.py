@@ -83,6 +83,8 @@ def _lib():
     lib.gw_grad.restype = I32
     lib.gw_sinkhorn.argtypes = [P, I64, I64, I64, D, P, P, D, I32, I32, P, P, P, I64, P, SZ, P]
     lib.gw_sinkhorn.restype = I32
+    lib.gw_sinkhorn_noalloc.argtypes = [P, I64, I64, I64, D, P, P, D, I32, I32, P, P, P, I64, P]
+    lib.gw_sinkhorn_noalloc.restype = I32
     lib.gw_solve.argtypes = [G, G, P, P, D, I32, I32, I32, I32, P, I64, P, P, P, P, SZ, P]
     lib.gw_solve.restype = I32
     lib.gw_objective.argtypes = [G, G, P, I64, D, P, P, SZ, P]
@@ -272,6 +274,28 @@ def sinkhorn(C, p, q, eps: float, iters: int, c_scale: float = 1.0, f=None, g=No
                             T.stride(0) if T is not None else N, _ptr(ws), ws.numel(), _stream())
     _raise(st, "gw_sinkhorn")
     return (f, g, T) if plan else (f, g)
+
+
+def sinkhorn_noalloc(C, p, q, eps: float, iters: int, c_scale: float = 1.0, f=None, g=None,
+                     T=None):
+    """gw_sinkhorn_noalloc: the Sinkhorn call whose scratch is the library's
+    static device array (no workspace).  f, g (and T for the plan) are caller
+    buffers; missing f, g are allocated here by torch before the call, which
+    itself allocates nothing.  Returns (f, g) or (f, g, T)."""
+    M, N = C.shape
+    _check_f64("C", C, (M, N)); _check_f64("p", p, (M,)); _check_f64("q", q, (N,))
+    init_zero = 1 if (f is None and g is None) else 0
+    if f is None:
+        f = torch.zeros(M, dtype=torch.float64, device=C.device)
+    if g is None:
+        g = torch.zeros(N, dtype=torch.float64, device=C.device)
+    if T is not None:
+        _check_f64("T", T, (M, N))
+    st = _lib().gw_sinkhorn_noalloc(_ptr(C), C.stride(0), M, N, float(c_scale), _ptr(p), _ptr(q),
+                                    float(eps), int(iters), init_zero, _ptr(f), _ptr(g), _ptr(T),
+                                    T.stride(0) if T is not None else N, _stream())
+    _raise(st, "gw_sinkhorn_noalloc")
+    return (f, g, T) if T is not None else (f, g)
 
 
 def sinkhorn_tol(C, p, q, eps: float, max_iters: int, check_every: int, tol: float,
