@@ -428,9 +428,13 @@ gw_status gw_check_status(void* ws, void* stream);
  * gw_profile_enable(mask) records the families whose bit (1 << family) is set
  * in `mask` (0 stops recording; every call clears the counts); gw_profile_read
  * waits for the recorded events and returns total milliseconds and launch
- * count of a family.  Timing adds an event pair around each recorded launch. */
+ * count of a family (the launches timed).  Timing adds an event pair around
+ * each timed launch; gw_profile_sample(every) times only the first of every
+ * `every` launches of each family (default 1: all), which keeps that cost off
+ * the untimed ones.  every < 1 returns GW_EINVAL. */
 void gw_profile_enable(int32_t mask);
 gw_status gw_profile_read(int32_t family, double* total_ms, int64_t* launches);
+gw_status gw_profile_sample(int32_t every);
 
 /* Library version string. */
 const char* gw_version(void);

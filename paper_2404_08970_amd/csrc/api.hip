@@ -179,6 +179,8 @@ struct ProfState {
   double total_ms[kNumFamilies] = {};
   int64_t launches[kNumFamilies] = {};
   hipEvent_t open[kNumFamilies] = {};
+  int32_t every = 1;                    // time one launch in `every`
+  int64_t seq[kNumFamilies] = {};       // launches seen since the last enable
 };
 ProfState& prof() {
   static ProfState* p = new ProfState();
@@ -206,10 +208,15 @@ void drain(ProfState& P, int fam) {
 }
 }  // namespace
 
+// The launches of a family are counted and every P.every-th one is timed.
+bool sampled(ProfState& P, int fam) { return P.seq[fam]++ % P.every == 0; }
+
 void prof_begin(int fam, hipStream_t s) {
   ProfState& P = prof();
   if (!(P.mask & (1 << fam))) return;
   std::lock_guard<std::mutex> g(P.mu);
+  P.open[fam] = nullptr;
+  if (!sampled(P, fam)) return;
   if (P.used[fam] + 2 > (size_t(1) << 20)) drain(P, fam);
   hipEvent_t e = pool_event(P, fam);
   if (e) (void)hipEventRecord(e, s);
@@ -221,6 +228,7 @@ void prof_dispatch_events(int fam, hipEvent_t* b, hipEvent_t* e) {
   ProfState& P = prof();
   if (!(P.mask & (1 << fam))) return;
   std::lock_guard<std::mutex> g(P.mu);
+  if (!sampled(P, fam)) return;
   if (P.used[fam] + 2 > (size_t(1) << 20)) drain(P, fam);
   *b = pool_event(P, fam);
   *e = pool_event(P, fam);
@@ -789,8 +797,18 @@ void gw_profile_enable(int32_t mask) {
     P.total_ms[f] = 0.0;
     P.launches[f] = 0;
     P.open[f] = nullptr;
+    P.seq[f] = 0;
   }
   P.mask = mask;
+}
+
+gw_status gw_profile_sample(int32_t every) {
+  if (every < 1) return GW_EINVAL;
+  gwr::ProfState& P = gwr::prof();
+  std::lock_guard<std::mutex> g(P.mu);
+  P.every = every;
+  for (int f = 0; f < gwr::kNumFamilies; ++f) P.seq[f] = 0;
+  return GW_OK;
 }
 
 gw_status gw_profile_read(int32_t family, double* total_ms, int64_t* launches) {

@@ -64,6 +64,8 @@ struct SkSlot {
   gwr::StatusWord* status;
   double* lse;    // [M] upper bounds of the rows' log-sum-exp (row shifts)
   double* gprev;  // [N] g before the last column merge
+  const int* kq;  // [N] column frames of the fast pass
+  int* bmode;     // [nb] pass kind of each band's partials
   double cs, inv_eps, eps;
   int32_t M, N, RB, nb;
   int32_t its;   // Sinkhorn iterations this request takes in the current step
@@ -88,7 +90,8 @@ gw_status sk_batch_launch(int cls, int j, const gwb::SkSlot* slots, const gwb::S
 // log-marginals (and zero potentials if init_zero), and after the last
 // iteration f from (m, s) and the plan.
 gw_status sinkhorn_prep(const double* p, const double* q, int64_t M, int64_t N, int init_zero,
-                        double* logp, double* logq, double* f, double* g, hipStream_t s);
+                        double* logp, double* logq, int* kq, double* f, double* g,
+                        hipStream_t s);
 gw_status sinkhorn_finish(const double* C, int64_t ldC, int64_t M, int64_t N, double c_scale,
                           const double* p, const double* logp, const double* ms, double eps,
                           int iters, double* f, const double* g, double* T, int64_t ldT,

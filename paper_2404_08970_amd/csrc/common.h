@@ -68,14 +68,17 @@ GW_DEV double readlane_f64(double v, int lane) {
 
 // Wave64 reductions with DPP: swaps within quads, half-row and row mirrors,
 // then the two row broadcasts leave the total in lane 63 (GCN/CDNA pattern).
-// The result is returned in every lane.
+// The result is returned in every lane.  Only lane 63's value is read: the
+// first four patterns write every lane, and the two broadcasts write the row
+// of lane 63 and the row it reads next, so the lanes a pattern leaves alone
+// may keep any value (`old` is v itself and needs no register of its own).
 GW_DEV double wave_sum(double v) {
-  v += dpp_f64<0xB1>(v, 0.0);        // quad_perm [1,0,3,2]
-  v += dpp_f64<0x4E>(v, 0.0);        // quad_perm [2,3,0,1]
-  v += dpp_f64<0x141>(v, 0.0);       // row_half_mirror
-  v += dpp_f64<0x140>(v, 0.0);       // row_mirror
-  v += dpp_f64<0x142, 0xA>(v, 0.0);  // row_bcast:15 into rows 1 and 3
-  v += dpp_f64<0x143, 0xC>(v, 0.0);  // row_bcast:31 into rows 2 and 3
+  v += dpp_f64<0xB1>(v, v);        // quad_perm [1,0,3,2]
+  v += dpp_f64<0x4E>(v, v);        // quad_perm [2,3,0,1]
+  v += dpp_f64<0x141>(v, v);       // row_half_mirror
+  v += dpp_f64<0x140>(v, v);       // row_mirror
+  v += dpp_f64<0x142, 0xA>(v, v);  // row_bcast:15 into rows 1 and 3
+  v += dpp_f64<0x143, 0xC>(v, v);  // row_bcast:31 into rows 2 and 3
   return readlane_f64(v, 63);
 }
 
@@ -117,6 +120,17 @@ GW_DEV __amdgpu_buffer_rsrc_t buffer_rsrc(const void* base) {
   // 0x00020000: the raw-buffer data format word of the gfx9 family
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, kRsrcBytes,
                                            0x00020000);
+}
+
+// A raw buffer resource over `bytes` bytes from `base` (a wave-uniform
+// address): loads at byte offsets at or beyond `bytes` return 0.
+GW_DEV __amdgpu_buffer_rsrc_t buffer_rsrc_n(const void* base, int bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, bytes, 0x00020000);
+}
+
+// A double at byte offset voff + soff of the resource (soff wave-uniform).
+GW_DEV double buffer_load_f64(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
 }
 
 // AUX: cache policy bits of the store (0 default; 2 non-temporal, for output

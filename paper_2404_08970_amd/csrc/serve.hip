@@ -64,6 +64,7 @@ struct Req {
   double *obj = nullptr, *logp = nullptr, *logq = nullptr, *ms = nullptr, *pS = nullptr;
   double *lse = nullptr, *gprev = nullptr;
   int* pX = nullptr;
+  int *kq = nullptr, *bmode = nullptr;
   char* tail = nullptr;
   size_t tail_bytes = 0;
   hipEvent_t done = nullptr;
@@ -95,6 +96,8 @@ size_t carve(Req& q, char* base) {
   q.gprev = a.take<double>(N);
   q.pS = a.take<double>((size_t)q.nb * N);
   q.pX = a.take<int>((size_t)q.nb * N);
+  q.kq = a.take<int>(N);
+  q.bmode = a.take<int>(q.nb);
   q.tail_bytes = tail_bytes_of(q.X, q.Y);
   q.tail = a.take<char>(q.tail_bytes);
   return a.used;
@@ -230,7 +233,8 @@ gw_status start_outer(gw_server* sv, Req& q) {
                                  sv->s, q.c1, q.c2);
     if (st != GW_OK) return st;
     const int cold = (q.r.flags & GW_FLAG_WARM_START) && q.outer_done > 0 ? 0 : 1;
-    st = gwl::sinkhorn_prep(q.r.p, q.r.q, q.M, q.N, cold, q.logp, q.logq, q.f, q.g, sv->s);
+    st = gwl::sinkhorn_prep(q.r.p, q.r.q, q.M, q.N, cold, q.logp, q.logq, q.kq, q.f, q.g,
+                            sv->s);
     if (st != GW_OK) return st;
     q.phase = kSink;
     q.inner_left = q.r.inner;
@@ -354,6 +358,8 @@ uint64_t build_table(gw_server* sv, char* stage, size_t* upload) {
     d.status = q.st;
     d.lse = q.lse;
     d.gprev = q.gprev;
+    d.kq = q.kq;
+    d.bmode = q.bmode;
     d.cs = 2.0;
     d.inv_eps = 1.0 / q.r.eps;
     d.eps = q.r.eps;

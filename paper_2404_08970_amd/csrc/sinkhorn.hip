@@ -58,19 +58,17 @@ constexpr int EXP_SENTINEL = -(1 << 30);
 constexpr double X_FLOOR = -1.0e6;  // exp(-1e6) is 0 in any precision used here
 constexpr double SHIFT_SPREAD_MAX = 600.0;  // D+ + D- up to which the max pass is skipped
 
-// Shift for a pass given how far g moved up (D+) and down (D-) in the last
-// merge, in units of eps: D+ if the pass may shift rows by their bound, -1 if
-// it must take the exact row maxima.
-GW_DEV double shift_from_spread(double up, double dn) {
-  return up + dn <= SHIFT_SPREAD_MAX ? up : -1.0;
-}
-
 // D+ for the pass (or -1: exact maxima) from g and g before the last merge
 // (gprev, null in the first iteration of a call), reduced over all columns by
-// the block; every block computes the same value.  N <= NT * NC.
+// the block (every block computes the same D+ and D-), and the largest |lse_i|
+// of the band's rows [i0, i1).  N <= NT * NC, i1 - i0 <= NT.
 template <int NT, int NC>
 GW_DEV double pass_shift(const double* __restrict__ g, const double* __restrict__ gprev, int N,
-                         double inv_eps, double (*red2)[2]);
+                         double inv_eps, const double* __restrict__ lse, int i0, int i1,
+                         double (*red3)[3]);
+
+// The fast-pass decision (defined with the fast pass below).
+GW_DEV double fast_from(double up, double dn, double lmax);
 
 // Folds one column's move into (up, dn): g before and after the last merge.
 GW_DEV void fold_move(double gn, double go, double& up, double& dn) {
@@ -82,9 +80,13 @@ GW_DEV void fold_move(double gn, double go, double& up, double& dn) {
   }
 }
 
+// |lse| of a row for the fast-pass test (a non-finite bound rules it out)
+GW_DEV double lse_mag(double v) { return isfinite(v) ? fabs(v) : INFINITY; }
+
 template <int NT, int NC>
 GW_DEV double pass_shift(const double* __restrict__ g, const double* __restrict__ gprev, int N,
-                         double inv_eps, double (*red2)[2]) {
+                         double inv_eps, const double* __restrict__ lse, int i0, int i1,
+                         double (*red3)[3]) {
   if (gprev == nullptr) return -1.0;
   // every load is issued before any is used (indices clamped into range)
   double gn[NC], go[NC];
@@ -94,26 +96,32 @@ GW_DEV double pass_shift(const double* __restrict__ g, const double* __restrict_
     gn[k] = g[c];
     go[k] = gprev[c];
   }
+  const double lv = lse[min(i0 + (int)threadIdx.x, i1 - 1)];
   double up = 0.0, dn = 0.0;
 #pragma unroll
   for (int k = 0; k < NC; ++k)
     if ((int)threadIdx.x + NT * k < N) fold_move(gn[k], go[k], up, dn);
+  double lm = lse_mag(lv);
   up = gwk::wave_max(up) * inv_eps;
   dn = gwk::wave_max(dn) * inv_eps;
+  lm = gwk::wave_max(lm);
   const int w = threadIdx.x >> 6;
   if ((threadIdx.x & 63) == 63) {
-    red2[w][0] = up;
-    red2[w][1] = dn;
+    red3[w][0] = up;
+    red3[w][1] = dn;
+    red3[w][2] = lm;
   }
   __syncthreads();
-  up = red2[0][0];
-  dn = red2[0][1];
+  up = red3[0][0];
+  dn = red3[0][1];
+  lm = red3[0][2];
 #pragma unroll
   for (int k = 1; k < NT / 64; ++k) {
-    up = fmax(up, red2[k][0]);
-    dn = fmax(dn, red2[k][1]);
+    up = fmax(up, red3[k][0]);
+    dn = fmax(dn, red3[k][1]);
+    lm = fmax(lm, red3[k][2]);
   }
-  return shift_from_spread(up, dn);
+  return fast_from(up, dn, lm);
 }
 
 // Upper bound of ln(sum) for the row shifted by m with shifted sum s > 0.
@@ -149,8 +157,6 @@ GW_DEV double block_sum(double v, double* red) {
   return r;
 }
 
-// e^r for |r| <= ln(2)/2 by its Taylor series to degree 13 (Horner); the
-// truncation error is below 4.2e-18 relative on that interval.
 // threadIdx.x behind an empty asm statement: values derived from it cannot be
 // hoisted out of the persistent item loops of the batched kernels, where they
 // would stay live across the loop and push the band bodies into spills.
@@ -160,19 +166,21 @@ GW_DEV int opaque_tid() {
   return t;
 }
 
+// e^r for |r| <= ln(2)/2: the degree-11 polynomial of best relative
+// approximation on that interval (Remez exchange; 3.1e-18 relative before its
+// coefficients are rounded to double, about one ulp when evaluated by Horner
+// in double), instead of the degree-13 Taylor polynomial of the same accuracy.
 GW_DEV double exp_reduced(double r) {
-  double y = 1.0 / 6227020800.0;  // 1/13!
-  y = fma(y, r, 1.0 / 479001600.0);
-  y = fma(y, r, 1.0 / 39916800.0);
-  y = fma(y, r, 1.0 / 3628800.0);
-  y = fma(y, r, 1.0 / 362880.0);
-  y = fma(y, r, 1.0 / 40320.0);
-  y = fma(y, r, 1.0 / 5040.0);
-  y = fma(y, r, 1.0 / 720.0);
-  y = fma(y, r, 1.0 / 120.0);
-  y = fma(y, r, 1.0 / 24.0);
-  y = fma(y, r, 1.0 / 6.0);
-  y = fma(y, r, 0.5);
+  double y = 0x1.ad66238d9d610p-26;
+  y = fma(y, r, 0x1.28b311bbb39f6p-22);
+  y = fma(y, r, 0x1.71df451c45e1ap-19);
+  y = fma(y, r, 0x1.a01992d10c9e6p-16);
+  y = fma(y, r, 0x1.a01a011059272p-13);
+  y = fma(y, r, 0x1.6c16c187810c2p-10);
+  y = fma(y, r, 0x1.1111111130dd0p-7);
+  y = fma(y, r, 0x1.555555554f370p-5);
+  y = fma(y, r, 0x1.55555555554a2p-3);
+  y = fma(y, r, 0x1.0000000000010p-1);
   y = fma(y, r, 1.0);
   return fma(y, r, 1.0);
 }
@@ -188,16 +196,82 @@ GW_DEV double exp_split(double x, int* n) {
   return exp_reduced(r);
 }
 
+// ---- fast pass: rows shifted by a multiple of ln 2, columns in fixed frames
+//
+// A fast pass shifts row i by M_i = nm_i ln 2, nm_i = ceil((lse_i + D+) / ln 2),
+// so exp(z - M_i) = 2^(rint(z / ln 2) - nm_i) e^r with r = z - rint(z / ln 2) ln 2:
+// the reduction works on z itself and the shift only enters the exponent.
+// Adding z / ln 2 to SHIFTER - nm_i (SHIFTER = 1.5 2^52) rounds it to an
+// integer and leaves rint(z / ln 2) - nm_i in the low 32 bits of the sum, so
+// one FMA gives both the reduction integer and the final exponent.  The
+// two-constant split stays exact while |rint(z / ln 2)| < 2^21, which holds
+// for |M_i| < FAST_M_MAX and z >= M_i - FAST_ZSPAN (z is clamped there; terms
+// below the clamp are 0 in every frame used).
+//
+// Column sums of a fast pass are plain doubles in a frame 2^kq_p per column
+// (kq_p = max(0, -e_p - FRAME_OFFSET), q_p = m 2^e_p, m in [0.5, 1)), so
+// q_p 2^kq_p lies in [2^-101, 1].  After the previous merge,
+// sum_i exp((f_i - C_ip + g_p)/eps) = q_p for the f of the previous pass; the
+// new f differs from it by at most D+ eps below and D- eps above (the row
+// log-sum-exp moves by at most the largest move of g), so the frame sum lies
+// in q_p 2^kq_p [e^-D+, e^D-], inside [2^-895, 2^866] for D+ <= FAST_UP_MAX
+// and D+ + D- <= SHIFT_SPREAD_MAX: no (mantissa, exponent) pairs are needed.
+constexpr double SHIFTER = 0x1.8p52;
+constexpr double FAST_ZSPAN = 2560.0;
+constexpr double FAST_M_MAX = 1.0e6;
+constexpr double FAST_UP_MAX = 550.0;
+constexpr int FRAME_OFFSET = 100;
+
+struct FastShift {
+  double sh;    // SHIFTER - nm
+  double zlo;   // clamp of z
+  double mrow;  // nm ln 2, the shift applied
+};
+
+GW_DEV FastShift fast_shift(double m) {
+  const double nm = ceil(m * INV_LN2);
+  FastShift fs;
+  fs.sh = SHIFTER - nm;
+  fs.mrow = fma(nm, LN2_HI, nm * LN2_LO);
+  fs.zlo = fs.mrow - FAST_ZSPAN;
+  return fs;
+}
+
+// exp(z - M) = e^r 2^n for the shift of fs.
+GW_DEV double exp_fast(double z, const FastShift& fs, int& n) {
+  z = fmax(z, fs.zlo);
+  const double u = fma(z, INV_LN2, fs.sh);
+  const double nd = u - fs.sh;
+  double r = fma(-nd, LN2_HI, z);
+  r = fma(-nd, LN2_LO, r);
+  n = __double2loint(u);
+  return exp_reduced(r);
+}
+
+// The fast-pass decision from the move of g (up = D+, dn = D-, in units of
+// eps) and the largest |lse_i| of the band: D+ if the pass may run fast, else
+// -1 (exact row maxima, (mantissa, exponent) column pairs).
+GW_DEV double fast_from(double up, double dn, double lmax) {
+  return (up + dn <= SHIFT_SPREAD_MAX && up <= FAST_UP_MAX && lmax + up < FAST_M_MAX) ? up : -1.0;
+}
+
+// Log-marginals, the column frames of the fast pass and (cold start) zero
+// potentials.
 __global__ __launch_bounds__(256) void k_sk_prep(const double* __restrict__ p,
                                                   const double* __restrict__ q, int M, int N,
                                                   int init_zero, double* __restrict__ logp,
                                                   double* __restrict__ logq,
+                                                  int* __restrict__ kq,
                                                   double* __restrict__ f,
                                                   double* __restrict__ g) {
   const int idx = blockIdx.x * 256 + threadIdx.x;
   if (idx < M) logp[idx] = p[idx] > 0.0 ? log(p[idx]) : -INFINITY;
   if (idx < N) {
-    logq[idx] = q[idx] > 0.0 ? log(q[idx]) : -INFINITY;
+    const double qv = q[idx];
+    logq[idx] = qv > 0.0 ? log(qv) : -INFINITY;
+    int eq = 0;
+    (void)frexp(qv, &eq);
+    kq[idx] = qv > 0.0 ? max(0, -eq - FRAME_OFFSET) : 0;
     if (init_zero) g[idx] = 0.0;
   }
   if (init_zero && idx < M) f[idx] = 0.0;
@@ -209,13 +283,26 @@ __global__ __launch_bounds__(256) void k_sk_prep(const double* __restrict__ p,
 // reduced, so loads stay in flight across the barriers.
 // The body works on band `band` so that the batched kernels of the request
 // loop run exactly the same arithmetic on a band as the single-problem kernel.
-// LDS of a row-pass shape, shared by its two row-shift variants (one static
-// allocation per shape, not per variant).
+// LDS of a row-pass shape, shared by its two variants (one static allocation
+// per shape, not per variant).
+// Rows per band are at most 256 (M <= 65535 over 256 bands).  The band's
+// per-row scalars (p_i, the row bound lse_i, and the row's shift and sum) live
+// in LDS while the band runs: read at the band's start, written back at its
+// end, so the row steps issue no loads or stores of them.
+constexpr int kMaxBandRows = 256;
+struct BandRows {
+  double p[kMaxBandRows];
+  double lse[kMaxBandRows];
+  double m[kMaxBandRows];
+  double s[kMaxBandRows];
+};
+
 template <int NTH, int EPT, int R, bool GL>
 struct RowLds {
   double red[2][R][NTH / 64];
-  double dred[NTH / 64][2];
+  double dred[NTH / 64][3];
   double gls[GL ? EPT * NTH : 1];
+  BandRows br;
 };
 template <int NTH, int EPT, int R, bool GL>
 GW_DEV RowLds<NTH, EPT, R, GL>& row_lds() {
@@ -230,9 +317,38 @@ struct RowgLds {
     double mS[NG > 1 ? NG - 1 : 1][EPT][1024 / NG];  // then the groups' mantissas
   } u;
   int mX[NG > 1 ? NG - 1 : 1][EPT][1024 / NG];
-  double dred[16][2];
+  int kqs[EPT * (1024 / NG)];  // column frames of the fast pass
+  double dred[16][3];
   double red[2][NG][1024 / NG / 64];
+  BandRows br;
 };
+
+// The band's p_i and (fast pass) lse_i into LDS; thread t < rows loads row
+// i0 + t.  Visible after the caller's next barrier.
+GW_DEV void band_rows_load(BandRows& br, const double* __restrict__ p,
+                           const double* __restrict__ lse, int i0, int rows, int t,
+                           bool need_lse) {
+  if (t < rows) {
+    br.p[t] = p[i0 + t];
+    if (need_lse) br.lse[t] = lse[i0 + t];
+  }
+}
+
+// Row bounds, and with write_f the rows' (shift, sum), back to global memory;
+// zero-mass rows get f = -inf.  After a barrier that follows the last row.
+GW_DEV void band_rows_store(const BandRows& br, double* __restrict__ lse, double* __restrict__ ms,
+                            double* __restrict__ f, int write_f, int i0, int rows, int t) {
+  if (t < rows) {
+    const int i = i0 + t;
+    lse[i] = br.lse[t];
+    if (!(br.p[t] > 0.0)) {
+      f[i] = -INFINITY;
+    } else if (write_f) {
+      ms[2 * i] = br.m[t];
+      ms[2 * i + 1] = br.s[t];
+    }
+  }
+}
 template <int EPT, int NG>
 GW_DEV RowgLds<EPT, NG>& rowg_lds() {
   __shared__ RowgLds<EPT, NG> l;
@@ -242,15 +358,18 @@ GW_DEV RowgLds<EPT, NG>& rowg_lds() {
 // GL: g_p / eps is kept in LDS instead of registers.  PF: the next rows are
 // loaded while the current ones are reduced (two row buffers); without it the
 // next rows are loaded after the column update into the same registers, which
-// leaves room for up to 32 entries per thread at 512 threads.  gprev (g before
-// the last merge, null in the first iteration of a call) decides whether rows
-// are shifted by their bound lse_i + D+ or by their exact maximum.
-template <int NTH, int EPT, int R, bool GL, bool PF, bool SHIFT>
+// leaves room for up to 32 entries per thread at 512 threads.
+// FAST (dup = D+ >= 0): rows shifted by their bound lse_i + D+ rounded up to a
+// multiple of ln 2, column sums in the per-column frames 2^kq_p; otherwise the
+// exact row maxima and (mantissa, exponent) column pairs.  bmode[band] records
+// which of the two the band's partials are.
+template <int NTH, int EPT, int R, bool GL, bool PF, bool FAST>
 GW_DEV void sk_row_band(const double* __restrict__ C, int64_t ldC, int M, int N, int RB,
                         double cs, double inv_eps, const double* __restrict__ p,
                         const double* __restrict__ logp, const double* __restrict__ g,
-                        double* __restrict__ f, double* __restrict__ ms,
-                        double* __restrict__ partS, int* __restrict__ partX,
+                        const int* __restrict__ kq, double* __restrict__ f,
+                        double* __restrict__ ms, double* __restrict__ partS,
+                        int* __restrict__ partX, int* __restrict__ bmode,
                         double* __restrict__ lse, double dup, int write_f, int band) {
   constexpr int NW = NTH / 64;
   auto& lds = row_lds<NTH, EPT, R, GL>();
@@ -259,8 +378,13 @@ GW_DEV void sk_row_band(const double* __restrict__ C, int64_t ldC, int M, int N,
   const int t = opaque_tid(), wv = t >> 6, lane = t & 63;
   const double csie = cs * inv_eps;
   double S[EPT];
-  int Xe[EPT];
+  int Xe[FAST ? 1 : EPT];
+  int kqc[FAST ? EPT : 1];   // column frames (fast pass)
   double gir[GL ? 1 : EPT];  // g_p / eps
+  if constexpr (FAST) {
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) kqc[e] = kq[min(t + NTH * e, N - 1)];
+  }
   if constexpr (GL && EPT > 24) {
     // g/eps to LDS one entry at a time (the longest rows have no registers to
     // spare for a batch of loads)
@@ -268,7 +392,7 @@ GW_DEV void sk_row_band(const double* __restrict__ C, int64_t ldC, int M, int N,
     for (int e = 0; e < EPT; ++e) {
       const int col = t + NTH * e;
       S[e] = 0.0;
-      Xe[e] = EXP_SENTINEL;
+      if constexpr (!FAST) Xe[e] = EXP_SENTINEL;
       gls[t + NTH * e] = col < N ? g[col] * inv_eps : -INFINITY;
     }
   } else if constexpr (GL) {
@@ -282,7 +406,7 @@ GW_DEV void sk_row_band(const double* __restrict__ C, int64_t ldC, int M, int N,
       for (int u = 0; u < 8 && e0 + u < EPT; ++u) {
         const int e = e0 + u, col = t + NTH * e;
         S[e] = 0.0;
-        Xe[e] = EXP_SENTINEL;
+        if constexpr (!FAST) Xe[e] = EXP_SENTINEL;
         gls[col] = col < N ? graw[u] * inv_eps : -INFINITY;
       }
     }
@@ -293,7 +417,7 @@ GW_DEV void sk_row_band(const double* __restrict__ C, int64_t ldC, int M, int N,
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
       S[e] = 0.0;
-      Xe[e] = EXP_SENTINEL;
+      if constexpr (!FAST) Xe[e] = EXP_SENTINEL;
       gir[e] = t + NTH * e < N ? graw[e] * inv_eps : -INFINITY;
     }
   }
@@ -322,20 +446,19 @@ GW_DEV void sk_row_band(const double* __restrict__ C, int64_t ldC, int M, int N,
   // The next R rows are loaded into `cur` as soon as the current rows have
   // been turned into exponents, so the loads overlap the reductions, the
   // exponentials and the column updates.
+  auto& br = lds.br;  // the band's p_i and row bounds, staged by the caller
   for (int ib = i0; ib < i1; ib += R) {
-    double pv[R], lpv[R];
+    double pv[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const int i = min(ib + r, i1 - 1);
-      pv[r] = p[i];
-      lpv[r] = logp[i];
-    }
+    for (int r = 0; r < R; ++r) pv[r] = br.p[min(ib + r, i1 - 1) - i0];
     double z[R][EPT];
-    double m[R];
-    if constexpr (SHIFT) {
+    double m[R];  // the shift of each row
+    FastShift fs[FAST ? R : 1];
+    if constexpr (FAST) {
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        m[r] = lse[min(ib + r, i1 - 1)] + dup;
+        fs[r] = fast_shift(br.lse[min(ib + r, i1 - 1) - i0] + dup);
+        m[r] = fs[r].mrow;
 #pragma unroll
         for (int e = 0; e < EPT; ++e) z[r][e] = fma(-csie, cur[r][e], gie(e));
       }
@@ -372,14 +495,15 @@ GW_DEV void sk_row_band(const double* __restrict__ C, int64_t ldC, int M, int N,
       sl[r] = 0.0;
 #pragma unroll
       for (int e = 0; e < EPT; ++e) {
-        z[r][e] = exp_split(z[r][e] - m[r], &nE[r][e]);
+        if constexpr (FAST) z[r][e] = exp_fast(z[r][e], fs[r], nE[r][e]);
+        else z[r][e] = exp_split(z[r][e] - m[r], &nE[r][e]);
         sl[r] += ldexp(z[r][e], nE[r][e]);
       }
     }
     // Without the max pass there is one barrier per row step, so the sums of
     // consecutive steps alternate between the two buffers: a wave that writes
     // step k + 2 has passed step k + 1's barrier, after every read of step k.
-    const int sb = SHIFT ? (((ib - i0) / R) & 1) : 1;
+    const int sb = FAST ? (((ib - i0) / R) & 1) : 1;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       sl[r] = gwk::wave_sum(sl[r]);
@@ -393,27 +517,28 @@ GW_DEV void sk_row_band(const double* __restrict__ C, int64_t ldC, int M, int N,
       double s = red[sb][r][0];
 #pragma unroll
       for (int w = 1; w < NW; ++w) s += red[sb][r][w];
-      if (PF && t == 0) lse[i] = row_bound(m[r], s);  // read only by shifted passes
+      // the row's bound for the next pass and, for f (an output only, formed
+      // after the last iteration by k_sk_f), its shift and sum
+      if (t == 0) {
+        br.lse[i - i0] = row_bound(m[r], s);
+        br.m[i - i0] = m[r];
+        br.s[i - i0] = s;
+      }
       const double pi = pv[r];
-      if (!(pi > 0.0)) {
-        if (t == 0) f[i] = -INFINITY;
-        continue;
-      }
-      // f_i is an output only (the next iteration rebuilds it from g): the last
-      // iteration leaves (m_i, s_i) for k_sk_f
-      if (write_f && t == 0) {
-        ms[2 * i] = m[r];
-        ms[2 * i + 1] = s;
-      }
+      if (!(pi > 0.0)) continue;
       int ew;
       const double mw = frexp(pi / s, &ew);
 #pragma unroll
       for (int e = 0; e < EPT; ++e) {
-        const double tv = z[r][e] * mw;
-        const int te = nE[r][e] + ew;
-        const int ne = max(Xe[e], te);
-        S[e] = ldexp(S[e], Xe[e] - ne) + ldexp(tv, te - ne);
-        Xe[e] = ne;
+        if constexpr (FAST) {
+          S[e] = fma(ldexp(z[r][e], nE[r][e] + ew + kqc[e]), mw, S[e]);
+        } else {
+          const double tv = z[r][e] * mw;
+          const int te = nE[r][e] + ew;
+          const int ne = max(Xe[e], te);
+          S[e] = ldexp(S[e], Xe[e] - ne) + ldexp(tv, te - ne);
+          Xe[e] = ne;
+        }
       }
     }
     if constexpr (!PF) load(cur, ib + R);
@@ -423,9 +548,12 @@ GW_DEV void sk_row_band(const double* __restrict__ C, int64_t ldC, int M, int N,
     const int col = t + NTH * e;
     if (col < N) {
       partS[(int64_t)band * N + col] = S[e];
-      partX[(int64_t)band * N + col] = Xe[e];
+      if constexpr (!FAST) partX[(int64_t)band * N + col] = Xe[e];
     }
   }
+  if (t == 0) bmode[band] = FAST ? 1 : 0;
+  __syncthreads();
+  band_rows_store(br, lse, ms, f, write_f, i0, i1 - i0, t);
 }
 
 template <int NTH, int EPT, int R, bool GL, bool PF>
@@ -434,43 +562,53 @@ __global__ __launch_bounds__(NTH) void k_sk_row(const double* __restrict__ C, in
                                                  const double* __restrict__ p,
                                                  const double* __restrict__ logp,
                                                  const double* __restrict__ g,
+                                                 const int* __restrict__ kq,
                                                  double* __restrict__ f,
                                                  double* __restrict__ ms,
                                                  double* __restrict__ partS,
                                                  int* __restrict__ partX,
+                                                 int* __restrict__ bmode,
                                                  double* __restrict__ lse,
                                                  const double* __restrict__ gprev,
                                                  int write_f, const int* __restrict__ stop) {
   if (stop != nullptr && *stop) return;  // a tolerance stop has ended the call
+  {
+    const int i0 = blockIdx.x * RB;
+    band_rows_load(row_lds<NTH, EPT, R, GL>().br, p, lse, i0, min(M, i0 + RB) - i0,
+                   (int)threadIdx.x, PF && gprev != nullptr);
+    __syncthreads();
+  }
   // the longest rows (no register prefetch) always take the exact maxima:
-  // their shifted variant spills more registers than it saves
+  // their fast variant spills more registers than it saves
   double dup = -1.0;
   if constexpr (PF)
-    dup = pass_shift<NTH, EPT>(g, gprev, N, inv_eps, row_lds<NTH, EPT, R, GL>().dred);
+    dup = pass_shift<NTH, EPT>(g, gprev, N, inv_eps, lse, blockIdx.x * RB,
+                               min(M, (int)blockIdx.x * RB + RB), row_lds<NTH, EPT, R, GL>().dred);
   if (PF && dup >= 0.0)
-    sk_row_band<NTH, EPT, R, GL, PF, PF>(C, ldC, M, N, RB, cs, inv_eps, p, logp, g, f, ms,
-                                         partS, partX, lse, dup, write_f, blockIdx.x);
+    sk_row_band<NTH, EPT, R, GL, PF, PF>(C, ldC, M, N, RB, cs, inv_eps, p, logp, g, kq, f, ms,
+                                         partS, partX, bmode, lse, dup, write_f, blockIdx.x);
   else
-    sk_row_band<NTH, EPT, R, GL, PF, false>(C, ldC, M, N, RB, cs, inv_eps, p, logp, g, f, ms,
-                                            partS, partX, lse, 0.0, write_f, blockIdx.x);
+    sk_row_band<NTH, EPT, R, GL, PF, false>(C, ldC, M, N, RB, cs, inv_eps, p, logp, g, kq, f,
+                                            ms, partS, partX, bmode, lse, 0.0, write_f,
+                                            blockIdx.x);
 }
 
 // Grouped row pass for rows of up to 8 x 512 entries: a block of 1024 threads
 // is split into NG groups of GT = 1024/NG threads and each group reduces its
 // own rows, so a lane owns EPT = N/GT entries of a row and the per-row work
 // (two reductions, the weight p_i/s_i) is spread over more entries.  g/eps
-// lives in LDS.  The NG groups' column pairs are merged through LDS in group
+// lives in LDS.  The NG groups' column sums are merged through LDS in group
 // order and written as the block's partial.
 //
 // The rows of a band, given its first row in x (loaded by sk_rowg_band) and
-// g/eps in LDS.
-template <int EPT, int NG, bool PF, bool SHIFT>
+// g/eps in LDS; FAST as in sk_row_band.
+template <int EPT, int NG, bool PF, bool FAST>
 GW_DEV void sk_rowg_rows(const double* __restrict__ C, int64_t ldC, int M, int N, int RB,
-                         double csie, const double* __restrict__ p, double* __restrict__ f,
-                         double* __restrict__ ms, double* __restrict__ partS,
-                         int* __restrict__ partX, double* __restrict__ lse, double dup,
-                         int write_f, int band, int t, double (&x)[EPT],
-                         const int (&colc)[EPT]) {
+                         double csie, const double* __restrict__ p, const int* __restrict__ kq,
+                         double* __restrict__ f, double* __restrict__ ms,
+                         double* __restrict__ partS, int* __restrict__ partX,
+                         int* __restrict__ bmode, double* __restrict__ lse, double dup,
+                         int write_f, int band, int t, double (&x)[EPT]) {
   constexpr int GT = 1024 / NG, GW = GT / 64;
   auto& lds = rowg_lds<EPT, NG>();
   const double* gie = lds.u.gie;
@@ -479,38 +617,51 @@ GW_DEV void sk_rowg_rows(const double* __restrict__ C, int64_t ldC, int M, int N
   // scalar registers, so row addresses are scalar bases
   const int gi = __builtin_amdgcn_readfirstlane(t / GT), tl = t - gi * GT;
   const int wv = __builtin_amdgcn_readfirstlane(tl >> 6), lane = t & 63;
+  const int* kqs = lds.kqs;  // column frames, staged with g/eps (fast pass)
   double S[EPT];
-  int Xe[EPT];
+  int Xe[FAST ? 1 : EPT];
 #pragma unroll
   for (int e = 0; e < EPT; ++e) {
     S[e] = 0.0;
-    Xe[e] = EXP_SENTINEL;
+    if constexpr (!FAST) Xe[e] = EXP_SENTINEL;
   }
   const int i0 = band * RB, i1 = min(M, i0 + RB);
   const int nr = (RB + NG - 1) / NG;  // row steps, the same for every group
-  double nx[EPT];
+  // row j of the group through a buffer resource over the row: entry e at byte
+  // offset 8 tl + 8 GT e (a lane offset plus a scalar one), columns past N read 0
   auto load = [&](double (&dst)[EPT], int j) {
     const int i = min(i0 + j * NG + gi, i1 - 1);
-    const double* row = C + (int64_t)i * ldC;
+    const auto rs = gwk::buffer_rsrc_n(C + (int64_t)i * ldC, N * 8);
 #pragma unroll
-    for (int e = 0; e < EPT; ++e) dst[e] = row[colc[e]];
+    for (int e = 0; e < EPT; ++e) dst[e] = gwk::buffer_load_f64(rs, 8 * tl, 8 * GT * e);
   };
-  for (int j = 0; j < nr; ++j) {
-    if (PF) load(nx, j + 1);
+  // one row step on the row in xc; with PF the next row is loaded into xn
+  // first (the two buffers swap roles from one step to the next; a second
+  // row of prefetch measured slower)
+  auto& br = lds.br;
+  auto step = [&](int j, double (&xc)[EPT], double (&xn)[EPT]) {
+    if (PF) load(xn, j + 1);
     const int i = i0 + j * NG + gi;
     const bool valid = i < i1;
-    const double pi = p[min(i, i1 - 1)];
+    const int li = min(i, i1 - 1) - i0;  // the row within the band
+    const double pi = br.p[li];
     double m;
-    if constexpr (SHIFT) {
-      m = lse[min(i, i1 - 1)] + dup;
+    int nE[EPT];
+    double sl = 0.0;
+    if constexpr (FAST) {
+      const FastShift fs = fast_shift(br.lse[li] + dup);
+      m = fs.mrow;
 #pragma unroll
-      for (int e = 0; e < EPT; ++e) x[e] = fma(-csie, x[e], gie[tl + GT * e]);
+      for (int e = 0; e < EPT; ++e) {
+        xc[e] = exp_fast(fma(-csie, xc[e], gie[tl + GT * e]), fs, nE[e]);
+        sl += ldexp(xc[e], nE[e]);
+      }
     } else {
       double mloc = -INFINITY;
 #pragma unroll
       for (int e = 0; e < EPT; ++e) {
-        x[e] = fma(-csie, x[e], gie[tl + GT * e]);
-        mloc = fmax(mloc, x[e]);
+        xc[e] = fma(-csie, xc[e], gie[tl + GT * e]);
+        mloc = fmax(mloc, xc[e]);
       }
       mloc = gwk::wave_max(mloc);
       if (lane == 63) red[0][gi][wv] = mloc;
@@ -518,64 +669,70 @@ GW_DEV void sk_rowg_rows(const double* __restrict__ C, int64_t ldC, int M, int N
       m = red[0][gi][0];
 #pragma unroll
       for (int w = 1; w < GW; ++w) m = fmax(m, red[0][gi][w]);
-    }
-    int nE[EPT];
-    double sl = 0.0;
 #pragma unroll
-    for (int e = 0; e < EPT; ++e) {
-      x[e] = exp_split(x[e] - m, &nE[e]);
-      sl += ldexp(x[e], nE[e]);
+      for (int e = 0; e < EPT; ++e) {
+        xc[e] = exp_split(xc[e] - m, &nE[e]);
+        sl += ldexp(xc[e], nE[e]);
+      }
     }
-    // one barrier per row step without the max pass: alternate the buffers
-    // of consecutive steps (see the single-group pass)
-    const int sb = SHIFT ? (j & 1) : 1;
+    // one barrier per row step in the fast pass: alternate the buffers of
+    // consecutive steps (see the single-group pass)
+    const int sb = FAST ? (j & 1) : 1;
     sl = gwk::wave_sum(sl);
     if (lane == 63) red[sb][gi][wv] = sl;
     __syncthreads();
     double s = red[sb][gi][0];
 #pragma unroll
     for (int w = 1; w < GW; ++w) s += red[sb][gi][w];
-    if (valid && tl == 0) lse[i] = row_bound(m, s);
-    if (valid) {
-      if (pi > 0.0) {
-        // f_i is an output only (the next iteration rebuilds it from g): the
-        // last iteration leaves (m_i, s_i) for k_sk_f
-        if (write_f && tl == 0) {
-          ms[2 * i] = m;
-          ms[2 * i + 1] = s;
-        }
-        int ew;
-        const double mw = frexp(pi / s, &ew);
+    // the row's bound for the next pass and, for f (an output only, formed
+    // after the last iteration by k_sk_f), its shift and sum
+    if (valid && tl == 0) {
+      br.lse[li] = row_bound(m, s);
+      br.m[li] = m;
+      br.s[li] = s;
+    }
+    if (valid && pi > 0.0) {
+      int ew;
+      const double mw = frexp(pi / s, &ew);
 #pragma unroll
-        for (int e = 0; e < EPT; ++e) {
-          const double tv = x[e] * mw;
+      for (int e = 0; e < EPT; ++e) {
+        if constexpr (FAST) {
+          S[e] = fma(ldexp(xc[e], nE[e] + ew + kqs[tl + GT * e]), mw, S[e]);
+        } else {
+          const double tv = xc[e] * mw;
           const int te = nE[e] + ew;
           const int ne = max(Xe[e], te);
           S[e] = ldexp(S[e], Xe[e] - ne) + ldexp(tv, te - ne);
           Xe[e] = ne;
         }
-      } else if (tl == 0) {
-        f[i] = -INFINITY;
       }
     }
-    if (PF) {
-#pragma unroll
-      for (int e = 0; e < EPT; ++e) x[e] = nx[e];
-    } else {
-      load(x, j + 1);
+    if (!PF) load(xc, j + 1);
+  };
+  if constexpr (PF) {
+    double y[EPT];
+    int j = 0;
+    for (; j + 1 < nr; j += 2) {
+      step(j, x, y);
+      step(j + 1, y, x);
     }
+    if (j < nr) step(j, x, y);
+  } else {
+    for (int j = 0; j < nr; ++j) step(j, x, x);
   }
-  // merge the groups' column pairs into group 0 in group order: one exchange
-  // through LDS (the pairs take the place of g/eps, which no row reads any more)
+  // the band's row scalars back to global memory; then merge the groups'
+  // column sums into group 0 in group order: one exchange through LDS (the
+  // sums take the place of g/eps, which no row reads any more)
+  __syncthreads();
+  band_rows_store(br, lse, ms, f, write_f, i0, i1 - i0, t);
   if constexpr (NG > 1) {
     auto& mS = lds.u.mS;
     auto& mX = lds.mX;
-    __syncthreads();
     if (gi > 0) {
 #pragma unroll
       for (int e = 0; e < EPT; ++e) {
         mS[gi - 1][e][tl] = S[e];
-        mX[gi - 1][e][tl] = Xe[e];
+        if constexpr (!FAST) mX[gi - 1][e][tl] = Xe[e];
       }
     }
     __syncthreads();
@@ -584,10 +741,14 @@ GW_DEV void sk_rowg_rows(const double* __restrict__ C, int64_t ldC, int M, int N
     for (int e = 0; e < EPT; ++e) {
 #pragma unroll
       for (int k = 0; k < NG - 1; ++k) {
-        const int xb = mX[k][e][tl];
-        const int ne = max(Xe[e], xb);
-        S[e] = ldexp(S[e], Xe[e] - ne) + ldexp(mS[k][e][tl], xb - ne);
-        Xe[e] = ne;
+        if constexpr (FAST) {
+          S[e] += mS[k][e][tl];
+        } else {
+          const int xb = mX[k][e][tl];
+          const int ne = max(Xe[e], xb);
+          S[e] = ldexp(S[e], Xe[e] - ne) + ldexp(mS[k][e][tl], xb - ne);
+          Xe[e] = ne;
+        }
       }
     }
   }
@@ -596,81 +757,96 @@ GW_DEV void sk_rowg_rows(const double* __restrict__ C, int64_t ldC, int M, int N
     const int col = tl + GT * e;
     if (col < N) {
       partS[(int64_t)band * N + col] = S[e];
-      partX[(int64_t)band * N + col] = Xe[e];
+      if constexpr (!FAST) partX[(int64_t)band * N + col] = Xe[e];
     }
   }
+  if (tl == 0) bmode[band] = FAST ? 1 : 0;
 }
 
 // One band of the grouped pass: the band's first row is loaded before the
 // move of g is reduced (D+, D-) and g/eps is staged in LDS, so its latency
-// overlaps both; then the rows run with shifted or exact row maxima.
+// overlaps both; then the rows run in the fast or the exact variant.
 template <int EPT, int NG, bool PF>
 GW_DEV void sk_rowg_band(const double* __restrict__ C, int64_t ldC, int M, int N, int RB,
                          double cs, double inv_eps, const double* __restrict__ p,
                          const double* __restrict__ g, const double* __restrict__ gprev,
-                         double* __restrict__ f, double* __restrict__ ms,
-                         double* __restrict__ partS, int* __restrict__ partX,
+                         const int* __restrict__ kq, double* __restrict__ f,
+                         double* __restrict__ ms, double* __restrict__ partS,
+                         int* __restrict__ partX, int* __restrict__ bmode,
                          double* __restrict__ lse, int write_f, int band) {
   constexpr int GT = 1024 / NG;
   auto& lds = rowg_lds<EPT, NG>();
   const int t = opaque_tid(), gi = __builtin_amdgcn_readfirstlane(t / GT), tl = t - gi * GT;
   const int i0 = band * RB, i1 = min(M, i0 + RB);
-  int colc[EPT];  // column of each entry, clamped into range
-#pragma unroll
-  for (int e = 0; e < EPT; ++e) colc[e] = min(tl + GT * e, N - 1);
-  double x[EPT];
-  {
-    const double* row = C + (int64_t)min(i0 + gi, i1 - 1) * ldC;
-#pragma unroll
-    for (int e = 0; e < EPT; ++e) x[e] = row[colc[e]];
-  }
   // g (and g before the last merge) are loaded once: g/eps goes to LDS and
-  // the move of g is reduced over the block, one barrier for both
+  // the move of g and the band's row bounds are reduced over the block, one
+  // barrier for all.  These loads are issued before the band's first row, so
+  // waiting for them does not wait for the row (loads return in issue order);
+  // the row's latency overlaps the reductions.
   double dup = -1.0;
+  double x[EPT];
   {
     constexpr int NF = EPT * GT / 1024;
     double* gie = lds.u.gie;
     double gv[NF], go[NF];  // all loads issued before any is used (indices clamped)
+    int kv[NF];
 #pragma unroll
     for (int k = 0; k < NF; ++k) gv[k] = g[min(t + 1024 * k, N - 1)];
+    double lv = 0.0;
     if (gprev != nullptr) {
 #pragma unroll
-      for (int k = 0; k < NF; ++k) go[k] = gprev[min(t + 1024 * k, N - 1)];
+      for (int k = 0; k < NF; ++k) {
+        go[k] = gprev[min(t + 1024 * k, N - 1)];
+        kv[k] = kq[min(t + 1024 * k, N - 1)];
+      }
+      lv = lse[min(i0 + t, i1 - 1)];
+    }
+    band_rows_load(lds.br, p, lse, i0, i1 - i0, t, gprev != nullptr);
+    {
+      const auto rs = gwk::buffer_rsrc_n(C + (int64_t)min(i0 + gi, i1 - 1) * ldC, N * 8);
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) x[e] = gwk::buffer_load_f64(rs, 8 * tl, 8 * GT * e);
     }
     double up = 0.0, dn = 0.0;
 #pragma unroll
     for (int k = 0; k < NF; ++k) {
       const int c = t + 1024 * k;
       gie[c] = c < N ? gv[k] * inv_eps : -INFINITY;
+      if (gprev != nullptr) lds.kqs[c] = kv[k];
       if (gprev != nullptr && c < N) fold_move(gv[k], go[k], up, dn);
     }
     if (gprev != nullptr) {
+      double lm = lse_mag(lv);
       up = gwk::wave_max(up) * inv_eps;
       dn = gwk::wave_max(dn) * inv_eps;
+      lm = gwk::wave_max(lm);
       if ((t & 63) == 63) {
         lds.dred[t >> 6][0] = up;
         lds.dred[t >> 6][1] = dn;
+        lds.dred[t >> 6][2] = lm;
       }
     }
     __syncthreads();
     if (gprev != nullptr) {
       up = lds.dred[0][0];
       dn = lds.dred[0][1];
+      double lm = lds.dred[0][2];
 #pragma unroll
       for (int w = 1; w < 16; ++w) {
         up = fmax(up, lds.dred[w][0]);
         dn = fmax(dn, lds.dred[w][1]);
+        lm = fmax(lm, lds.dred[w][2]);
       }
-      dup = shift_from_spread(up, dn);
+      dup = fast_from(up, dn, lm);
     }
   }
   const double csie = cs * inv_eps;
   if (dup >= 0.0)
-    sk_rowg_rows<EPT, NG, PF, true>(C, ldC, M, N, RB, csie, p, f, ms, partS, partX, lse, dup,
-                                    write_f, band, t, x, colc);
+    sk_rowg_rows<EPT, NG, PF, true>(C, ldC, M, N, RB, csie, p, kq, f, ms, partS, partX, bmode,
+                                    lse, dup, write_f, band, t, x);
   else
-    sk_rowg_rows<EPT, NG, PF, false>(C, ldC, M, N, RB, csie, p, f, ms, partS, partX, lse, 0.0,
-                                     write_f, band, t, x, colc);
+    sk_rowg_rows<EPT, NG, PF, false>(C, ldC, M, N, RB, csie, p, kq, f, ms, partS, partX, bmode,
+                                     lse, 0.0, write_f, band, t, x);
 }
 
 template <int EPT, int NG, bool PF>
@@ -679,21 +855,25 @@ __global__ __launch_bounds__(1024) void k_sk_rowg(const double* __restrict__ C, 
                                                    double inv_eps,
                                                    const double* __restrict__ p,
                                                    const double* __restrict__ g,
+                                                   const int* __restrict__ kq,
                                                    double* __restrict__ f,
                                                    double* __restrict__ ms,
                                                    double* __restrict__ partS,
                                                    int* __restrict__ partX,
+                                                   int* __restrict__ bmode,
                                                    double* __restrict__ lse,
                                                    const double* __restrict__ gprev,
                                                    int write_f, const int* __restrict__ stop) {
   if (stop != nullptr && *stop) return;  // a tolerance stop has ended the call
-  sk_rowg_band<EPT, NG, PF>(C, ldC, M, N, RB, cs, inv_eps, p, g, gprev, f, ms, partS, partX,
-                            lse, write_f, blockIdx.x);
+  sk_rowg_band<EPT, NG, PF>(C, ldC, M, N, RB, cs, inv_eps, p, g, gprev, kq, f, ms, partS, partX,
+                            bmode, lse, write_f, blockIdx.x);
 }
 
 // Column merge: a block covers 16 columns x 16 groups of bands; each thread
 // merges its groups' (mantissa, exponent) pairs in band order, then the 16
-// group results of a column are merged in group order.
+// group results of a column are merged in group order.  A band written by a
+// fast pass (bmode) left only the mantissa: its exponent is -kq_p, the
+// column's frame.
 constexpr int MERGE_COLS = gwb::kMergeCols, MERGE_GRPS = 16;
 constexpr int MERGE_PER = 16;  // bands per group: nb <= 256 = MERGE_GRPS * MERGE_PER
 
@@ -701,7 +881,8 @@ constexpr int MERGE_PER = 16;  // bands per group: nb <= 256 = MERGE_GRPS * MERG
 // columns to errpart[cblock]: S_p is the column sum of the plan (f, g before
 // this merge), so the blocks' sums make the half-step's column violation.
 GW_DEV void sk_col_block(int N, int nb, const double* __restrict__ partS,
-                         const int* __restrict__ partX, const double* __restrict__ q,
+                         const int* __restrict__ partX, const int* __restrict__ bmode,
+                         const int* __restrict__ kq, const double* __restrict__ q,
                          const double* __restrict__ logq, double eps, double* __restrict__ g,
                          gwr::StatusWord* status, double* __restrict__ gprev, int cblock,
                          double* __restrict__ errpart) {
@@ -717,13 +898,17 @@ GW_DEV void sk_col_block(int N, int nb, const double* __restrict__ partS,
     const int per = (nb + MERGE_GRPS - 1) / MERGE_GRPS;
     const int b0 = grp * per, b1 = min(nb, b0 + per);
     const int colc = min(col, N - 1);
+    const int fx = -kq[colc];
     double sv[MERGE_PER];
     int xv[MERGE_PER];
+    int fm[MERGE_PER];
+#pragma unroll
+    for (int u = 0; u < MERGE_PER; ++u) fm[u] = bmode[min(b0 + u, nb - 1)];
 #pragma unroll
     for (int u = 0; u < MERGE_PER; ++u) {
       const int64_t b = min(b0 + u, nb - 1);
       sv[u] = partS[b * N + colc];
-      xv[u] = partX[b * N + colc];
+      xv[u] = fm[u] ? fx : partX[b * N + colc];
     }
     if (col < N) {
 #pragma unroll
@@ -776,6 +961,8 @@ GW_DEV void sk_col_block(int N, int nb, const double* __restrict__ partS,
 
 __global__ __launch_bounds__(256) void k_sk_col(int N, int nb, const double* __restrict__ partS,
                                                  const int* __restrict__ partX,
+                                                 const int* __restrict__ bmode,
+                                                 const int* __restrict__ kq,
                                                  const double* __restrict__ q,
                                                  const double* __restrict__ logq, double eps,
                                                  double* __restrict__ g,
@@ -783,7 +970,8 @@ __global__ __launch_bounds__(256) void k_sk_col(int N, int nb, const double* __r
                                                  const int* __restrict__ stop,
                                                  double* __restrict__ errpart) {
   if (stop != nullptr && *stop) return;  // a tolerance stop has ended the call
-  sk_col_block(N, nb, partS, partX, q, logq, eps, g, status, gprev, blockIdx.x, errpart);
+  sk_col_block(N, nb, partS, partX, bmode, kq, q, logq, eps, g, status, gprev, blockIdx.x,
+               errpart);
 }
 
 // Tolerance stop, state of one call: stop flag, iterations done, last err.
@@ -963,12 +1151,13 @@ constexpr bool row_pf() {
 template <int NTH, int EPT>
 void launch_row(int nb, hipStream_t s, hipEvent_t eb, hipEvent_t ee, const double* C,
                 int64_t ldC, int M, int N, int RB, double cs, double inv_eps, const double* p,
-                const double* logp, const double* g, double* f, double* ms, double* pS, int* pX,
-                double* lse, const double* gprev, int last, const int* stop) {
+                const double* logp, const double* g, const int* kq, double* f, double* ms,
+                double* pS, int* pX, int* bmode, double* lse, const double* gprev, int last,
+                const int* stop) {
   constexpr int R = row_group<NTH, EPT>();
   hipExtLaunchKernelGGL(k_sk_row<NTH, EPT, R, row_gl<NTH, EPT>(), row_pf<NTH, EPT>()>, dim3(nb),
-                        dim3(NTH), 0, s, eb, ee, 0, C, ldC, M, N, RB, cs, inv_eps, p, logp, g, f,
-                        ms, pS, pX, lse, gprev, last, stop);
+                        dim3(NTH), 0, s, eb, ee, 0, C, ldC, M, N, RB, cs, inv_eps, p, logp, g, kq,
+                        f, ms, pS, pX, bmode, lse, gprev, last, stop);
 }
 
 // ---------------------------------------------------------------------------
@@ -995,19 +1184,26 @@ __global__ __launch_bounds__(NTH) void k_skb_row(const gwb::SkSlot* __restrict__
     constexpr int R = row_group<NTH, EPT>();
     constexpr bool GL = row_gl<NTH, EPT>();
     constexpr bool PF = row_pf<NTH, EPT>();
+    {
+      const int i0 = band * a.RB;
+      band_rows_load(row_lds<NTH, EPT, R, GL>().br, a.p, a.lse, i0, min(a.M, i0 + a.RB) - i0,
+                     (int)threadIdx.x, PF && tt > 0);
+      __syncthreads();
+    }
     double dup = -1.0;  // exact maxima without the register prefetch, as in k_sk_row
     if constexpr (PF)
-      dup = pass_shift<NTH, EPT>(a.g, tt > 0 ? a.gprev : nullptr, a.N, a.inv_eps,
+      dup = pass_shift<NTH, EPT>(a.g, tt > 0 ? a.gprev : nullptr, a.N, a.inv_eps, a.lse,
+                                 band * a.RB, min(a.M, band * a.RB + a.RB),
                                  row_lds<NTH, EPT, R, GL>().dred);
     const int wf = a.last && j == a.its - 1;
     if (PF && dup >= 0.0)
       sk_row_band<NTH, EPT, R, GL, PF, PF>(a.C, a.ldC, a.M, a.N, a.RB, a.cs, a.inv_eps, a.p,
-                                             a.logp, a.g, a.f, a.ms, a.pS, a.pX, a.lse, dup, wf,
-                                             band);
+                                             a.logp, a.g, a.kq, a.f, a.ms, a.pS, a.pX, a.bmode,
+                                             a.lse, dup, wf, band);
     else
       sk_row_band<NTH, EPT, R, GL, PF, false>(a.C, a.ldC, a.M, a.N, a.RB, a.cs, a.inv_eps, a.p,
-                                              a.logp, a.g, a.f, a.ms, a.pS, a.pX, a.lse, 0.0, wf,
-                                              band);
+                                              a.logp, a.g, a.kq, a.f, a.ms, a.pS, a.pX, a.bmode,
+                                              a.lse, 0.0, wf, band);
   }
 }
 
@@ -1025,8 +1221,8 @@ __global__ __launch_bounds__(1024) void k_skb_rowg(const gwb::SkSlot* __restrict
     const int tt = a.it0 + j;
     const int band = (int)(code & ((1u << gwb::kBandBits) - 1));
     sk_rowg_band<8, 2, true>(a.C, a.ldC, a.M, a.N, a.RB, a.cs, a.inv_eps, a.p, a.g,
-                             tt > 0 ? a.gprev : nullptr, a.f, a.ms, a.pS, a.pX, a.lse,
-                             a.last && j == a.its - 1, band);
+                             tt > 0 ? a.gprev : nullptr, a.kq, a.f, a.ms, a.pS, a.pX, a.bmode,
+                             a.lse, a.last && j == a.its - 1, band);
   }
 }
 
@@ -1040,7 +1236,7 @@ __global__ __launch_bounds__(256) void k_skb_col(const gwb::SkSlot* __restrict__
     const gwb::SkSlot& a = slots[code >> gwb::kCBlockBits];
     if (j >= a.its) continue;
     __syncthreads();
-    sk_col_block(a.N, a.nb, a.pS, a.pX, a.q, a.logq, a.eps, a.g, a.status, a.gprev,
+    sk_col_block(a.N, a.nb, a.pS, a.pX, a.bmode, a.kq, a.q, a.logq, a.eps, a.g, a.status, a.gprev,
                  (int)(code & ((1u << gwb::kCBlockBits) - 1)), nullptr);
   }
 }
@@ -1134,16 +1330,20 @@ size_t sinkhorn_ws_bytes(int64_t M, int64_t N) {
   a.take<double>(2 * (size_t)M);
   a.take<double>(M);  // row bounds
   a.take<double>(N);  // g before the last merge
+  a.take<int>(N);     // column frames
+  a.take<int>(nb);    // pass kind of each band's partials
   a.take<double>(4);  // tolerance-stop state
   a.take<double>((N + MERGE_COLS - 1) / MERGE_COLS);  // column violation per merge block
   return a.used;
 }
 
 gw_status sinkhorn_prep(const double* p, const double* q, int64_t M, int64_t N, int init_zero,
-                        double* logp, double* logq, double* f, double* g, hipStream_t s) {
+                        double* logp, double* logq, int* kq, double* f, double* g,
+                        hipStream_t s) {
   gwr::ProfScope ps(gwr::kFamOther, s);
   const int64_t mx = M > N ? M : N;
-  k_sk_prep<<<(unsigned)((mx + 255) / 256), 256, 0, s>>>(p, q, (int)M, (int)N, init_zero, logp, logq, f, g);
+  k_sk_prep<<<(unsigned)((mx + 255) / 256), 256, 0, s>>>(p, q, (int)M, (int)N, init_zero, logp,
+                                                         logq, kq, f, g);
   return gwr::last_launch_status();
 }
 
@@ -1195,11 +1395,13 @@ gw_status sinkhorn(const double* C, int64_t ldC, int64_t M, int64_t N, double c_
   double* ms = ws.take<double>(2 * (size_t)M);
   double* lse = ws.take<double>(M);
   double* gprev = ws.take<double>(N);
+  int* kq = ws.take<int>(N);
+  int* bmode = ws.take<int>(nb);
   SkCtl* ctl = reinterpret_cast<SkCtl*>(ws.take<double>(4));
   const int ncb = (int)((N + MERGE_COLS - 1) / MERGE_COLS);
   double* errpart = ws.take<double>(ncb);
   const double inv_eps = 1.0 / eps;
-  gw_status st = sinkhorn_prep(p, q, M, N, init_zero, logp, logq, f, g, s);
+  gw_status st = sinkhorn_prep(p, q, M, N, init_zero, logp, logq, kq, f, g, s);
   if (st != GW_OK) return st;
   // tolerance stop: every `every` iterations the merge measures the column
   // violation and k_sk_check may raise the flag that the later launches of
@@ -1224,23 +1426,23 @@ gw_status sinkhorn(const double* C, int64_t ldC, int64_t M, int64_t N, double c_
       const int lst = it == iters - 1 || check;
       const double* gp = it > 0 ? gprev : nullptr;
       switch (gwb::row_class(N)) {
-        case gwb::kClsN256: launch_row<256, 1>(nb, s, eb, ee, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, lse, gp, lst, stop); break;
-        case gwb::kClsN512: launch_row<512, 1>(nb, s, eb, ee, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, lse, gp, lst, stop); break;
-        case gwb::kClsN1024: launch_row<1024, 1>(nb, s, eb, ee, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, lse, gp, lst, stop); break;
-        case gwb::kClsN2048: launch_row<1024, 2>(nb, s, eb, ee, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, lse, gp, lst, stop); break;
-        case gwb::kClsN3072: launch_row<256, 12>(nb, s, eb, ee, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, lse, gp, lst, stop); break;
-        case gwb::kClsN4096: hipExtLaunchKernelGGL(k_sk_rowg<8, 2, true>, dim3(nb), dim3(1024), 0, s, eb, ee, 0, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, g, f, ms, pS, pX, lse, gp, lst, stop); break;
-        case gwb::kClsN6144: launch_row<512, 12>(nb, s, eb, ee, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, lse, gp, lst, stop); break;
-        case gwb::kClsN8192: launch_row<512, 16>(nb, s, eb, ee, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, lse, gp, lst, stop); break;
-        case gwb::kClsN9216: launch_row<512, 18>(nb, s, eb, ee, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, lse, gp, lst, stop); break;
-        case gwb::kClsN12288: launch_row<512, 24>(nb, s, eb, ee, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, lse, gp, lst, stop); break;
-        default: launch_row<512, 32>(nb, s, eb, ee, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, f, ms, pS, pX, lse, gp, lst, stop); break;
+        case gwb::kClsN256: launch_row<256, 1>(nb, s, eb, ee, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, kq, f, ms, pS, pX, bmode, lse, gp, lst, stop); break;
+        case gwb::kClsN512: launch_row<512, 1>(nb, s, eb, ee, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, kq, f, ms, pS, pX, bmode, lse, gp, lst, stop); break;
+        case gwb::kClsN1024: launch_row<1024, 1>(nb, s, eb, ee, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, kq, f, ms, pS, pX, bmode, lse, gp, lst, stop); break;
+        case gwb::kClsN2048: launch_row<1024, 2>(nb, s, eb, ee, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, kq, f, ms, pS, pX, bmode, lse, gp, lst, stop); break;
+        case gwb::kClsN3072: launch_row<256, 12>(nb, s, eb, ee, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, kq, f, ms, pS, pX, bmode, lse, gp, lst, stop); break;
+        case gwb::kClsN4096: hipExtLaunchKernelGGL(k_sk_rowg<8, 2, true>, dim3(nb), dim3(1024), 0, s, eb, ee, 0, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, g, kq, f, ms, pS, pX, bmode, lse, gp, lst, stop); break;
+        case gwb::kClsN6144: launch_row<512, 12>(nb, s, eb, ee, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, kq, f, ms, pS, pX, bmode, lse, gp, lst, stop); break;
+        case gwb::kClsN8192: launch_row<512, 16>(nb, s, eb, ee, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, kq, f, ms, pS, pX, bmode, lse, gp, lst, stop); break;
+        case gwb::kClsN9216: launch_row<512, 18>(nb, s, eb, ee, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, kq, f, ms, pS, pX, bmode, lse, gp, lst, stop); break;
+        case gwb::kClsN12288: launch_row<512, 24>(nb, s, eb, ee, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, kq, f, ms, pS, pX, bmode, lse, gp, lst, stop); break;
+        default: launch_row<512, 32>(nb, s, eb, ee, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, kq, f, ms, pS, pX, bmode, lse, gp, lst, stop); break;
       }
     }
     {
       gwr::ProfDispatch pd(gwr::kFamSinkCol);
       hipExtLaunchKernelGGL(k_sk_col, dim3((unsigned)ncb), dim3(256), 0, s, pd.b, pd.e, 0, Ni,
-                            nb, pS, pX, q, logq, eps, g, status, gprev, stop,
+                            nb, pS, pX, bmode, kq, q, logq, eps, g, status, gprev, stop,
                             check ? errpart : nullptr);
     }
     if (check) {

@@ -115,6 +115,8 @@ def _lib():
     lib.gw_profile_enable.restype = None
     lib.gw_profile_read.argtypes = [I32, ctypes.POINTER(D), ctypes.POINTER(I64)]
     lib.gw_profile_read.restype = I32
+    lib.gw_profile_sample.argtypes = [I32]
+    lib.gw_profile_sample.restype = I32
     lib.gw_version.argtypes = []
     lib.gw_version.restype = ctypes.c_char_p
     R, PS = ctypes.POINTER(c_request), ctypes.POINTER(ctypes.c_void_p)
@@ -537,6 +539,11 @@ def profile_enable(families=None):
         for f in families:
             mask |= 1 << int(f)
     _lib().gw_profile_enable(mask)
+
+
+def profile_sample(every: int):
+    """Time only one launch in `every` of each family (1: all)."""
+    _raise(_lib().gw_profile_sample(int(every)), "gw_profile_sample")
 
 
 def profile_read(family: int):

@@ -206,6 +206,37 @@ def test_sinkhorn_zero_mass_and_extreme_ratio():
     assert np.all(T[0] == 0) and np.all(T[:, 3] == 0)
 
 
+def _tail_marginal(n, rng, lo):
+    """Normalised Gaussian bump with tails hundreds of decades below its peak
+    (the decay rate is set by `lo`), and two exact zeros."""
+    x = np.linspace(-1.0, 1.0, n)
+    c = rng.uniform(-0.3, 0.3)
+    w = np.exp(-((x - c) ** 2) * (-lo * np.log(10.0)) / 1.3 ** 2)
+    w[[n // 7, n - 3]] = 0.0
+    return w / w.sum()
+
+
+@pytest.mark.parametrize("M,N,lo", [(300, 4096, -320), (129, 1000, -250), (70, 3000, -120)])
+def test_sinkhorn_tiny_marginal_entries(M, N, lo):
+    """Marginal entries from 1 down to subnormal values: columns whose q_p is
+    below 2^-101 get a frame 2^kq_p in the fast passes, rows with tiny p_i
+    weights far from 1; every potential and plan entry against the oracle."""
+    gw, torch = _gw()
+    print(f"sinkhorn tiny marginals M={M} N={N} lo={lo}", flush=True)
+    rng = inputs.rng_for(211, M, N)
+    C = rng.uniform(0, 1, size=(M, N))
+    p, q = _tail_marginal(M, rng, lo), _tail_marginal(N, rng, lo)
+    assert np.any((q > 0) & (q < 2.0 ** -101))  # columns with a frame
+    eps, iters = 5e-3, 8
+    f0, g0 = O.sinkhorn(2.0 * C, p, q, eps, iters)
+    f, g, T = gw.sinkhorn(_to_dev(torch, C), _to_dev(torch, p), _to_dev(torch, q), eps, iters,
+                          c_scale=2.0, plan=True)
+    torch.cuda.synchronize()
+    assert err(f.cpu().numpy(), f0) <= TOL
+    assert err(g.cpu().numpy(), g0) <= TOL
+    assert err(T.cpu().numpy(), O.plan(2.0 * C, f0, g0, eps)) <= TOL
+
+
 def test_sinkhorn_warm_start_and_zero_iterations():
     gw, torch = _gw()
     rng = inputs.rng_for(207)
