@@ -617,13 +617,14 @@ GW_DEV void sk_rowg_rows(const double* __restrict__ C, int64_t ldC, int M, int N
   // scalar registers, so row addresses are scalar bases
   const int gi = __builtin_amdgcn_readfirstlane(t / GT), tl = t - gi * GT;
   const int wv = __builtin_amdgcn_readfirstlane(tl >> 6), lane = t & 63;
-  const int* kqs = lds.kqs;  // column frames, staged with g/eps (fast pass)
   double S[EPT];
   int Xe[FAST ? 1 : EPT];
+  int kqc[FAST ? EPT : 1];  // column frames (fast pass), staged with g/eps
 #pragma unroll
   for (int e = 0; e < EPT; ++e) {
     S[e] = 0.0;
-    if constexpr (!FAST) Xe[e] = EXP_SENTINEL;
+    if constexpr (FAST) kqc[e] = lds.kqs[tl + GT * e];
+    else Xe[e] = EXP_SENTINEL;
   }
   const int i0 = band * RB, i1 = min(M, i0 + RB);
   const int nr = (RB + NG - 1) / NG;  // row steps, the same for every group
@@ -697,7 +698,7 @@ GW_DEV void sk_rowg_rows(const double* __restrict__ C, int64_t ldC, int M, int N
 #pragma unroll
       for (int e = 0; e < EPT; ++e) {
         if constexpr (FAST) {
-          S[e] = fma(ldexp(xc[e], nE[e] + ew + kqs[tl + GT * e]), mw, S[e]);
+          S[e] = fma(ldexp(xc[e], nE[e] + ew + kqc[e]), mw, S[e]);
         } else {
           const double tv = xc[e] * mw;
           const int te = nE[e] + ew;
