@@ -7,11 +7,13 @@ timed region.  `value` is solves per second over the K timed steps.
 
 Beside the headline the JSON line carries: gradient evaluations per second for
 the FAST recursion and the dense FP64 matrix-core product at n = 4096 (and the
-FAST/dense ratio at n = 16384), the roofline of the dominant kernel (the
-Sinkhorn row pass) measured with HIP events over the timed region, the CPU
-oracle timed on a bounded sample, and the request loop on a stream of uneven
-solves (saturated throughput, then Poisson arrivals at 0.8x of it: p50/p99
-latency and solves/s).
+FAST/dense ratio at n = 16384), the same solve with the dense gradient, the
+n = 200 uniform-marginal dense workload, the roofline of the dominant kernel
+(the Sinkhorn row pass) measured with HIP events over the timed region, warm
+and with its cost matrix streamed from HBM, and its VALU issue rate, the CPU
+oracle timed on a bounded sample (which also checks the audited GPU results),
+and the request loop on a stream of 2000 uneven solves (saturated throughput,
+then Poisson arrivals at 0.8x of it: p50/p99 latency and solves/s).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-big]
                        [--no-serve] [--serve-requests R] [--serve-only] [--serve-boost B]
@@ -62,33 +64,58 @@ def time_gpu(fn, reps, torch):
     return start.elapsed_time(stop) / reps
 
 
-def cpu_baseline(k=2):
-    """The oracle (numpy FP64, single thread for these routines) on one outer
-    step of the same workload: its recursion gradient, a 10-iteration Sinkhorn
-    sample and the plan; scaled to solves/s for 100 x 100."""
+def cpu_baseline(k=2, audits=None):
+    """The oracle (numpy FP64, held to one thread) on one outer step of the same
+    workload: its recursion gradient, a 10-iteration Sinkhorn sample and the
+    plan; scaled to solves/s for 100 x 100.  The oracle also checks the GPU
+    results collected for audit (`audits`: name -> (problem, GPU plan)): their
+    relative plan and objective errors go under `oracle_audits`."""
     import numpy as np
+    from threadpoolctl import threadpool_limits
     from oracle import gw_oracle as O
-    p, q = marginals(N, k)
-    g = O.Grid((N,), 1.0 / (N - 1), k)
-    T = np.outer(p, q)
-    t0 = time.perf_counter()
-    G = O.grad_pascal(g, g, p, q, T)
-    t1 = time.perf_counter()
-    its = 10
-    f, gg = O.sinkhorn(2.0 * G, p, q, EPS, its)
-    t2 = time.perf_counter()
-    O.plan(2.0 * G, f, gg, EPS)
-    t3 = time.perf_counter()
+    with threadpool_limits(limits=1):
+        p, q = marginals(N, k)
+        g = O.Grid((N,), 1.0 / (N - 1), k)
+        T = np.outer(p, q)
+        t0 = time.perf_counter()
+        G = O.grad_pascal(g, g, p, q, T)
+        t1 = time.perf_counter()
+        its = 10
+        f, gg = O.sinkhorn(2.0 * G, p, q, EPS, its)
+        t2 = time.perf_counter()
+        O.plan(2.0 * G, f, gg, EPS)
+        t3 = time.perf_counter()
     per_outer = (t1 - t0) + (t2 - t1) / its * INNER + (t3 - t2)
-    return {
+    out = {
         "value": 1.0 / (OUTER * per_outer),
         "unit": "solves/s",
         "cores": 1,
         "kind": "oracle",
         "sample": (f"n=4096 k={k}: one recursion gradient ({t1 - t0:.2f} s), {its} Sinkhorn "
                    f"iterations ({t2 - t1:.2f} s) and one plan ({t3 - t2:.2f} s), scaled to "
-                   f"{OUTER} outer x {INNER} inner iterations"),
+                   f"{OUTER} outer x {INNER} inner iterations; numpy held to one thread"),
     }
+    if audits:
+        res = {}
+        for name, (prob, Tg, Eg) in audits.items():
+            og = O.Grid(tuple(prob["shape"]), prob["h"], prob["k"])
+            T0, _, _, (E0, _) = O.solve(og, og, prob["p"], prob["q"], prob["eps"], prob["outer"],
+                                        prob["inner"], gradient=prob.get("gradient", "dense"))
+            cands = {"T": T0}
+            if prob.get("reflection"):
+                cands["R_X T"] = T0[::-1]
+            errs = {c: float(np.max(np.abs(Tg - v)) / np.max(np.abs(v))) for c, v in cands.items()}
+            pick = min(errs, key=errs.get)
+            r = {"shape": list(prob["shape"]), "k": prob["k"], "eps": round(prob["eps"], 6),
+                 "rel_err_T": errs[pick]}
+            if len(cands) > 1:
+                r["matched"] = pick
+            if Eg is not None:
+                r["rel_err_objective"] = abs(Eg - E0) / abs(E0)
+            res[name] = r
+        out["oracle_audits"] = res
+        out["oracle_audits_max_rel_err_T"] = max(r["rel_err_T"] for r in res.values())
+    return out
 
 
 def profile_target(target: str, reps: int):
@@ -355,12 +382,70 @@ def fgw_bench(n: int = 4000, theta: float = 0.5, eps: float = 2e-3, outer: int =
     fgw(); torch.cuda.synchronize()
     gf_ms = time_gpu(lambda: gw.grad_fgw(X, X, p, q, x, x, theta, T, out=G, ws=gws), 20, torch)
     gg_ms = time_gpu(lambda: gw.grad(X, X, p, q, T, out=G, ws=gws), 20, torch)
+    # the workload as printed: the feature cost is the index difference |i - p|
+    idx = torch.arange(n, dtype=torch.float64, device=dev)
+    lit = lambda: gw.solve_fgw(X, X, p, q, idx, idx, theta, eps, outer, inner, T=T, f=f, g=g,
+                               obj=obj, ws=ws)
+    lit_ms = time_gpu(lit, reps, torch)
+    E_lit = float(obj[0].item())
+    gw.check_status(ws)
     return {"workload": f"1D FGW n = {n}, k = 1, uniform-random marginals, theta = {theta}, "
                         f"c_ip = |x_i - y_p|, eps = {eps}, {outer} outer x {inner} Sinkhorn",
             "fgw_solves_per_s": round(1e3 / fgw_ms, 3), "fgw_ms_per_solve": round(fgw_ms, 2),
             "gw_ms_per_solve_same_problem": round(gw_ms, 2),
             "fgw_grad_us": round(gf_ms * 1e3, 1), "gw_grad_us": round(gg_ms * 1e3, 1),
-            "objective_fgw": E_fgw}
+            "objective_fgw": E_fgw,
+            "index_cost": {"workload": "the same with c_ip = |i - p| (index difference)",
+                           "fgw_solves_per_s": round(1e3 / lit_ms, 3),
+                           "fgw_ms_per_solve": round(lit_ms, 2), "objective_fgw": E_lit}}
+
+
+def dense_solve_bench(torch, gw, X, pq, outer: int = OUTER, inner: int = INNER):
+    """One solve of the headline workload (k = 2) with the dense FP64 matrix-core
+    gradient instead of the FAST recursion (same Sinkhorn)."""
+    p, q = pq
+    T = torch.empty((N, N), dtype=torch.float64, device=p.device)
+    f = torch.empty(N, dtype=torch.float64, device=p.device)
+    g = torch.empty(N, dtype=torch.float64, device=p.device)
+    obj = torch.empty(2, dtype=torch.float64, device=p.device)
+    ws = gw.workspace(gw.workspace_bytes(X, X, gw.PATH_DENSE_F64, gw.OP_SOLVE), p.device, key="ds")
+    gw.solve(X, X, p, q, EPS, 1, 2, path="dense", T=T, f=f, g=g, obj=obj, ws=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gw.solve(X, X, p, q, EPS, outer, inner, path="dense", T=T, f=f, g=g, obj=obj, ws=ws)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    gw.check_status(ws)
+    return {"workload": f"1D n = {N}, k = 2, the headline solve ({outer} x {inner}) with the "
+                        "dense FP64 gradient", "dense_f64_solves_per_s": round(1.0 / dt, 4),
+            "ms_per_solve": round(dt * 1e3, 1), "objective": float(obj[0].item())}
+
+
+def uniform_n200_bench():
+    """The 1D uniform workload: n = 200 on [0,1], |x_i - x_j|^2, p = q uniform,
+    eps = 5e-3, 50 outer x 100 Sinkhorn, dense FP64 gradient; solves/s, and the
+    plan (handed to the oracle audit of the CPU leg, which compares it with the
+    oracle's T or its reflection R_X T: GW is reflection invariant and this
+    start is symmetric)."""
+    import torch
+    from paper_2404_08970_amd import gw
+    dev = torch.device("cuda:0")
+    n, k, eps, outer, inner = 200, 2, 5e-3, 50, 100
+    X = gw.unit_grid((n,), k)
+    pd = torch.full((n,), 1.0 / n, dtype=torch.float64, device=dev)
+    gw.solve(X, X, pd, pd, eps, 2, 5, path="dense")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    T, f, g, obj = gw.solve(X, X, pd, pd, eps, outer, inner, path="dense")
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prob = {"shape": (n,), "h": X.h, "k": k, "p": np.full(n, 1.0 / n), "q": np.full(n, 1.0 / n),
+            "eps": eps, "outer": outer, "inner": inner, "reflection": True}
+    audit = (prob, T.cpu().numpy(), float(obj[0].item()))
+    return {"workload": f"1D n = {n} on [0,1], k = {k}, p = q uniform, eps = {eps}, {outer} outer x "
+                        f"{inner} Sinkhorn, dense FP64", "solves_per_s": round(1.0 / dt, 2),
+            "ms_per_solve": round(dt * 1e3, 2),
+            "accuracy": "checked by the oracle in cpu_baseline.oracle_audits (T or R_X T)"}, audit
 
 
 def tolerance_bench(tol: float = 1e-4, every: int = 10):
@@ -439,19 +524,21 @@ def precision_study(n: int = 16384, k: int = 2, rows: int = 6):
     return out
 
 
-def serve_bench(n_req: int = 200, slots: int = 32, iters: int = 10, load: float = 0.8,
-                arena_gb: float = 48.0, outer: int = 10, inner: int = 100, boost: int = 4):
+def serve_bench(n_req: int = 2000, slots: int = 32, iters: int = 10, load: float = 0.8,
+                arena_gb: float = 48.0, outer: int = 10, inner: int = 100, boost: int = 4,
+                n_cmp: int = 200):
     """Request loop on the serving stream: 70% 1D n ~ U{128..8192}, 30% 2D
     s ~ U{16..96} (L1POW), k ~ U{1,2}, eps ~ U[1e-3,1e-2], mixture / blob
-    marginals, 10 outer x 100 Sinkhorn iterations each.  The `n_req` requests
-    all submitted at t = 0 give the saturated rate; the same requests with
-    Poisson arrivals at `load` x that rate give p50/p99 of completion minus
-    arrival.  Completion times come from each request's HIP completion event.
-    Both are measured with equal iteration quotas and with size quotas
-    (`boost`), the Poisson runs on the same arrival times."""
+    marginals, 10 outer x 100 Sinkhorn iterations each.  The first `n_cmp`
+    requests all submitted at t = 0 give the saturated rate; the `n_req`
+    requests with Poisson arrivals at `load` x that rate give p50/p99 of
+    completion minus arrival (size quotas, `boost`).  Completion times come
+    from each request's HIP completion event.  Equal iteration quotas are
+    measured on the first `n_cmp` requests (saturated and Poisson, the same
+    arrival times) for comparison.  Results of a few requests of each kind
+    are audited against the oracle."""
     import numpy as np
     import torch
-    from oracle import gw_oracle as O
     from paper_2404_08970_amd import gw, inputs
     dev = torch.device("cuda:0")
     reqs = inputs.serving_requests(n_req, seed=5)
@@ -495,40 +582,53 @@ def serve_bench(n_req: int = 200, slots: int = 32, iters: int = 10, load: float 
     # warm-up (not timed): one short solve of each request shape class in the stream
     run(dreqs[:24], [0.0] * 24, 1, iters)
     torch.cuda.synchronize()
-    lat_sat, fin_sat, steps_sat = run(dreqs, [0.0] * n_req, outer, inner, "saturated, equal quotas")
-    sat = n_req / float(fin_sat.max())
-    rate = load * sat
-    arr = np.array([r["arrival"] for r in reqs])
-    arr = (arr - arr[0]) / rate
-    lat_eq, fin_eq, steps_eq = run(dreqs, arr.tolist(), outer, inner, "Poisson, equal quotas")
+    cmp = dreqs[:n_cmp]
+    lat_sat, fin_sat, steps_sat = run(cmp, [0.0] * n_cmp, outer, inner, "saturated, equal quotas")
+    sat = n_cmp / float(fin_sat.max())
+    arr_all = np.array([r["arrival"] for r in reqs])
+    arr_all = arr_all - arr_all[0]
+    arr_eq = (arr_all[:n_cmp] / (load * sat)).tolist()
+    lat_eq, fin_eq, steps_eq = run(cmp, arr_eq, outer, inner, "Poisson, equal quotas")
     sv.set_boost(boost)
     run(dreqs[:24], [0.0] * 24, 1, iters)
     torch.cuda.synchronize()
-    lat_satb, fin_satb, _ = run(dreqs, [0.0] * n_req, outer, inner, "saturated, size quotas")
-    lat, fin, steps = run(dreqs, arr.tolist(), outer, inner, "Poisson, size quotas")
+    lat_satb, fin_satb, _ = run(cmp, [0.0] * n_cmp, outer, inner, "saturated, size quotas")
+    satb = n_cmp / float(fin_satb.max())
+    rate = load * satb
+    lat, fin, steps = run(dreqs, (arr_all / rate).tolist(), outer, inner, "Poisson, size quotas")
 
-    # accuracy: the smallest 1D request of the stream against the oracle (the
-    # result of a request is the same in any mix, so it is solved alone here)
+    # accuracy: a few requests of each kind against the oracle (the result of a
+    # request is the same in any mix, so they are solved alone here): the
+    # smallest 1D one, a 1D one near n = 300, the smallest 2D one of each k
     ones = [i for i in range(len(reqs)) if len(reqs[i]["shape"]) == 1]
-    ic = min(ones, key=lambda i: reqs[i]["shape"][0])
-    X, p, q, eps = dreqs[ic]
-    rid = sv.submit(X, X, p, q, eps, outer, inner)
-    while sv.poll(rid) != gw.REQ_DONE:
-        sv.step()
-    T = sv.result(rid)["T"].cpu().numpy()
-    sv.release(rid)
+    twos = [i for i in range(len(reqs)) if len(reqs[i]["shape"]) == 2]
+    picks = [min(ones, key=lambda i: reqs[i]["shape"][0]),
+             min(ones, key=lambda i: abs(reqs[i]["shape"][0] - 300))]
+    for kk in (1, 2):
+        cand = [i for i in twos if reqs[i]["k"] == kk]
+        if cand:
+            picks.append(min(cand, key=lambda i: reqs[i]["shape"][0]))
+    audit = {}
+    for ic in picks:
+        X, p, q, eps = dreqs[ic]
+        rid = sv.submit(X, X, p, q, eps, outer, inner)
+        while sv.poll(rid) != gw.REQ_DONE:
+            sv.step()
+        T = sv.result(rid)["T"].cpu().numpy()
+        sv.release(rid)
+        prob = {"shape": tuple(reqs[ic]["shape"]), "h": X.h, "k": X.k, "p": reqs[ic]["p"],
+                "q": reqs[ic]["q"], "eps": eps, "outer": outer, "inner": inner}
+        audit[f"serving_request_{ic}"] = (prob, T, None)
     sv.close()
-    og = O.Grid(reqs[ic]["shape"], X.h, X.k)
-    T0 = O.solve(og, og, reqs[ic]["p"], reqs[ic]["q"], eps, outer, inner)[0]
-    acc = float(np.max(np.abs(T - T0)) / np.max(np.abs(T0)))
     n1 = sum(1 for r in reqs if len(r["shape"]) == 1)
     return {
         "workload": (f"{n_req} requests, Poisson arrivals at {load}x the saturated rate; "
                      f"{n1} 1D n~U{{128..8192}}, {n_req - n1} 2D s~U{{16..96}} (L1POW); "
                      f"k~U{{1,2}}, eps~U[1e-3,1e-2]; {outer} outer x {inner} Sinkhorn iterations"),
         "size_quota_boost": boost,
-        "saturated_solves_per_s": round(n_req / float(fin_satb.max()), 2),
+        "saturated_solves_per_s": round(satb, 2),
         "saturated_p50_ms": round(float(np.percentile(lat_satb, 50)) * 1e3, 1),
+        "saturated_measured_on": f"the first {n_cmp} requests",
         "offered_rate_per_s": round(rate, 2),
         "solves_per_s": round(n_req / float(fin.max()), 2),
         "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 1),
@@ -536,18 +636,20 @@ def serve_bench(n_req: int = 200, slots: int = 32, iters: int = 10, load: float 
         "mean_ms": round(float(lat.mean()) * 1e3, 1),
         "steps": steps,
         "equal_quotas": {
+            "requests": n_cmp,
             "saturated_solves_per_s": round(sat, 2),
             "saturated_p50_ms": round(float(np.percentile(lat_sat, 50)) * 1e3, 1),
-            "solves_per_s": round(n_req / float(fin_eq.max()), 2),
+            "solves_per_s": round(n_cmp / float(fin_eq.max()), 2),
             "p50_ms": round(float(np.percentile(lat_eq, 50)) * 1e3, 1),
             "p99_ms": round(float(np.percentile(lat_eq, 99)) * 1e3, 1),
             "mean_ms": round(float(lat_eq.mean()) * 1e3, 1),
             "steps": steps_eq},
         "max_slots": slots, "iters_per_step": iters, "arena_GB": arena_gb,
-        "accuracy": {"request_n": reqs[ic]["shape"][0], "k": X.k, "eps": round(eps, 6),
-                     "rel_err_T_vs_oracle": acc,
-                     "note": "each result equals gw_solve (FAST FP64) bit for bit in any mix"},
-    }
+        "accuracy": {"audited_requests": sorted(audit),
+                     "note": "each result equals gw_solve (FAST FP64) bit for bit in any mix; "
+                             "the audited requests' plans are checked by the oracle in "
+                             "cpu_baseline.oracle_audits"},
+    }, audit
 
 
 def main():
@@ -574,7 +676,7 @@ def main():
     ap.add_argument("--only-fgw", action="store_true", help="run only the 1D fused GW solve and exit")
     ap.add_argument("--only-2d", action="store_true", help="run only the 2D 64x64 solve and exit")
     ap.add_argument("--serve-only", action="store_true", help="run only the request loop and exit")
-    ap.add_argument("--serve-requests", type=int, default=200)
+    ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-slots", type=int, default=32)
     ap.add_argument("--serve-iters", type=int, default=10)
     ap.add_argument("--serve-boost", type=int, default=4,
@@ -599,7 +701,11 @@ def main():
         print(json.dumps(grid2d_bench()))
         return
     if args.serve_only:
-        print(json.dumps(serve_bench(args.serve_requests, args.serve_slots, args.serve_iters, boost=args.serve_boost)))
+        res, audit = serve_bench(args.serve_requests, args.serve_slots, args.serve_iters,
+                                 boost=args.serve_boost)
+        if not args.no_cpu:
+            res["oracle_audits"] = cpu_baseline(audits=audit)["oracle_audits"]
+        print(json.dumps(res))
         return
     if args.profile_target:
         profile_target(args.profile_target, args.reps)
@@ -746,6 +852,9 @@ def main():
                 tb / (main_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
         del Tb, Gb, wsb
 
+    dense_solve = dense_solve_bench(torch, gw, X[2], pq[2])
+    uniform, audits = uniform_n200_bench()
+    audits = {"uniform_1d_n200": audits}
     grid2d = None if args.no_2d else grid2d_bench()
     fused = None if args.no_fgw else fgw_bench()
     grid3d = None if args.no_3d else grid3d_bench()
@@ -753,7 +862,9 @@ def main():
     stopped = None if args.no_tol else tolerance_bench()
     serving = None
     if not args.no_serve:
-        serving = serve_bench(args.serve_requests, args.serve_slots, args.serve_iters, boost=args.serve_boost)
+        serving, serve_audit = serve_bench(args.serve_requests, args.serve_slots, args.serve_iters,
+                                           boost=args.serve_boost)
+        audits.update(serve_audit)
 
     out = {
         "metric": METRIC,
@@ -774,6 +885,8 @@ def main():
                    "n": N, "solves_per_step": len(KS), "path": "fast_f64"},
         "roofline": roofline,
         "grads": grads,
+        "dense_solve_n4096": dense_solve,
+        "uniform_1d_n200": uniform,
         "n16384": big,
         "objective": objs,
         "grid2d_64x64": grid2d,
@@ -784,7 +897,7 @@ def main():
         "serving": serving,
     }
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline()
+        out["cpu_baseline"] = cpu_baseline(audits=audits)
     print(json.dumps(out))
 
 
