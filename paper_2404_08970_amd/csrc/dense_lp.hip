@@ -6,7 +6,8 @@
 //   F32:        operands rounded to FP32, v_mfma_f32_16x16x4f32, FP32
 //               accumulation over the whole K; A = T D~_Y kept in FP32.
 //   BF16:       operands rounded to BF16, v_mfma_f32_16x16x32_bf16, FP32
-//               accumulation over the whole K; A kept in FP32.
+//               accumulation over the whole K; A rounded to BF16 as the
+//               second product's operand.
 //   *_SPLIT:    each operand x = x_hi + x_lo (x_hi = round(x), x_lo =
 //               round(x - x_hi)); the products hi*hi and hi*lo + lo*hi are
 //               accumulated in FP32 over chunks of k (4 for FP32: one
@@ -14,6 +15,15 @@
 //               FP64; A kept in FP64.
 // A-priori bound for FP32 accumulation over K terms of non-negative products:
 // |dB| <= gamma_K |D~| |T| |D~| with gamma_K = K u / (1 - K u).
+//
+// The BF16 paths run as two matrix-core GEMMs on BF16 copies made once per
+// call (T, D~_Y and D~_X rounded, split into hi/lo for *_SPLIT), padded with
+// zeros to whole tiles so the K loop needs no bounds:
+//   A^T = D~_Y T^T   (A operand D~_Y, B operand T: both have K contiguous)
+//   B   = D~_X A     (A operand D~_X, B operand A^T), epilogue writes G.
+// Block tiles double-buffered through LDS (256 x 256 with 8 waves of
+// 64 x 128; the split path 128 x 128 with waves of 32 x 64, as its three
+// products per pair and the FP64 chunk sums need the registers).
 #include "common.h"
 #include "runtime.h"
 
@@ -210,6 +220,264 @@ __global__ __launch_bounds__(256) void k_dense_lp(const MemT* __restrict__ Xmem,
       }
 }
 
+// ---------------------------------------------------------------- BF16 GEMMs
+__host__ __device__ inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+constexpr int GB_K = 64, GB_PAD = 8;  // K per stage, LDS row padding (bf16 elements)
+
+// BF16 copies (hi, and lo if lo != null) of a row-major FP64 matrix
+// src[rows x cols] into dst[rp x kp] (ld kp), zero outside the matrix.
+__global__ __launch_bounds__(256) void k_to_bf16(const double* __restrict__ src, int64_t lds,
+                                                  int rows, int cols, __bf16* __restrict__ hi,
+                                                  __bf16* __restrict__ lo, int64_t rp, int64_t kp) {
+  const int64_t c8 = (int64_t)blockIdx.x * 256 + threadIdx.x;  // 8-element chunk
+  const int64_t nchunks = rp * (kp / 8);
+  if (c8 >= nchunks) return;
+  const int64_t r = c8 / (kp / 8), c0 = (c8 - r * (kp / 8)) * 8;
+  bf8 h, l;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const double x = (r < rows && c0 + e < cols) ? src[r * lds + c0 + e] : 0.0;
+    h[e] = hi_bf16(x);
+    l[e] = lo_bf16(x);
+  }
+  *reinterpret_cast<bf8*>(hi + r * kp + c0) = h;
+  if (lo) *reinterpret_cast<bf8*>(lo + r * kp + c0) = l;
+}
+
+// BF16 copies of the integer distance matrix |i - j|^k (n x n) into
+// dst[rp x kp], zero outside it.
+__global__ __launch_bounds__(256) void k_dist_bf16(int n, int kd, __bf16* __restrict__ hi,
+                                                    __bf16* __restrict__ lo, int64_t rp,
+                                                    int64_t kp) {
+  const int64_t c8 = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t nchunks = rp * (kp / 8);
+  if (c8 >= nchunks) return;
+  const int64_t r = c8 / (kp / 8), c0 = (c8 - r * (kp / 8)) * 8;
+  bf8 h, l;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const int64_t c = c0 + e;
+    const double x = (r < n && c < n) ? dist_pow((int)r, (int)c, kd) : 0.0;
+    h[e] = hi_bf16(x);
+    l[e] = lo_bf16(x);
+  }
+  *reinterpret_cast<bf8*>(hi + r * kp + c0) = h;
+  if (lo) *reinterpret_cast<bf8*>(lo + r * kp + c0) = l;
+}
+
+// C = A Bt^T over k in [0, kp): A [>= grid rows][lda], Bt [>= grid cols][ldb],
+// BF16, row-major with K contiguous; kp a multiple of GB_K, lda and ldb of 8,
+// rows of A and Bt allocated (and zero) up to whole block tiles.
+//   OUT 0: C[m][n] to BF16 hi (and lo) at O[m * ldo + n] for m < Mo, n < No
+//          (the padded range: zero rows and columns give zeros);
+//   OUT 1: G[m][n] = (c1[m] + c2[n]) - s2 C for m < M, n < N (FP64).
+// Plain: 128 x 128 block tiles, 2 x 2 waves of 64 x 64 (4 x 4 MFMA tiles of
+// 16 x 16); split: 64 x 64 block tiles, waves of 32 x 32, products hi*hi and
+// hi*lo + lo*hi in FP32 over KC = 256 k, chunk sums in FP64.
+// Tile shapes: the plain path runs 256 x 256 block tiles with 8 waves of
+// 64 x 128 (fewer LDS reads per matrix-core operation); the split path 128 x 128
+// block tiles with 8 waves of 32 x 64.
+template <bool SPLIT>
+struct GemmShape;
+template <>
+struct GemmShape<false> {
+  static constexpr int BM = 256, BN = 256, WGM = 4, WGN = 2, NTH = 512;
+};
+template <>
+struct GemmShape<true> {
+  static constexpr int BM = 128, BN = 128, WGM = 4, WGN = 2, NTH = 512;
+};
+
+template <bool SPLIT, int OUT>
+__global__ __launch_bounds__(GemmShape<SPLIT>::NTH) void k_gemm_bt(
+    const __bf16* __restrict__ Ah, const __bf16* __restrict__ Al, int64_t lda,
+    const __bf16* __restrict__ Bh, const __bf16* __restrict__ Bl, int64_t ldb, int kp, int Mo,
+    int No, __bf16* __restrict__ Oh, __bf16* __restrict__ Ol, int64_t ldo,
+    const double* __restrict__ c1, const double* __restrict__ c2, double s2,
+    double* __restrict__ G, int64_t ldG) {
+  using S = GemmShape<SPLIT>;
+  constexpr int BM = S::BM, BN = S::BN, NTH = S::NTH;
+  constexpr int WM = BM / S::WGM, WN = BN / S::WGN;  // wave tile
+  constexpr int NTM = WM / 16, NTN = WN / 16;         // MFMA tiles per wave
+  constexpr int NMAT = SPLIT ? 2 : 1;                 // hi (and lo) of each operand
+  constexpr int LDK = GB_K + GB_PAD;
+  constexpr int CHA = BM * GB_K / 8 / NTH, CHB = BN * GB_K / 8 / NTH;  // 16-byte chunks per thread
+  __shared__ __bf16 As[2][NMAT][BM][LDK];
+  __shared__ __bf16 Bs[2][NMAT][BN][LDK];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int wm = (wave / S::WGN) * WM, wn = (wave % S::WGN) * WN;
+  const int64_t m0 = (int64_t)blockIdx.y * BM, n0 = (int64_t)blockIdx.x * BN;
+  const int li = lane & 15, lq = lane >> 4;
+  f4 acc[NTM][NTN], accx[SPLIT ? NTM : 1][SPLIT ? NTN : 1];
+  double dacc[SPLIT ? NTM : 1][SPLIT ? NTN : 1][4];
+#pragma unroll
+  for (int i = 0; i < NTM; ++i)
+#pragma unroll
+    for (int j = 0; j < NTN; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+  if constexpr (SPLIT) {
+#pragma unroll
+    for (int i = 0; i < NTM; ++i)
+#pragma unroll
+      for (int j = 0; j < NTN; ++j) {
+        accx[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int v = 0; v < 4; ++v) dacc[i][j][v] = 0.0;
+      }
+  }
+  // global -> registers -> LDS, 16-byte chunks: chunk c = t + NTH u of a tile
+  // is row c / 8, k (c % 8) * 8
+  bf8 ra[NMAT][CHA], rb[NMAT][CHB];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < CHA; ++u) {
+      const int c = t + NTH * u, r = c >> 3, kc = (c & 7) * 8;
+      ra[0][u] = *reinterpret_cast<const bf8*>(Ah + (m0 + r) * lda + k0 + kc);
+      if constexpr (SPLIT) ra[1][u] = *reinterpret_cast<const bf8*>(Al + (m0 + r) * lda + k0 + kc);
+    }
+#pragma unroll
+    for (int u = 0; u < CHB; ++u) {
+      const int c = t + NTH * u, r = c >> 3, kc = (c & 7) * 8;
+      rb[0][u] = *reinterpret_cast<const bf8*>(Bh + (n0 + r) * ldb + k0 + kc);
+      if constexpr (SPLIT) rb[1][u] = *reinterpret_cast<const bf8*>(Bl + (n0 + r) * ldb + k0 + kc);
+    }
+  };
+  auto lstore = [&](int buf) {
+#pragma unroll
+    for (int mt = 0; mt < NMAT; ++mt) {
+#pragma unroll
+      for (int u = 0; u < CHA; ++u) {
+        const int c = t + NTH * u, r = c >> 3, kc = (c & 7) * 8;
+        *reinterpret_cast<bf8*>(&As[buf][mt][r][kc]) = ra[mt][u];
+      }
+#pragma unroll
+      for (int u = 0; u < CHB; ++u) {
+        const int c = t + NTH * u, r = c >> 3, kc = (c & 7) * 8;
+        *reinterpret_cast<bf8*>(&Bs[buf][mt][r][kc]) = rb[mt][u];
+      }
+    }
+  };
+  auto flush = [&]() {
+    if constexpr (SPLIT) {
+#pragma unroll
+      for (int i = 0; i < NTM; ++i)
+#pragma unroll
+        for (int j = 0; j < NTN; ++j) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            dacc[i][j][v] += (double)acc[i][j][v] + (double)accx[i][j][v];
+          acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+          accx[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+        }
+    }
+  };
+  auto compute = [&](int buf) {
+#pragma unroll
+    for (int ks = 0; ks < GB_K; ks += 32) {
+      bf8 fa[NMAT][NTM], fb[NMAT][NTN];
+#pragma unroll
+      for (int mt = 0; mt < NMAT; ++mt) {
+#pragma unroll
+        for (int i = 0; i < NTM; ++i)
+          fa[mt][i] = *reinterpret_cast<const bf8*>(&As[buf][mt][wm + 16 * i + li][ks + 8 * lq]);
+#pragma unroll
+        for (int j = 0; j < NTN; ++j)
+          fb[mt][j] = *reinterpret_cast<const bf8*>(&Bs[buf][mt][wn + 16 * j + li][ks + 8 * lq]);
+      }
+#pragma unroll
+      for (int i = 0; i < NTM; ++i)
+#pragma unroll
+        for (int j = 0; j < NTN; ++j) {
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[0][i], fb[0][j], acc[i][j], 0, 0, 0);
+          if constexpr (SPLIT) {
+            accx[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[0][i], fb[1][j], accx[i][j], 0, 0, 0);
+            accx[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[1][i], fb[0][j], accx[i][j], 0, 0, 0);
+          }
+        }
+    }
+  };
+  const int nk = kp / GB_K;
+  gload(0);
+  lstore(0);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    if (kt + 1 < nk) gload((kt + 1) * GB_K);
+    compute(kt & 1);
+    if (SPLIT && ((kt + 1) * GB_K) % KC == 0) flush();
+    if (kt + 1 < nk) lstore((kt + 1) & 1);
+    __syncthreads();
+  }
+  flush();
+  // FP32 16x16 accumulator layout: slot v of a lane holds row 4 * (lane / 16) + v
+#pragma unroll
+  for (int i = 0; i < NTM; ++i)
+#pragma unroll
+    for (int j = 0; j < NTN; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t gm = m0 + wm + i * 16 + 4 * lq + v;
+        const int64_t gn = n0 + wn + j * 16 + li;
+        double x;
+        if constexpr (SPLIT) x = dacc[i][j][v];
+        else x = (double)acc[i][j][v];
+        if constexpr (OUT == 0) {
+          if (gm < Mo && gn < No) {
+            Oh[gm * ldo + gn] = hi_bf16(x);
+            if constexpr (SPLIT) Ol[gm * ldo + gn] = lo_bf16(x);
+          }
+        } else {
+          if (gm < Mo && gn < No) G[gm * ldG + gn] = (c1[gm] + c2[gn]) - s2 * x;
+        }
+      }
+}
+
+struct Bf16Layout {
+  int64_t Mp, Np, kN, kM;  // padded rows (block tiles) and K extents
+  size_t t, dy, dx, at;    // elements of each BF16 copy
+};
+
+Bf16Layout bf16_layout(int64_t M, int64_t N, bool split) {
+  const int64_t BMx = split ? GemmShape<true>::BM : GemmShape<false>::BM;
+  Bf16Layout L;
+  L.Mp = round_up(M, BMx);
+  L.Np = round_up(N, BMx);
+  L.kN = round_up(N, GB_K);
+  L.kM = round_up(M, GB_K);
+  L.t = (size_t)L.Mp * L.kN;   // T        [Mp][kN]
+  L.dy = (size_t)L.Np * L.kN;  // D~_Y     [Np][kN]
+  L.dx = (size_t)L.Mp * L.kM;  // D~_X     [Mp][kM]
+  L.at = (size_t)L.Np * L.Mp;  // A^T      [Np][Mp]
+  return L;
+}
+
+template <bool SPLIT>
+gw_status run_bf16(int M, int N, int kx, int ky, const double* T, int64_t ldT, double* G,
+                   int64_t ldG, const double* c1, const double* c2, double s2, __bf16* w,
+                   hipStream_t s) {
+  const Bf16Layout L = bf16_layout(M, N, SPLIT);
+  const int nm = SPLIT ? 2 : 1;
+  __bf16* th = w;
+  __bf16* tl = SPLIT ? th + L.t : nullptr;
+  __bf16* dyh = w + nm * L.t;
+  __bf16* dyl = SPLIT ? dyh + L.dy : nullptr;
+  __bf16* dxh = dyh + nm * L.dy;
+  __bf16* dxl = SPLIT ? dxh + L.dx : nullptr;
+  __bf16* ath = dxh + nm * L.dx;
+  __bf16* atl = SPLIT ? ath + L.at : nullptr;
+  auto blocks = [](size_t elems) { return (unsigned)((elems / 8 + 255) / 256); };
+  k_to_bf16<<<blocks(L.t), 256, 0, s>>>(T, ldT, M, N, th, tl, L.Mp, L.kN);
+  k_dist_bf16<<<blocks(L.dy), 256, 0, s>>>(N, ky, dyh, dyl, L.Np, L.kN);
+  k_dist_bf16<<<blocks(L.dx), 256, 0, s>>>(M, kx, dxh, dxl, L.Mp, L.kM);
+  using S = GemmShape<SPLIT>;
+  // A^T = D~_Y T^T: rows n < Np, columns m < Mp (the padding comes out zero)
+  k_gemm_bt<SPLIT, 0><<<dim3((unsigned)(L.Mp / S::BN), (unsigned)(L.Np / S::BM)), S::NTH, 0, s>>>(
+      dyh, dyl, L.kN, th, tl, L.kN, (int)L.kN, (int)L.Np, (int)L.Mp, ath, atl, L.Mp, nullptr,
+      nullptr, 0.0, nullptr, 0);
+  // B = D~_X A, G = c1 + c2 - s2 B
+  k_gemm_bt<SPLIT, 1><<<dim3((unsigned)(L.Np / S::BN), (unsigned)(L.Mp / S::BM)), S::NTH, 0, s>>>(
+      dxh, dxl, L.kM, ath, atl, L.Mp, (int)L.kM, M, N, nullptr, nullptr, 0, c1, c2, s2, G, ldG);
+  return gwr::last_launch_status();
+}
+
 template <int MODE>
 gw_status run_lp(int M, int N, int kx, int ky, const double* T, int64_t ldT, double* G,
                  int64_t ldG, const double* c1, const double* c2, double s2, void* Abuf,
@@ -241,10 +509,15 @@ namespace gwl {
 
 size_t dense_lp_ws_bytes(const gwr::Grid& X, const gwr::Grid& Y, int path) {
   gwr::Arena a{nullptr, 0, 0};
-  if (split_path(path))
+  if (path == GW_PATH_DENSE_BF16 || path == GW_PATH_DENSE_BF16_SPLIT) {
+    const bool split = path == GW_PATH_DENSE_BF16_SPLIT;
+    const Bf16Layout L = bf16_layout(X.n(), Y.n(), split);
+    a.take<__bf16>((split ? 2 : 1) * (L.t + L.dy + L.dx + L.at));
+  } else if (split_path(path)) {
     a.take<double>((size_t)X.n() * Y.n());
-  else
+  } else {
     a.take<float>((size_t)X.n() * Y.n());
+  }
   return a.used;
 }
 
@@ -253,18 +526,21 @@ gw_status dense_lp(const gwr::Grid& X, const gwr::Grid& Y, const double* T, int6
                    const double* c1, const double* c2) {
   const int M = (int)X.n(), N = (int)Y.n();
   const double s2 = 2.0 * (X.hk() * Y.hk());
+  gwr::ProfScope ps(gwr::kFamDense, s);
+  if (path == GW_PATH_DENSE_BF16 || path == GW_PATH_DENSE_BF16_SPLIT) {
+    const bool split = path == GW_PATH_DENSE_BF16_SPLIT;
+    const Bf16Layout L = bf16_layout(M, N, split);
+    __bf16* w = ws.take<__bf16>((split ? 2 : 1) * (L.t + L.dy + L.dx + L.at));
+    return split ? run_bf16<true>(M, N, X.k1d(), Y.k1d(), T, ldT, G, ldG, c1, c2, s2, w, s)
+                 : run_bf16<false>(M, N, X.k1d(), Y.k1d(), T, ldT, G, ldG, c1, c2, s2, w, s);
+  }
   void* A = split_path(path) ? (void*)ws.take<double>((size_t)M * N)
                              : (void*)ws.take<float>((size_t)M * N);
-  gwr::ProfScope ps(gwr::kFamDense, s);
   switch (path) {
     case GW_PATH_DENSE_F32:
       return run_lp<LP_F32>(M, N, X.k1d(), Y.k1d(), T, ldT, G, ldG, c1, c2, s2, A, s);
-    case GW_PATH_DENSE_BF16:
-      return run_lp<LP_BF16>(M, N, X.k1d(), Y.k1d(), T, ldT, G, ldG, c1, c2, s2, A, s);
     case GW_PATH_DENSE_F32_SPLIT:
       return run_lp<LP_F32_SPLIT>(M, N, X.k1d(), Y.k1d(), T, ldT, G, ldG, c1, c2, s2, A, s);
-    case GW_PATH_DENSE_BF16_SPLIT:
-      return run_lp<LP_BF16_SPLIT>(M, N, X.k1d(), Y.k1d(), T, ldT, G, ldG, c1, c2, s2, A, s);
   }
   return GW_EUNSUPPORTED;
 }
