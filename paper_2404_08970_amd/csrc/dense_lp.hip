@@ -430,6 +430,136 @@ __global__ __launch_bounds__(GemmShape<SPLIT>::NTH) void k_gemm_bt(
       }
 }
 
+// FP32 operands on the FP32 matrix cores: the same two products and tiling
+// as the BF16 path (v_mfma_f32_16x16x4f32: a lane holds one operand element,
+// row lane % 16, k = lane / 16), FP32 accumulation over the whole K; A^T stays
+// FP32.  OUT as in k_gemm_bt (0: FP32 output, 1: G).
+template <int OUT>
+__global__ __launch_bounds__(256) void k_gemm_bt_f32(const float* __restrict__ A, int64_t lda,
+                                                      const float* __restrict__ Bt, int64_t ldb,
+                                                      int kp, int Mo, int No,
+                                                      float* __restrict__ O, int64_t ldo,
+                                                      const double* __restrict__ c1,
+                                                      const double* __restrict__ c2, double s2,
+                                                      double* __restrict__ G, int64_t ldG) {
+  constexpr int BM = 128, NTH = 256, WT = 64, NT = WT / 16;  // 2 x 2 waves of 64 x 64
+  constexpr int BK = 32, LDK = BK + 4;                        // K per stage; LDS row padding
+  constexpr int CH = BM * BK / 4 / NTH;                        // 16-byte chunks per thread
+  typedef float fl4 __attribute__((ext_vector_type(4)));
+  __shared__ float As[2][BM][LDK];
+  __shared__ float Bs[2][BM][LDK];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int wm = (wave >> 1) * WT, wn = (wave & 1) * WT;
+  const int64_t m0 = (int64_t)blockIdx.y * BM, n0 = (int64_t)blockIdx.x * BM;
+  const int li = lane & 15, lq = lane >> 4;
+  f4 acc[NT][NT];
+#pragma unroll
+  for (int i = 0; i < NT; ++i)
+#pragma unroll
+    for (int j = 0; j < NT; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+  fl4 ra[CH], rb[CH];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      const int c = t + NTH * u, r = c >> 3, kc = (c & 7) * 4;
+      ra[u] = *reinterpret_cast<const fl4*>(A + (m0 + r) * lda + k0 + kc);
+      rb[u] = *reinterpret_cast<const fl4*>(Bt + (n0 + r) * ldb + k0 + kc);
+    }
+  };
+  auto lstore = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      const int c = t + NTH * u, r = c >> 3, kc = (c & 7) * 4;
+      *reinterpret_cast<fl4*>(&As[buf][r][kc]) = ra[u];
+      *reinterpret_cast<fl4*>(&Bs[buf][r][kc]) = rb[u];
+    }
+  };
+  auto compute = [&](int buf) {
+#pragma unroll
+    for (int ks = 0; ks < BK; ks += 4) {
+      float fa[NT], fb[NT];
+#pragma unroll
+      for (int i = 0; i < NT; ++i) fa[i] = As[buf][wm + 16 * i + li][ks + lq];
+#pragma unroll
+      for (int j = 0; j < NT; ++j) fb[j] = Bs[buf][wn + 16 * j + li][ks + lq];
+#pragma unroll
+      for (int i = 0; i < NT; ++i)
+#pragma unroll
+        for (int j = 0; j < NT; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[i], fb[j], acc[i][j], 0, 0, 0);
+    }
+  };
+  const int nk = kp / BK;
+  gload(0);
+  lstore(0);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    if (kt + 1 < nk) gload((kt + 1) * BK);
+    compute(kt & 1);
+    if (kt + 1 < nk) lstore((kt + 1) & 1);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < NT; ++i)
+#pragma unroll
+    for (int j = 0; j < NT; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t gm = m0 + wm + i * 16 + 4 * lq + v;
+        const int64_t gn = n0 + wn + j * 16 + li;
+        if (gm < Mo && gn < No) {
+          if constexpr (OUT == 0) O[gm * ldo + gn] = acc[i][j][v];
+          else G[gm * ldG + gn] = (c1[gm] + c2[gn]) - s2 * (double)acc[i][j][v];
+        }
+      }
+}
+
+// FP32 copies of a row-major FP64 matrix, or of |i - j|^k (src null: n x n),
+// into dst[rp x kp], zero outside.
+__global__ __launch_bounds__(256) void k_to_f32(const double* __restrict__ src, int64_t lds,
+                                                 int rows, int cols, int kd,
+                                                 float* __restrict__ dst, int64_t rp, int64_t kp) {
+  const int64_t c4 = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (c4 >= rp * (kp / 4)) return;
+  const int64_t r = c4 / (kp / 4), c0 = (c4 - r * (kp / 4)) * 4;
+  typedef float fl4 __attribute__((ext_vector_type(4)));
+  fl4 v;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int64_t c = c0 + e;
+    double x = 0.0;
+    if (r < rows && c < cols) x = src ? src[r * lds + c] : dist_pow((int)r, (int)c, kd);
+    v[e] = (float)x;
+  }
+  *reinterpret_cast<fl4*>(dst + r * kp + c0) = v;
+}
+
+gw_status run_f32(int M, int N, int kx, int ky, const double* T, int64_t ldT, double* G,
+                  int64_t ldG, const double* c1, const double* c2, double s2, float* w,
+                  hipStream_t s) {
+  const int64_t Mp = round_up(M, 128), Np = round_up(N, 128);
+  const int64_t kN = round_up(N, 32), kM = round_up(M, 32);
+  float* tf = w;              // T       [Mp][kN]
+  float* dy = tf + Mp * kN;   // D~_Y    [Np][kN]
+  float* dx = dy + Np * kN;   // D~_X    [Mp][kM]
+  float* at = dx + Mp * kM;   // A^T     [Np][Mp]
+  auto blocks = [](int64_t elems) { return (unsigned)((elems / 4 + 255) / 256); };
+  k_to_f32<<<blocks(Mp * kN), 256, 0, s>>>(T, ldT, M, N, 0, tf, Mp, kN);
+  k_to_f32<<<blocks(Np * kN), 256, 0, s>>>(nullptr, 0, N, N, ky, dy, Np, kN);
+  k_to_f32<<<blocks(Mp * kM), 256, 0, s>>>(nullptr, 0, M, M, kx, dx, Mp, kM);
+  k_gemm_bt_f32<0><<<dim3((unsigned)(Mp / 128), (unsigned)(Np / 128)), 256, 0, s>>>(
+      dy, kN, tf, kN, (int)kN, (int)Np, (int)Mp, at, Mp, nullptr, nullptr, 0.0, nullptr, 0);
+  k_gemm_bt_f32<1><<<dim3((unsigned)(Np / 128), (unsigned)(Mp / 128)), 256, 0, s>>>(
+      dx, kM, at, Mp, (int)kM, M, N, nullptr, 0, c1, c2, s2, G, ldG);
+  return gwr::last_launch_status();
+}
+
+size_t f32_ws_floats(int64_t M, int64_t N) {
+  const int64_t Mp = round_up(M, 128), Np = round_up(N, 128);
+  const int64_t kN = round_up(N, 32), kM = round_up(M, 32);
+  return (size_t)(Mp * kN + Np * kN + Mp * kM + Np * Mp);
+}
+
 struct Bf16Layout {
   int64_t Mp, Np, kN, kM;  // padded rows (block tiles) and K extents
   size_t t, dy, dx, at;    // elements of each BF16 copy
@@ -516,7 +646,7 @@ size_t dense_lp_ws_bytes(const gwr::Grid& X, const gwr::Grid& Y, int path) {
   } else if (split_path(path)) {
     a.take<double>((size_t)X.n() * Y.n());
   } else {
-    a.take<float>((size_t)X.n() * Y.n());
+    a.take<float>(f32_ws_floats(X.n(), Y.n()));
   }
   return a.used;
 }
@@ -534,11 +664,12 @@ gw_status dense_lp(const gwr::Grid& X, const gwr::Grid& Y, const double* T, int6
     return split ? run_bf16<true>(M, N, X.k1d(), Y.k1d(), T, ldT, G, ldG, c1, c2, s2, w, s)
                  : run_bf16<false>(M, N, X.k1d(), Y.k1d(), T, ldT, G, ldG, c1, c2, s2, w, s);
   }
-  void* A = split_path(path) ? (void*)ws.take<double>((size_t)M * N)
-                             : (void*)ws.take<float>((size_t)M * N);
+  if (path == GW_PATH_DENSE_F32) {
+    float* w = ws.take<float>(f32_ws_floats(M, N));
+    return run_f32(M, N, X.k1d(), Y.k1d(), T, ldT, G, ldG, c1, c2, s2, w, s);
+  }
+  void* A = (void*)ws.take<double>((size_t)M * N);
   switch (path) {
-    case GW_PATH_DENSE_F32:
-      return run_lp<LP_F32>(M, N, X.k1d(), Y.k1d(), T, ldT, G, ldG, c1, c2, s2, A, s);
     case GW_PATH_DENSE_F32_SPLIT:
       return run_lp<LP_F32_SPLIT>(M, N, X.k1d(), Y.k1d(), T, ldT, G, ldG, c1, c2, s2, A, s);
   }
