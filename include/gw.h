@@ -128,7 +128,9 @@ gw_status gw_grad(const gw_grid* X, const gw_grid* Y, const double* p, const dou
  *   f [M], g [N]: device FP64 in/out.
  *   T: optional (may be NULL) device FP64 [M x N, ldT >= N]; receives the plan
  *      P_ip = exp((f_i + g_p - C_eff_ip)/eps) after the last iteration.
- * Requires N <= 16384 (a row is held on chip) and eps > 0. */
+ * eps > 0; M, N <= 65535.  Rows of up to 16384 entries are held on chip (one
+ * pass over C per iteration); longer rows run in slabs of 8192 columns with
+ * two passes per iteration. */
 gw_status gw_sinkhorn(const double* C, int64_t ldC, int64_t M, int64_t N, double c_scale,
                       const double* p, const double* q, double eps, int32_t iters,
                       int32_t init_zero, double* f, double* g, double* T, int64_t ldT, void* ws,

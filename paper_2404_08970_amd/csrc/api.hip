@@ -436,7 +436,6 @@ gw_status sinkhorn_impl(const double* C, int64_t ldC, int64_t M, int64_t N, doub
   gw_status st;
   if (M < 1 || N < 1) return GW_EINVAL;
   if (M > gwr::kMaxExtent || N > gwr::kMaxExtent) return GW_EUNSUPPORTED;
-  if (N > 16384) return GW_EUNSUPPORTED;
   if (!(eps > 0.0) || !isfinite(eps) || !isfinite(c_scale) || iters < 0) return GW_EINVAL;
   if (so && (st = check_stop(*so)) != GW_OK) return st;
   if ((st = check_matrix(C, M, N, ldC)) != GW_OK) return st;
@@ -499,7 +498,6 @@ gw_status solve_impl(const gw_grid* Xp, const gw_grid* Yp, const double* p, cons
   if (fgw && (st = check_fgw(*fgw)) != GW_OK) return st;
   if (so && (st = check_stop(*so)) != GW_OK) return st;
   const int64_t M = X.n(), N = Y.n();
-  if (N > 16384) return GW_EUNSUPPORTED;
   if ((st = check_vec(p)) != GW_OK || (st = check_vec(q)) != GW_OK) return st;
   if ((st = check_vec(f)) != GW_OK || (st = check_vec(g)) != GW_OK) return st;
   if ((st = check_matrix(T, M, N, ldT)) != GW_OK) return st;
@@ -615,7 +613,7 @@ gw_status gw_sinkhorn_noalloc(const double* C, int64_t ldC, int64_t M, int64_t N
                               int32_t iters, int32_t init_zero, double* f, double* g, double* T,
                               int64_t ldT, void* stream) {
   // sizes the Sinkhorn kernels take but the static scratch does not hold
-  if (M >= 1 && N >= 1 && M <= gwr::kMaxExtent && N <= 16384 &&
+  if (M >= 1 && N >= 1 && M <= gwr::kMaxExtent && N <= gwr::kMaxExtent &&
       gwr::ws_status_bytes() + gwr::ws_sinkhorn_bytes(M, N) > kStaticScratchBytes)
     return GW_ENOMEM;
   void* ws = nullptr;

@@ -870,6 +870,145 @@ __global__ __launch_bounds__(1024) void k_sk_rowg(const double* __restrict__ C, 
                             bmode, lse, write_f, blockIdx.x);
 }
 
+// ---------------------------------------------------------------- wide rows
+// Rows of more than 16384 entries do not fit on chip; they run in slabs of
+// WIDE_SLAB columns and two passes over C per iteration:
+//   k_skw_rowpart  block (band, slab): each row's maximum over the slab and
+//                  its sum of exp(z - max) there, z = (g - C_eff)/eps;
+//   k_skw_colpart  block (band, slab): each row's maximum and shifted sum over
+//                  all slabs (the same arithmetic in every block of the row),
+//                  then the exponentials again, weighted by p_i / s_i, into
+//                  (mantissa, exponent) column pairs for the band, as the exact
+//                  single-pass variant writes them; k_sk_col merges the bands.
+constexpr int WIDE_NT = 512, WIDE_EPT = 16, WIDE_SLAB = WIDE_NT * WIDE_EPT;
+
+// g/eps of the slab's columns and the slab's first column
+GW_DEV void wide_gie(const double* __restrict__ g, int N, double inv_eps, int c0, int t,
+                     double (&gie)[WIDE_EPT]) {
+  double graw[WIDE_EPT];
+#pragma unroll
+  for (int e = 0; e < WIDE_EPT; ++e) graw[e] = g[min(c0 + t + WIDE_NT * e, N - 1)];
+#pragma unroll
+  for (int e = 0; e < WIDE_EPT; ++e)
+    gie[e] = c0 + t + WIDE_NT * e < N ? graw[e] * inv_eps : -INFINITY;
+}
+
+__global__ __launch_bounds__(WIDE_NT) void k_skw_rowpart(const double* __restrict__ C,
+                                                         int64_t ldC, int M, int N, int RB,
+                                                         double cs, double inv_eps,
+                                                         const double* __restrict__ g,
+                                                         double* __restrict__ part_m,
+                                                         double* __restrict__ part_s,
+                                                         const int* __restrict__ stop) {
+  if (stop != nullptr && *stop) return;  // a tolerance stop has ended the call
+  __shared__ double red[2][WIDE_NT / 64];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int band = blockIdx.x, slab = blockIdx.y, c0 = slab * WIDE_SLAB;
+  const int i0 = band * RB, i1 = min(M, i0 + RB);
+  const double csie = cs * inv_eps;
+  double gie[WIDE_EPT];
+  wide_gie(g, N, inv_eps, c0, t, gie);
+  for (int i = i0; i < i1; ++i) {
+    const double* row = C + (int64_t)i * ldC;
+    double z[WIDE_EPT];
+    double mloc = -INFINITY;
+#pragma unroll
+    for (int e = 0; e < WIDE_EPT; ++e) {
+      z[e] = fma(-csie, row[min(c0 + t + WIDE_NT * e, N - 1)], gie[e]);
+      mloc = fmax(mloc, z[e]);
+    }
+    mloc = gwk::wave_max(mloc);
+    if (lane == 63) red[0][wv] = mloc;
+    __syncthreads();
+    double m = red[0][0];
+#pragma unroll
+    for (int w = 1; w < WIDE_NT / 64; ++w) m = fmax(m, red[0][w]);
+    double sl = 0.0;
+    if (m > -INFINITY) {
+#pragma unroll
+      for (int e = 0; e < WIDE_EPT; ++e) {
+        int n;
+        const double x = exp_split(z[e] - m, &n);
+        sl += ldexp(x, n);
+      }
+    }
+    sl = gwk::wave_sum(sl);
+    if (lane == 63) red[1][wv] = sl;
+    __syncthreads();
+    if (t == 0) {
+      double s = red[1][0];
+#pragma unroll
+      for (int w = 1; w < WIDE_NT / 64; ++w) s += red[1][w];
+      part_m[(int64_t)slab * M + i] = m;
+      part_s[(int64_t)slab * M + i] = s;
+    }
+  }
+}
+
+__global__ __launch_bounds__(WIDE_NT) void k_skw_colpart(
+    const double* __restrict__ C, int64_t ldC, int M, int N, int RB, int ns, double cs,
+    double inv_eps, const double* __restrict__ p, const double* __restrict__ g,
+    const double* __restrict__ part_m, const double* __restrict__ part_s, double* __restrict__ f,
+    double* __restrict__ ms, double* __restrict__ partS, int* __restrict__ partX,
+    int* __restrict__ bmode, int write_f, const int* __restrict__ stop) {
+  if (stop != nullptr && *stop) return;  // a tolerance stop has ended the call
+  const int t = threadIdx.x;
+  const int band = blockIdx.x, slab = blockIdx.y, c0 = slab * WIDE_SLAB;
+  const int i0 = band * RB, i1 = min(M, i0 + RB);
+  const double csie = cs * inv_eps;
+  double gie[WIDE_EPT];
+  wide_gie(g, N, inv_eps, c0, t, gie);
+  double S[WIDE_EPT];
+  int Xe[WIDE_EPT];
+#pragma unroll
+  for (int e = 0; e < WIDE_EPT; ++e) {
+    S[e] = 0.0;
+    Xe[e] = EXP_SENTINEL;
+  }
+  for (int i = i0; i < i1; ++i) {
+    const double pi = p[i];
+    // the row's maximum and shifted sum over all slabs, in slab order
+    double m = -INFINITY;
+    for (int j = 0; j < ns; ++j) m = fmax(m, part_m[(int64_t)j * M + i]);
+    double s = 0.0;
+    for (int j = 0; j < ns; ++j) {
+      const double mj = part_m[(int64_t)j * M + i];
+      if (mj > -INFINITY) s += part_s[(int64_t)j * M + i] * exp(mj - m);
+    }
+    if (!(pi > 0.0)) {
+      if (slab == 0 && t == 0) f[i] = -INFINITY;
+      continue;
+    }
+    // f_i is an output only: the last iteration leaves (m_i, s_i) for k_sk_f
+    if (write_f && slab == 0 && t == 0) {
+      ms[2 * i] = m;
+      ms[2 * i + 1] = s;
+    }
+    int ew;
+    const double mw = frexp(pi / s, &ew);
+    const double* row = C + (int64_t)i * ldC;
+#pragma unroll
+    for (int e = 0; e < WIDE_EPT; ++e) {
+      int n;
+      const double x = exp_split(fma(-csie, row[min(c0 + t + WIDE_NT * e, N - 1)], gie[e]) - m, &n);
+      const double tv = x * mw;
+      const int te = n + ew;
+      const int ne = max(Xe[e], te);
+      S[e] = ldexp(S[e], Xe[e] - ne) + ldexp(tv, te - ne);
+      Xe[e] = ne;
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < WIDE_EPT; ++e) {
+    const int col = c0 + t + WIDE_NT * e;
+    if (col < N) {
+      partS[(int64_t)band * N + col] = S[e];
+      partX[(int64_t)band * N + col] = Xe[e];
+    }
+  }
+  if (slab == 0 && t == 0) bmode[band] = 0;
+}
+
 // Column merge: a block covers 16 columns x 16 groups of bands; each thread
 // merges its groups' (mantissa, exponent) pairs in band order, then the 16
 // group results of a column are merged in group order.  A band written by a
@@ -1333,6 +1472,11 @@ size_t sinkhorn_ws_bytes(int64_t M, int64_t N) {
   a.take<double>(N);  // g before the last merge
   a.take<int>(N);     // column frames
   a.take<int>(nb);    // pass kind of each band's partials
+  if (N > 16384) {    // wide rows: per-slab row maxima and sums
+    const int64_t ns = (N + WIDE_SLAB - 1) / WIDE_SLAB;
+    a.take<double>((size_t)ns * M);
+    a.take<double>((size_t)ns * M);
+  }
   a.take<double>(4);  // tolerance-stop state
   a.take<double>((N + MERGE_COLS - 1) / MERGE_COLS);  // column violation per merge block
   return a.used;
@@ -1386,7 +1530,6 @@ gw_status sinkhorn(const double* C, int64_t ldC, int64_t M, int64_t N, double c_
                    const double* p, const double* q, double eps, int iters, int init_zero,
                    double* f, double* g, double* T, int64_t ldT, gwr::Arena& ws, hipStream_t s,
                    gwr::StatusWord* status, const gwr::SkStop* stop_opts) {
-  if (N > 16384) return GW_EUNSUPPORTED;
   const int rb = sk_rows_per_block(M);
   const int nb = (int)((M + rb - 1) / rb);
   double* logp = ws.take<double>(M);
@@ -1398,6 +1541,10 @@ gw_status sinkhorn(const double* C, int64_t ldC, int64_t M, int64_t N, double c_
   double* gprev = ws.take<double>(N);
   int* kq = ws.take<int>(N);
   int* bmode = ws.take<int>(nb);
+  const bool wide = N > 16384;
+  const int ns = wide ? (int)((N + WIDE_SLAB - 1) / WIDE_SLAB) : 0;
+  double* part_m = wide ? ws.take<double>((size_t)ns * M) : nullptr;
+  double* part_s = wide ? ws.take<double>((size_t)ns * M) : nullptr;
   SkCtl* ctl = reinterpret_cast<SkCtl*>(ws.take<double>(4));
   const int ncb = (int)((N + MERGE_COLS - 1) / MERGE_COLS);
   double* errpart = ws.take<double>(ncb);
@@ -1426,7 +1573,13 @@ gw_status sinkhorn(const double* C, int64_t ldC, int64_t M, int64_t N, double c_
       // a pass that may be the last one leaves (m_i, s_i) for k_sk_f
       const int lst = it == iters - 1 || check;
       const double* gp = it > 0 ? gprev : nullptr;
-      switch (gwb::row_class(N)) {
+      if (wide) {
+        hipExtLaunchKernelGGL(k_skw_rowpart, dim3(nb, ns), dim3(WIDE_NT), 0, s, eb, nullptr, 0, C,
+                              ldC, Mi, Ni, rb, c_scale, inv_eps, g, part_m, part_s, stop);
+        hipExtLaunchKernelGGL(k_skw_colpart, dim3(nb, ns), dim3(WIDE_NT), 0, s, nullptr, ee, 0,
+                              C, ldC, Mi, Ni, rb, ns, c_scale, inv_eps, p, g, part_m, part_s, f,
+                              ms, pS, pX, bmode, lst, stop);
+      } else switch (gwb::row_class(N)) {
         case gwb::kClsN256: launch_row<256, 1>(nb, s, eb, ee, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, kq, f, ms, pS, pX, bmode, lse, gp, lst, stop); break;
         case gwb::kClsN512: launch_row<512, 1>(nb, s, eb, ee, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, kq, f, ms, pS, pX, bmode, lse, gp, lst, stop); break;
         case gwb::kClsN1024: launch_row<1024, 1>(nb, s, eb, ee, C, ldC, Mi, Ni, rb, c_scale, inv_eps, p, logp, g, kq, f, ms, pS, pX, bmode, lse, gp, lst, stop); break;

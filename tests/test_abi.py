@@ -111,9 +111,9 @@ def test_sinkhorn_and_solve_validation():
     st = lib.gw_sinkhorn(P(big), 16, 16, 16, 1.0, P(big), P(big), 0.0, 10, 1, P(big), P(big),
                          P(0), 16, P(big), 1 << 30, P(0))
     assert st == gw.GW_EINVAL
-    # rows longer than the on-chip limit
-    st = lib.gw_sinkhorn(P(big), 20000, 4, 20000, 1.0, P(big), P(big), 0.1, 10, 1, P(big),
-                         P(big), P(0), 20000, P(big), 1 << 40, P(0))
+    # rows longer than the largest extent (65535)
+    st = lib.gw_sinkhorn(P(big), 70000, 4, 70000, 1.0, P(big), P(big), 0.1, 10, 1, P(big),
+                         P(big), P(0), 70000, P(big), 1 << 40, P(0))
     assert st == gw.GW_EUNSUPPORTED
     X = gw.Grid((16,), 1.0, 1)
     xc = X.c()

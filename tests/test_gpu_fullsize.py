@@ -112,6 +112,24 @@ def test_sinkhorn_n4096_full():
     assert _rel(T.cpu().numpy(), T0) <= TOL
 
 
+def test_sinkhorn_wide_n32768_full():
+    """Rows of 32768 entries (two passes per iteration over slabs of 8192
+    columns), 4096 rows, mixture marginals with underflowing tails, a seeded
+    uniform cost: every potential and every plan entry."""
+    gw, torch = _gw()
+    M, N, k, eps, iters = 4096, 32768, 2, 1e-3, 3
+    print(f"fullsize wide sinkhorn M={M} N={N} iters={iters}", flush=True)
+    p = inputs.gauss_mixture_1d(M, inputs.rng_for(2, 0, k))
+    q = inputs.gauss_mixture_1d(N, inputs.rng_for(2, 1, k))
+    C = inputs.rng_for(601).uniform(0.0, 1.0, size=(M, N))
+    f, g, T = gw.sinkhorn(_dev(torch, C), _dev(torch, p), _dev(torch, q), eps, iters, plan=True)
+    torch.cuda.synchronize()
+    f0, g0 = O.sinkhorn(C, p, q, eps, iters)
+    assert _rel(f.cpu().numpy(), f0) <= TOL
+    assert _rel(g.cpu().numpy(), g0) <= TOL
+    assert _rel(T.cpu().numpy(), O.plan(C, f0, g0, eps)) <= TOL
+
+
 def test_solve_n4096_one_outer_full():
     gw, torch = _gw()
     n, k, eps = 4096, 2, 1e-3

@@ -206,6 +206,60 @@ def test_sinkhorn_zero_mass_and_extreme_ratio():
     assert np.all(T[0] == 0) and np.all(T[:, 3] == 0)
 
 
+# rows of more than 16384 entries: slabs of 8192 columns, two passes per iteration
+WIDE_CASES = [(40, 20000, 2e-3, 3), (70, 16385, 1e-3, 4), (300, 33000, 5e-3, 3),
+              (3, 65535, 5e-3, 2)]
+
+
+@pytest.mark.parametrize("M,N,eps,iters", WIDE_CASES)
+def test_sinkhorn_wide_rows_match_oracle(M, N, eps, iters):
+    gw, torch = _gw()
+    print(f"sinkhorn wide rows M={M} N={N} eps={eps} iters={iters}", flush=True)
+    rng = inputs.rng_for(212, M, N)
+    C = rng.uniform(0, 2, size=(M, N))
+    p, q = inputs.dirichlet(M, rng), inputs.dirichlet(N, rng)
+    p[M // 2] = 0.0; p /= p.sum()
+    q[[7, N - 2]] = 0.0; q /= q.sum()
+    f0, g0 = O.sinkhorn(2.0 * C, p, q, eps, iters)
+    f, g, T = gw.sinkhorn(_to_dev(torch, C), _to_dev(torch, p), _to_dev(torch, q), eps, iters,
+                          c_scale=2.0, plan=True)
+    torch.cuda.synchronize()
+    assert err(f.cpu().numpy(), f0) <= TOL
+    assert err(g.cpu().numpy(), g0) <= TOL
+    assert err(T.cpu().numpy(), O.plan(2.0 * C, f0, g0, eps)) <= TOL
+
+
+def test_sinkhorn_wide_rows_warm_start():
+    gw, torch = _gw()
+    rng = inputs.rng_for(213)
+    M, N = 50, 17000
+    C = rng.uniform(0, 1, size=(M, N))
+    p, q = inputs.dirichlet(M, rng), inputs.dirichlet(N, rng)
+    f1, g1 = O.sinkhorn(C, p, q, 0.02, 3)
+    f2, g2 = O.sinkhorn(C, p, q, 0.02, 2, f1, g1)
+    fd, gd = gw.sinkhorn(_to_dev(torch, C), _to_dev(torch, p), _to_dev(torch, q), 0.02, 3)
+    fd, gd = gw.sinkhorn(_to_dev(torch, C), _to_dev(torch, p), _to_dev(torch, q), 0.02, 2, f=fd, g=gd)
+    torch.cuda.synchronize()
+    assert err(fd.cpu().numpy(), f2) <= TOL and err(gd.cpu().numpy(), g2) <= TOL
+
+
+def test_solve_wide_rows_match_oracle():
+    """A solve whose Y grid has more than 16384 points (the Sinkhorn calls run
+    the slab path), against the oracle with its recursion gradient."""
+    gw, torch = _gw()
+    X, Y = gw.unit_grid((200,), 2), gw.unit_grid((17000,), 1)
+    rng = inputs.rng_for(214)
+    p, q = inputs.gauss_mixture_1d(200, rng), inputs.gauss_mixture_1d(17000, rng)
+    eps, outer, inner = 5e-3, 2, 6
+    T0, f0, g0, (E0, R0) = O.solve(ogrid(X), ogrid(Y), p, q, eps, outer, inner, gradient="pascal")
+    T, f, g, obj = gw.solve(X, Y, _to_dev(torch, p), _to_dev(torch, q), eps, outer, inner)
+    torch.cuda.synchronize()
+    assert err(T.cpu().numpy(), T0) <= TOL
+    assert err(f.cpu().numpy(), f0) <= TOL and err(g.cpu().numpy(), g0) <= TOL
+    o = obj.cpu().numpy()
+    assert abs(o[0] - E0) <= TOL * abs(E0)
+
+
 def _tail_marginal(n, rng, lo):
     """Normalised Gaussian bump with tails hundreds of decades below its peak
     (the decay rate is set by `lo`), and two exact zeros."""
