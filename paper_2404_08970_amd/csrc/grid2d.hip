@@ -394,10 +394,175 @@ __device__ void line_op(int m, const double* x, int64_t xs, double* y, int64_t y
   }
 }
 
+// ------------------------------------------- 1D operator on rows, one wave each
+// y = D^m x for every row x of `in` (a 1D grid of unit spacing, m >= 1), with
+// the recursion of Sec. 3, Eq. (1d recursive relation) cut into pieces.  A
+// row is taken in chunks of 64 runs of LE entries, one run per lane.  The
+// recursion is linear in (state, entry), so the state after a run is the
+// state carried in, advanced LE positions with no entry (pascal_shift), plus
+// the state the run's own entries build from zero: the lanes' own states
+// combine by a scan over the wave and the chunks by a carry.  The suffix half
+// (entries to the right) runs first, from the last chunk down, keeping the
+// carry that enters each chunk in LDS; the prefix half then runs from the
+// first chunk up, and each entry of y = prefix + suffix is written once.
+constexpr int LE = 8;                            // entries per lane and chunk
+constexpr int LCH = 64 * LE;                     // entries per chunk
+constexpr int LMAXCH = (65535 + LCH - 1) / LCH;  // chunks of the longest axis
+constexpr int LWAVES = 4;                        // rows per block
+
+// Inclusive scan of run states over the wave: towards higher lanes (UP, the
+// prefix half) or towards lower lanes (the suffix half).
+template <int K, bool UP>
+__device__ void wave_scan_runs(double (&a)[K + 1], int lane) {
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    double n[K + 1];
+#pragma unroll
+    for (int r = 0; r <= K; ++r) n[r] = UP ? __shfl_up(a[r], d, 64) : __shfl_down(a[r], d, 64);
+    gwk::pascal_shift<K>(n, (double)(d * LE));
+    if (UP ? lane >= d : lane + d < 64) {
+#pragma unroll
+      for (int r = 0; r <= K; ++r) a[r] += n[r];
+    }
+  }
+}
+
+template <int K>
+__global__ __launch_bounds__(64 * LWAVES) void k_line_rows(const double* __restrict__ in,
+                                                            int64_t ldi, int64_t rows, int64_t W,
+                                                            double* __restrict__ out, int64_t ldo) {
+  __shared__ double buf[LWAVES][LCH + 64];         // a chunk; run l at l * (LE + 1)
+  __shared__ double carry[LWAVES][LMAXCH][K + 1];  // suffix state entering each chunk
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t row = (int64_t)blockIdx.x * LWAVES + wv;
+  const bool live = row < rows;  // every wave runs the loops: the barriers are block-wide
+  const double* x = in + (live ? row : 0) * ldi;
+  const int nch = (int)((W + LCH - 1) / LCH);
+  double* b = buf[wv];
+  auto load = [&](int c, double (&v)[LE]) {
+    const int64_t c0 = (int64_t)c * LCH;
+#pragma unroll
+    for (int e = 0; e < LE; ++e) {
+      const int i = e * 64 + lane;
+      const int64_t j = c0 + i;
+      b[i + i / LE] = (live && j < W) ? x[j] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < LE; ++e) v[e] = b[lane * (LE + 1) + e];
+    __syncthreads();
+  };
+  double v[LE];
+  double cs[K + 1];  // suffix state entering the current chunk from the right
+#pragma unroll
+  for (int r = 0; r <= K; ++r) cs[r] = 0.0;
+  for (int c = nch - 1;; --c) {
+    if (lane == 0)
+#pragma unroll
+      for (int r = 0; r <= K; ++r) carry[wv][c][r] = cs[r];
+    if (c == 0) break;
+    load(c, v);
+    double s[K + 1];
+#pragma unroll
+    for (int r = 0; r <= K; ++r) s[r] = 0.0;
+#pragma unroll
+    for (int e = LE - 1; e >= 0; --e) gwk::pascal_step<K>(s, v[e]);
+    wave_scan_runs<K, false>(s, lane);
+    gwk::pascal_shift<K>(cs, (double)LCH);
+#pragma unroll
+    for (int r = 0; r <= K; ++r) cs[r] += __shfl(s[r], 0, 64);
+  }
+  __syncthreads();
+  double cp[K + 1];  // prefix state entering the current chunk from the left
+#pragma unroll
+  for (int r = 0; r <= K; ++r) cp[r] = 0.0;
+  for (int c = 0; c < nch; ++c) {
+    load(c, v);
+    double p[K + 1], s[K + 1];
+#pragma unroll
+    for (int r = 0; r <= K; ++r) p[r] = s[r] = 0.0;
+#pragma unroll
+    for (int e = 0; e < LE; ++e) gwk::pascal_step<K>(p, v[e]);
+#pragma unroll
+    for (int e = LE - 1; e >= 0; --e) gwk::pascal_step<K>(s, v[e]);
+    wave_scan_runs<K, true>(p, lane);
+    wave_scan_runs<K, false>(s, lane);
+    // states entering this lane's run: the lanes before it in the chunk plus
+    // the chunk's carry, advanced over the runs in between
+    double pn[K + 1], sn[K + 1], tot[K + 1];
+#pragma unroll
+    for (int r = 0; r <= K; ++r) {
+      const double pl = __shfl_up(p[r], 1, 64), sl = __shfl_down(s[r], 1, 64);
+      pn[r] = lane > 0 ? pl : 0.0;
+      sn[r] = lane < 63 ? sl : 0.0;
+      tot[r] = __shfl(p[r], 63, 64);
+    }
+    double ca[K + 1], cb[K + 1];
+#pragma unroll
+    for (int r = 0; r <= K; ++r) {
+      ca[r] = cp[r];
+      cb[r] = carry[wv][c][r];
+    }
+    gwk::pascal_shift<K>(ca, (double)(lane * LE));
+    gwk::pascal_shift<K>(cb, (double)((63 - lane) * LE));
+#pragma unroll
+    for (int r = 0; r <= K; ++r) {
+      pn[r] += ca[r];
+      sn[r] += cb[r];
+    }
+    gwk::pascal_shift<K>(cp, (double)LCH);
+#pragma unroll
+    for (int r = 0; r <= K; ++r) cp[r] += tot[r];
+    double yv[LE];
+#pragma unroll
+    for (int e = 0; e < LE; ++e) {
+      yv[e] = pn[K];
+      gwk::pascal_step<K>(pn, v[e]);
+    }
+#pragma unroll
+    for (int e = LE - 1; e >= 0; --e) {
+      yv[e] += sn[K];
+      gwk::pascal_step<K>(sn, v[e]);
+    }
+#pragma unroll
+    for (int e = 0; e < LE; ++e) b[lane * (LE + 1) + e] = yv[e];
+    __syncthreads();
+    const int64_t c0 = (int64_t)c * LCH;
+    if (live) {
+      double* y = out + row * ldo;
+#pragma unroll
+      for (int e = 0; e < LE; ++e) {
+        const int i = e * 64 + lane;
+        const int64_t j = c0 + i;
+        if (j < W) y[j] = b[i + i / LE];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <int K>
+void launch_line_rows(const double* in, int64_t ldi, int64_t rows, int64_t W, double* out,
+                      int64_t ldo, hipStream_t s) {
+  if (rows <= 0 || W <= 0) return;
+  const unsigned nb = (unsigned)((rows + LWAVES - 1) / LWAVES);
+  k_line_rows<K><<<nb, 64 * LWAVES, 0, s>>>(in, ldi, rows, W, out, ldo);
+}
+
+// y = D^m x on every row (1D grid, unit spacing), m in [1, GW_KMAX].
+void line_rows(int m, const double* in, int64_t ldi, int64_t rows, int64_t W, double* out,
+               int64_t ldo, hipStream_t s) {
+  switch (m) {
+    case 1: launch_line_rows<1>(in, ldi, rows, W, out, ldo, s); break;
+    case 2: launch_line_rows<2>(in, ldi, rows, W, out, ldo, s); break;
+    case 3: launch_line_rows<3>(in, ldi, rows, W, out, ldo, s); break;
+    default: launch_line_rows<4>(in, ldi, rows, W, out, ldo, s); break;
+  }
+}
+
 // Apply the (unscaled) grid operator to each row of `in` (rows x n,
-// n = Z*H*W) treating the row as a Z x H x W array; one block per row.  `tmp`
-// (and `tmp2` for 3D) are rows x n scratch.  1D grids use a single sequential
-// line per row.
+// n = Z*H*W) treating the row as a Z x H x W array (2D and 3D grids); one
+// block per row.  `tmp` (and `tmp2` for 3D) are rows x n scratch.
 __global__ __launch_bounds__(NT) void k_rowop(const double* __restrict__ in, int64_t ldi,
                                                int64_t rows, int ndim, int k, int metric,
                                                int64_t Z, int64_t H, int64_t W,
@@ -410,10 +575,6 @@ __global__ __launch_bounds__(NT) void k_rowop(const double* __restrict__ in, int
   const int64_t hw = H * W;
   double* t = tmp + row * (Z * hw);
   const int tid = threadIdx.x;
-  if (ndim == 1) {
-    if (tid == 0) line_op(metric == GW_METRIC_SQEUCLID ? 2 : k, x, 1, y, 1, W, 1.0, false);
-    return;
-  }
   if (ndim == 3) {
     // (l1)^k: (dz + dr + dc)^k = sum over a + b + c = k of k!/(a! b! c!) dz^a dr^b dc^c,
     // one Kronecker term per (a, b, c); SQEUCLID: the three squared axes
@@ -1334,14 +1495,18 @@ gw_status fast_generic(const gwr::Grid& X, const gwr::Grid& Y, const double* p,
   }
   // generic: A = T D^_Y (rows), At = A^T, Bt = At D^_X (rows), G = epilogue(Bt^T)
   // images of up to 64 x 64 points (3D: 16 per axis): the LDS kernels, one block per row
-  if (gwl::img_rowop(T, ldT, M, Y, A, N, s) == GW_EUNSUPPORTED &&
-      gwl::img3_rowop(T, ldT, M, Y, A, N, s) == GW_EUNSUPPORTED)
+  if (Y.ndim == 1)
+    line_rows(Y.metric == GW_METRIC_SQEUCLID ? 2 : Y.k, T, ldT, M, N, A, N, s);
+  else if (gwl::img_rowop(T, ldT, M, Y, A, N, s) == GW_EUNSUPPORTED &&
+           gwl::img3_rowop(T, ldT, M, Y, A, N, s) == GW_EUNSUPPORTED)
     k_rowop<<<(unsigned)M, NT, 0, s>>>(T, ldT, M, Y.ndim, Y.k, Y.metric, Y.Z, Y.H, Y.W, A, N, tmp,
                                        tmp2);
   dim3 tg1((unsigned)((N + 31) / 32), (unsigned)((M + 31) / 32));
   k_transpose<<<tg1, NT, 0, s>>>(A, N, M, N, At, M, nullptr, nullptr, 0.0);
-  if (gwl::img_rowop(At, M, N, X, A, M, s) == GW_EUNSUPPORTED &&
-      gwl::img3_rowop(At, M, N, X, A, M, s) == GW_EUNSUPPORTED)
+  if (X.ndim == 1)
+    line_rows(X.metric == GW_METRIC_SQEUCLID ? 2 : X.k, At, M, N, M, A, M, s);
+  else if (gwl::img_rowop(At, M, N, X, A, M, s) == GW_EUNSUPPORTED &&
+           gwl::img3_rowop(At, M, N, X, A, M, s) == GW_EUNSUPPORTED)
     k_rowop<<<(unsigned)N, NT, 0, s>>>(At, M, N, X.ndim, X.k, X.metric, X.Z, X.H, X.W, A, M, tmp,
                                        tmp2);
   dim3 tg2((unsigned)((M + 31) / 32), (unsigned)((N + 31) / 32));

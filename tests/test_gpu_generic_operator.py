@@ -2,7 +2,9 @@
 Eq. (2D kronecker) and Eq. (2d gradient); the 3D form adds one Kronecker
 factor) whose cross terms cannot be separated, on images larger than the LDS
 kernels take (2D sides above 64, 3D axes above 16), and mixed pairs whose 1D
-side goes through the same operator.  Expected values: the oracle's plain
+side goes through the wave-parallel line kernel (one wave per row, runs of
+eight entries per lane, chunks of 512 combined by a carry: sides of 1 to
+several chunks, ragged).  Expected values: the oracle's plain
 definition, in full where the distance matrices are small and on sampled rows
 (grad_rows) where they are not.  Tolerance: relative 1e-10."""
 import numpy as np
@@ -52,6 +54,10 @@ CASES = [
     ((70, 66), 2, (300,), 3),       # 2D generic x 1D
     ((257,), 2, (66, 65), 2),       # 1D x 2D generic
     ((18, 5, 5), 2, (129,), 1),     # 3D generic x 1D
+    ((4096,), 2, (70, 66), 2),      # long 1D side: eight chunks
+    ((66, 65), 2, (1100,), 4),      # three chunks, the last ragged, k = 4
+    ((1,), 3, (65, 66), 2),         # one-point 1D side
+    ((513,), 1, (17, 4, 3), 3),     # one chunk and one entry
 ]
 
 
@@ -78,7 +84,8 @@ def test_generic_operator_grad_matches_oracle(sx, kx, sy, ky):
     assert e <= TOL
 
 
-@pytest.mark.parametrize("sx,kx,sy,ky", [((66, 70), 2, (9, 7), 3), ((17, 4, 3), 3, (5, 3, 2), 2)])
+@pytest.mark.parametrize("sx,kx,sy,ky", [((66, 70), 2, (9, 7), 3), ((17, 4, 3), 3, (5, 3, 2), 2),
+                                          ((66, 70), 2, (120,), 3), ((1030,), 2, (5, 40), 2)])
 def test_generic_operator_integer_inputs_bit_exact(sx, kx, sy, ky):
     """h = 1 and integer T, p, q: every intermediate is an integer below 2^53,
     so the generic operator's result equals the plain definition exactly."""
