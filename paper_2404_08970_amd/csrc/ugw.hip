@@ -10,13 +10,16 @@
 // The scalars of a step (m, the shift g(Th), e, tau, the rescale factor) stay
 // in device memory, so a solve needs no host synchronisation.
 //
-// Kernels: the row update is one block per row (each thread holds its entries
-// of the row, block max then block sum of the exponentials); the column update
-// runs an online log-sum-exp over row chunks (a block per 64 columns x chunk,
-// 16 waves splitting the chunk) and merges the chunks per column in order.
-// Every reduction has a fixed order.  This path is not tuned like the balanced
-// Sinkhorn: it reads C twice per iteration.
+// Kernels: rows of up to 8192 entries take one pass over C per iteration (a
+// block per band of rows updates f and keeps the band's column sums, a small
+// merge sets g; described above k_uot_fused).  Longer rows take two: the row
+// update is one block per row (each thread holds its entries of the row,
+// block max then block sum of the exponentials); the column update runs an
+// online log-sum-exp over row chunks (a block per 64 columns x chunk, 16 waves
+// splitting the chunk) and merges the chunks per column in order.  Every
+// reduction has a fixed order.
 #include "common.h"
+#include "expx.h"
 #include "runtime.h"
 
 namespace {
@@ -127,6 +130,229 @@ __global__ __launch_bounds__(NTH) void k_uot_row(const double* __restrict__ C, i
     f[i] = -sc->tau * sc->e * L;
   }
 }
+
+// ---- one pass per iteration, rows of up to 8192 entries
+// With b_p = (g_p - shift)/e + ln v_p and z_ip = b_p - C_ip/e the row update
+// is f_i = -tau e (m_i + ln s_i), m_i = max_p z_ip, s_i = sum_p exp(z_ip - m_i).
+// The column update needs exp((f_i - C_ip - shift)/e + ln u_i)
+//   = exp(z_ip - m_i) exp(lam_i) exp(-b_p),  lam_i = m_i + (f_i - shift)/e + ln u_i,
+// so the row's own exponentials feed the column sums.  A column with v_p = 0
+// is left out of the row maxima and sums and takes b_p = (g_p - shift)/e for
+// its exponentials (its g_p is still defined by the column update).  A
+// column's largest term can lie far below every row maximum, so each
+// exponential is kept as a mantissa times 2^n and a band's column sums as
+// (mantissa, binary exponent) pairs; the merge adds the bands in order and
+// sets g_p = -tau e (ln S_p - b_p) with the b_p of the pass.
+constexpr int UF_BANDS = 256;  // bands of rows per pass (at most)
+constexpr double LAM_MAX = 1.0e6;
+
+GW_DEV double col_base(double gp, double lvp, double shift, double ie) {
+  const double gb = (gp - shift) * ie;
+  return lvp > -INFINITY ? gb + lvp : gb;
+}
+
+template <int NTH, int EPT, int R>
+__global__ __launch_bounds__(NTH) void k_uot_fused(const double* __restrict__ C, int64_t ldC,
+                                                   int M, int N, int RB,
+                                                   const double* __restrict__ g,
+                                                   const double* __restrict__ lu,
+                                                   const double* __restrict__ lv,
+                                                   const UgwScal* __restrict__ sc,
+                                                   double* __restrict__ f,
+                                                   double* __restrict__ partS,
+                                                   int* __restrict__ partX) {
+  constexpr int NW = NTH / 64;
+  constexpr bool BL = EPT >= 16;  // b_p in LDS for the longest rows (registers are short)
+  __shared__ double red[2][R][NW];
+  __shared__ double bls[BL ? NTH * EPT : 1];
+  const int t = threadIdx.x, wv = t >> 6, lane = t & 63;
+  const double shift = sc->shift, e = sc->e, ie = 1.0 / e, tau = sc->tau;
+  double breg[BL ? 1 : EPT], S[EPT];
+  int X[EPT], colc[EPT];
+  unsigned inrow = 0;  // bit e: entry e counts in the row maxima and sums
+#pragma unroll
+  for (int k = 0; k < EPT; ++k) {
+    const int col = t + NTH * k;
+    colc[k] = min(col, N - 1);
+    const double lvv = lv[colc[k]];
+    const double bv = col_base(g[colc[k]], lvv, shift, ie);
+    if constexpr (BL) bls[t + NTH * k] = bv;
+    else breg[k] = bv;
+    if (col < N && lvv > -INFINITY) inrow |= 1u << k;
+    S[k] = 0.0;
+    X[k] = gwx::EXP_SENTINEL;
+  }
+  // each thread reads back only its own entries: no barrier needed
+  auto b = [&](int k) -> double {
+    if constexpr (BL) return bls[t + NTH * k];
+    else return breg[k];
+  };
+  const int i0 = blockIdx.x * RB, i1 = min(M, i0 + RB);
+  double cur[R][EPT];
+  auto load = [&](int ib) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const double* row = C + (int64_t)min(ib + r, i1 - 1) * ldC;
+#pragma unroll
+      for (int k = 0; k < EPT; ++k) cur[r][k] = row[colc[k]];
+    }
+  };
+  if (i0 < i1) load(i0);
+  for (int ib = i0; ib < i1; ib += R) {
+    double z[R][EPT], m[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      double ml = -INFINITY;
+#pragma unroll
+      for (int k = 0; k < EPT; ++k) {
+        z[r][k] = fma(-ie, cur[r][k], b(k));
+        if (inrow >> k & 1u) ml = fmax(ml, z[r][k]);
+      }
+      m[r] = ml;
+    }
+    load(ib + R);  // the next rows (clamped: past the band it re-reads the last row)
+    double lui[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      lui[r] = lu[min(ib + r, i1 - 1)];
+      const double ml = gwk::wave_max(m[r]);
+      if (lane == 63) red[0][r][wv] = ml;
+    }
+    __syncthreads();
+    int nE[R][EPT];
+    double sl[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      double mr = red[0][r][0];
+#pragma unroll
+      for (int w = 1; w < NW; ++w) mr = fmax(mr, red[0][r][w]);
+      m[r] = mr;
+      const double ms = mr > -INFINITY ? mr : 0.0;
+      sl[r] = 0.0;
+#pragma unroll
+      for (int k = 0; k < EPT; ++k) {
+        z[r][k] = gwx::exp_split(fmin(z[r][k] - ms, LAM_MAX), &nE[r][k]);
+        if (inrow >> k & 1u) sl[r] += ldexp(z[r][k], nE[r][k]);
+      }
+      sl[r] = gwk::wave_sum(sl[r]);
+      if (lane == 63) red[1][r][wv] = sl[r];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int i = ib + r;
+      if (i >= i1) break;
+      double s = red[1][r][0];
+#pragma unroll
+      for (int w = 1; w < NW; ++w) s += red[1][r][w];
+      const double lse = m[r] + log(s);
+      const double fi = -tau * e * lse;
+      if (t == 0) f[i] = fi;
+      if (!(s > 0.0) || !(lui[r] > -INFINITY)) continue;  // no terms, or u_i = 0
+      const double lam = fmax(fmin(m[r] + ((fi - shift) * ie + lui[r]), LAM_MAX), -LAM_MAX);
+      const double nd = rint(lam * gwx::INV_LN2);
+      double rr = fma(-nd, gwx::LN2_HI, lam);
+      rr = fma(-nd, gwx::LN2_LO, rr);
+      const double mw = gwx::exp_reduced(rr);
+      const int ew = (int)nd;
+#pragma unroll
+      for (int k = 0; k < EPT; ++k) {
+        const int te = nE[r][k] + ew;
+        const int ne = max(X[k], te);
+        S[k] = ldexp(S[k], X[k] - ne) + ldexp(z[r][k] * mw, te - ne);
+        X[k] = ne;
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < EPT; ++k) {
+    const int col = t + NTH * k;
+    if (col < N) {
+      partS[(int64_t)blockIdx.x * N + col] = S[k];
+      partX[(int64_t)blockIdx.x * N + col] = X[k];
+    }
+  }
+}
+
+// Merge of the bands' column pairs, in band order: 16 columns x 16 groups of
+// bands per block, the groups merged in order; g_p = -tau e (ln S_p - b_p).
+constexpr int UM_COLS = 16, UM_GRPS = 16, UM_BATCH = 8;
+
+__global__ __launch_bounds__(UM_COLS * UM_GRPS) void k_uot_merge(
+    int N, int nb, const double* __restrict__ partS, const int* __restrict__ partX,
+    const double* __restrict__ lv, const UgwScal* __restrict__ sc, double* __restrict__ g,
+    gwr::StatusWord* status) {
+  __shared__ double ms[UM_GRPS][UM_COLS];
+  __shared__ int mx[UM_GRPS][UM_COLS];
+  const int c = threadIdx.x % UM_COLS, grp = threadIdx.x / UM_COLS;
+  const int col = blockIdx.x * UM_COLS + c, colc = min(col, N - 1);
+  const int per = (nb + UM_GRPS - 1) / UM_GRPS;
+  const int b0 = grp * per, b1 = min(nb, b0 + per);
+  double S = 0.0;
+  int X = gwx::EXP_SENTINEL;
+  for (int bb = b0; bb < b1; bb += UM_BATCH) {
+    double sv[UM_BATCH];
+    int xv[UM_BATCH];
+#pragma unroll
+    for (int u = 0; u < UM_BATCH; ++u) {
+      const int64_t band = min(bb + u, nb - 1);
+      sv[u] = partS[band * N + colc];
+      xv[u] = partX[band * N + colc];
+    }
+#pragma unroll
+    for (int u = 0; u < UM_BATCH; ++u) {
+      if (bb + u < b1) {
+        const int ne = max(X, xv[u]);
+        S = ldexp(S, X - ne) + ldexp(sv[u], xv[u] - ne);
+        X = ne;
+      }
+    }
+  }
+  ms[grp][c] = S;
+  mx[grp][c] = X;
+  __syncthreads();
+  if (grp != 0 || col >= N) return;
+  for (int k = 1; k < UM_GRPS; ++k) {
+    const int ne = max(X, mx[k][c]);
+    S = ldexp(S, X - ne) + ldexp(ms[k][c], mx[k][c] - ne);
+    X = ne;
+  }
+  const double shift = sc->shift, e = sc->e, ie = 1.0 / e;
+  const double bp = col_base(g[col], lv[col], shift, ie);
+  const double lnS =
+      S > 0.0 ? fma((double)X, gwx::LN2_HI, fma((double)X, gwx::LN2_LO, log(S))) : -INFINITY;
+  const double gn = -sc->tau * e * (lnS - bp);
+  g[col] = gn;
+  if (isnan(gn)) status->nonfinite = 1;
+}
+
+// Rows per band of the one-pass update: at most UF_BANDS bands, a multiple of
+// the rows a step takes (2).
+int uot_band_rows(int64_t M) {
+  int64_t rb = (M + UF_BANDS - 1) / UF_BANDS;
+  rb = (rb + 1) / 2 * 2;
+  return (int)(rb < 2 ? 2 : rb);
+}
+
+gw_status launch_uot_fused(const double* C, int64_t ldC, int64_t M, int64_t N, int RB,
+                           const double* g, const double* lu, const double* lv,
+                           const UgwScal* sc, double* f, double* partS, int* partX,
+                           hipStream_t s) {
+  const unsigned nb = (unsigned)((M + RB - 1) / RB);
+  const int m = (int)M, n = (int)N;
+#define UF_ARGS C, ldC, m, n, RB, g, lu, lv, sc, f, partS, partX
+  if (N <= 256) k_uot_fused<256, 1, 2><<<nb, 256, 0, s>>>(UF_ARGS);
+  else if (N <= 512) k_uot_fused<256, 2, 2><<<nb, 256, 0, s>>>(UF_ARGS);
+  else if (N <= 1024) k_uot_fused<256, 4, 2><<<nb, 256, 0, s>>>(UF_ARGS);
+  else if (N <= 2048) k_uot_fused<256, 8, 2><<<nb, 256, 0, s>>>(UF_ARGS);
+  else if (N <= 4096) k_uot_fused<512, 8, 2><<<nb, 512, 0, s>>>(UF_ARGS);
+  else if (N <= 8192) k_uot_fused<512, 16, 1><<<nb, 512, 0, s>>>(UF_ARGS);
+  else return GW_EUNSUPPORTED;
+#undef UF_ARGS
+  return GW_OK;
+}
+
+constexpr int64_t UF_MAX_N = 8192;
 
 // Column update, first stage: (m, s) of LSE_i((f_i - C_ip - shift)/e + ln u_i)
 // over the rows of chunk blockIdx.y, for 64 columns; each wave takes a
@@ -378,9 +604,15 @@ size_t uot_ws_bytes(int64_t M, int64_t N) {
   gwr::Arena a{nullptr, 0, 0};
   a.take<double>(M);  // ln u
   a.take<double>(N);  // ln v
-  const int R = uot_chunks(M);
-  a.take<double>((size_t)R * N);
-  a.take<double>((size_t)R * N);
+  if (N <= UF_MAX_N) {  // the bands' column pairs of the one-pass update
+    const int64_t nb = (M + uot_band_rows(M) - 1) / uot_band_rows(M);
+    a.take<double>((size_t)nb * N);
+    a.take<int>((size_t)nb * N);
+  } else {
+    const int R = uot_chunks(M);
+    a.take<double>((size_t)R * N);
+    a.take<double>((size_t)R * N);
+  }
   a.take<double>(M);  // row sums of the plan
   return a.used;
 }
@@ -400,9 +632,19 @@ gw_status uot_sinkhorn(const double* C, int64_t ldC, int64_t M, int64_t N, const
   UgwScal* sc = static_cast<UgwScal*>(scal);
   double* lu = ws.take<double>(M);
   double* lv = ws.take<double>(N);
+  const bool fused = N <= UF_MAX_N;
+  const int RB = uot_band_rows(M);
+  const int64_t nb = (M + RB - 1) / RB;
   const int R = uot_chunks(M);
-  double* pm = ws.take<double>((size_t)R * N);
-  double* ps = ws.take<double>((size_t)R * N);
+  double *pm = nullptr, *ps = nullptr, *partS = nullptr;
+  int* partX = nullptr;
+  if (fused) {
+    partS = ws.take<double>((size_t)nb * N);
+    partX = ws.take<int>((size_t)nb * N);
+  } else {
+    pm = ws.take<double>((size_t)R * N);
+    ps = ws.take<double>((size_t)R * N);
+  }
   double* rowsum = ws.take<double>(M);
   gwr::ProfScope prof(gwr::kFamOther, s);
   const int64_t mx = M > N ? M : N;
@@ -410,7 +652,13 @@ gw_status uot_sinkhorn(const double* C, int64_t ldC, int64_t M, int64_t N, const
                                                           init_zero);
   const int rpc = (int)((M + R - 1) / R);
   const dim3 cgrid((unsigned)((N + UC_COLS - 1) / UC_COLS), (unsigned)R);
-  for (int it = 0; it < iters; ++it) {
+  for (int it = 0; it < iters && fused; ++it) {
+    gw_status st = launch_uot_fused(C, ldC, M, N, RB, g, lu, lv, sc, f, partS, partX, s);
+    if (st != GW_OK) return st;
+    k_uot_merge<<<(unsigned)((N + UM_COLS - 1) / UM_COLS), UM_COLS * UM_GRPS, 0, s>>>(
+        (int)N, (int)nb, partS, partX, lv, sc, g, status);
+  }
+  for (int it = 0; it < iters && !fused; ++it) {
     gw_status st = launch_uot_row(C, ldC, M, N, g, lv, sc, f, s);
     if (st != GW_OK) return st;
     k_uot_colpart<<<cgrid, UC_COLS * UC_WAVES, 0, s>>>(C, ldC, (int)M, (int)N, rpc, f, lu, sc,

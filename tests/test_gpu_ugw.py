@@ -1,6 +1,6 @@
 """GPU parity of unbalanced GW (Remark on UGW) against the oracle: the
 unbalanced Sinkhorn in every row-length class (zero-mass entries, a cost
-shift, warm start) and the UGW solve on 1D (FAST and dense), 2D and mixed grids,
+shift, warm start; one row, one column, costs up to 1000 eps) and the UGW solve on 1D (FAST and dense), 2D and mixed grids,
 including outer = 0 and the n = 1024 problem in full."""
 import math
 
@@ -29,6 +29,36 @@ def test_uot_sinkhorn_matches_oracle(M, N, rho, eps, shift, iters):
     u, v = rng.uniform(0.0, 2.0 / M, M), rng.uniform(0.0, 3.0 / N, N)
     u[M // 3] = 0.0
     v[[1, N // 2]] = 0.0
+    f0, g0 = O.uot_sinkhorn(C + shift, u, v, rho, eps, iters)
+    T0 = O.uot_plan(C + shift, f0, g0, u, v, eps)
+    d = lambda a: _to_dev(torch, a)
+    f, g, T = gw.uot_sinkhorn(d(C), d(u), d(v), rho, eps, iters, c_shift=shift, plan=True)
+    torch.cuda.synchronize()
+    assert err(f.cpu().numpy(), f0) <= TOL
+    assert err(g.cpu().numpy(), g0) <= TOL
+    assert err(T.cpu().numpy(), T0) <= TOL
+
+
+UOT_EDGE = [(700, 300, 1.0, 0.002, 0.0, 4),    # 175 bands of 4 rows, C/eps up to 500
+            (1, 5000, 0.5, 0.01, 0.0, 3),      # one row
+            (3000, 1, 0.5, 0.01, 0.0, 3),      # one column
+            (513, 2048, 2.0, 0.001, 0.0, 3)]   # C/eps up to 1000, a ragged last band
+
+
+@pytest.mark.parametrize("M,N,rho,eps,shift,iters", UOT_EDGE)
+def test_uot_sinkhorn_edge_shapes_match_oracle(M, N, rho, eps, shift, iters):
+    """Shapes at the edges of the one-pass update's banding, and costs far
+    above eps, where a column's largest term lies many binades below the row
+    maxima of the pass (the extended-exponent column sums)."""
+    gw, torch = _gw()
+    print(f"uot edge M={M} N={N} rho={rho} eps={eps}", flush=True)
+    rng = inputs.rng_for(951, M, N)
+    C = rng.uniform(0, 1, (M, N))
+    u, v = rng.uniform(0.0, 2.0 / M, M), rng.uniform(0.0, 3.0 / N, N)
+    if M > 2:
+        u[M // 3] = 0.0
+    if N > 2:
+        v[[1, N // 2]] = 0.0
     f0, g0 = O.uot_sinkhorn(C + shift, u, v, rho, eps, iters)
     T0 = O.uot_plan(C + shift, f0, g0, u, v, eps)
     d = lambda a: _to_dev(torch, a)
