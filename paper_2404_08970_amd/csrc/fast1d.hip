@@ -263,24 +263,26 @@ __global__ __launch_bounds__(256) void k_p1_moments(const double* __restrict__ T
 // (layout base[((dir * ntiles + tile) * (K+1) + r) * stride + line]): prefix
 // from the left (dir 0), suffix from the right (dir 1); the state is advanced
 // over the width of each tile it passes.  The tiles of a line are cut into
-// SCAN_CH chunks, one thread per (line, chunk): each thread folds its chunk
+// CH chunks, one thread per (line, chunk): each thread folds its chunk
 // into an aggregate, the aggregates of the earlier chunks (shifted over the
 // chunks between) give the thread's incoming state, and a second pass over
-// the chunk writes the exclusive states.
-constexpr int SCAN_LINES = 64, SCAN_CH = 4;
-// With at least this many lines the scan runs one thread per line (one read
-// and one write of the moments); below it, SCAN_CH threads share a line.
-constexpr int64_t SCAN_ONE_THREAD_LINES = 16384;
+// the chunk writes the exclusive states.  A block takes LN lines x CH chunks.
+// With at least SCAN_ONE_THREAD_LINES lines the scan runs one thread per line
+// (one read and one write of the moments, which then stream at about the
+// copy rate); with fewer lines, one thread per line would leave most CUs idle,
+// so chunked threads share a line at the price of a second read.
+constexpr int64_t SCAN_ONE_THREAD_LINES = 32768;
+constexpr int SCAN_MAXCH = 16;
 
 GW_DEV int tile_width(int tt, int64_t extent) {
   const int64_t w = extent - (int64_t)tt * TS;
   return w < TS ? (int)w : TS;
 }
 
-template <int K, int CH>
+template <int K, int LN, int CH>
 GW_DEV void scan_lines(double* base, size_t stride, int line, bool valid, int ntiles,
-                       int64_t extent, double (*agg)[SCAN_CH][SCAN_LINES][K + 1],
-                       double (*span)[SCAN_CH], int ln, int ch) {
+                       int64_t extent, double (*agg)[CH][LN][K + 1], double (*span)[CH], int ln,
+                       int ch) {
   constexpr int PF = 8;  // tiles loaded ahead of the recurrence
   const int cs = (ntiles + CH - 1) / CH;
   const int s0 = ch * cs, s1 = min(ntiles, s0 + cs);
@@ -366,24 +368,24 @@ GW_DEV void scan_lines(double* base, size_t stride, int line, bool valid, int nt
 // ------------------------------------------- P2a/b: row and column carries of T
 // Blocks [0, ceil(M/64)) scan the row moments of 64 rows each, the rest the
 // column moments of 64 columns each.
-template <int KX, int KY, int CH>
-__global__ __launch_bounds__(SCAN_LINES * CH) void k_p2_scan(int M, int N, int nI, int nJ,
+template <int KX, int KY, int LN, int CH>
+__global__ __launch_bounds__(LN * CH) void k_p2_scan(int M, int N, int nI, int nJ,
                                                               double* __restrict__ rowmom,
                                                               double* __restrict__ colmom) {
   constexpr int KM = (KX > KY ? KX : KY) + 1;
-  __shared__ double agg[2][SCAN_CH][SCAN_LINES][KM];
-  __shared__ double span[2][SCAN_CH];
-  const int ln = threadIdx.x & (SCAN_LINES - 1), ch = threadIdx.x / SCAN_LINES;
-  const int rblocks = (M + SCAN_LINES - 1) / SCAN_LINES;
+  __shared__ double agg[2][CH][LN][KM];
+  __shared__ double span[2][CH];
+  const int ln = threadIdx.x % LN, ch = threadIdx.x / LN;
+  const int rblocks = (M + LN - 1) / LN;
   if ((int)blockIdx.x < rblocks) {
-    const int line = blockIdx.x * SCAN_LINES + ln;
-    scan_lines<KY, CH>(rowmom, (size_t)M, min(line, M - 1), line < M, nJ, N,
-                       reinterpret_cast<double (*)[SCAN_CH][SCAN_LINES][KY + 1]>(&agg[0][0][0][0]),
+    const int line = blockIdx.x * LN + ln;
+    scan_lines<KY, LN, CH>(rowmom, (size_t)M, min(line, M - 1), line < M, nJ, N,
+                           reinterpret_cast<double (*)[CH][LN][KY + 1]>(&agg[0][0][0][0]),
                        span, ln, ch);
   } else {
-    const int line = (blockIdx.x - rblocks) * SCAN_LINES + ln;
-    scan_lines<KX, CH>(colmom, (size_t)N, min(line, N - 1), line < N, nI, M,
-                       reinterpret_cast<double (*)[SCAN_CH][SCAN_LINES][KX + 1]>(&agg[0][0][0][0]),
+    const int line = (blockIdx.x - rblocks) * LN + ln;
+    scan_lines<KX, LN, CH>(colmom, (size_t)N, min(line, N - 1), line < N, nI, M,
+                           reinterpret_cast<double (*)[CH][LN][KX + 1]>(&agg[0][0][0][0]),
                        span, ln, ch);
   }
 }
@@ -793,11 +795,15 @@ gw_status run_fast1d(const Layout& L, const double* T, int64_t ldT, double* G, i
   {
     gwr::ProfScope ps(gwr::kFamFastCarry, s);
     k_p1_moments<KX, KY><<<persistent_blocks(k_p1_moments<KX, KY>, ntiles), 256, 0, s>>>(T, ldT, M, N, L.nI, L.nJ, rowmom, colmom);
-    const unsigned sblocks = (unsigned)((M + SCAN_LINES - 1) / SCAN_LINES + (N + SCAN_LINES - 1) / SCAN_LINES);
-    if ((int64_t)M + N >= SCAN_ONE_THREAD_LINES)
-      k_p2_scan<KX, KY, 1><<<sblocks, SCAN_LINES, 0, s>>>(M, N, L.nI, L.nJ, rowmom, colmom);
+    auto sblocks = [&](int ln) { return (unsigned)((M + ln - 1) / ln + (N + ln - 1) / ln); };
+    const int64_t lines = (int64_t)M + N;
+    if (lines >= SCAN_ONE_THREAD_LINES)
+      k_p2_scan<KX, KY, 64, 1><<<sblocks(64), 64, 0, s>>>(M, N, L.nI, L.nJ, rowmom, colmom);
+    else if (lines >= SCAN_ONE_THREAD_LINES / 2)
+      k_p2_scan<KX, KY, 32, 8><<<sblocks(32), 256, 0, s>>>(M, N, L.nI, L.nJ, rowmom, colmom);
     else
-      k_p2_scan<KX, KY, SCAN_CH><<<sblocks, SCAN_LINES * SCAN_CH, 0, s>>>(M, N, L.nI, L.nJ, rowmom, colmom);
+      k_p2_scan<KX, KY, 16, SCAN_MAXCH><<<sblocks(16), 16 * SCAN_MAXCH, 0, s>>>(M, N, L.nI, L.nJ,
+                                                                               rowmom, colmom);
     const int nvec = 2 * L.nI * (KX + 1);
     const size_t shm = (size_t)L.nJ * 2 * (KY + 1) * sizeof(double);
     if (L.nJ <= 4 * P2C_TILES) {
