@@ -60,6 +60,15 @@ GW_DEV double dpp_f64(double v, double old) {
   return __hiloint2double(hi, lo);
 }
 
+// The same move where the lanes the pattern does not write may hold any value
+// (no register has to be initialised with an `old` value first).
+template <int CTRL, int ROW_MASK = 0xF>
+GW_DEV double dpp_any_f64(double v) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, ROW_MASK, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, ROW_MASK, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
 GW_DEV double readlane_f64(double v, int lane) {
   const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
   const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
@@ -70,25 +79,25 @@ GW_DEV double readlane_f64(double v, int lane) {
 // then the two row broadcasts leave the total in lane 63 (GCN/CDNA pattern).
 // The result is returned in every lane.  Only lane 63's value is read: the
 // first four patterns write every lane, and the two broadcasts write the row
-// of lane 63 and the row it reads next, so the lanes a pattern leaves alone
-// may keep any value (`old` is v itself and needs no register of its own).
+// of lane 63 and the row it reads next (from lanes the earlier patterns
+// wrote), so the lanes a pattern leaves alone may hold any value.
 GW_DEV double wave_sum(double v) {
-  v += dpp_f64<0xB1>(v, v);        // quad_perm [1,0,3,2]
-  v += dpp_f64<0x4E>(v, v);        // quad_perm [2,3,0,1]
-  v += dpp_f64<0x141>(v, v);       // row_half_mirror
-  v += dpp_f64<0x140>(v, v);       // row_mirror
-  v += dpp_f64<0x142, 0xA>(v, v);  // row_bcast:15 into rows 1 and 3
-  v += dpp_f64<0x143, 0xC>(v, v);  // row_bcast:31 into rows 2 and 3
+  v += dpp_any_f64<0xB1>(v);        // quad_perm [1,0,3,2]
+  v += dpp_any_f64<0x4E>(v);        // quad_perm [2,3,0,1]
+  v += dpp_any_f64<0x141>(v);       // row_half_mirror
+  v += dpp_any_f64<0x140>(v);       // row_mirror
+  v += dpp_any_f64<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+  v += dpp_any_f64<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
   return readlane_f64(v, 63);
 }
 
 GW_DEV double wave_max(double v) {
-  v = fmax(v, dpp_f64<0xB1>(v, v));
-  v = fmax(v, dpp_f64<0x4E>(v, v));
-  v = fmax(v, dpp_f64<0x141>(v, v));
-  v = fmax(v, dpp_f64<0x140>(v, v));
-  v = fmax(v, dpp_f64<0x142, 0xA>(v, v));
-  v = fmax(v, dpp_f64<0x143, 0xC>(v, v));
+  v = fmax(v, dpp_any_f64<0xB1>(v));
+  v = fmax(v, dpp_any_f64<0x4E>(v));
+  v = fmax(v, dpp_any_f64<0x141>(v));
+  v = fmax(v, dpp_any_f64<0x140>(v));
+  v = fmax(v, dpp_any_f64<0x142, 0xA>(v));
+  v = fmax(v, dpp_any_f64<0x143, 0xC>(v));
   return readlane_f64(v, 63);
 }
 

@@ -59,20 +59,20 @@ constexpr int SEG = 16;
 constexpr int NSEG = TS / SEG;
 
 // Prefix summary at the segment's end and suffix summary at its start - 1 of
-// x[0..SEG) (zero state on entry): pre_r = sum_c (SEG - c)^r x_c,
+// x[0..L) (zero state on entry): pre_r = sum_c (L - c)^r x_c,
 // suf_r = sum_c (c + 1)^r x_c.  The weights are compile-time integers.
-template <int K>
-GW_DEV void seg_summaries(const double (&x)[SEG], double (&pre)[K + 1], double (&suf)[K + 1]) {
+template <int K, int L>
+GW_DEV void seg_summaries(const double (&x)[L], double (&pre)[K + 1], double (&suf)[K + 1]) {
 #pragma unroll
   for (int r = 0; r <= K; ++r) pre[r] = suf[r] = 0.0;
 #pragma unroll
-  for (int c = 0; c < SEG; ++c) {
+  for (int c = 0; c < L; ++c) {
     double wp = 1.0, ws = 1.0;
 #pragma unroll
     for (int r = 0; r <= K; ++r) {
       pre[r] = fma(wp, x[c], pre[r]);
       suf[r] = fma(ws, x[c], suf[r]);
-      wp *= (double)(SEG - c);
+      wp *= (double)(L - c);
       ws *= (double)(c + 1);
     }
   }
@@ -80,16 +80,16 @@ GW_DEV void seg_summaries(const double (&x)[SEG], double (&pre)[K + 1], double (
 
 // out[c] = a_K(c) + b_K(c) over the segment, starting from prefix state `a`
 // (at the segment's first entry) and suffix state `b` (at its last entry).
-template <int K>
-GW_DEV void seg_sweep(const double (&x)[SEG], double (&a)[K + 1], double (&b)[K + 1],
-                      double (&out)[SEG]) {
+template <int K, int L>
+GW_DEV void seg_sweep(const double (&x)[L], double (&a)[K + 1], double (&b)[K + 1],
+                      double (&out)[L]) {
 #pragma unroll
-  for (int c = 0; c < SEG; ++c) {
+  for (int c = 0; c < L; ++c) {
     out[c] = a[K];
     gwk::pascal_step<K>(a, x[c]);
   }
 #pragma unroll
-  for (int c = SEG - 1; c >= 0; --c) {
+  for (int c = L - 1; c >= 0; --c) {
     out[c] += b[K];
     gwk::pascal_step<K>(b, x[c]);
   }
@@ -858,14 +858,25 @@ gw_status dispatch_ky(int ky, const Layout& L, const double* T, int64_t ldT, dou
 // result staged in LDS, then along the image columns (exponent mh), summed over
 // the terms in registers.  The thread keeps its row segment of the image in
 // registers for every term.
+constexpr int IMG_MAX = 96;  // longest image side of the LDS image operator
+
 struct ImgTerms {
   int n;
   int coef[GW_KMAX + 1], mh[GW_KMAX + 1], mw[GW_KMAX + 1];
 };
 
-template <int K>
-GW_DEV void img_line(const double (&x)[SEG], double (&out)[SEG],
-                     double (*sums)[NSEG][TS][GW_KMAX + 1], int lane, int seg) {
+// An image of up to ITS x ITS points: thread (lane, seg) holds segment seg
+// (ITS / NS entries) of line `lane`; NS ITS threads.  64-point images take 4
+// segments of 16, 96-point ones 8 of 12 (fewer registers per thread).
+template <int ITS>
+struct ImgShape {
+  static constexpr int NS = ITS == 64 ? 4 : 8, SL = ITS / NS, NT = NS * ITS;
+};
+
+template <int K, int ITS>
+GW_DEV void img_line(const double (&x)[ImgShape<ITS>::SL], double (&out)[ImgShape<ITS>::SL],
+                     double (*sums)[ImgShape<ITS>::NS][ITS][GW_KMAX + 1], int lane, int seg) {
+  constexpr int NS = ImgShape<ITS>::NS, SL = ImgShape<ITS>::SL;
   double pre[K + 1], suf[K + 1];
   seg_summaries<K>(x, pre, suf);
 #pragma unroll
@@ -878,86 +889,92 @@ GW_DEV void img_line(const double (&x)[SEG], double (&out)[SEG],
 #pragma unroll
   for (int r = 0; r <= K; ++r) a[r] = b[r] = 0.0;
   for (int sg = 0; sg < seg; ++sg) {
-    gwk::pascal_shift<K>(a, (double)SEG);
+    gwk::pascal_shift<K>(a, (double)SL);
 #pragma unroll
     for (int r = 0; r <= K; ++r) a[r] += sums[0][sg][lane][r];
   }
-  for (int sg = NSEG - 1; sg > seg; --sg) {
-    gwk::pascal_shift<K>(b, (double)SEG);
+  for (int sg = NS - 1; sg > seg; --sg) {
+    gwk::pascal_shift<K>(b, (double)SL);
 #pragma unroll
     for (int r = 0; r <= K; ++r) b[r] += sums[1][sg][lane][r];
   }
   seg_sweep<K>(x, a, b, out);
   if constexpr (K == 0) {  // J: the entry itself belongs to the line sum
 #pragma unroll
-    for (int c = 0; c < SEG; ++c) out[c] += x[c];
+    for (int c = 0; c < SL; ++c) out[c] += x[c];
   }
   __syncthreads();  // the summaries are read before the next line pass writes them
 }
 
-GW_DEV void img_line_m(int m, const double (&x)[SEG], double (&out)[SEG],
-                       double (*sums)[NSEG][TS][GW_KMAX + 1], int lane, int seg) {
+template <int ITS>
+GW_DEV void img_line_m(int m, const double (&x)[ImgShape<ITS>::SL],
+                       double (&out)[ImgShape<ITS>::SL],
+                       double (*sums)[ImgShape<ITS>::NS][ITS][GW_KMAX + 1], int lane, int seg) {
   switch (m) {
-    case 0: img_line<0>(x, out, sums, lane, seg); break;
-    case 1: img_line<1>(x, out, sums, lane, seg); break;
-    case 2: img_line<2>(x, out, sums, lane, seg); break;
-    case 3: img_line<3>(x, out, sums, lane, seg); break;
-    default: img_line<4>(x, out, sums, lane, seg); break;
+    case 0: img_line<0, ITS>(x, out, sums, lane, seg); break;
+    case 1: img_line<1, ITS>(x, out, sums, lane, seg); break;
+    case 2: img_line<2, ITS>(x, out, sums, lane, seg); break;
+    case 3: img_line<3, ITS>(x, out, sums, lane, seg); break;
+    default: img_line<4, ITS>(x, out, sums, lane, seg); break;
   }
 }
 
-__global__ __launch_bounds__(256) void k_img_rowop(const double* __restrict__ in, int64_t ldi,
-                                                   int H, int W, ImgTerms terms,
-                                                   double* __restrict__ out, int64_t ldo) {
-  __shared__ double Y[TS][LDS_STRIDE];
-  __shared__ double sums[2][NSEG][TS][GW_KMAX + 1];
-  __shared__ double vec[4][TS];  // row sums, column sums, D^m (row sums), (column sums) D^m
-  const int t = threadIdx.x, lane = t & (TS - 1), seg = __builtin_amdgcn_readfirstlane(t >> 6);
+template <int ITS>
+__global__ __launch_bounds__(ImgShape<ITS>::NT) void k_img_rowop(const double* __restrict__ in,
+                                                       int64_t ldi, int H, int W, ImgTerms terms,
+                                                       double* __restrict__ out, int64_t ldo) {
+  constexpr int NT = ImgShape<ITS>::NT, NS = ImgShape<ITS>::NS, SL = ImgShape<ITS>::SL;
+  __shared__ double Y[ITS][ITS + 1];
+  __shared__ double sums[2][NS][ITS][GW_KMAX + 1];
+  __shared__ double vec[4][ITS];  // row sums, column sums, D^m (row sums), (column sums) D^m
+  const int t = threadIdx.x, lane = t % ITS;
+  // with 64-point lines a segment is a wave: keep its index in a scalar register
+  const int seg = ITS == 64 ? __builtin_amdgcn_readfirstlane(t >> 6) : t / ITS;
   const int64_t row = blockIdx.x;
   const double* src = in + row * ldi;
   // the image into LDS (zero padded to the tile; consecutive threads read
   // consecutive entries of an image row), then the thread's row segment: image
-  // row `lane`, columns seg*SEG + c
+  // row `lane`, columns seg*SL + c
   {
     // all loads issued before any is used (indices clamped into the image)
-    constexpr int PER = TS * TS / 256;
+    constexpr int PER = ITS * ITS / NT;
     double v[PER];
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
-      const int e = t + 256 * u, r = e / TS, c = e % TS;
+      const int e = t + NT * u, r = e / ITS, c = e % ITS;
       v[u] = src[min(r, H - 1) * W + min(c, W - 1)];
     }
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
-      const int e = t + 256 * u, r = e / TS, c = e % TS;
+      const int e = t + NT * u, r = e / ITS, c = e % ITS;
       Y[r][c] = (r < H && c < W) ? v[u] : 0.0;
     }
   }
   __syncthreads();
-  double xr[SEG];
+  double xr[SL];
 #pragma unroll
-  for (int c = 0; c < SEG; ++c) xr[c] = Y[lane][seg * SEG + c];
-  double acc[SEG];
+  for (int c = 0; c < SL; ++c) xr[c] = Y[lane][seg * SL + c];
+  double acc[SL];
 #pragma unroll
-  for (int i = 0; i < SEG; ++i) acc[i] = 0.0;
-  double o[SEG], x[SEG];
+  for (int i = 0; i < SL; ++i) acc[i] = 0.0;
+  double o[SL], x[SL];
   // Terms with a J factor act on the image's line sums only:
   //   D_H^{o m} X J = (D^{o m} X 1) 1^T,   J X D_W^{o m} = 1 (1^T X D^{o m}).
   // Row and column sums first (segments, then the segments in order).
   {
     double rp = 0.0;
 #pragma unroll
-    for (int c = 0; c < SEG; ++c) rp += xr[c];
+    for (int c = 0; c < SL; ++c) rp += xr[c];
     sums[0][seg][lane][0] = rp;
     double cp = 0.0;
 #pragma unroll
-    for (int i = 0; i < SEG; ++i) cp += Y[seg * SEG + i][lane];
+    for (int i = 0; i < SL; ++i) cp += Y[seg * SL + i][lane];
     sums[1][seg][lane][0] = cp;
     __syncthreads();
     if (seg < 2) {
       double v = sums[seg][0][lane][0];
 #pragma unroll
-      for (int sg = 1; sg < NSEG; ++sg) v += sums[seg][sg][lane][0];
+      for (int sg = 1; sg < NS; ++sg) v += sums[seg][sg][lane][0];
       vec[seg][lane] = v;
     }
     __syncthreads();
@@ -971,12 +988,12 @@ __global__ __launch_bounds__(256) void k_img_rowop(const double* __restrict__ in
       const int m = mw == 0 ? mh : mw;
       const int which = mw == 0 ? 0 : 1;
       {
-        // output `lane`: thread (lane, seg) sums the segment's 16 sums, the
+        // output `lane`: thread (lane, seg) sums the segment's SL sums, the
         // segments are added in order
         double v = 0.0;
 #pragma unroll
-        for (int jj = 0; jj < SEG; ++jj) {
-          const int j = seg * SEG + jj;
+        for (int jj = 0; jj < SL; ++jj) {
+          const int j = seg * SL + jj;
           const int d = lane > j ? lane - j : j - lane;
           double w = 1.0;
           for (int u = 0; u < m; ++u) w *= (double)d;
@@ -988,32 +1005,32 @@ __global__ __launch_bounds__(256) void k_img_rowop(const double* __restrict__ in
       if (seg == 0) {
         double v = sums[0][0][lane][0];
 #pragma unroll
-        for (int sg = 1; sg < NSEG; ++sg) v += sums[0][sg][lane][0];
+        for (int sg = 1; sg < NS; ++sg) v += sums[0][sg][lane][0];
         vec[2 + which][lane] = v;
       }
       __syncthreads();
 #pragma unroll
-      for (int i = 0; i < SEG; ++i)
-        acc[i] = fma(cf, which == 0 ? vec[2][seg * SEG + i] : vec[3][lane], acc[i]);
+      for (int i = 0; i < SL; ++i)
+        acc[i] = fma(cf, which == 0 ? vec[2][seg * SL + i] : vec[3][lane], acc[i]);
       __syncthreads();  // vec[2 + which] is rewritten by the next such term
       continue;
     }
     // cross terms: along the image rows: Y[r][.] = (row r) D_W^{o mw}
-    img_line_m(mw, xr, o, sums, lane, seg);
+    img_line_m<ITS>(mw, xr, o, sums, lane, seg);
 #pragma unroll
-    for (int c = 0; c < SEG; ++c) Y[lane][seg * SEG + c] = o[c];
+    for (int c = 0; c < SL; ++c) Y[lane][seg * SL + c] = o[c];
     __syncthreads();
-    // along the image columns: column `lane`, rows seg*SEG + i
+    // along the image columns: column `lane`, rows seg*SL + i
 #pragma unroll
-    for (int i = 0; i < SEG; ++i) x[i] = Y[seg * SEG + i][lane];
-    img_line_m(mh, x, o, sums, lane, seg);
+    for (int i = 0; i < SL; ++i) x[i] = Y[seg * SL + i][lane];
+    img_line_m<ITS>(mh, x, o, sums, lane, seg);
 #pragma unroll
-    for (int i = 0; i < SEG; ++i) acc[i] = fma(cf, o[i], acc[i]);
+    for (int i = 0; i < SL; ++i) acc[i] = fma(cf, o[i], acc[i]);
   }
   double* dst = out + row * ldo;
 #pragma unroll
-  for (int i = 0; i < SEG; ++i) {
-    const int r = seg * SEG + i;
+  for (int i = 0; i < SL; ++i) {
+    const int r = seg * SL + i;
     if (r < H && lane < W) dst[r * W + lane] = acc[i];
   }
 }
@@ -1161,11 +1178,12 @@ gw_status fast1d(const gwr::Grid& X, const gwr::Grid& Y, const double* p, const 
   return GW_EUNSUPPORTED;
 }
 
-// The image operator on every row of `in` for a 2D grid of at most 64 x 64
-// points (GW_EUNSUPPORTED otherwise).
+// The image operator on every row of `in` for a 2D grid of at most
+// IMG_MAX x IMG_MAX points (GW_EUNSUPPORTED otherwise): 64-point tiles up to
+// 64 x 64 (256 threads), 96-point tiles above (768 threads).
 gw_status img_rowop(const double* in, int64_t ldi, int64_t rows, const gwr::Grid& g,
                     double* out, int64_t ldo, hipStream_t s) {
-  if (g.ndim != 2 || g.H > TS || g.W > TS) return GW_EUNSUPPORTED;
+  if (g.ndim != 2 || g.H > IMG_MAX || g.W > IMG_MAX) return GW_EUNSUPPORTED;
   ImgTerms tm{};
   if (g.metric == GW_METRIC_SQEUCLID) {
     tm.n = 2;
@@ -1181,7 +1199,12 @@ gw_status img_rowop(const double* in, int64_t ldi, int64_t rows, const gwr::Grid
       cb = cb * (g.k - r) / (r + 1);
     }
   }
-  k_img_rowop<<<(unsigned)rows, 256, 0, s>>>(in, ldi, (int)g.H, (int)g.W, tm, out, ldo);
+  if (g.H <= TS && g.W <= TS)
+    k_img_rowop<TS><<<(unsigned)rows, ImgShape<TS>::NT, 0, s>>>(in, ldi, (int)g.H, (int)g.W, tm,
+                                                                out, ldo);
+  else
+    k_img_rowop<IMG_MAX><<<(unsigned)rows, ImgShape<IMG_MAX>::NT, 0, s>>>(in, ldi, (int)g.H,
+                                                                          (int)g.W, tm, out, ldo);
   return gwr::last_launch_status();
 }
 

@@ -58,6 +58,7 @@ CASES = [
     ((66, 65), 2, (1100,), 4),      # three chunks, the last ragged, k = 4
     ((1,), 3, (65, 66), 2),         # one-point 1D side
     ((513,), 1, (17, 4, 3), 3),     # one chunk and one entry
+    ((65535,), 2, (2, 33), 2),      # the longest axis: 128 chunks, the last ragged
 ]
 
 
