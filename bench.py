@@ -609,6 +609,7 @@ def serve_bench(n_req: int = 2000, slots: int = 32, iters: int = 10, load: float
     # warm-up (not timed): one short solve of each request shape class in the stream
     run(dreqs[:24], [0.0] * 24, 1, iters)
     torch.cuda.synchronize()
+    n_cmp = min(n_cmp, len(dreqs))
     cmp = dreqs[:n_cmp]
     lat_sat, fin_sat, steps_sat = run(cmp, [0.0] * n_cmp, outer, inner, "saturated, equal quotas")
     sat = n_cmp / float(fin_sat.max())
