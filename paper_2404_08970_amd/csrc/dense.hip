@@ -13,62 +13,67 @@ namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-constexpr int BM = 64, BN = 64, BK = 16;
-constexpr int NTHR = 256;
+constexpr int DM = 128, DK = 16;  // block tile DM x DM, DK of K per stage
+constexpr int NTHR = 512;           // 4 x 2 waves of 32 x 64
+constexpr int WTM = 32, WTN = 64, NTI = WTM / 16, NTJ = WTN / 16;
 
 // C = op(A) * op(B) where exactly one operand is the distance matrix
 // |i-j|^kd generated from indices.
 //   SYN_B: C[M x N] = A[M x K] (memory, lda) * D[K x N]  (D[k][n] = |k-n|^kd)
 //   !SYN_B: C[M x N] = D[M x K] (D[m][k] = |m-k|^kd) * B[K x N] (memory, ldb)
 // Epilogue: if c1 != null, C = (c1[m] + c2[n]) - s2 * acc; else C = acc.
+// The memory operand goes through LDS in two buffers: the next tile is loaded
+// into registers while the current one feeds the matrix cores, then stored
+// into the other buffer (one barrier per stage).  The distance operand is
+// formed in registers from the lane's row/column and k (exact integers).
+// 128 x 128 block tiles of 8 waves (32 x 64 each) keep the accumulators in
+// 64 registers, so two blocks share a CU.
 template <bool SYN_B>
 __global__ __launch_bounds__(NTHR) void k_dense_f64(const double* __restrict__ Amem, int64_t lda,
                                                      int M, int N, int K, int kd,
                                                      double* __restrict__ C, int64_t ldc,
                                                      const double* __restrict__ c1,
                                                      const double* __restrict__ c2, double s2) {
-  // SYN_B: stage A tile [BM][BK]; else stage B tile [BK][BN].
-  __shared__ double As[SYN_B ? BM : BK][SYN_B ? BK + 1 : BN + 1];
+  // SYN_B: A tiles [DM rows][DK k]; else B tiles [DK k][DM cols]; padded rows
+  constexpr int R0 = SYN_B ? DM : DK, R1 = SYN_B ? DK + 1 : DM + 1;
+  constexpr int PER = DM * DK / NTHR;  // memory-operand entries per thread and stage
+  __shared__ double Ms[2][R0][R1];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;  // wave tile origin in block
-  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
-  d4 acc[2][2];
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+  const int wm = (wave >> 1) * WTM, wn = (wave & 1) * WTN;  // wave tile origin in block
+  const int m0 = blockIdx.y * DM, n0 = blockIdx.x * DM;
   const int li = lane & 15, lk = lane >> 4;  // operand lane mapping
-  for (int k0 = 0; k0 < K; k0 += BK) {
-    __syncthreads();
-    if (SYN_B) {
-      // A tile: 64 rows x 16 k; thread t loads row t/4, k (t%4)*4 .. +4
-      const int r = t >> 2, kk = (t & 3) * 4;
-      const int gm = m0 + r;
+  d4 acc[NTI][NTJ];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int gk = k0 + kk + u;
-        As[r][kk + u] = (gm < M && gk < K) ? Amem[(int64_t)gm * lda + gk] : 0.0;
-      }
-    } else {
-      // B tile: 16 k x 64 cols; thread t loads row t/16, cols (t%16)*4 .. +4
-      const int r = t >> 4, cc = (t & 15) * 4;
-      const int gk = k0 + r;
+  for (int i = 0; i < NTI; ++i)
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int gn = n0 + cc + u;
-        As[r][cc + u] = (gk < K && gn < N) ? Amem[(int64_t)gk * lda + gn] : 0.0;
-      }
+    for (int j = 0; j < NTJ; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+  // thread t's entries of a stage: SYN_B row t/4, k (t%4)*PER + u; else k row
+  // t/32, columns (t%32)*PER + u (zero outside the matrix)
+  const int lr = SYN_B ? t >> 2 : t >> 5, lc = SYN_B ? (t & 3) * PER : (t & 31) * PER;
+  double rv[PER];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int gr = SYN_B ? m0 + lr : k0 + lr;         // row of the memory operand
+      const int gc = SYN_B ? k0 + lc + u : n0 + lc + u;  // its column
+      const bool in = SYN_B ? (gr < M && gc < K) : (gr < K && gc < N);
+      rv[u] = in ? Amem[(int64_t)gr * lda + gc] : 0.0;
     }
-    __syncthreads();
+  };
+  auto lstore = [&](int buf) {
 #pragma unroll
-    for (int ks = 0; ks < BK; ks += 4) {
-      const int kg = k0 + ks + lk;  // global k of this lane's operand element
-      double a[2], b[2];
+    for (int u = 0; u < PER; ++u) Ms[buf][lr][lc + u] = rv[u];
+  };
+  auto compute = [&](int buf, int k0) {
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
+    for (int ks = 0; ks < DK; ks += 4) {
+      const int kg = k0 + ks + lk;  // global k of this lane's operand elements
+      double a[NTI], b[NTJ];
+#pragma unroll
+      for (int i = 0; i < NTI; ++i) {
         const int row = wm + i * 16 + li;
         if (SYN_B) {
-          a[i] = As[row][ks + lk];
+          a[i] = Ms[buf][row][ks + lk];
         } else {
           const int gm = m0 + row;
           const int d = gm > kg ? gm - kg : kg - gm;
@@ -76,29 +81,39 @@ __global__ __launch_bounds__(NTHR) void k_dense_f64(const double* __restrict__ A
         }
       }
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
+      for (int j = 0; j < NTJ; ++j) {
         const int col = wn + j * 16 + li;
         if (SYN_B) {
           const int gn = n0 + col;
           const int d = gn > kg ? gn - kg : kg - gn;
           b[j] = gwk::ipow((double)d, kd);
         } else {
-          b[j] = As[ks + lk][col];
+          b[j] = Ms[buf][ks + lk][col];
         }
       }
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < NTI; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < NTJ; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
     }
+  };
+  const int nk = (K + DK - 1) / DK;
+  gload(0);
+  lstore(0);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    if (kt + 1 < nk) gload((kt + 1) * DK);
+    compute(kt & 1, kt * DK);
+    if (kt + 1 < nk) lstore((kt + 1) & 1);
+    __syncthreads();
   }
   // store: for the FP64 16x16x4 instruction, accumulator slot v of a lane holds
   // row 4 * v + lane / 16 and column lane % 16 of its 16 x 16 block
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < NTI; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < NTJ; ++j)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int gm = m0 + wm + i * 16 + 4 * v + lk;
@@ -143,7 +158,7 @@ gw_status dense(const gwr::Grid& X, const gwr::Grid& Y, const double* p, const d
   if (path != GW_PATH_DENSE_F64) return dense_lp(X, Y, T, ldT, G, ldG, path, ws, s, c1, c2);
   double* A = ws.take<double>((size_t)M * N);
   gwr::ProfScope ps(gwr::kFamDense, s);
-  dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM);
+  dim3 grid((N + DM - 1) / DM, (M + DM - 1) / DM);
   // A = T D~_Y
   k_dense_f64<true><<<grid, NTHR, 0, s>>>(T, ldT, M, N, N, Y.k1d(), A, N, nullptr, nullptr, 0.0);
   // B = D~_X A, G = (c1 + c2) - s2 B
