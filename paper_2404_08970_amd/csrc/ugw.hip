@@ -345,7 +345,7 @@ gw_status launch_uot_fused(const double* C, int64_t ldC, int64_t M, int64_t N, i
   else if (N <= 512) k_uot_fused<256, 2, 2><<<nb, 256, 0, s>>>(UF_ARGS);
   else if (N <= 1024) k_uot_fused<256, 4, 2><<<nb, 256, 0, s>>>(UF_ARGS);
   else if (N <= 2048) k_uot_fused<256, 8, 2><<<nb, 256, 0, s>>>(UF_ARGS);
-  else if (N <= 4096) k_uot_fused<512, 8, 2><<<nb, 512, 0, s>>>(UF_ARGS);
+  else if (N <= 4096) k_uot_fused<512, 8, 1><<<nb, 512, 0, s>>>(UF_ARGS);
   else if (N <= 8192) k_uot_fused<512, 16, 1><<<nb, 512, 0, s>>>(UF_ARGS);
   else return GW_EUNSUPPORTED;
 #undef UF_ARGS
