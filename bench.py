@@ -105,34 +105,57 @@ def cpu_baseline(k=2, audits=None):
         text = (f"n=4096 k={k}: one recursion gradient ({t1 - t0:.2f} s), {its} Sinkhorn "
                 f"iterations ({t2 - t1:.2f} s) and one plan ({t3 - t2:.2f} s), scaled to "
                 f"{OUTER} outer x {INNER} inner iterations")
-        return 1.0 / (OUTER * per_outer), text
+        parts = {"recursion_gradient_s": round(t1 - t0, 3),
+                 "sinkhorn_iteration_s": round((t2 - t1) / its, 4), "plan_s": round(t3 - t2, 3)}
+        return 1.0 / (OUTER * per_outer), text, parts
 
-    v1, text1 = sample(1)
+    v1, text1, parts1 = sample(1)
     out = {
         "value": v1,
         "unit": "solves/s",
         "cores": 1,
         "kind": "oracle",
         "sample": text1 + "; numpy held to one thread",
+        "parts": parts1,
     }
     # the same sample with numpy's thread pools given the host's cores (only the
     # library products of the oracle use them; its loops stay on one thread)
     ncores = int(os.environ.get("OMP_NUM_THREADS") or len(os.sched_getaffinity(0)))
-    va, texta = sample(ncores)
-    out["all_cores"] = {"value": va, "unit": "solves/s", "cores": ncores, "sample": texta}
+    va, texta, partsa = sample(ncores)
+    out["all_cores"] = {"value": va, "unit": "solves/s", "cores": ncores, "sample": texta,
+                        "parts": partsa}
+    # the plain-definition (dense) gradient of the oracle at the same size, on
+    # all host cores (its two n^3 products go to the BLAS)
+    with threadpool_limits(limits=ncores):
+        p, q = marginals(N, k)
+        g = O.Grid((N,), 1.0 / (N - 1), k)
+        T = np.outer(p, q)
+        t0 = time.perf_counter()
+        O.grad_dense(g, g, p, q, T)
+        out["all_cores"]["parts"]["dense_gradient_s"] = round(time.perf_counter() - t0, 3)
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
+    except OSError:
+        pass
+    out["host"] = {"cpu_model": model, "logical_cpus": os.cpu_count(),
+                   "usable_cpus": len(os.sched_getaffinity(0))}
     if audits:
         res = {}
         for name, (prob, Tg, Eg) in audits.items():
             og = O.Grid(tuple(prob["shape"]), prob["h"], prob["k"])
+            ts = time.perf_counter()
             T0, _, _, (E0, _) = O.solve(og, og, prob["p"], prob["q"], prob["eps"], prob["outer"],
                                         prob["inner"], gradient=prob.get("gradient", "dense"))
+            solve_s = time.perf_counter() - ts
             cands = {"T": T0}
             if prob.get("reflection"):
                 cands["R_X T"] = T0[::-1]
             errs = {c: float(np.max(np.abs(Tg - v)) / np.max(np.abs(v))) for c, v in cands.items()}
             pick = min(errs, key=errs.get)
             r = {"shape": list(prob["shape"]), "k": prob["k"], "eps": round(prob["eps"], 6),
-                 "rel_err_T": errs[pick]}
+                 "rel_err_T": errs[pick], "oracle_solve_s": round(solve_s, 2)}
             if len(cands) > 1:
                 r["matched"] = pick
             if Eg is not None:
