@@ -604,7 +604,8 @@ def serve_bench(n_req: int = 2000, slots: int = 32, iters: int = 10, load: float
     completion minus arrival (size quotas, `boost`).  Completion times come
     from each request's HIP completion event.  Equal iteration quotas are
     measured on the first `n_cmp` requests (saturated and Poisson, the same
-    arrival times) for comparison.  Results of a few requests of each kind
+    arrival times) for comparison, and size quotas again at 0.5x and 1.0x the
+    saturated rate on those requests.  Results of a few requests of each kind
     are audited against the oracle."""
     import numpy as np
     import torch
@@ -666,6 +667,16 @@ def serve_bench(n_req: int = 2000, slots: int = 32, iters: int = 10, load: float
     satb = n_cmp / float(fin_satb.max())
     rate = load * satb
     lat, fin, steps = run(dreqs, (arr_all / rate).tolist(), outer, inner, "Poisson, size quotas")
+    # the same policy at lighter and full offered load, on the first n_cmp requests
+    sweep = {}
+    for ld in (0.5, 1.0):
+        l_s, f_s, _ = run(cmp, (arr_all[:n_cmp] / (ld * satb)).tolist(), outer, inner,
+                          f"Poisson {ld}x, size quotas")
+        sweep[f"{ld}x"] = {"requests": n_cmp, "offered_rate_per_s": round(ld * satb, 2),
+                           "solves_per_s": round(n_cmp / float(f_s.max()), 2),
+                           "p50_ms": round(float(np.percentile(l_s, 50)) * 1e3, 1),
+                           "p99_ms": round(float(np.percentile(l_s, 99)) * 1e3, 1),
+                           "mean_ms": round(float(l_s.mean()) * 1e3, 1)}
 
     # accuracy: a few requests of each kind against the oracle (the result of a
     # request is the same in any mix, so they are solved alone here): the
@@ -705,6 +716,7 @@ def serve_bench(n_req: int = 2000, slots: int = 32, iters: int = 10, load: float
         "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 1),
         "mean_ms": round(float(lat.mean()) * 1e3, 1),
         "steps": steps,
+        "load_sweep_size_quotas": sweep,
         "equal_quotas": {
             "requests": n_cmp,
             "saturated_solves_per_s": round(sat, 2),
