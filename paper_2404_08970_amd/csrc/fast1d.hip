@@ -848,16 +848,16 @@ gw_status dispatch_ky(int ky, const Layout& L, const double* T, int64_t ldT, dou
 }
 
 // ------------------------------------------------ image operator (2D rows)
-// For 2D grids whose image fits one 64 x 64 tile: each row of `in` is an
-// H x W image (zero padded to the tile) and receives
+// For 2D grids whose image fits one 64 x 64 or 96 x 96 tile: each row of `in`
+// is an H x W image (zero padded to the tile) and receives
 //   sum_t coef_t  D_H^{o mh_t} X D_W^{o mw_t}   (D^{o0} = J, the diagonal included),
-// the Kronecker expansion of Sec. 3.1 applied to one image.  A block of 256
-// threads owns one row: thread (line, seg) applies the recursion to a 16-entry
-// segment of a line, with the carries of the other segments combined through
-// LDS (as the tile sweep does), first along the image rows (exponent mw), the
-// result staged in LDS, then along the image columns (exponent mh), summed over
-// the terms in registers.  The thread keeps its row segment of the image in
-// registers for every term.
+// the Kronecker expansion of Sec. 3.1 applied to one image.  A block owns one
+// row: thread (line, seg) applies the recursion to one segment of a line (16
+// entries of a 64-point line, 12 of a 96-point one), with the carries of the
+// other segments combined through LDS (as the tile sweep does), first along
+// the image rows (exponent mw), the result staged in LDS, then along the image
+// columns (exponent mh), summed over the terms in registers.  The thread keeps
+// its row segment of the image in registers for every term.
 constexpr int IMG_MAX = 96;  // longest image side of the LDS image operator
 
 struct ImgTerms {

@@ -1494,7 +1494,8 @@ gw_status fast_generic(const gwr::Grid& X, const gwr::Grid& Y, const double* p,
     return gwr::last_launch_status();
   }
   // generic: A = T D^_Y (rows), At = A^T, Bt = At D^_X (rows), G = epilogue(Bt^T)
-  // images of up to 64 x 64 points (3D: 16 per axis): the LDS kernels, one block per row
+  // 1D sides: one wave per row; images of up to 96 x 96 points (3D: 16 per axis): the LDS
+  // kernels, one block per row; larger ones: k_rowop
   if (Y.ndim == 1)
     line_rows(Y.metric == GW_METRIC_SQEUCLID ? 2 : Y.k, T, ldT, M, N, A, N, s);
   else if (gwl::img_rowop(T, ldT, M, Y, A, N, s) == GW_EUNSUPPORTED &&
