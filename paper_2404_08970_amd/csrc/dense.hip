@@ -24,8 +24,9 @@ constexpr int WTM = 32, WTN = 64, NTI = WTM / 16, NTJ = WTN / 16;
 // Epilogue: if c1 != null, C = (c1[m] + c2[n]) - s2 * acc; else C = acc.
 // The memory operand goes through LDS in two buffers: the next tile is loaded
 // into registers while the current one feeds the matrix cores, then stored
-// into the other buffer (one barrier per stage).  The distance operand is
-// formed in registers from the lane's row/column and k (exact integers).
+// into the other buffer (one barrier per stage).  The distance operand of a
+// stage is formed from its indices (exact integers) once per block, into LDS
+// beside it, instead of by every wave that reads it.
 // 128 x 128 block tiles of 8 waves (32 x 64 each) keep the accumulators in
 // 64 registers, so two blocks share a CU.
 template <bool SYN_B>
@@ -38,6 +39,7 @@ __global__ __launch_bounds__(NTHR) void k_dense_f64(const double* __restrict__ A
   constexpr int R0 = SYN_B ? DM : DK, R1 = SYN_B ? DK + 1 : DM + 1;
   constexpr int PER = DM * DK / NTHR;  // memory-operand entries per thread and stage
   __shared__ double Ms[2][R0][R1];
+  __shared__ double Ds[2][SYN_B ? DK : DM][SYN_B ? DM + 1 : DK + 1];  // distance tile
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int wm = (wave >> 1) * WTM, wn = (wave & 1) * WTN;  // wave tile origin in block
   const int m0 = blockIdx.y * DM, n0 = blockIdx.x * DM;
@@ -60,36 +62,32 @@ __global__ __launch_bounds__(NTHR) void k_dense_f64(const double* __restrict__ A
       rv[u] = in ? Amem[(int64_t)gr * lda + gc] : 0.0;
     }
   };
-  auto lstore = [&](int buf) {
+  auto lstore = [&](int buf, int k0) {
 #pragma unroll
     for (int u = 0; u < PER; ++u) Ms[buf][lr][lc + u] = rv[u];
+    // the distance tile of the stage: SYN_B D[k][n], else D[m][k]
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = t * PER + u;
+      const int r = SYN_B ? e / DM : e / DK, c = SYN_B ? e % DM : e % DK;
+      const int i = SYN_B ? k0 + r : m0 + r, j = SYN_B ? n0 + c : k0 + c;
+      const int d = i > j ? i - j : j - i;
+      Ds[buf][r][c] = gwk::ipow((double)d, kd);
+    }
   };
-  auto compute = [&](int buf, int k0) {
+  auto compute = [&](int buf) {
 #pragma unroll
     for (int ks = 0; ks < DK; ks += 4) {
-      const int kg = k0 + ks + lk;  // global k of this lane's operand elements
       double a[NTI], b[NTJ];
 #pragma unroll
       for (int i = 0; i < NTI; ++i) {
         const int row = wm + i * 16 + li;
-        if (SYN_B) {
-          a[i] = Ms[buf][row][ks + lk];
-        } else {
-          const int gm = m0 + row;
-          const int d = gm > kg ? gm - kg : kg - gm;
-          a[i] = gwk::ipow((double)d, kd);
-        }
+        a[i] = SYN_B ? Ms[buf][row][ks + lk] : Ds[buf][row][ks + lk];
       }
 #pragma unroll
       for (int j = 0; j < NTJ; ++j) {
         const int col = wn + j * 16 + li;
-        if (SYN_B) {
-          const int gn = n0 + col;
-          const int d = gn > kg ? gn - kg : kg - gn;
-          b[j] = gwk::ipow((double)d, kd);
-        } else {
-          b[j] = Ms[buf][ks + lk][col];
-        }
+        b[j] = SYN_B ? Ds[buf][ks + lk][col] : Ms[buf][ks + lk][col];
       }
 #pragma unroll
       for (int i = 0; i < NTI; ++i)
@@ -100,12 +98,12 @@ __global__ __launch_bounds__(NTHR) void k_dense_f64(const double* __restrict__ A
   };
   const int nk = (K + DK - 1) / DK;
   gload(0);
-  lstore(0);
+  lstore(0, 0);
   __syncthreads();
   for (int kt = 0; kt < nk; ++kt) {
     if (kt + 1 < nk) gload((kt + 1) * DK);
-    compute(kt & 1, kt * DK);
-    if (kt + 1 < nk) lstore((kt + 1) & 1);
+    compute(kt & 1);
+    if (kt + 1 < nk) lstore((kt + 1) & 1, (kt + 1) * DK);
     __syncthreads();
   }
   // store: for the FP64 16x16x4 instruction, accumulator slot v of a lane holds
