@@ -25,7 +25,7 @@ constexpr int WTM = 32, WTN = 64, NTI = WTM / 16, NTJ = WTN / 16;
 // The memory operand goes through LDS in two buffers: the next tile is loaded
 // into registers while the current one feeds the matrix cores, then stored
 // into the other buffer (one barrier per stage).  The distance operand of a
-// stage is formed from its indices (exact integers) once per block, into LDS
+// stage is formed from its indices (integers, exact below 2^53) once per block, into LDS
 // beside it, instead of by every wave that reads it.
 // 128 x 128 block tiles of 8 waves (32 x 64 each) keep the accumulators in
 // 64 registers, so two blocks share a CU.
