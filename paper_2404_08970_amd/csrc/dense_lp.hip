@@ -430,33 +430,34 @@ __global__ __launch_bounds__(GemmShape<SPLIT>::NTH) void k_gemm_bt(
       }
 }
 
-// FP32 operands on the FP32 matrix cores: the same two products and tiling
-// as the BF16 path (v_mfma_f32_16x16x4f32: a lane holds one operand element,
-// row lane % 16, k = lane / 16), FP32 accumulation over the whole K; A^T stays
-// FP32.  OUT as in k_gemm_bt (0: FP32 output, 1: G).
+// FP32 operands on the FP32 matrix cores: the same two products as the BF16
+// path on 128 x 128 block tiles of 8 waves (v_mfma_f32_16x16x4f32: a lane
+// holds one operand element, row lane % 16, k = lane / 16), FP32 accumulation
+// over the whole K; A^T stays FP32.  OUT as in k_gemm_bt (0: FP32 output, 1: G).
 template <int OUT>
-__global__ __launch_bounds__(256) void k_gemm_bt_f32(const float* __restrict__ A, int64_t lda,
+__global__ __launch_bounds__(512) void k_gemm_bt_f32(const float* __restrict__ A, int64_t lda,
                                                       const float* __restrict__ Bt, int64_t ldb,
                                                       int kp, int Mo, int No,
                                                       float* __restrict__ O, int64_t ldo,
                                                       const double* __restrict__ c1,
                                                       const double* __restrict__ c2, double s2,
                                                       double* __restrict__ G, int64_t ldG) {
-  constexpr int BM = 128, NTH = 256, WT = 64, NT = WT / 16;  // 2 x 2 waves of 64 x 64
+  // 4 x 2 waves of 32 x 64 (64 accumulator registers: 4 waves per SIMD)
+  constexpr int BM = 128, NTH = 512, WTM = 32, WTN = 64, NTI = WTM / 16, NTJ = WTN / 16;
   constexpr int BK = 32, LDK = BK + 4;                        // K per stage; LDS row padding
   constexpr int CH = BM * BK / 4 / NTH;                        // 16-byte chunks per thread
   typedef float fl4 __attribute__((ext_vector_type(4)));
   __shared__ float As[2][BM][LDK];
   __shared__ float Bs[2][BM][LDK];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const int wm = (wave >> 1) * WT, wn = (wave & 1) * WT;
+  const int wm = (wave >> 1) * WTM, wn = (wave & 1) * WTN;
   const int64_t m0 = (int64_t)blockIdx.y * BM, n0 = (int64_t)blockIdx.x * BM;
   const int li = lane & 15, lq = lane >> 4;
-  f4 acc[NT][NT];
+  f4 acc[NTI][NTJ];
 #pragma unroll
-  for (int i = 0; i < NT; ++i)
+  for (int i = 0; i < NTI; ++i)
 #pragma unroll
-    for (int j = 0; j < NT; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < NTJ; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
   fl4 ra[CH], rb[CH];
   auto gload = [&](int k0) {
 #pragma unroll
@@ -477,15 +478,15 @@ __global__ __launch_bounds__(256) void k_gemm_bt_f32(const float* __restrict__ A
   auto compute = [&](int buf) {
 #pragma unroll
     for (int ks = 0; ks < BK; ks += 4) {
-      float fa[NT], fb[NT];
+      float fa[NTI], fb[NTJ];
 #pragma unroll
-      for (int i = 0; i < NT; ++i) fa[i] = As[buf][wm + 16 * i + li][ks + lq];
+      for (int i = 0; i < NTI; ++i) fa[i] = As[buf][wm + 16 * i + li][ks + lq];
 #pragma unroll
-      for (int j = 0; j < NT; ++j) fb[j] = Bs[buf][wn + 16 * j + li][ks + lq];
+      for (int j = 0; j < NTJ; ++j) fb[j] = Bs[buf][wn + 16 * j + li][ks + lq];
 #pragma unroll
-      for (int i = 0; i < NT; ++i)
+      for (int i = 0; i < NTI; ++i)
 #pragma unroll
-        for (int j = 0; j < NT; ++j)
+        for (int j = 0; j < NTJ; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[i], fb[j], acc[i][j], 0, 0, 0);
     }
   };
@@ -500,9 +501,9 @@ __global__ __launch_bounds__(256) void k_gemm_bt_f32(const float* __restrict__ A
     __syncthreads();
   }
 #pragma unroll
-  for (int i = 0; i < NT; ++i)
+  for (int i = 0; i < NTI; ++i)
 #pragma unroll
-    for (int j = 0; j < NT; ++j)
+    for (int j = 0; j < NTJ; ++j)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int64_t gm = m0 + wm + i * 16 + 4 * lq + v;
@@ -547,9 +548,9 @@ gw_status run_f32(int M, int N, int kx, int ky, const double* T, int64_t ldT, do
   k_to_f32<<<blocks(Mp * kN), 256, 0, s>>>(T, ldT, M, N, 0, tf, Mp, kN);
   k_to_f32<<<blocks(Np * kN), 256, 0, s>>>(nullptr, 0, N, N, ky, dy, Np, kN);
   k_to_f32<<<blocks(Mp * kM), 256, 0, s>>>(nullptr, 0, M, M, kx, dx, Mp, kM);
-  k_gemm_bt_f32<0><<<dim3((unsigned)(Mp / 128), (unsigned)(Np / 128)), 256, 0, s>>>(
+  k_gemm_bt_f32<0><<<dim3((unsigned)(Mp / 128), (unsigned)(Np / 128)), 512, 0, s>>>(
       dy, kN, tf, kN, (int)kN, (int)Np, (int)Mp, at, Mp, nullptr, nullptr, 0.0, nullptr, 0);
-  k_gemm_bt_f32<1><<<dim3((unsigned)(Np / 128), (unsigned)(Mp / 128)), 256, 0, s>>>(
+  k_gemm_bt_f32<1><<<dim3((unsigned)(Np / 128), (unsigned)(Mp / 128)), 512, 0, s>>>(
       dx, kM, at, Mp, (int)kM, M, N, nullptr, 0, c1, c2, s2, G, ldG);
   return gwr::last_launch_status();
 }
