@@ -1,5 +1,6 @@
 // Exponentials with an unbounded binary exponent for the log-domain
-// Sinkhorn passes (balanced and unbalanced).
+// Sinkhorn passes (balanced and unbalanced), and the test that lets a pass
+// skip its row maxima.
 #pragma once
 #include "common.h"
 
@@ -41,6 +42,47 @@ GW_DEV double exp_split(double x, int* n) {
   r = fma(-nd, LN2_LO, r);
   *n = (int)nd;
   return exp_reduced(r);
+}
+
+// ---- the shifted pass
+// A row pass may shift each row by an upper bound of its log-sum-exp instead
+// of reducing the row maximum: the previous pass's bound a_i (below) plus D+,
+// the largest move of the row's exponents since that pass (a log-sum-exp
+// moves by at most the largest move of its arguments).  D- is the largest
+// move down.  Then the shifted row sum lies in [e^-(D+ + D- + ln 2), 1], and
+// column sums can be kept as plain doubles in per-column frames.
+constexpr double SHIFT_SPREAD_MAX = 600.0;  // D+ + D- up to which the max pass is skipped
+constexpr double FAST_UP_MAX = 550.0;       // largest D+ of a shifted pass
+constexpr double FAST_M_MAX = 1.0e6;        // bound on |a_i| + D+
+
+// Folds one column's move into (up, dn): its value now (gn) and before the
+// last update (go).  A column that became or stopped being finite rules the
+// shifted pass out.
+GW_DEV void fold_move(double gn, double go, double& up, double& dn) {
+  if (isfinite(gn) && isfinite(go)) {
+    up = fmax(up, gn - go);
+    dn = fmax(dn, go - gn);
+  } else if (isfinite(gn) != isfinite(go)) {
+    up = dn = INFINITY;
+  }
+}
+
+// |a_i| of a row for the test (a non-finite bound rules it out).
+GW_DEV double lse_mag(double v) { return isfinite(v) ? fabs(v) : INFINITY; }
+
+// Upper bound of ln(sum) for a row shifted by m with shifted sum s > 0:
+// m + e ln 2 for s = f 2^e, f in [0.5, 1).
+GW_DEV double row_bound(double m, double s) {
+  int es;
+  (void)frexp(s, &es);
+  return m + (double)es * 0.6931471805599453;
+}
+
+// The decision from the moves (up = D+, dn = D-, in units of the exponents)
+// and the largest |a_i| of the band: D+ if the pass may be shifted, else -1
+// (exact row maxima).
+GW_DEV double fast_from(double up, double dn, double lmax) {
+  return (up + dn <= SHIFT_SPREAD_MAX && up <= FAST_UP_MAX && lmax + up < FAST_M_MAX) ? up : -1.0;
 }
 
 }  // namespace gwx

@@ -57,7 +57,13 @@ using gwx::LN2_LO;
 using gwx::X_FLOOR;
 using gwx::exp_reduced;
 using gwx::exp_split;
-constexpr double SHIFT_SPREAD_MAX = 600.0;  // D+ + D- up to which the max pass is skipped
+using gwx::FAST_M_MAX;
+using gwx::FAST_UP_MAX;
+using gwx::SHIFT_SPREAD_MAX;
+using gwx::fast_from;
+using gwx::fold_move;
+using gwx::lse_mag;
+using gwx::row_bound;
 
 // D+ for the pass (or -1: exact maxima) from g and g before the last merge
 // (gprev, null in the first iteration of a call), reduced over all columns by
@@ -68,21 +74,6 @@ GW_DEV double pass_shift(const double* __restrict__ g, const double* __restrict_
                          double inv_eps, const double* __restrict__ lse, int i0, int i1,
                          double (*red3)[3]);
 
-// The fast-pass decision (defined with the fast pass below).
-GW_DEV double fast_from(double up, double dn, double lmax);
-
-// Folds one column's move into (up, dn): g before and after the last merge.
-GW_DEV void fold_move(double gn, double go, double& up, double& dn) {
-  if (isfinite(gn) && isfinite(go)) {
-    up = fmax(up, gn - go);
-    dn = fmax(dn, go - gn);
-  } else if (isfinite(gn) != isfinite(go)) {
-    up = dn = INFINITY;
-  }
-}
-
-// |lse| of a row for the fast-pass test (a non-finite bound rules it out)
-GW_DEV double lse_mag(double v) { return isfinite(v) ? fabs(v) : INFINITY; }
 
 template <int NT, int NC>
 GW_DEV double pass_shift(const double* __restrict__ g, const double* __restrict__ gprev, int N,
@@ -123,13 +114,6 @@ GW_DEV double pass_shift(const double* __restrict__ g, const double* __restrict_
     lm = fmax(lm, red3[k][2]);
   }
   return fast_from(up, dn, lm);
-}
-
-// Upper bound of ln(sum) for the row shifted by m with shifted sum s > 0.
-GW_DEV double row_bound(double m, double s) {
-  int es;
-  (void)frexp(s, &es);
-  return m + (double)es * 0.6931471805599453;
 }
 
 template <int NTH>
@@ -189,8 +173,6 @@ GW_DEV int opaque_tid() {
 // and D+ + D- <= SHIFT_SPREAD_MAX: no (mantissa, exponent) pairs are needed.
 constexpr double SHIFTER = 0x1.8p52;
 constexpr double FAST_ZSPAN = 2560.0;
-constexpr double FAST_M_MAX = 1.0e6;
-constexpr double FAST_UP_MAX = 550.0;
 constexpr int FRAME_OFFSET = 100;
 
 struct FastShift {
@@ -219,12 +201,6 @@ GW_DEV double exp_fast(double z, const FastShift& fs, int& n) {
   return exp_reduced(r);
 }
 
-// The fast-pass decision from the move of g (up = D+, dn = D-, in units of
-// eps) and the largest |lse_i| of the band: D+ if the pass may run fast, else
-// -1 (exact row maxima, (mantissa, exponent) column pairs).
-GW_DEV double fast_from(double up, double dn, double lmax) {
-  return (up + dn <= SHIFT_SPREAD_MAX && up <= FAST_UP_MAX && lmax + up < FAST_M_MAX) ? up : -1.0;
-}
 
 // Log-marginals, the column frames of the fast pass and (cold start) zero
 // potentials.

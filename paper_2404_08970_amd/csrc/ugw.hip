@@ -138,63 +138,133 @@ __global__ __launch_bounds__(NTH) void k_uot_row(const double* __restrict__ C, i
 //   = exp(z_ip - m_i) exp(lam_i) exp(-b_p),  lam_i = m_i + (f_i - shift)/e + ln u_i,
 // so the row's own exponentials feed the column sums.  A column with v_p = 0
 // is left out of the row maxima and sums and takes b_p = (g_p - shift)/e for
-// its exponentials (its g_p is still defined by the column update).  A
-// column's largest term can lie far below every row maximum, so each
-// exponential is kept as a mantissa times 2^n and a band's column sums as
-// (mantissa, binary exponent) pairs; the merge adds the bands in order and
-// sets g_p = -tau e (ln S_p - b_p) with the b_p of the pass.
-constexpr int UF_BANDS = 256;  // bands of rows per pass (at most)
+// its exponentials (its g_p is still defined by the column update).  The
+// merge adds the bands in order and sets g_p = -tau e (ln S_p - b_p) with the
+// b_p of the pass, S_p = sum_i exp(z_ip - m_i + lam_i).
+//
+// Two kinds of pass.  The exact pass reduces each row's maximum and keeps the
+// band's column sums as (mantissa, binary exponent) pairs (a column's largest
+// term can lie far below every row maximum).  The shifted pass (rows of up to
+// 4096 entries, after the first iteration of a call, when the moves of g
+// allow it) takes m_i = a_i + D+ instead of the maximum, a_i the previous
+// pass's bound of the row's log-sum-exp and D+ the largest move up of b_p
+// over the columns in the rows since then, and keeps plain doubles in a frame
+// 2^kq_p per column.  After the previous merge,
+//   sum_i exp((f_i - C_ip - shift)/e + ln u_i) = exp(-g_p/(tau e))
+// for the f of the previous pass, and the new f moves by at most tau e D+
+// down and tau e D- up, so S_p lies within e^(D+) and e^(D-) of exp(P_p),
+// P_p = b_p - g_p/(tau e); kq_p = -rint(P_p / ln 2) puts it in
+// [2^-795, 2^867] for D+ <= 550 and D+ + D- <= 600.  Each band records its
+// kind (bmode) and block 0 the frames, which the merge reads.
+constexpr int UF_BANDS = 256;   // bands of rows per pass (at most)
+constexpr int UF_MAX_RB = 256;  // rows per band (M <= 65535 over 256 bands)
 constexpr double LAM_MAX = 1.0e6;
+constexpr double FRAME_P_MAX = 1.0e8;  // |P_p| of a shifted pass (frames fit an int)
 
 GW_DEV double col_base(double gp, double lvp, double shift, double ie) {
   const double gb = (gp - shift) * ie;
   return lvp > -INFINITY ? gb + lvp : gb;
 }
 
-template <int NTH, int EPT, int R>
+template <int NTH, int EPT, int R, bool SHIFT>
 __global__ __launch_bounds__(NTH) void k_uot_fused(const double* __restrict__ C, int64_t ldC,
                                                    int M, int N, int RB,
                                                    const double* __restrict__ g,
+                                                   const double* __restrict__ gprev,
                                                    const double* __restrict__ lu,
                                                    const double* __restrict__ lv,
                                                    const UgwScal* __restrict__ sc,
                                                    double* __restrict__ f,
+                                                   double* __restrict__ lse,
+                                                   int* __restrict__ kq,
+                                                   int* __restrict__ bmode,
                                                    double* __restrict__ partS,
                                                    int* __restrict__ partX) {
   constexpr int NW = NTH / 64;
-  constexpr bool BL = EPT >= 16;  // b_p in LDS for the longest rows (registers are short)
+  constexpr bool BL = EPT >= 16;  // b_p and the frames in LDS for the longest rows
   __shared__ double red[2][R][NW];
+  __shared__ double dred[NW][3];
   __shared__ double bls[BL ? NTH * EPT : 1];
+  __shared__ int kqs[BL ? NTH * EPT : 1];
+  __shared__ double lse_b[UF_MAX_RB];  // the band's row bounds from the previous pass
   const int t = threadIdx.x, wv = t >> 6, lane = t & 63;
   const double shift = sc->shift, e = sc->e, ie = 1.0 / e, tau = sc->tau;
+  const int i0 = blockIdx.x * RB, i1 = min(M, i0 + RB);
   double breg[BL ? 1 : EPT], S[EPT];
-  int X[EPT], colc[EPT];
-  unsigned inrow = 0;  // bit e: entry e counts in the row maxima and sums
+  int X[EPT], kqr[BL ? 1 : EPT];
+  unsigned inrow = 0;  // bit k: entry k counts in the row maxima and sums
+  // the columns: b_p, and with gprev the move of g (columns in the rows) and
+  // the frames; every block reduces the same D+ and D-
+  double up = 0.0, dn = 0.0;
+  const double itaue = 1.0 / (tau * e);
 #pragma unroll
   for (int k = 0; k < EPT; ++k) {
     const int col = t + NTH * k;
-    colc[k] = min(col, N - 1);
-    const double lvv = lv[colc[k]];
-    const double bv = col_base(g[colc[k]], lvv, shift, ie);
+    const int cc = min(col, N - 1);
+    const double lvv = lv[cc];
+    const double gv = g[cc];
+    const double bv = col_base(gv, lvv, shift, ie);
     if constexpr (BL) bls[t + NTH * k] = bv;
     else breg[k] = bv;
     if (col < N && lvv > -INFINITY) inrow |= 1u << k;
+    int kv = 0;
+    if (gprev != nullptr && col < N) {
+      if (lvv > -INFINITY) gwx::fold_move(gv, gprev[cc], up, dn);
+      const double P = bv - gv * itaue;
+      if (fabs(P) <= FRAME_P_MAX) kv = -(int)rint(P * gwx::INV_LN2);
+      else up = INFINITY;  // also a non-finite P
+    }
+    if constexpr (BL) kqs[t + NTH * k] = kv;
+    else kqr[k] = kv;
+    if (blockIdx.x == 0 && gprev != nullptr && col < N) kq[col] = kv;
     S[k] = 0.0;
     X[k] = gwx::EXP_SENTINEL;
   }
+  double dup = -1.0;  // D+ of a shifted pass, or -1: exact maxima
+  if (SHIFT && gprev != nullptr) {
+    double lm = 0.0;
+    for (int r = t; r < i1 - i0; r += NTH) {
+      const double a = lse[i0 + r];
+      lse_b[r] = a;
+      lm = fmax(lm, gwx::lse_mag(a));
+    }
+    up = gwk::wave_max(up) * ie;
+    dn = gwk::wave_max(dn) * ie;
+    lm = gwk::wave_max(lm);
+    if (lane == 63) {
+      dred[wv][0] = up;
+      dred[wv][1] = dn;
+      dred[wv][2] = lm;
+    }
+    __syncthreads();
+    up = dred[0][0];
+    dn = dred[0][1];
+    lm = dred[0][2];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) {
+      up = fmax(up, dred[w][0]);
+      dn = fmax(dn, dred[w][1]);
+      lm = fmax(lm, dred[w][2]);
+    }
+    dup = gwx::fast_from(up, dn, lm);
+  }
+  const bool fast = SHIFT && dup >= 0.0;
   // each thread reads back only its own entries: no barrier needed
   auto b = [&](int k) -> double {
     if constexpr (BL) return bls[t + NTH * k];
     else return breg[k];
   };
-  const int i0 = blockIdx.x * RB, i1 = min(M, i0 + RB);
+  auto kqf = [&](int k) -> int {
+    if constexpr (BL) return kqs[t + NTH * k];
+    else return kqr[k];
+  };
   double cur[R][EPT];
   auto load = [&](int ib) {
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const double* row = C + (int64_t)min(ib + r, i1 - 1) * ldC;
 #pragma unroll
-      for (int k = 0; k < EPT; ++k) cur[r][k] = row[colc[k]];
+      for (int k = 0; k < EPT; ++k) cur[r][k] = row[min(t + NTH * k, N - 1)];
     }
   };
   if (i0 < i1) load(i0);
@@ -206,28 +276,43 @@ __global__ __launch_bounds__(NTH) void k_uot_fused(const double* __restrict__ C,
 #pragma unroll
       for (int k = 0; k < EPT; ++k) {
         z[r][k] = fma(-ie, cur[r][k], b(k));
-        if (inrow >> k & 1u) ml = fmax(ml, z[r][k]);
+        if (!fast && (inrow >> k & 1u)) ml = fmax(ml, z[r][k]);
       }
       m[r] = ml;
     }
     load(ib + R);  // the next rows (clamped: past the band it re-reads the last row)
     double lui[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      lui[r] = lu[min(ib + r, i1 - 1)];
-      const double ml = gwk::wave_max(m[r]);
-      if (lane == 63) red[0][r][wv] = ml;
+    for (int r = 0; r < R; ++r) lui[r] = lu[min(ib + r, i1 - 1)];
+    if (fast) {
+      // the shift: the row's previous bound plus D+ (no maximum)
+#pragma unroll
+      for (int r = 0; r < R; ++r) m[r] = lse_b[min(ib + r, i1 - 1) - i0] + dup;
+    } else {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const double ml = gwk::wave_max(m[r]);
+        if (lane == 63) red[0][r][wv] = ml;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        double mr = red[0][r][0];
+#pragma unroll
+        for (int w = 1; w < NW; ++w) mr = fmax(mr, red[0][r][w]);
+        m[r] = mr;
+      }
     }
-    __syncthreads();
+    // the sums go to red[1] in the exact pass (its maxima used red[0] before
+    // a barrier) and alternate between the two buffers in the shifted pass,
+    // which has one barrier per step
+    const int sb = fast ? ((ib - i0) / R) & 1 : 1;
     int nE[R][EPT];
     double sl[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      double mr = red[0][r][0];
-#pragma unroll
-      for (int w = 1; w < NW; ++w) mr = fmax(mr, red[0][r][w]);
-      m[r] = mr;
-      const double ms = mr > -INFINITY ? mr : 0.0;
+      const double ms = m[r] > -INFINITY ? m[r] : 0.0;
+      m[r] = ms;
       sl[r] = 0.0;
 #pragma unroll
       for (int k = 0; k < EPT; ++k) {
@@ -235,19 +320,21 @@ __global__ __launch_bounds__(NTH) void k_uot_fused(const double* __restrict__ C,
         if (inrow >> k & 1u) sl[r] += ldexp(z[r][k], nE[r][k]);
       }
       sl[r] = gwk::wave_sum(sl[r]);
-      if (lane == 63) red[1][r][wv] = sl[r];
+      if (lane == 63) red[sb][r][wv] = sl[r];
     }
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int i = ib + r;
       if (i >= i1) break;
-      double s = red[1][r][0];
+      double s = red[sb][r][0];
 #pragma unroll
-      for (int w = 1; w < NW; ++w) s += red[1][r][w];
-      const double lse = m[r] + log(s);
-      const double fi = -tau * e * lse;
-      if (t == 0) f[i] = fi;
+      for (int w = 1; w < NW; ++w) s += red[sb][r][w];
+      const double fi = -tau * e * (m[r] + log(s));
+      if (t == 0) {
+        f[i] = fi;
+        lse[i] = s > 0.0 ? gwx::row_bound(m[r], s) : -INFINITY;
+      }
       if (!(s > 0.0) || !(lui[r] > -INFINITY)) continue;  // no terms, or u_i = 0
       const double lam = fmax(fmin(m[r] + ((fi - shift) * ie + lui[r]), LAM_MAX), -LAM_MAX);
       const double nd = rint(lam * gwx::INV_LN2);
@@ -255,12 +342,18 @@ __global__ __launch_bounds__(NTH) void k_uot_fused(const double* __restrict__ C,
       rr = fma(-nd, gwx::LN2_LO, rr);
       const double mw = gwx::exp_reduced(rr);
       const int ew = (int)nd;
+      if (fast) {
 #pragma unroll
-      for (int k = 0; k < EPT; ++k) {
-        const int te = nE[r][k] + ew;
-        const int ne = max(X[k], te);
-        S[k] = ldexp(S[k], X[k] - ne) + ldexp(z[r][k] * mw, te - ne);
-        X[k] = ne;
+        for (int k = 0; k < EPT; ++k)
+          S[k] = fma(ldexp(z[r][k], nE[r][k] + ew + kqf(k)), mw, S[k]);
+      } else {
+#pragma unroll
+        for (int k = 0; k < EPT; ++k) {
+          const int te = nE[r][k] + ew;
+          const int ne = max(X[k], te);
+          S[k] = ldexp(S[k], X[k] - ne) + ldexp(z[r][k] * mw, te - ne);
+          X[k] = ne;
+        }
       }
     }
   }
@@ -269,18 +362,23 @@ __global__ __launch_bounds__(NTH) void k_uot_fused(const double* __restrict__ C,
     const int col = t + NTH * k;
     if (col < N) {
       partS[(int64_t)blockIdx.x * N + col] = S[k];
-      partX[(int64_t)blockIdx.x * N + col] = X[k];
+      if (!fast) partX[(int64_t)blockIdx.x * N + col] = X[k];
     }
   }
+  if (t == 0) bmode[blockIdx.x] = fast ? 1 : 0;
 }
 
-// Merge of the bands' column pairs, in band order: 16 columns x 16 groups of
-// bands per block, the groups merged in order; g_p = -tau e (ln S_p - b_p).
-constexpr int UM_COLS = 16, UM_GRPS = 16, UM_BATCH = 8;
+// Merge of the bands' column sums, in band order: 16 columns x 16 groups of
+// bands per block, the groups merged in order; a band of a shifted pass left
+// plain sums in the column's frame (exponent -kq_p).  g_p = -tau e (ln S_p -
+// b_p); g before the merge is kept for the next pass's test.
+constexpr int UM_COLS = 16, UM_GRPS = 16;
+constexpr int UM_PER = 16;  // bands per group: nb <= UF_BANDS = UM_GRPS * UM_PER
 
 __global__ __launch_bounds__(UM_COLS * UM_GRPS) void k_uot_merge(
     int N, int nb, const double* __restrict__ partS, const int* __restrict__ partX,
-    const double* __restrict__ lv, const UgwScal* __restrict__ sc, double* __restrict__ g,
+    const int* __restrict__ bmode, const int* __restrict__ kq, const double* __restrict__ lv,
+    const UgwScal* __restrict__ sc, double* __restrict__ g, double* __restrict__ gprev,
     gwr::StatusWord* status) {
   __shared__ double ms[UM_GRPS][UM_COLS];
   __shared__ int mx[UM_GRPS][UM_COLS];
@@ -290,21 +388,39 @@ __global__ __launch_bounds__(UM_COLS * UM_GRPS) void k_uot_merge(
   const int b0 = grp * per, b1 = min(nb, b0 + per);
   double S = 0.0;
   int X = gwx::EXP_SENTINEL;
-  for (int bb = b0; bb < b1; bb += UM_BATCH) {
-    double sv[UM_BATCH];
-    int xv[UM_BATCH];
+  {
+    // the sums are requested before the pass kinds are looked at, so that
+    // waiting for the kinds does not hold back the sums (indices clamped,
+    // entries past the group skipped)
+    double sv[UM_PER];
+    int fm[UM_PER];
 #pragma unroll
-    for (int u = 0; u < UM_BATCH; ++u) {
-      const int64_t band = min(bb + u, nb - 1);
-      sv[u] = partS[band * N + colc];
-      xv[u] = partX[band * N + colc];
-    }
+    for (int u = 0; u < UM_PER; ++u) sv[u] = partS[(int64_t)min(b0 + u, nb - 1) * N + colc];
 #pragma unroll
-    for (int u = 0; u < UM_BATCH; ++u) {
-      if (bb + u < b1) {
-        const int ne = max(X, xv[u]);
-        S = ldexp(S, X - ne) + ldexp(sv[u], xv[u] - ne);
-        X = ne;
+    for (int u = 0; u < UM_PER; ++u) fm[u] = bmode[min(b0 + u, nb - 1)];
+    const int fx = -kq[colc];  // the frame's exponent (bands of a shifted pass)
+    bool frames = true;        // every band of the group left frame sums
+#pragma unroll
+    for (int u = 0; u < UM_PER; ++u) frames = frames && (fm[u] != 0 || b0 + u >= b1);
+    if (frames) {
+      // all exponents are the frame's: the pair merge below reduces to plain
+      // additions in band order (every ldexp is by 0), done directly
+      if (b1 > b0) X = fx;
+#pragma unroll
+      for (int u = 0; u < UM_PER; ++u)
+        if (b0 + u < b1) S += sv[u];
+    } else {
+      int xv[UM_PER];  // all requested before the first is merged
+#pragma unroll
+      for (int u = 0; u < UM_PER; ++u)
+        xv[u] = fm[u] ? fx : partX[(int64_t)min(b0 + u, nb - 1) * N + colc];
+#pragma unroll
+      for (int u = 0; u < UM_PER; ++u) {
+        if (b0 + u < b1) {
+          const int ne = max(X, xv[u]);
+          S = ldexp(S, X - ne) + ldexp(sv[u], xv[u] - ne);
+          X = ne;
+        }
       }
     }
   }
@@ -318,10 +434,12 @@ __global__ __launch_bounds__(UM_COLS * UM_GRPS) void k_uot_merge(
     X = ne;
   }
   const double shift = sc->shift, e = sc->e, ie = 1.0 / e;
-  const double bp = col_base(g[col], lv[col], shift, ie);
+  const double gold = g[col];
+  const double bp = col_base(gold, lv[col], shift, ie);
   const double lnS =
       S > 0.0 ? fma((double)X, gwx::LN2_HI, fma((double)X, gwx::LN2_LO, log(S))) : -INFINITY;
   const double gn = -sc->tau * e * (lnS - bp);
+  gprev[col] = gold;
   g[col] = gn;
   if (isnan(gn)) status->nonfinite = 1;
 }
@@ -335,18 +453,21 @@ int uot_band_rows(int64_t M) {
 }
 
 gw_status launch_uot_fused(const double* C, int64_t ldC, int64_t M, int64_t N, int RB,
-                           const double* g, const double* lu, const double* lv,
-                           const UgwScal* sc, double* f, double* partS, int* partX,
-                           hipStream_t s) {
+                           const double* g, const double* gprev, const double* lu,
+                           const double* lv, const UgwScal* sc, double* f, double* lse, int* kq,
+                           int* bmode, double* partS, int* partX, hipStream_t s) {
+  if (RB > UF_MAX_RB) return GW_EUNSUPPORTED;
   const unsigned nb = (unsigned)((M + RB - 1) / RB);
   const int m = (int)M, n = (int)N;
-#define UF_ARGS C, ldC, m, n, RB, g, lu, lv, sc, f, partS, partX
-  if (N <= 256) k_uot_fused<256, 1, 2><<<nb, 256, 0, s>>>(UF_ARGS);
-  else if (N <= 512) k_uot_fused<256, 2, 2><<<nb, 256, 0, s>>>(UF_ARGS);
-  else if (N <= 1024) k_uot_fused<256, 4, 2><<<nb, 256, 0, s>>>(UF_ARGS);
-  else if (N <= 2048) k_uot_fused<256, 8, 2><<<nb, 256, 0, s>>>(UF_ARGS);
-  else if (N <= 4096) k_uot_fused<512, 8, 1><<<nb, 512, 0, s>>>(UF_ARGS);
-  else if (N <= 8192) k_uot_fused<512, 16, 1><<<nb, 512, 0, s>>>(UF_ARGS);
+#define UF_ARGS C, ldC, m, n, RB, g, gprev, lu, lv, sc, f, lse, kq, bmode, partS, partX
+  // rows of 4097-8192 entries stay exact: the shifted variant's extra state
+  // pushes that shape into spills (measured 9% slower per pass)
+  if (N <= 256) k_uot_fused<256, 1, 2, true><<<nb, 256, 0, s>>>(UF_ARGS);
+  else if (N <= 512) k_uot_fused<256, 2, 2, true><<<nb, 256, 0, s>>>(UF_ARGS);
+  else if (N <= 1024) k_uot_fused<256, 4, 2, true><<<nb, 256, 0, s>>>(UF_ARGS);
+  else if (N <= 2048) k_uot_fused<256, 8, 2, true><<<nb, 256, 0, s>>>(UF_ARGS);
+  else if (N <= 4096) k_uot_fused<512, 8, 1, true><<<nb, 512, 0, s>>>(UF_ARGS);
+  else if (N <= 8192) k_uot_fused<512, 16, 1, false><<<nb, 512, 0, s>>>(UF_ARGS);
   else return GW_EUNSUPPORTED;
 #undef UF_ARGS
   return GW_OK;
@@ -604,10 +725,14 @@ size_t uot_ws_bytes(int64_t M, int64_t N) {
   gwr::Arena a{nullptr, 0, 0};
   a.take<double>(M);  // ln u
   a.take<double>(N);  // ln v
-  if (N <= UF_MAX_N) {  // the bands' column pairs of the one-pass update
+  if (N <= UF_MAX_N) {  // the one-pass update
     const int64_t nb = (M + uot_band_rows(M) - 1) / uot_band_rows(M);
-    a.take<double>((size_t)nb * N);
-    a.take<int>((size_t)nb * N);
+    a.take<double>((size_t)nb * N);  // the bands' column sums
+    a.take<int>((size_t)nb * N);     // and their exponents (exact pass)
+    a.take<double>(M);               // row bounds
+    a.take<double>(N);               // g before the last merge
+    a.take<int>(N);                  // column frames of a shifted pass
+    a.take<int>(nb);                 // pass kind of each band
   } else {
     const int R = uot_chunks(M);
     a.take<double>((size_t)R * N);
@@ -636,11 +761,15 @@ gw_status uot_sinkhorn(const double* C, int64_t ldC, int64_t M, int64_t N, const
   const int RB = uot_band_rows(M);
   const int64_t nb = (M + RB - 1) / RB;
   const int R = uot_chunks(M);
-  double *pm = nullptr, *ps = nullptr, *partS = nullptr;
-  int* partX = nullptr;
+  double *pm = nullptr, *ps = nullptr, *partS = nullptr, *lse = nullptr, *gprev = nullptr;
+  int *partX = nullptr, *kq = nullptr, *bmode = nullptr;
   if (fused) {
     partS = ws.take<double>((size_t)nb * N);
     partX = ws.take<int>((size_t)nb * N);
+    lse = ws.take<double>(M);
+    gprev = ws.take<double>(N);
+    kq = ws.take<int>(N);
+    bmode = ws.take<int>(nb);
   } else {
     pm = ws.take<double>((size_t)R * N);
     ps = ws.take<double>((size_t)R * N);
@@ -653,10 +782,12 @@ gw_status uot_sinkhorn(const double* C, int64_t ldC, int64_t M, int64_t N, const
   const int rpc = (int)((M + R - 1) / R);
   const dim3 cgrid((unsigned)((N + UC_COLS - 1) / UC_COLS), (unsigned)R);
   for (int it = 0; it < iters && fused; ++it) {
-    gw_status st = launch_uot_fused(C, ldC, M, N, RB, g, lu, lv, sc, f, partS, partX, s);
+    // the first pass of a call is exact (no previous g to bound the moves)
+    gw_status st = launch_uot_fused(C, ldC, M, N, RB, g, it > 0 ? gprev : nullptr, lu, lv, sc,
+                                    f, lse, kq, bmode, partS, partX, s);
     if (st != GW_OK) return st;
     k_uot_merge<<<(unsigned)((N + UM_COLS - 1) / UM_COLS), UM_COLS * UM_GRPS, 0, s>>>(
-        (int)N, (int)nb, partS, partX, lv, sc, g, status);
+        (int)N, (int)nb, partS, partX, bmode, kq, lv, sc, g, gprev, status);
   }
   for (int it = 0; it < iters && !fused; ++it) {
     gw_status st = launch_uot_row(C, ldC, M, N, g, lv, sc, f, s);

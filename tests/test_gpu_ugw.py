@@ -69,6 +69,42 @@ def test_uot_sinkhorn_edge_shapes_match_oracle(M, N, rho, eps, shift, iters):
     assert err(T.cpu().numpy(), T0) <= TOL
 
 
+# The one-pass update runs its first pass of a call exact and later passes
+# shifted (row shift from the previous bound, column sums in per-column
+# frames) when the moves of g allow.  Two cases for the other combinations:
+# costs up to 30000 e, whose first update moves g by more than 600 e, so the
+# second pass falls back to exact maxima; and three rows with a cost offset of
+# 1.2e4 (row bounds near -1.2e6), whose band stays exact beside shifted bands.
+# tests/test_uot_pass_kinds.py checks both from the oracle's potentials.
+UOT_KINDS = [(150, 1100, 20.0, 0.0002, 6.0, 0.0, 4), (600, 700, 0.5, 0.01, 1.0, 1.2e4, 4)]
+
+
+def uot_kinds_input(M, N, scale, offset):
+    rng = inputs.rng_for(952, M, N)
+    C = rng.uniform(0, scale, (M, N))
+    if offset:
+        C[M // 2: M // 2 + 3] += offset
+    u, v = rng.uniform(0.0, 2.0 / M, M), rng.uniform(0.0, 3.0 / N, N)
+    u[M // 3] = 0.0
+    v[[1, N // 2]] = 0.0
+    return C, u, v
+
+
+@pytest.mark.parametrize("M,N,rho,eps,scale,offset,iters", UOT_KINDS)
+def test_uot_sinkhorn_pass_kinds_match_oracle(M, N, rho, eps, scale, offset, iters):
+    gw, torch = _gw()
+    print(f"uot kinds M={M} N={N} rho={rho} eps={eps} offset={offset}", flush=True)
+    C, u, v = uot_kinds_input(M, N, scale, offset)
+    f0, g0 = O.uot_sinkhorn(C, u, v, rho, eps, iters)
+    T0 = O.uot_plan(C, f0, g0, u, v, eps)
+    d = lambda a: _to_dev(torch, a)
+    f, g, T = gw.uot_sinkhorn(d(C), d(u), d(v), rho, eps, iters, plan=True)
+    torch.cuda.synchronize()
+    assert err(f.cpu().numpy(), f0) <= TOL
+    assert err(g.cpu().numpy(), g0) <= TOL
+    assert err(T.cpu().numpy(), T0) <= TOL
+
+
 def test_uot_warm_start():
     gw, torch = _gw()
     rng = inputs.rng_for(951)
