@@ -179,6 +179,28 @@ def test_solve_ugw_n1024_in_full():
     assert abs(obj.cpu().numpy()[0] - U0) <= TOL * abs(U0)
 
 
+def test_uot_sinkhorn_n4096_in_full():
+    """The unbalanced Sinkhorn at the UGW workload's size and launch shape
+    (rows of 4096 entries, shifted passes after the first): 3-Gaussian-mixture
+    measures of mass 1 and 1.5, cost (x_i - y_p)^2 on the [0,1] grid,
+    eps = 2e-3, 20 iterations; f, g and the plan in full."""
+    gw, torch = _gw()
+    n = 4096
+    print(f"uot full n={n}", flush=True)
+    rng = inputs.rng_for(13, n)
+    u, v = inputs.gauss_mixture_1d(n, rng), 1.5 * inputs.gauss_mixture_1d(n, rng)
+    x = np.arange(n) / (n - 1)
+    C = (x[:, None] - x[None, :]) ** 2
+    f0, g0 = O.uot_sinkhorn(C, u, v, 1.0, 2e-3, 20)
+    T0 = O.uot_plan(C, f0, g0, u, v, 2e-3)
+    d = lambda a: _to_dev(torch, a)
+    f, g, T = gw.uot_sinkhorn(d(C), d(u), d(v), 1.0, 2e-3, 20, plan=True)
+    torch.cuda.synchronize()
+    assert err(f.cpu().numpy(), f0) <= TOL
+    assert err(g.cpu().numpy(), g0) <= TOL
+    assert err(T.cpu().numpy(), T0) <= TOL
+
+
 def test_ugw_rejects_bad_arguments():
     gw, torch = _gw()
     X = gw.unit_grid((4,), 1)
