@@ -179,6 +179,46 @@ def test_solve_ugw_n1024_in_full():
     assert abs(obj.cpu().numpy()[0] - U0) <= TOL * abs(U0)
 
 
+def _random_uot_case(c):
+    """Seeded random shape, parameters, costs and measures (some zero-mass
+    rows and columns) for the sweep below."""
+    rng = inputs.rng_for(955, c)
+    M = int(rng.integers(1, 700))
+    N = int(rng.choice([int(rng.integers(1, 300)), int(rng.integers(300, 2049)),
+                        int(rng.integers(2049, 4097))]))
+    rho, eps = float(10 ** rng.uniform(-1.3, 1.3)), float(10 ** rng.uniform(-3.5, -1))
+    shift, scale = float(rng.uniform(-0.5, 0.5)), float(10 ** rng.uniform(-1, 0.7))
+    iters = int(rng.integers(2, 9))
+    C = rng.uniform(0, scale, (M, N))
+    u, v = rng.uniform(0.0, 2.0 / M, M), rng.uniform(0.0, 3.0 / N, N)
+    if M > 3:
+        u[rng.choice(M, size=max(1, M // 10), replace=False)] = 0.0
+    if N > 3 and rng.uniform() < 0.7:
+        v[rng.choice(N, size=max(1, N // 10), replace=False)] = 0.0
+    return C, u, v, rho, eps, shift, iters
+
+
+@pytest.mark.parametrize("c", range(12))
+def test_uot_sinkhorn_random_cases_match_oracle(c):
+    """A seeded sweep over shapes (rows of 1-4096 entries), rho, eps, cost
+    scales and shifts, with zero-mass entries: both pass kinds of the
+    one-pass update under parameters no hand-picked case fixes."""
+    gw, torch = _gw()
+    C, u, v, rho, eps, shift, iters = _random_uot_case(c)
+    M, N = C.shape
+    print(f"uot random case {c}: M={M} N={N} rho={rho:.3g} eps={eps:.3g} shift={shift:.2f}", flush=True)
+    f0, g0 = O.uot_sinkhorn(C + shift, u, v, rho, eps, iters)
+    T0 = O.uot_plan(C + shift, f0, g0, u, v, eps)
+    d = lambda a: _to_dev(torch, a)
+    f, g, T = gw.uot_sinkhorn(d(C), d(u), d(v), rho, eps, iters, c_shift=shift, plan=True)
+    torch.cuda.synchronize()
+    fin = np.isfinite(f0)
+    assert np.array_equal(np.isfinite(f.cpu().numpy()), fin)
+    assert err(f.cpu().numpy()[fin], f0[fin]) <= TOL
+    assert err(g.cpu().numpy(), g0) <= TOL
+    assert err(T.cpu().numpy(), T0) <= TOL
+
+
 def test_uot_sinkhorn_n4096_in_full():
     """The unbalanced Sinkhorn at the UGW workload's size and launch shape
     (rows of 4096 entries, shifted passes after the first): 3-Gaussian-mixture
