@@ -168,6 +168,53 @@ def test_sinkhorn_matches_oracle(M, N, eps, iters):
     assert err(T.cpu().numpy(), P0) <= TOL
 
 
+def _random_sk_case(c):
+    """Seeded random shape (rows of 1-24000 entries), eps, cost scale and
+    marginals (some zero-mass entries), iteration count and start."""
+    rng = inputs.rng_for(207, c)
+    M = int(rng.integers(1, 700))
+    N = int(rng.choice([int(rng.integers(1, 300)), int(rng.integers(300, 4097)),
+                        int(rng.integers(4097, 16385)), int(rng.integers(16385, 24000))],
+                       p=[0.25, 0.35, 0.3, 0.1]))
+    eps, scale = float(10 ** rng.uniform(-3.3, -1)), float(10 ** rng.uniform(-1, 0.7))
+    iters = int(rng.integers(2, 9))
+    C = rng.uniform(0, scale, (M, N))
+    p, q = inputs.dirichlet(M, rng), inputs.dirichlet(N, rng)
+    if M > 3 and rng.uniform() < 0.5:
+        p[rng.choice(M, size=max(1, M // 20), replace=False)] = 0.0
+        p /= p.sum()
+    if N > 3 and rng.uniform() < 0.5:
+        q[rng.choice(N, size=max(1, N // 20), replace=False)] = 0.0
+        q /= q.sum()
+    warm = bool(rng.uniform() < 0.3)
+    return C, p, q, eps, iters, warm
+
+
+@pytest.mark.parametrize("c", range(12))
+def test_sinkhorn_random_cases_match_oracle(c):
+    """A seeded sweep over shapes, eps, cost scales, zero-mass entries and
+    warm starts (from the oracle's potentials after two iterations): the row
+    pass classes, both pass kinds and the wide-row slabs under parameters no
+    hand-picked case fixes."""
+    gw, torch = _gw()
+    C, p, q, eps, iters, warm = _random_sk_case(c)
+    M, N = C.shape
+    print(f"sinkhorn random case {c}: M={M} N={N} eps={eps:.3g} iters={iters} warm={warm}",
+          flush=True)
+    d = lambda a: _to_dev(torch, a)
+    if warm:
+        fw, gw0 = O.sinkhorn(C, p, q, eps, 2)
+        f0, g0 = O.sinkhorn(C, p, q, eps, iters, fw, gw0)
+        f, g, T = gw.sinkhorn(d(C), d(p), d(q), eps, iters, f=d(fw), g=d(gw0), plan=True)
+    else:
+        f0, g0 = O.sinkhorn(C, p, q, eps, iters)
+        f, g, T = gw.sinkhorn(d(C), d(p), d(q), eps, iters, plan=True)
+    torch.cuda.synchronize()
+    assert err(f.cpu().numpy(), f0) <= TOL
+    assert err(g.cpu().numpy(), g0) <= TOL
+    assert err(T.cpu().numpy(), O.plan(C, f0, g0, eps)) <= TOL
+
+
 def test_sinkhorn_extreme_ratio_exact_then_shifted_passes():
     """C/eps up to 7000: the first update moves g by more than 600 eps (the
     next pass takes exact maxima), later ones by a few eps (shifted passes)."""
