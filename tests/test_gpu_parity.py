@@ -69,6 +69,40 @@ def test_grad_1d_matches_oracle(M, N, kx, ky, path):
     assert err(G, ref) <= TOL
 
 
+def _random_grid_spec(rng):
+    """A seeded random grid of at most 800 points: 1D, 2D (sides up to 80)
+    or 3D, k in 1..4 or squared Euclidean."""
+    nd = int(rng.choice([1, 2, 3], p=[0.4, 0.4, 0.2]))
+    if nd == 1:
+        shape = (int(rng.integers(1, 801)),)
+    elif nd == 2:
+        H = int(rng.integers(1, 81))
+        shape = (H, int(rng.integers(1, 800 // H + 1)))
+    else:
+        shape = tuple(int(rng.integers(1, 10)) for _ in range(3))
+    if rng.uniform() < 0.25:
+        return shape, 2, 1
+    return shape, int(rng.integers(1, 5)), 0
+
+
+@pytest.mark.parametrize("c", range(16))
+def test_grad_random_cases_match_oracle(c):
+    """A seeded sweep over pairs of 1D, 2D and 3D grids (mixed pairs, ragged
+    tiles, k = 1..4, both metrics), random plans and marginals; 1D pairs also
+    on the dense path."""
+    gw, torch = _gw()
+    rng = inputs.rng_for(208, c)
+    (sx, kx, mx), (sy, ky, my) = _random_grid_spec(rng), _random_grid_spec(rng)
+    X, Y = gw.unit_grid(sx, kx, mx), gw.unit_grid(sy, ky, my)
+    path = "dense" if len(sx) == 1 and len(sy) == 1 and rng.uniform() < 0.5 else "fast"
+    print(f"grad random case {c}: {sx} k{kx} m{mx} x {sy} k{ky} m{my} {path}", flush=True)
+    T = inputs.random_plan(X.size, Y.size, rng)
+    p, q = inputs.dirichlet(X.size, rng), inputs.dirichlet(Y.size, rng)
+    ref = O.grad_dense(ogrid(X), ogrid(Y), p, q, T)
+    G = _grad(gw, torch, X, Y, p, q, T, path)
+    assert err(G, ref) <= TOL
+
+
 @pytest.mark.parametrize("M,N,kx,ky", [(97, 64, 1, 2), (64, 100, 2, 2), (129, 31, 2, 1)])
 @pytest.mark.parametrize("path", ["fast", "dense"])
 def test_grad_1d_integer_inputs_bit_exact(M, N, kx, ky, path):
