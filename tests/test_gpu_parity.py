@@ -69,17 +69,18 @@ def test_grad_1d_matches_oracle(M, N, kx, ky, path):
     assert err(G, ref) <= TOL
 
 
-def _random_grid_spec(rng):
-    """A seeded random grid of at most 800 points: 1D, 2D (sides up to 80)
-    or 3D, k in 1..4 or squared Euclidean."""
+def _random_grid_spec(rng, npts=800):
+    """A seeded random grid of at most npts points: 1D, 2D (sides up to
+    npts / 10) or 3D, k in 1..4 or squared Euclidean."""
     nd = int(rng.choice([1, 2, 3], p=[0.4, 0.4, 0.2]))
     if nd == 1:
-        shape = (int(rng.integers(1, 801)),)
+        shape = (int(rng.integers(1, npts + 1)),)
     elif nd == 2:
-        H = int(rng.integers(1, 81))
-        shape = (H, int(rng.integers(1, 800 // H + 1)))
+        H = int(rng.integers(1, npts // 10 + 1))
+        shape = (H, int(rng.integers(1, npts // H + 1)))
     else:
-        shape = tuple(int(rng.integers(1, 10)) for _ in range(3))
+        side = int(round(npts ** (1.0 / 3.0)))
+        shape = tuple(int(rng.integers(1, side + 1)) for _ in range(3))
     if rng.uniform() < 0.25:
         return shape, 2, 1
     return shape, int(rng.integers(1, 5)), 0
@@ -322,6 +323,48 @@ def test_sinkhorn_wide_rows_warm_start():
     fd, gd = gw.sinkhorn(_to_dev(torch, C), _to_dev(torch, p), _to_dev(torch, q), 0.02, 2, f=fd, g=gd)
     torch.cuda.synchronize()
     assert err(fd.cpu().numpy(), f2) <= TOL and err(gd.cpu().numpy(), g2) <= TOL
+
+
+def _max_distance(G):
+    """The largest distance on a grid: (h sum (side - 1))^k, or h^2 sum
+    (side - 1)^2 for squared Euclidean."""
+    ext = [s - 1 for s in G.shape]
+    if G.metric == 1:
+        return G.h * G.h * sum(e * e for e in ext)
+    return (G.h * sum(ext)) ** G.k
+
+
+@pytest.mark.parametrize("c", range(8))
+def test_solve_random_cases_match_oracle(c):
+    """A seeded sweep of short solves over random grid pairs (1D, 2D, 3D,
+    mixed; k = 1..4, both metrics), Dirichlet marginals, eps, outer and inner
+    counts, cold or warm Sinkhorn starts, FAST or (1D pairs) dense: T, f, g
+    and both objectives."""
+    gw, torch = _gw()
+    rng = inputs.rng_for(215, c)
+    (sx, kx, mx), (sy, ky, my) = _random_grid_spec(rng, 300), _random_grid_spec(rng, 300)
+    X, Y = gw.unit_grid(sx, kx, mx), gw.unit_grid(sy, ky, my)
+    path = "dense" if len(sx) == 1 and len(sy) == 1 and rng.uniform() < 0.5 else "fast"
+    # eps relative to the squared largest distance (the cost's scale), so that
+    # C/eps stays in the thousands: far beyond, the plan's exponentials turn
+    # rounding in C into relative errors above the tolerance on any FP64 path
+    dmax = max(_max_distance(X), _max_distance(Y))
+    eps = float(10 ** rng.uniform(-3.5, -1.8)) * (dmax * dmax if dmax > 0 else 1.0)
+    outer, inner = int(rng.integers(1, 4)), int(rng.integers(5, 31))
+    warm = bool(rng.uniform() < 0.3)
+    p, q = inputs.dirichlet(X.size, rng), inputs.dirichlet(Y.size, rng)
+    print(f"solve random case {c}: {sx} k{kx} m{mx} x {sy} k{ky} m{my} eps={eps:.3g} "
+          f"{outer}x{inner} warm={warm} {path}", flush=True)
+    T0, f0, g0, (E0, R0) = O.solve(ogrid(X), ogrid(Y), p, q, eps, outer, inner, warm=warm)
+    T, f, g, obj = gw.solve(X, Y, _to_dev(torch, p), _to_dev(torch, q), eps, outer, inner,
+                            path=path, warm=warm)
+    torch.cuda.synchronize()
+    assert err(T.cpu().numpy(), T0) <= TOL
+    assert err(f.cpu().numpy(), f0) <= TOL
+    assert err(g.cpu().numpy(), g0) <= TOL
+    o = obj.cpu().numpy()
+    assert abs(o[0] - E0) <= TOL * abs(E0)
+    assert abs(o[1] - R0) <= TOL * max(abs(R0), abs(E0))
 
 
 def test_solve_wide_rows_match_oracle():
