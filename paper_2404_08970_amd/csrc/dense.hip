@@ -28,10 +28,11 @@ constexpr int WTM = 32, WTN = 64, NTI = WTM / 16, NTJ = WTN / 16;
 // stage is formed from its indices (integers, exact below 2^53) once per block, into LDS
 // beside it, instead of by every wave that reads it.
 // 128 x 128 block tiles of 8 waves (32 x 64 each) keep the accumulators in
-// 64 registers, so two blocks share a CU.
-template <bool SYN_B>
+// 64 registers, so two blocks share a CU.  KD is the distance exponent (the
+// powers unroll into KD - 1 multiplications).
+template <bool SYN_B, int KD>
 __global__ __launch_bounds__(NTHR) void k_dense_f64(const double* __restrict__ Amem, int64_t lda,
-                                                     int M, int N, int K, int kd,
+                                                     int M, int N, int K,
                                                      double* __restrict__ C, int64_t ldc,
                                                      const double* __restrict__ c1,
                                                      const double* __restrict__ c2, double s2) {
@@ -71,8 +72,11 @@ __global__ __launch_bounds__(NTHR) void k_dense_f64(const double* __restrict__ A
       const int e = t * PER + u;
       const int r = SYN_B ? e / DM : e / DK, c = SYN_B ? e % DM : e % DK;
       const int i = SYN_B ? k0 + r : m0 + r, j = SYN_B ? n0 + c : k0 + c;
-      const int d = i > j ? i - j : j - i;
-      Ds[buf][r][c] = gwk::ipow((double)d, kd);
+      const double d = (double)(i > j ? i - j : j - i);
+      double dk = d;
+#pragma unroll
+      for (int e = 1; e < KD; ++e) dk *= d;
+      Ds[buf][r][c] = dk;
     }
   };
   auto compute = [&](int buf) {
@@ -107,7 +111,17 @@ __global__ __launch_bounds__(NTHR) void k_dense_f64(const double* __restrict__ A
     __syncthreads();
   }
   // store: for the FP64 16x16x4 instruction, accumulator slot v of a lane holds
-  // row 4 * v + lane / 16 and column lane % 16 of its 16 x 16 block
+  // row 4 * v + lane / 16 and column lane % 16 of its 16 x 16 block; the
+  // constant terms of the lane's rows and columns are all requested first
+  double c1v[NTI][4], c2v[NTJ];
+  if (c1) {
+#pragma unroll
+    for (int i = 0; i < NTI; ++i)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) c1v[i][v] = c1[min(m0 + wm + i * 16 + 4 * v + lk, M - 1)];
+#pragma unroll
+    for (int j = 0; j < NTJ; ++j) c2v[j] = c2[min(n0 + wn + j * 16 + li, N - 1)];
+  }
 #pragma unroll
   for (int i = 0; i < NTI; ++i)
 #pragma unroll
@@ -118,7 +132,7 @@ __global__ __launch_bounds__(NTHR) void k_dense_f64(const double* __restrict__ A
         const int gn = n0 + wn + j * 16 + li;
         if (gm < M && gn < N) {
           const double x = acc[i][j][v];
-          C[(int64_t)gm * ldc + gn] = c1 ? (c1[gm] + c2[gn]) - s2 * x : x;
+          C[(int64_t)gm * ldc + gn] = c1 ? (c1v[i][v] + c2v[j]) - s2 * x : x;
         }
       }
 }
@@ -158,9 +172,21 @@ gw_status dense(const gwr::Grid& X, const gwr::Grid& Y, const double* p, const d
   gwr::ProfScope ps(gwr::kFamDense, s);
   dim3 grid((N + DM - 1) / DM, (M + DM - 1) / DM);
   // A = T D~_Y
-  k_dense_f64<true><<<grid, NTHR, 0, s>>>(T, ldT, M, N, N, Y.k1d(), A, N, nullptr, nullptr, 0.0);
+  switch (Y.k1d()) {
+    case 1: k_dense_f64<true, 1><<<grid, NTHR, 0, s>>>(T, ldT, M, N, N, A, N, nullptr, nullptr, 0.0); break;
+    case 2: k_dense_f64<true, 2><<<grid, NTHR, 0, s>>>(T, ldT, M, N, N, A, N, nullptr, nullptr, 0.0); break;
+    case 3: k_dense_f64<true, 3><<<grid, NTHR, 0, s>>>(T, ldT, M, N, N, A, N, nullptr, nullptr, 0.0); break;
+    case 4: k_dense_f64<true, 4><<<grid, NTHR, 0, s>>>(T, ldT, M, N, N, A, N, nullptr, nullptr, 0.0); break;
+    default: return GW_EUNSUPPORTED;
+  }
   // B = D~_X A, G = (c1 + c2) - s2 B
-  k_dense_f64<false><<<grid, NTHR, 0, s>>>(A, N, M, N, M, X.k1d(), G, ldG, c1, c2, s2);
+  switch (X.k1d()) {
+    case 1: k_dense_f64<false, 1><<<grid, NTHR, 0, s>>>(A, N, M, N, M, G, ldG, c1, c2, s2); break;
+    case 2: k_dense_f64<false, 2><<<grid, NTHR, 0, s>>>(A, N, M, N, M, G, ldG, c1, c2, s2); break;
+    case 3: k_dense_f64<false, 3><<<grid, NTHR, 0, s>>>(A, N, M, N, M, G, ldG, c1, c2, s2); break;
+    case 4: k_dense_f64<false, 4><<<grid, NTHR, 0, s>>>(A, N, M, N, M, G, ldG, c1, c2, s2); break;
+    default: return GW_EUNSUPPORTED;
+  }
   return gwr::last_launch_status();
 }
 
