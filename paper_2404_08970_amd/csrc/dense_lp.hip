@@ -407,7 +407,19 @@ __global__ __launch_bounds__(GemmShape<SPLIT>::NTH) void k_gemm_bt(
     __syncthreads();
   }
   flush();
-  // FP32 16x16 accumulator layout: slot v of a lane holds row 4 * (lane / 16) + v
+  // FP32 16x16 accumulator layout: slot v of a lane holds row 4 * (lane / 16) + v;
+  // with G, the constant terms of the lane's rows and columns are all
+  // requested before the stores
+  double c1v[OUT ? NTM : 1][4], c2v[OUT ? NTN : 1];
+  if constexpr (OUT != 0) {
+#pragma unroll
+    for (int i = 0; i < NTM; ++i)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        c1v[i][v] = c1[min(m0 + wm + i * 16 + 4 * lq + v, (int64_t)Mo - 1)];
+#pragma unroll
+    for (int j = 0; j < NTN; ++j) c2v[j] = c2[min(n0 + wn + j * 16 + li, (int64_t)No - 1)];
+  }
 #pragma unroll
   for (int i = 0; i < NTM; ++i)
 #pragma unroll
@@ -425,7 +437,7 @@ __global__ __launch_bounds__(GemmShape<SPLIT>::NTH) void k_gemm_bt(
             if constexpr (SPLIT) Ol[gm * ldo + gn] = lo_bf16(x);
           }
         } else {
-          if (gm < Mo && gn < No) G[gm * ldG + gn] = (c1[gm] + c2[gn]) - s2 * x;
+          if (gm < Mo && gn < No) G[gm * ldG + gn] = (c1v[i][v] + c2v[j]) - s2 * x;
         }
       }
 }
@@ -500,6 +512,18 @@ __global__ __launch_bounds__(512) void k_gemm_bt_f32(const float* __restrict__ A
     if (kt + 1 < nk) lstore((kt + 1) & 1);
     __syncthreads();
   }
+  // with G, the constant terms of the lane's rows and columns are all
+  // requested before the stores
+  double c1v[OUT ? NTI : 1][4], c2v[OUT ? NTJ : 1];
+  if constexpr (OUT != 0) {
+#pragma unroll
+    for (int i = 0; i < NTI; ++i)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        c1v[i][v] = c1[min(m0 + wm + i * 16 + 4 * lq + v, (int64_t)Mo - 1)];
+#pragma unroll
+    for (int j = 0; j < NTJ; ++j) c2v[j] = c2[min(n0 + wn + j * 16 + li, (int64_t)No - 1)];
+  }
 #pragma unroll
   for (int i = 0; i < NTI; ++i)
 #pragma unroll
@@ -510,7 +534,7 @@ __global__ __launch_bounds__(512) void k_gemm_bt_f32(const float* __restrict__ A
         const int64_t gn = n0 + wn + j * 16 + li;
         if (gm < Mo && gn < No) {
           if constexpr (OUT == 0) O[gm * ldo + gn] = acc[i][j][v];
-          else G[gm * ldG + gn] = (c1[gm] + c2[gn]) - s2 * (double)acc[i][j][v];
+          else G[gm * ldG + gn] = (c1v[i][v] + c2v[j]) - s2 * (double)acc[i][j][v];
         }
       }
 }
