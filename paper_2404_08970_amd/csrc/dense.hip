@@ -36,11 +36,15 @@ __global__ __launch_bounds__(NTHR) void k_dense_f64(const double* __restrict__ A
                                                      double* __restrict__ C, int64_t ldc,
                                                      const double* __restrict__ c1,
                                                      const double* __restrict__ c2, double s2) {
-  // SYN_B: A tiles [DM rows][DK k]; else B tiles [DK k][DM cols]; padded rows
-  constexpr int R0 = SYN_B ? DM : DK, R1 = SYN_B ? DK + 1 : DM + 1;
+  // SYN_B: A tiles [DM rows][DK k]; else B tiles [DK k][DM cols].  Rows are
+  // padded so that a wave's 64 operand reads (16 rows or columns x 4 k) fall
+  // at most two to a pair of LDS banks: DK + 2 for the row-operand layout,
+  // DM + 8 for the column-operand layout
+  constexpr int PA = DK + 2, PB = DM + 8;
+  constexpr int R0 = SYN_B ? DM : DK, R1 = SYN_B ? PA : PB;
   constexpr int PER = DM * DK / NTHR;  // memory-operand entries per thread and stage
   __shared__ double Ms[2][R0][R1];
-  __shared__ double Ds[2][SYN_B ? DK : DM][SYN_B ? DM + 1 : DK + 1];  // distance tile
+  __shared__ double Ds[2][SYN_B ? DK : DM][SYN_B ? PB : PA];  // distance tile
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int wm = (wave >> 1) * WTM, wn = (wave & 1) * WTN;  // wave tile origin in block
   const int m0 = blockIdx.y * DM, n0 = blockIdx.x * DM;
