@@ -56,6 +56,33 @@ def test_grad_fgw_2d_matches_oracle(sx, sy, kx, ky, mx, my, theta):
     assert err(G.cpu().numpy(), ref) <= TOL
 
 
+@pytest.mark.parametrize("c", range(10))
+def test_grad_fgw_random_cases_match_oracle(c):
+    """A seeded sweep over grid pairs (1D, 2D, 3D, mixed; k = 1..4, both
+    metrics), theta in [0, 1], N(0,1) or gray-level features; 1D pairs also on
+    the dense path."""
+    from test_gpu_parity import _random_grid_spec
+    gw, torch = _gw()
+    rng = inputs.rng_for(803, c)
+    (sx, kx, mx), (sy, ky, my) = _random_grid_spec(rng, 600), _random_grid_spec(rng, 600)
+    X, Y = gw.unit_grid(sx, kx, mx), gw.unit_grid(sy, ky, my)
+    path = "dense" if len(sx) == 1 and len(sy) == 1 and rng.uniform() < 0.5 else "fast"
+    theta = float(rng.choice([0.0, 1.0, rng.uniform()], p=[0.15, 0.15, 0.7]))
+    print(f"grad_fgw random case {c}: {sx} k{kx} m{mx} x {sy} k{ky} m{my} theta={theta:.3f} {path}",
+          flush=True)
+    T = inputs.random_plan(X.size, Y.size, rng)
+    p, q = inputs.dirichlet(X.size, rng), inputs.dirichlet(Y.size, rng)
+    if rng.uniform() < 0.5:
+        fa, fb = _features(X.size, Y.size, rng)
+    else:
+        fa, fb = rng.uniform(0, 1, X.size), rng.uniform(0, 1, Y.size)
+    ref = O.grad_fgw(ogrid(X), ogrid(Y), p, q, T, fa, fb, theta)
+    d = lambda a: _to_dev(torch, a)
+    G = gw.grad_fgw(X, Y, d(p), d(q), d(fa), d(fb), theta, d(T), path=path)
+    torch.cuda.synchronize()
+    assert err(G.cpu().numpy(), ref) <= TOL
+
+
 SOLVE_CASES = [((96,), (80,), 1, 1, 0.5, 0.02, 3, 30, "fast"),
                ((150,), (129,), 1, 2, 0.3, 0.01, 4, 25, "dense"),
                ((64,), (200,), 2, 1, 0.0, 0.05, 2, 40, "fast"),
